@@ -1,0 +1,228 @@
+"""FP64 CPU oracle for list-mode TOF-weighted MLEM (test infrastructure).
+
+Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It shares no code with the HIP
+library; see ``oracle.c`` for what it computes and which passages of the
+paper each part follows.  This wrapper only marshals arrays (and holds the
+oracle's own packed-event codec, written with NumPy from the record layout).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+N_PHI = 2048  # azimuth nodes of the acceptance quadrature
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c (gcc -O2, IEEE semantics: no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fno-fast-math", "-shared", "-fPIC", "-std=c99",
+                               "-D_DEFAULT_SOURCE", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Geom(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("pad_", C.c_int32),
+                ("x0", C.c_double), ("y0", C.c_double), ("z0", C.c_double),
+                ("vx", C.c_double), ("vy", C.c_double), ("vz", C.c_double),
+                ("R", C.c_double), ("H", C.c_double), ("max_axial_deg", C.c_double),
+                ("tof_fwhm_ps", C.c_double), ("trunc_sigmas", C.c_double), ("c_mm_per_ps", C.c_double)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_eff", C.c_int64), ("sum_sx", C.c_double), ("loglik", C.c_double)]
+
+
+_lib = None
+
+
+def _L():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        lib = C.CDLL(_LIB)
+        P = C.POINTER
+        G = P(Geom)
+        d = P(C.c_double)
+        lib.or_sigma_mm.argtypes = [C.c_double, C.c_double]
+        lib.or_sigma_mm.restype = C.c_double
+        lib.or_system_row.argtypes = [G, d, P(C.c_int64), d, C.c_int64]
+        lib.or_system_row.restype = C.c_int64
+        lib.or_windows.argtypes = [G, d, C.c_int64, d, d]
+        lib.or_forward.argtypes = [G, d, C.c_int64, d, d]
+        lib.or_back.argtypes = [G, d, C.c_int64, d, d]
+        lib.or_acceptance.argtypes = [G, d, C.c_int]
+        lib.or_acceptance.restype = C.c_double
+        lib.or_acceptance_points.argtypes = [G, d, C.c_int64, C.c_int, d]
+        lib.or_sensitivity.argtypes = [G, C.c_int, d]
+        lib.or_mlem.argtypes = [G, d, C.c_int64, d, d, C.c_int, d, P(Stats)]
+        lib.or_initial_image.argtypes = [G, d, C.c_int64, d]
+        lib.or_num_threads.restype = C.c_int
+        _lib = lib
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def geom(g: dict) -> Geom:
+    """Oracle geometry from a plain dict (mm, ps): nx ny nz x0 y0 z0 vx vy vz
+    scanner_radius scanner_half_length max_axial_angle_deg tof_fwhm_ps
+    tof_trunc_sigmas c_mm_per_ps."""
+    o = Geom()
+    o.nx, o.ny, o.nz = int(g["nx"]), int(g["ny"]), int(g["nz"])
+    o.x0, o.y0, o.z0 = float(g["x0"]), float(g["y0"]), float(g["z0"])
+    o.vx, o.vy, o.vz = float(g["vx"]), float(g["vy"]), float(g["vz"])
+    o.R, o.H = float(g["scanner_radius"]), float(g["scanner_half_length"])
+    o.max_axial_deg = float(g.get("max_axial_angle_deg", 0.0))
+    o.tof_fwhm_ps = float(g.get("tof_fwhm_ps", 0.0))
+    o.trunc_sigmas = float(g.get("tof_trunc_sigmas", 3.0))
+    o.c_mm_per_ps = float(g.get("c_mm_per_ps", 0.299792458))
+    return o
+
+
+def _ev64(ev) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(ev, dtype=np.float64).reshape(-1, 7))
+    return a
+
+
+def sigma_mm(fwhm_ps: float, c_mm_per_ps: float = 0.299792458) -> float:
+    return _L().or_sigma_mm(fwhm_ps, c_mm_per_ps)
+
+
+def system_row(g: dict, ev):
+    """(voxel indices, weights) of one event's row of A."""
+    G = geom(g)
+    e = _ev64(ev)[0]
+    cap = G.nx + G.ny + G.nz + 5
+    jj = np.empty(cap, np.int64)
+    aa = np.empty(cap, np.float64)
+    m = _L().or_system_row(C.byref(G), _dp(e), jj.ctypes.data_as(C.POINTER(C.c_int64)), _dp(aa), cap)
+    return jj[:m].copy(), aa[:m].copy()
+
+
+def system_matrix(g: dict, ev) -> np.ndarray:
+    """Dense A (n_events x n_voxels); tiny problems only."""
+    e = _ev64(ev)
+    V = int(g["nx"]) * int(g["ny"]) * int(g["nz"])
+    A = np.zeros((len(e), V))
+    for i in range(len(e)):
+        j, a = system_row(g, e[i])
+        np.add.at(A[i], j, a)
+    return A
+
+
+def windows(g: dict, ev):
+    G = geom(g)
+    e = _ev64(ev)
+    lo = np.empty(len(e))
+    hi = np.empty(len(e))
+    _L().or_windows(C.byref(G), _dp(e), len(e), _dp(lo), _dp(hi))
+    return lo, hi
+
+
+def forward(g: dict, ev, x) -> np.ndarray:
+    G = geom(g)
+    e = _ev64(ev)
+    xx = np.ascontiguousarray(np.asarray(x, np.float64).ravel())
+    f = np.empty(len(e))
+    _L().or_forward(C.byref(G), _dp(e), len(e), _dp(xx), _dp(f))
+    return f
+
+
+def back(g: dict, ev, w) -> np.ndarray:
+    G = geom(g)
+    e = _ev64(ev)
+    ww = np.ascontiguousarray(np.asarray(w, np.float64).ravel())
+    b = np.empty(G.nx * G.ny * G.nz)
+    _L().or_back(C.byref(G), _dp(e), len(e), _dp(ww), _dp(b))
+    return b
+
+
+def acceptance(g: dict, pts, n_phi: int = N_PHI) -> np.ndarray:
+    G = geom(g)
+    p = np.ascontiguousarray(np.asarray(pts, np.float64).reshape(-1, 3))
+    out = np.empty(len(p))
+    _L().or_acceptance_points(C.byref(G), _dp(p), len(p), n_phi, _dp(out))
+    return out
+
+
+def sensitivity(g: dict, n_phi: int = N_PHI) -> np.ndarray:
+    G = geom(g)
+    s = np.empty(G.nx * G.ny * G.nz)
+    _L().or_sensitivity(C.byref(G), n_phi, _dp(s))
+    return s
+
+
+def initial_image(g: dict, s, n_events: int) -> np.ndarray:
+    G = geom(g)
+    ss = np.ascontiguousarray(np.asarray(s, np.float64).ravel())
+    x = np.empty_like(ss)
+    _L().or_initial_image(C.byref(G), _dp(ss), int(n_events), _dp(x))
+    return x
+
+
+def mlem(g: dict, ev, s, n_iter: int, x0: Optional[np.ndarray] = None, history: bool = False):
+    """Run n_iter MLEM iterations.  Returns (x, stats[, hist]) where stats is a
+    list of dicts (n_eff, sum_sx, loglik) and hist is (n_iter, V)."""
+    G = geom(g)
+    e = _ev64(ev)
+    ss = np.ascontiguousarray(np.asarray(s, np.float64).ravel())
+    x = initial_image(g, ss, len(e)) if x0 is None else np.array(x0, np.float64).ravel().copy()
+    st = (Stats * max(n_iter, 1))()
+    hist = np.empty((n_iter, len(ss))) if history else None
+    _L().or_mlem(C.byref(G), _dp(e), len(e), _dp(ss), _dp(x), n_iter,
+                 _dp(hist) if history else None, st)
+    stats = [dict(n_eff=int(st[k].n_eff), sum_sx=st[k].sum_sx, loglik=st[k].loglik) for k in range(n_iter)]
+    return (x, stats, hist) if history else (x, stats)
+
+
+def num_threads() -> int:
+    return _L().or_num_threads()
+
+
+# ------------------------------------------------------------ packed codec
+# Record: int16 q[6] (P1.xyz, P2.xyz in 0.1 mm quanta, scanner-centred),
+# uint16 dt (IEEE binary16 bits, ps), uint16 spare.  16 bytes.
+PACK_QUANTUM_MM = 0.1
+
+
+def pack_events(ev) -> np.ndarray:
+    """Oracle-side packer: q = round-half-even(x * 10) in FP32 arithmetic,
+    dt rounded to binary16 (nearest even).  Raises on int16 overflow."""
+    e = np.asarray(ev, np.float32).reshape(-1, 7)
+    q = np.rint(e[:, :6] * np.float32(10.0))
+    if np.any(np.abs(q) > 32767):
+        raise OverflowError("coordinate outside the int16 range at 0.1 mm")
+    out = np.zeros((len(e), 8), np.int16)
+    out[:, :6] = q.astype(np.int16)
+    out[:, 6] = e[:, 6].astype(np.float16).view(np.int16)
+    return out
+
+
+def decode_packed(p) -> np.ndarray:
+    """Packed records -> FP64 (n, 7): coordinate = q * 0.1 mm, dt exact."""
+    p = np.asarray(p, np.int16).reshape(-1, 8)
+    out = np.empty((len(p), 7))
+    out[:, :6] = p[:, :6].astype(np.float64) * PACK_QUANTUM_MM
+    out[:, 6] = p[:, 6].view(np.float16).astype(np.float64)
+    return out
+
+
+def rel_l2(a, ref) -> float:
+    a = np.asarray(a, np.float64).ravel()
+    r = np.asarray(ref, np.float64).ravel()
+    return float(np.linalg.norm(a - r) / max(np.linalg.norm(r), 1e-300))

@@ -1,0 +1,327 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+Each test compares the oracle with an independent route: the paper's printed
+constant, a brute-force per-voxel intersection, numerical quadrature, Monte
+Carlo detection, closed forms, or an algebraic property of EM.  A plausible
+slip in the oracle (a dropped term, a wrong sign or index, a transposed
+operand, a mis-scaled sigma) breaks at least one of them.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+from scipy import integrate
+from scipy.special import ndtr
+
+import oracle
+import synth
+from tests import brute
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+C = 0.299792458
+
+
+def tiny_geom(nx=8, ny=8, nz=8, v=(4.0, 4.0, 4.0), tof=300.0, R=60.0, H=40.0, origin=None, K=3.0):
+    if origin is None:
+        origin = (-nx * v[0] / 2, -ny * v[1] / 2, -nz * v[2] / 2)
+    return dict(nx=nx, ny=ny, nz=nz, vx=v[0], vy=v[1], vz=v[2], x0=origin[0], y0=origin[1], z0=origin[2],
+                scanner_radius=R, scanner_half_length=H, max_axial_angle_deg=0.0, tof_fwhm_ps=tof,
+                tof_trunc_sigmas=K, c_mm_per_ps=C)
+
+
+def events_through(g, n, seed, tof_sigma_ps=60.0, box_frac=0.45):
+    """Random events whose lines cross the grid; short TOF blur keeps the
+    TOF centre near the grid."""
+    lo, hi, _, _ = brute.box(g)
+    half = (hi - lo).max() * box_frac
+    ev = synth.random_events_in_box(n, seed, g["scanner_radius"], g["scanner_half_length"],
+                                    tof_sigma_ps=tof_sigma_ps, box=half)
+    return ev.astype(np.float64)
+
+
+# ------------------------------------------------------- paper constants
+def test_sigma_matches_paper_value():
+    gold = json.load(open(os.path.join(HERE, "golden", "paper_constants.json")))
+    s = oracle.sigma_mm(gold["tof_fwhm_ps"], gold["c_mm_per_ps_implied"])
+    assert round(s, gold["sigma_decimals"]) == gold["sigma_mm"]
+    # with the exact speed of light the value is 19.097 mm
+    assert abs(oracle.sigma_mm(300.0, C) - 19.0965) < 1e-3
+
+
+# ------------------------------------------------------ projector pins
+@pytest.mark.parametrize("tof", [300.0, 0.0])
+@pytest.mark.parametrize("shape", [(8, 8, 8, (4.0, 4.0, 4.0)), (6, 5, 4, (3.0, 5.0, 7.0))])
+def test_rows_match_bruteforce(tof, shape):
+    nx, ny, nz, v = shape
+    g = tiny_geom(nx, ny, nz, v, tof=tof, origin=(-9.5, -11.0, -13.0))
+    ev = events_through(g, 500, seed=3 + nx)
+    A = oracle.system_matrix(g, ev)
+    B = brute.dense_matrix(g, ev)
+    assert np.count_nonzero(B) > 2000
+    scale = 1.0 if tof > 0 else np.abs(B).max()
+    assert np.max(np.abs(A - B)) <= 1e-12 * scale
+
+
+def test_tof_weights_match_numerical_integral():
+    g = tiny_geom(tof=300.0)
+    s = brute.sigma_mm(300.0, C)
+    K = g["tof_trunc_sigmas"]
+    ev = events_through(g, 20, seed=5)
+    pdf = lambda t: np.exp(-0.5 * (t / s) ** 2) / (s * np.sqrt(2 * np.pi))
+    full, _ = integrate.quad(pdf, -K * s, K * s, epsabs=1e-14)
+    checked = 0
+    for e in ev:
+        j, a = oracle.system_row(g, e)
+        mu, u = brute.ray(g, e)
+        w0, w1 = brute.window(g, e)
+        lo, _, v, n = brute.box(g)
+        for jj, aa in zip(j, a):
+            ix, iy, iz = jj % n[0], (jj // n[0]) % n[1], jj // (n[0] * n[1])
+            vlo = lo + np.array([ix, iy, iz]) * v
+            t0, t1 = brute._interval(vlo, vlo + v, mu, u)
+            ta, tb = max(t0, w0), min(t1, w1)
+            val, _ = integrate.quad(pdf, ta, tb, epsabs=1e-14)
+            assert abs(aa - val / full) < 1e-11
+            checked += 1
+    assert checked > 100
+
+
+def test_invariant_a_chord_length_nontof():
+    g = tiny_geom(10, 9, 7, (4.0, 4.5, 5.0), tof=0.0)
+    ev = events_through(g, 300, seed=7)
+    for e in ev:
+        _, a = oracle.system_row(g, e)
+        L = brute.chord_length(g, e)
+        assert abs(a.sum() - L) <= 1e-12 * max(L, 1.0)
+
+
+def test_invariant_b_kernel_sums_to_one():
+    gold = json.load(open(os.path.join(HERE, "golden", "paper_constants.json")))
+    g = tiny_geom(64, 64, 64, (4.0, 4.0, 4.0), tof=300.0, R=400.0, H=200.0)
+    ev = events_through(g, 400, seed=9, box_frac=0.15)
+    inside = 0
+    sK = g["tof_trunc_sigmas"] * brute.sigma_mm(300.0, C)
+    for e in ev:
+        _, a = oracle.system_row(g, e)
+        mu, u = brute.ray(g, e)
+        lo, hi, _, _ = brute.box(g)
+        t0, t1 = brute._interval(lo, hi, mu, u)
+        if t0 <= -sK and t1 >= sK:
+            inside += 1
+            assert abs(a.sum() - gold["kernel_weight_sum"]) < 1e-13
+        else:
+            s = brute.sigma_mm(300.0, C)
+            ta, tb = max(t0, -sK), min(t1, sK)
+            expect = max(0.0, (ndtr(tb / s) - ndtr(ta / s)) / (ndtr(3.0) - ndtr(-3.0)))
+            assert abs(a.sum() - expect) < 1e-13
+    assert inside > 200
+
+
+def test_axis_parallel_ray_closed_form():
+    g = tiny_geom(16, 8, 8, (4.0, 4.0, 4.0), tof=300.0, R=200.0, H=100.0)
+    # line along +x through (y, z) = (1.3, -2.7): voxel row iy = 4, iz = 3
+    y, z, dt = 1.3, -2.7, 40.0
+    ev = np.array([-150.0, y, z, 150.0, y, z, dt])
+    j, a = oracle.system_row(g, ev)
+    s = brute.sigma_mm(300.0, C)
+    mu_x = C * dt / 2.0
+    planes = g["x0"] + 4.0 * np.arange(17)
+    expect = {}
+    for ix in range(16):
+        ta = max(planes[ix] - mu_x, -3 * s)
+        tb = min(planes[ix + 1] - mu_x, 3 * s)
+        if tb > ta:
+            expect[ix + 16 * (4 + 8 * 3)] = (ndtr(tb / s) - ndtr(ta / s)) / (ndtr(3) - ndtr(-3))
+    assert sorted(j.tolist()) == sorted(expect)
+    for jj, aa in zip(j, a):
+        assert abs(aa - expect[jj]) < 1e-13
+
+
+def test_main_diagonal_nontof():
+    g = tiny_geom(8, 8, 8, (4.0, 4.0, 4.0), tof=0.0, R=200.0, H=200.0)
+    ev = np.array([-100.0, -100.0, -100.0, 100.0, 100.0, 100.0, 0.0])
+    j, a = oracle.system_row(g, ev)
+    assert sorted(j.tolist()) == [i + 8 * (i + 8 * i) for i in range(8)]
+    assert np.allclose(a, 4.0 * np.sqrt(3.0), rtol=0, atol=1e-12)
+
+
+def test_endpoint_swap_symmetry():
+    g = tiny_geom(8, 8, 8, tof=300.0)
+    ev = events_through(g, 100, seed=11)
+    sw = ev[:, [3, 4, 5, 0, 1, 2, 6]].copy()
+    sw[:, 6] = -sw[:, 6]
+    A = oracle.system_matrix(g, ev)
+    B = oracle.system_matrix(g, sw)
+    assert np.max(np.abs(A - B)) < 1e-12
+
+
+def test_mirror_symmetry_x():
+    g = tiny_geom(8, 6, 4, (4.0, 4.0, 4.0), tof=300.0)
+    ev = events_through(g, 100, seed=13)
+    mi = ev.copy()
+    mi[:, 0] *= -1
+    mi[:, 3] *= -1
+    A = oracle.system_matrix(g, ev).reshape(-1, 4, 6, 8)
+    B = oracle.system_matrix(g, mi).reshape(-1, 4, 6, 8)
+    assert np.max(np.abs(A - B[..., ::-1])) < 1e-12
+
+
+def test_forward_back_adjoint_and_dense():
+    g = tiny_geom(8, 8, 8, tof=300.0)
+    ev = events_through(g, 200, seed=17)
+    rng = np.random.default_rng(1)
+    x = rng.uniform(0, 1, 512)
+    w = rng.uniform(0, 1, 200)
+    B = brute.dense_matrix(g, ev)
+    f = oracle.forward(g, ev, x)
+    b = oracle.back(g, ev, w)
+    assert np.max(np.abs(f - B @ x)) < 1e-12 * np.abs(B @ x).max()
+    assert np.max(np.abs(b - B.T @ w)) < 1e-12 * np.abs(B.T @ w).max()
+
+
+# ---------------------------------------------------- sensitivity pins
+def test_acceptance_centre_closed_forms():
+    g1 = synth.cylinder_workload().geometry()
+    assert abs(oracle.acceptance(g1, [[0, 0, 0]])[0] - 128.0 / np.hypot(128.0, 400.0)) < 1e-12
+    g2 = synth.wholebody_workload().geometry()
+    # atan(H/R) = 69.4 deg exceeds the 45 deg cut, so the cut decides
+    assert abs(oracle.acceptance(g2, [[0, 0, 0]])[0] - np.sin(np.pi / 4)) < 1e-12
+
+
+@pytest.mark.parametrize("z", [-90.0, 30.0, 110.0])
+def test_acceptance_on_axis_closed_form(z):
+    g = synth.cylinder_workload().geometry()
+    R, H = 400.0, 128.0
+    lam_hi = np.arctan(min((H - z) / R, (H + z) / R))
+    lam_lo = np.arctan(max(-(H + z) / R, -(H - z) / R))
+    expect = 0.5 * (np.sin(lam_hi) - np.sin(lam_lo))
+    assert abs(oracle.acceptance(g, [[0, 0, z]])[0] - expect) < 1e-12
+
+
+@pytest.mark.parametrize("wl", ["cylinder", "wholebody"])
+def test_acceptance_matches_monte_carlo_detection(wl):
+    w = synth.cylinder_workload() if wl == "cylinder" else synth.wholebody_workload()
+    g = w.geometry()
+    rng = np.random.default_rng(21)
+    n = 400_000
+    for k in range(4):
+        r = rng.uniform(0, 0.9 * w.radius * 0.45)
+        ph = rng.uniform(0, 2 * np.pi)
+        p = [r * np.cos(ph), r * np.sin(ph), rng.uniform(-0.9, 0.9) * w.half_length]
+        P = oracle.acceptance(g, [p])[0]
+        acc = synth.point_source(w, p, n, seed=100 + k)
+        se = np.sqrt(max(P * (1 - P), 1e-12) / n)
+        assert abs(acc / n - P) < 5 * se + 2e-5, (p, acc / n, P)
+
+
+def test_acceptance_quadrature_vs_adaptive():
+    """2048-node midpoint rule agrees with adaptive quadrature of the same
+    solid-angle integral (in lambda and phi) to 1e-6."""
+    g = synth.wholebody_workload().geometry()
+    R, H, lmax = 450.0, 1200.0, np.pi / 4
+    for p in [(100.0, -50.0, 300.0), (250.0, 180.0, -1100.0), (0.0, 290.0, 1150.0)]:
+        x, y, z = p
+
+        def inner(phi):
+            # both ends inside |z| <= H: test by direct endpoint heights
+            c, s = np.cos(phi), np.sin(phi)
+            b = x * c + y * s
+            sq = np.sqrt(b * b - (x * x + y * y) + R * R)
+            sp, sm = -b + sq, b + sq
+
+            def ok(lam):
+                t = np.tan(lam)
+                return float(abs(z + sp * t) <= H and abs(z - sm * t) <= H)
+
+            f = lambda lam: np.cos(lam) * ok(lam)
+            # integrate the indicator-weighted cos over the allowed band
+            val, _ = integrate.quad(f, -lmax, lmax, limit=200, points=[0.0], epsabs=1e-12)
+            return val
+
+        ref, _ = integrate.quad(inner, 0, 2 * np.pi, limit=400, epsabs=1e-11)
+        ref /= 4 * np.pi
+        assert abs(oracle.acceptance(g, [p])[0] - ref) < 2e-6
+
+
+def test_acceptance_symmetries():
+    g = synth.wholebody_workload().geometry()
+    rng = np.random.default_rng(3)
+    p = rng.uniform([-280, -280, -1150], [280, 280, 1150], size=(50, 3))
+    a = oracle.acceptance(g, p)
+    zm = p * np.array([1, 1, -1])
+    rot = np.stack([-p[:, 1], p[:, 0], p[:, 2]], 1)
+    assert np.max(np.abs(a - oracle.acceptance(g, zm))) < 1e-12
+    assert np.max(np.abs(a - oracle.acceptance(g, rot))) < 1e-12
+
+
+# ------------------------------------------------------------- EM pins
+def _small_problem(seed=1, n=3000):
+    g = tiny_geom(12, 12, 10, (4.0, 4.0, 4.0), tof=300.0, R=120.0, H=60.0)
+    ev = events_through(g, n, seed=seed, tof_sigma_ps=100.0, box_frac=0.3)
+    s = oracle.sensitivity(g, n_phi=512)
+    return g, ev, s
+
+
+def test_em_matches_dense_matrix_iteration():
+    g, ev, s = _small_problem(n=400)
+    A = brute.dense_matrix(g, ev)
+    x = oracle.initial_image(g, s, len(ev))
+    xo, st = oracle.mlem(g, ev, s, 4, x0=x)
+    for _ in range(4):
+        f = A @ x
+        r = np.where(f > 0, 1.0 / np.where(f > 0, f, 1.0), 0.0)
+        x = np.where(s > 0, x * (A.T @ r) / np.where(s > 0, s, 1.0), 0.0)
+    assert oracle.rel_l2(xo, x) < 1e-12
+
+
+def test_em_invariant_c_and_monotone_loglik_and_nonneg():
+    g, ev, s = _small_problem()
+    x, st, hist = oracle.mlem(g, ev, s, 8, history=True)
+    for k in range(8):
+        assert abs(st[k]["sum_sx"] - st[k]["n_eff"]) <= 1e-12 * st[k]["n_eff"]
+    ll = [q["loglik"] for q in st]
+    assert all(b >= a - 1e-9 * abs(a) for a, b in zip(ll, ll[1:]))
+    assert np.all(hist >= 0) and np.all(np.isfinite(hist))
+
+
+def test_em_single_voxel_fixed_point():
+    g = tiny_geom(1, 1, 1, (8.0, 8.0, 8.0), tof=300.0, R=60.0, H=40.0)
+    ev = events_through(g, 50, seed=2, box_frac=0.05)
+    s = oracle.sensitivity(g, n_phi=256)
+    x, st = oracle.mlem(g, ev, s, 1, x0=np.array([7.0]))
+    assert abs(x[0] - st[0]["n_eff"] / s[0]) < 1e-12 * x[0]
+
+
+def test_em_duplicate_and_permutation():
+    g, ev, s = _small_problem(n=1000)
+    x1, _ = oracle.mlem(g, ev, s, 3)
+    x2, _ = oracle.mlem(g, np.concatenate([ev, ev]), s, 3)
+    perm = np.random.default_rng(5).permutation(len(ev))
+    x3, _ = oracle.mlem(g, ev[perm], s, 3)
+    assert oracle.rel_l2(x2, 2 * x1) < 1e-12
+    assert oracle.rel_l2(x3, x1) < 1e-12
+
+
+def test_zero_sensitivity_voxels_stay_zero():
+    g, ev, s = _small_problem(n=500)
+    s = s.copy()
+    s[::7] = 0.0
+    x, _ = oracle.mlem(g, ev, s, 2)
+    assert np.all(x[::7] == 0.0)
+
+
+# --------------------------------------------------------- packed codec
+def test_packed_codec_roundtrip_and_overflow():
+    w = synth.wholebody_workload(n_events=20000)
+    ev = synth.events(w, n=20000)
+    p = oracle.pack_events(ev)
+    d = oracle.decode_packed(p)
+    # half a quantum, plus the FP32 rounding of x * 10 (|x * 10| < 2^14)
+    assert np.max(np.abs(d[:, :6] - ev[:, :6])) <= 0.05 + 2.0 ** -10 / 10
+    rel = np.abs(d[:, 6] - ev[:, 6]) / np.maximum(np.abs(ev[:, 6]), 1e-3)
+    assert np.max(rel[np.abs(ev[:, 6]) > 1.0]) <= 2.0 ** -11
+    bad = ev[:2].copy()
+    bad[0, 2] = 3300.0
+    with pytest.raises(OverflowError):
+        oracle.pack_events(bad)
