@@ -1,0 +1,217 @@
+/*
+ * lmtof — list-mode TOF-weighted MLEM on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of liblmtof.so.  All arguments are plain pointers and sizes; no C++
+ * or framework types cross this boundary.
+ *
+ * Problem (arXiv 1706.07075, Sections 2.3-2.5): reconstruct the activity
+ * image of a single-bed, long-axial-field-of-view cylindrical PET scanner
+ * from list-mode coincidences, each a pair of detection points plus a
+ * time-of-flight difference, with MLEM whose system model weights every
+ * event's line of response by a Gaussian TOF kernel normalised to one.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Return value: LMTOF_OK (0) or a negative LMTOF_E* code.  No C++ exception
+ *   or abort crosses the ABI.  On error the context is left valid and
+ *   unchanged (except that lmtof_last_error() holds the message).
+ * Units: millimetres and picoseconds.  Frame: origin at the scanner centre,
+ *   z along the scanner axis.
+ * Images: float32, x fastest: index ix + nx * (iy + ny * iz).
+ * Events: caller's order; outputs indexed per event (forward projections,
+ *   back-projection weights) use the caller's order too, whatever internal
+ *   order the library keeps.
+ * Memory kinds: `mem` = LMTOF_MEM_HOST (pageable or pinned host memory) or
+ *   LMTOF_MEM_DEVICE (device memory on the context's GPU).  Inputs are
+ *   copied into buffers the library owns; the caller may free its buffers
+ *   when the call returns.  Device inputs must be ready (their producers
+ *   synchronised) when passed.  Outputs go to caller-provided buffers.
+ * Streams: all work of a context runs on its stream; calls that return data
+ *   to the caller synchronise that stream before returning.
+ * Threads: a context is used by one host thread at a time.
+ */
+#ifndef LMTOF_H
+#define LMTOF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ error codes */
+#define LMTOF_OK 0
+#define LMTOF_EINVAL -1       /* bad argument, geometry, non-finite event, int16 overflow */
+#define LMTOF_ESTATE -2       /* call made in the wrong order (e.g. iterate before load) */
+#define LMTOF_ENOMEM -3       /* device allocation failed or over the memory budget */
+#define LMTOF_EHIP -4         /* HIP runtime error (message kept) */
+#define LMTOF_EUNSUPPORTED -5 /* valid request the library does not handle */
+#define LMTOF_EAGAIN -6       /* pool: request does not fit right now; retry later */
+
+/* --------------------------------------------------- event input formats */
+/* 7 x float32 per event: P1.x P1.y P1.z P2.x P2.y P2.z (mm), dt = t1 - t2 (ps),
+ * where t1 is the detection time at P1.  dt > 0 puts the TOF centre nearer P2. */
+#define LMTOF_FMT_F32X7 0
+/* 8 x int16 per event (16 bytes): q[0..5] = P1.xyz, P2.xyz in 0.1 mm quanta
+ * (scanner-centred), q[6] = dt as IEEE binary16 bits (ps), q[7] = spare (0). */
+#define LMTOF_FMT_PACKED16 1
+
+/* ------------------------------------------------------------ memory kinds */
+#define LMTOF_MEM_HOST 0
+#define LMTOF_MEM_DEVICE 1
+
+/* ----------------------------------------------------------------- options */
+/* Internal event storage: 0 = plain float32 (32 B/event), 1 = packed
+ * (16 B/event: int16 endpoints at 0.1 mm, binary16 dt; float32 input is
+ * rounded half-to-even on the GPU).  Takes effect at the next load.  Default 0. */
+#define LMTOF_OPT_STORAGE 1
+/* Reorder events at load by (TOF-centre cell, direction bin) so that
+ * neighbouring GPU lanes trace nearby, near-parallel rays.  0/1, default 1. */
+#define LMTOF_OPT_SORT 2
+/* Azimuth nodes of the sensitivity quadrature.  Default 2048. */
+#define LMTOF_OPT_SENS_NPHI 3
+/* Projector launch shape: threads per block (64..1024, multiple of 64) and
+ * events per thread (1..16).  0 = library default / autotuned value. */
+#define LMTOF_OPT_BLOCK 4
+#define LMTOF_OPT_EVENTS_PER_THREAD 5
+/* Edge of the cubic TOF-centre cell used by the sort key, in mm (default 16). */
+#define LMTOF_OPT_SORT_CELL_MM 6
+
+/* ------------------------------------------------------------------ types */
+typedef struct lmtof_ctx lmtof_ctx;
+
+/* Reconstruction geometry.  The voxel grid must lie inside the scanner
+ * cylinder (transaxial corners within the radius, z within the half length). */
+typedef struct {
+    int32_t nx, ny, nz;         /* voxels per axis, >= 1 */
+    int32_t reserved0;          /* must be 0 */
+    double vx, vy, vz;          /* voxel size (mm), > 0 */
+    double x0, y0, z0;          /* grid corner (mm): voxel (0,0,0) spans [x0, x0+vx) ... */
+    double scanner_radius;      /* barrel radius R (mm) */
+    double scanner_half_length; /* barrel half length H (mm) */
+    double max_axial_angle_deg; /* acceptance cut on the LOR elevation; 0 = none */
+    double tof_fwhm_ps;         /* coincidence time resolution (FWHM, ps); <= 0: non-TOF */
+    double tof_trunc_sigmas;    /* kernel truncation K (sigmas); 0 = default 3 */
+    double c_mm_per_ps;         /* speed of light; 0 = default 0.299792458 */
+} lmtof_geometry;
+
+/* Per-iteration statistics (iteration k maps image x^k to x^{k+1}). */
+typedef struct {
+    int32_t iter;     /* k, counted from the last lmtof_set_image */
+    int32_t reserved0;
+    int64_t n_eff;    /* events with forward projection (A x^k)_i > 0 */
+    double sum_sx;    /* sum_j s_j x^{k+1}_j, FP64 (equals n_eff up to rounding) */
+    double loglik;    /* sum_i log (A x^k)_i - sum_j s_j x^k_j over n_eff events */
+    float ms;         /* wall time of the iteration on the GPU (ms) */
+    float project_ms; /* of which: the fused projector kernel (ms) */
+} lmtof_iter_stats;
+
+/* ------------------------------------------------------------- lifecycle */
+/* Create a context on HIP device `hip_device`.  `hip_stream` is a
+ * hipStream_t to run on, or NULL to let the library create its own
+ * (default priority).  *out receives the context. */
+int lmtof_create(lmtof_ctx **out, int hip_device, void *hip_stream);
+/* Free every device buffer, graph and stream the context owns.  NULL is a no-op. */
+int lmtof_destroy(lmtof_ctx *ctx);
+/* Message of the last failing call on ctx ("" if none).  Valid until the
+ * next call on ctx.  With ctx == NULL: message of the last failed create. */
+const char *lmtof_last_error(const lmtof_ctx *ctx);
+/* Set an LMTOF_OPT_* option.  EINVAL for an unknown key or value. */
+int lmtof_set_option(lmtof_ctx *ctx, int key, int64_t value);
+int lmtof_get_option(const lmtof_ctx *ctx, int key, int64_t *value);
+
+/* -------------------------------------------------------------- geometry */
+/* Host-only validation of a geometry, without a context or a GPU: returns
+ * LMTOF_OK, or LMTOF_EINVAL with the reason copied (NUL-terminated,
+ * truncated) into msg[0..msg_len-1] when msg is non-NULL. */
+int lmtof_check_geometry(const lmtof_geometry *g, char *msg, int64_t msg_len);
+/* Section 2 (Materials and Methods): a voxelised image volume inside a
+ * single-bed cylindrical scanner; Section 2.3: Gaussian TOF kernel of the
+ * given FWHM.  Validates and stores the geometry.  Drops loaded events,
+ * sensitivity and image (they depend on it). */
+int lmtof_set_geometry(lmtof_ctx *ctx, const lmtof_geometry *g);
+
+/* ---------------------------------------------------------------- events */
+/* Load n >= 1 list-mode events (Section 1: list-mode processing, one event
+ * at a time, of the whole axial field of view) in `format` from `ev`
+ * (host or device memory per `mem`).  Every coordinate and dt must be
+ * finite (EINVAL otherwise); with packed storage every coordinate must fit
+ * int16 at 0.1 mm (EINVAL otherwise).  Replaces previously loaded events
+ * and resets the image.  Needs a geometry (ESTATE). */
+int lmtof_load_events(lmtof_ctx *ctx, const void *ev, int64_t n, int format, int mem);
+/* Number of loaded events. */
+int lmtof_num_events(const lmtof_ctx *ctx, int64_t *n);
+/* Copy the stored packed records (LMTOF_FMT_PACKED16 layout, caller's
+ * order) to `out` (n x 16 bytes).  ESTATE unless storage is packed. */
+int lmtof_read_packed_events(lmtof_ctx *ctx, void *out, int64_t n, int mem);
+
+/* ----------------------------------------------------------- sensitivity */
+/* Section 2.4 ("sensitive matrix"): s_j = probability that an isotropic
+ * back-to-back photon pair emitted at the centre of voxel j is detected,
+ * i.e. both ends meet the barrel within |z| <= H with elevation inside the
+ * axial acceptance cut (Section 2.1.2, 45 degrees).  Azimuth quadrature with
+ * LMTOF_OPT_SENS_NPHI midpoint nodes, FP64 accumulation, stored float32.
+ * Needs a geometry (ESTATE). */
+int lmtof_compute_sensitivity(lmtof_ctx *ctx);
+/* Copy s (n = nx*ny*nz floats) out, or set it from the caller. */
+int lmtof_read_sensitivity(lmtof_ctx *ctx, float *out, int64_t n, int mem);
+int lmtof_set_sensitivity(lmtof_ctx *ctx, const float *s, int64_t n, int mem);
+
+/* --------------------------------------------------------------- image */
+/* Set the MLEM start image x^0 (n = nx*ny*nz floats, >= 0, finite), or with
+ * x0 == NULL the uniform start x^0_j = N / sum_{s>0} s for s_j > 0, else 0
+ * (sum in FP64).  Resets the iteration counter.  Needs events and
+ * sensitivity (ESTATE). */
+int lmtof_set_image(lmtof_ctx *ctx, const float *x0, int64_t n, int mem);
+/* Copy the current image (n = nx*ny*nz floats) out. */
+int lmtof_read_image(lmtof_ctx *ctx, float *out, int64_t n, int mem);
+
+/* ------------------------------------------------------------ iterations */
+/* Section 2.4: run n_iter >= 1 list-mode MLEM iterations with the TOF
+ * kernel: f_i = sum_j a_ij x_j; b_j = sum_{i: f_i > 0} a_ij / f_i;
+ * x_j <- x_j b_j / s_j (0 where s_j = 0).  a_ij is the truncated (+-K sigma),
+ * renormalised Gaussian TOF kernel integrated over the piece of event i's
+ * line inside voxel j (Siddon traversal); non-TOF geometry: the piece
+ * length.  The n_iter iterations are replayed from one HIP graph.  If stats
+ * is non-NULL it receives n_iter entries.  Needs an image (ESTATE). */
+int lmtof_iterate(lmtof_ctx *ctx, int n_iter, lmtof_iter_stats *stats);
+
+/* --------------------------------------------------- projector (testing) */
+/* Forward projection f_i = sum_j a_ij x_j of image x (nx*ny*nz floats) for
+ * every loaded event, f in the caller's event order (n_events floats).
+ * x and f live in `mem`.  Needs events (ESTATE). */
+int lmtof_forward_project(lmtof_ctx *ctx, const float *x, int64_t nx_, float *f, int64_t nf, int mem);
+/* Back projection b_j = sum_i a_ij w_i of per-event weights w (caller's
+ * order, n_events floats) into b (nx*ny*nz floats, overwritten). */
+int lmtof_back_project(lmtof_ctx *ctx, const float *w, int64_t nw, float *b, int64_t nb, int mem);
+
+/* Diagnostic: total voxel pieces the loaded events' rays visit inside their
+ * windows (*visited; each costs one image gather in the forward pass) and
+ * how many have non-zero weight (*weighted; each costs one atomic add in the
+ * back pass).  Needs events (ESTATE). */
+int lmtof_count_segments(lmtof_ctx *ctx, int64_t *visited, int64_t *weighted);
+
+/* ------------------------------------------------------------- regions */
+/* Section 2.5, TOF-assisted data division: split the field of view into
+ * n_regions (1..64) axial core slabs given by n_regions+1 increasing slice
+ * indices z_bounds[0] = 0 < ... < z_bounds[n] = nz.  Each event goes to the
+ * core holding its TOF centre's z (clamped to the first/last core).  Region
+ * k is an independent MLEM problem on the sub-volume core_k widened by
+ * margin_slices on both sides (clamped to the grid); a negative margin asks
+ * for the default ceil(K sigma sin(lambda_max) / vz) + ceil(6 mm / vz).
+ * All regions iterate together in one batched launch per iteration.
+ * Needs events and sensitivity (ESTATE). */
+int lmtof_set_regions(lmtof_ctx *ctx, const int32_t *z_bounds, int n_regions, int margin_slices);
+/* Region k's sub-volume: out4[0] = first slice, out4[1] = slices,
+ * out4[2] = core first slice, out4[3] = core end slice; *n_events = events. */
+int lmtof_region_info(const lmtof_ctx *ctx, int k, int32_t *out4, int64_t *n_events);
+/* Region k's current image (nx*ny*slices floats). */
+int lmtof_read_region_image(lmtof_ctx *ctx, int k, float *out, int64_t n, int mem);
+/* Drop the region split (back to one whole-volume problem). */
+int lmtof_clear_regions(lmtof_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LMTOF_H */

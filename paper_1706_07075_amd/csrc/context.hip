@@ -1,0 +1,1008 @@
+// Host runtime and C ABI of liblmtof.so: context, device buffers, event
+// ingest, sensitivity, the graph-replayed MLEM iteration and the projector
+// testing surface.  See include/lmtof.h for the contract of each entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lmtof.h"
+#include "lmtof_internal.h"
+
+using namespace lmtof;
+
+namespace {
+
+constexpr double kDefaultC = 0.299792458;
+constexpr int kDefaultBlock = 256;
+constexpr int kDefaultEpt = 1;
+
+struct GraphEntry {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<hipEvent_t> ev;  // 3 per iteration: start, after projector, after finalize
+};
+
+struct Region {
+    int z_lo = 0, nz = 0, core_lo = 0, core_hi = 0;
+    int64_t n_events = 0, ev_offset = 0;
+    float *x = nullptr, *b = nullptr, *s = nullptr;
+};
+
+template <class T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+};
+
+}  // namespace
+
+struct lmtof_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+
+    // options
+    int opt_storage = 0, opt_sort = 1, opt_nphi = 2048, opt_block = 0, opt_ept = 0;
+    double opt_cell_mm = 16.0;
+
+    bool has_geom = false;
+    lmtof_geometry g{};
+    int64_t V = 0;
+
+    // events (stored order)
+    int64_t n_events = 0;
+    int stored_packed = 0;
+    void *d_events = nullptr;
+    int64_t *d_perm = nullptr;  // stored position -> caller index
+
+    // whole-volume images
+    float *d_s = nullptr, *d_x = nullptr, *d_b = nullptr;
+    bool has_sens = false, has_image = false;
+    int iter_count = 0;
+
+    // regions (empty: one whole-volume problem)
+    std::vector<Region> regions;
+    int margin_used = 0;
+
+    // batch of problems the iteration runs
+    std::vector<Problem> probs;
+    Problem *d_probs = nullptr;
+    int64_t n_chunks = 0, n_vchunks = 0;
+    int block_used = kDefaultBlock, ept_used = kDefaultEpt;
+    int *d_part_neff = nullptr;
+    double *d_part_ll = nullptr, *d_part_old = nullptr, *d_part_new = nullptr;
+    size_t part_cap = 0, vpart_cap = 0;
+    DevStats *d_stats = nullptr;
+    size_t stats_cap = 0;
+    double *d_scratch = nullptr;  // FP64 reduction scratch (partials + result)
+    bool probs_dirty = true;
+
+    std::map<int, GraphEntry> graphs;
+    bool graph_events_ok = true;
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+int fail(lmtof_ctx *c, int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+#define HIPCHK(c, expr)                                                                          \
+    do {                                                                                         \
+        hipError_t e__ = (expr);                                                                 \
+        if (e__ != hipSuccess) return fail((c), LMTOF_EHIP, "%s: %s", #expr, hipGetErrorString(e__)); \
+    } while (0)
+
+template <class T>
+int dev_alloc(lmtof_ctx *c, T **p, size_t n) {
+    *p = nullptr;
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc((void **)p, n * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return fail(c, LMTOF_ENOMEM, "device allocation of %zu bytes failed: %s", n * sizeof(T),
+                    hipGetErrorString(e));
+    }
+    return LMTOF_OK;
+}
+
+template <class T>
+void dev_free(T *&p) {
+    if (p) (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+void drop_graphs(lmtof_ctx *c) {
+    for (auto &kv : c->graphs) {
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+        for (hipEvent_t e : kv.second.ev) (void)hipEventDestroy(e);
+    }
+    c->graphs.clear();
+}
+
+void drop_regions(lmtof_ctx *c) {
+    for (auto &r : c->regions) {
+        dev_free(r.x);
+        dev_free(r.b);
+        dev_free(r.s);
+    }
+    c->regions.clear();
+    c->probs_dirty = true;
+}
+
+void drop_events(lmtof_ctx *c) {
+    dev_free(c->d_events);
+    dev_free(c->d_perm);
+    c->n_events = 0;
+    c->has_image = false;
+    drop_regions(c);
+    drop_graphs(c);
+    c->probs_dirty = true;
+}
+
+double sigma_mm(const lmtof_geometry &g) {
+    return (g.c_mm_per_ps * g.tof_fwhm_ps / 2.0) / (2.0 * std::sqrt(2.0 * std::log(2.0)));
+}
+
+// Kernel-side description of a grid (whole volume or a z-slab of it).
+Problem make_problem(const lmtof_ctx *c, int z_lo, int nz, float *x, float *b, const float *s) {
+    const lmtof_geometry &g = c->g;
+    Problem P{};
+    P.packed = c->stored_packed;
+    P.tof = g.tof_fwhm_ps > 0 ? 1 : 0;
+    P.nx = g.nx;
+    P.ny = g.ny;
+    P.nz = nz;
+    const double oz = g.z0 + z_lo * g.vz;
+    P.ox = (float)g.x0;
+    P.oy = (float)g.y0;
+    P.oz = (float)oz;
+    P.hx = (float)(g.x0 + g.nx * g.vx);
+    P.hy = (float)(g.y0 + g.ny * g.vy);
+    P.hz = (float)(oz + nz * g.vz);
+    P.vx = (float)g.vx;
+    P.vy = (float)g.vy;
+    P.vz = (float)g.vz;
+    P.ivx = (float)(1.0 / g.vx);
+    P.ivy = (float)(1.0 / g.vy);
+    P.ivz = (float)(1.0 / g.vz);
+    P.half_c = (float)(g.c_mm_per_ps / 2.0);
+    if (P.tof) {
+        const double sg = sigma_mm(g);
+        P.inv_sig_sqrt2 = (float)(1.0 / (sg * std::sqrt(2.0)));
+        P.k_sigma = (float)(g.tof_trunc_sigmas * sg);
+        P.norm = (float)(1.0 / (2.0 * std::erf(g.tof_trunc_sigmas / std::sqrt(2.0))));
+    }
+    P.x = x;
+    P.b = b;
+    P.s = s;
+    return P;
+}
+
+void launch_shape(const lmtof_ctx *c, int &block, int &ept) {
+    block = c->opt_block > 0 ? c->opt_block : kDefaultBlock;
+    ept = c->opt_ept > 0 ? c->opt_ept : kDefaultEpt;
+}
+
+// Upload a problem table (assigning chunk ranges) to *d (reallocated as needed).
+int upload_problems(lmtof_ctx *c, std::vector<Problem> &ps, int block, int ept, Problem **d, int64_t &n_chunks,
+                    int64_t &n_vchunks) {
+    const int64_t ce = project_chunk_events(block, ept), cv = update_chunk_voxels();
+    n_chunks = 0;
+    n_vchunks = 0;
+    for (auto &P : ps) {
+        P.chunk_begin = n_chunks;
+        P.vchunk_begin = n_vchunks;
+        n_chunks += (P.n_events + ce - 1) / ce;
+        n_vchunks += ((int64_t)P.nx * P.ny * P.nz + cv - 1) / cv;
+    }
+    if (n_chunks > 0x7fffffffLL) return fail(c, LMTOF_EUNSUPPORTED, "too many projector blocks (%lld)", (long long)n_chunks);
+    if (!*d) {
+        int rc = dev_alloc(c, d, kMaxProblems);
+        if (rc) return rc;
+    }
+    HIPCHK(c, hipMemcpyAsync(*d, ps.data(), sizeof(Problem) * ps.size(), hipMemcpyHostToDevice, c->stream));
+    return LMTOF_OK;
+}
+
+// (Re)build the batch the iteration runs: the whole volume, or one problem per region.
+int ensure_problems(lmtof_ctx *c) {
+    if (!c->probs_dirty) return LMTOF_OK;
+    drop_graphs(c);
+    std::vector<Problem> ps;
+    const size_t esz = c->stored_packed ? 16 : 32;
+    if (c->regions.empty()) {
+        Problem P = make_problem(c, 0, c->g.nz, c->d_x, c->d_b, c->d_s);
+        P.events = c->d_events;
+        P.n_events = c->n_events;
+        P.ev_offset = 0;
+        ps.push_back(P);
+    } else {
+        for (auto &r : c->regions) {
+            Problem P = make_problem(c, r.z_lo, r.nz, r.x, r.b, r.s);
+            P.events = (const char *)c->d_events + esz * r.ev_offset;
+            P.n_events = r.n_events;
+            P.ev_offset = r.ev_offset;
+            ps.push_back(P);
+        }
+    }
+    int block, ept;
+    launch_shape(c, block, ept);
+    int rc = upload_problems(c, ps, block, ept, &c->d_probs, c->n_chunks, c->n_vchunks);
+    if (rc) return rc;
+    c->probs = ps;
+    c->block_used = block;
+    c->ept_used = ept;
+    if ((size_t)c->n_chunks > c->part_cap) {
+        dev_free(c->d_part_neff);
+        dev_free(c->d_part_ll);
+        c->part_cap = 0;
+        if ((rc = dev_alloc(c, &c->d_part_neff, c->n_chunks))) return rc;
+        if ((rc = dev_alloc(c, &c->d_part_ll, c->n_chunks))) return rc;
+        c->part_cap = c->n_chunks;
+    }
+    if ((size_t)c->n_vchunks > c->vpart_cap) {
+        dev_free(c->d_part_old);
+        dev_free(c->d_part_new);
+        c->vpart_cap = 0;
+        if ((rc = dev_alloc(c, &c->d_part_old, c->n_vchunks))) return rc;
+        if ((rc = dev_alloc(c, &c->d_part_new, c->n_vchunks))) return rc;
+        c->vpart_cap = c->n_vchunks;
+    }
+    c->probs_dirty = false;
+    return LMTOF_OK;
+}
+
+int ensure_stats(lmtof_ctx *c, size_t n) {
+    if (n <= c->stats_cap) return LMTOF_OK;
+    dev_free(c->d_stats);
+    c->stats_cap = 0;
+    int rc = dev_alloc(c, &c->d_stats, n);
+    if (rc) return rc;
+    c->stats_cap = n;
+    return LMTOF_OK;
+}
+
+int build_graph(lmtof_ctx *c, int n_iter, GraphEntry &ge) {
+    const int np = (int)c->probs.size();
+    HIPCHK(c, hipGraphCreate(&ge.graph, 0));
+    ge.ev.assign(3 * n_iter, nullptr);
+    for (auto &e : ge.ev) HIPCHK(c, hipEventCreate(&e));
+    hipGraphNode_t prev = nullptr;
+    bool have_prev = false;
+    for (int k = 0; k < n_iter; ++k) {
+        Launch L;
+        L.graph = ge.graph;
+        hipGraphNode_t nA = nullptr, nP = nullptr, nB = nullptr, nU = nullptr, nF = nullptr, nC = nullptr;
+        if (c->graph_events_ok) {
+            hipError_t e = hipGraphAddEventRecordNode(&nA, ge.graph, have_prev ? &prev : nullptr, have_prev ? 1 : 0,
+                                                      ge.ev[3 * k]);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(c, LMTOF_EHIP, "hipGraphAddEventRecordNode: %s", hipGetErrorString(e));
+            }
+            prev = nA;
+            have_prev = true;
+        }
+        L.deps = have_prev ? &prev : nullptr;
+        L.n_deps = have_prev ? 1 : 0;
+        L.node = &nP;
+        HIPCHK(c, launch_project_fused(L, c->d_probs, np, c->n_chunks, c->block_used, c->ept_used, c->d_part_neff,
+                                       c->d_part_ll));
+        prev = nP;
+        have_prev = true;
+        if (c->graph_events_ok) {
+            HIPCHK(c, hipGraphAddEventRecordNode(&nB, ge.graph, &prev, 1, ge.ev[3 * k + 1]));
+            prev = nB;
+        }
+        L.deps = &prev;
+        L.n_deps = 1;
+        L.node = &nU;
+        HIPCHK(c, launch_update(L, c->d_probs, np, c->n_vchunks, c->d_part_old, c->d_part_new));
+        prev = nU;
+        L.deps = &prev;
+        L.node = &nF;
+        HIPCHK(c, launch_finalize(L, c->d_probs, np, c->n_chunks, c->n_vchunks, c->d_part_neff, c->d_part_ll,
+                                  c->d_part_old, c->d_part_new, c->d_stats, k));
+        prev = nF;
+        if (c->graph_events_ok) {
+            HIPCHK(c, hipGraphAddEventRecordNode(&nC, ge.graph, &prev, 1, ge.ev[3 * k + 2]));
+            prev = nC;
+        }
+    }
+    HIPCHK(c, hipGraphInstantiate(&ge.exec, ge.graph, nullptr, nullptr, 0));
+    return LMTOF_OK;
+}
+
+int copy_in(lmtof_ctx *c, void *dst, const void *src, size_t bytes, int mem) {
+    HIPCHK(c, hipMemcpyAsync(dst, src, bytes, mem == LMTOF_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
+                             c->stream));
+    return LMTOF_OK;
+}
+
+int copy_out(lmtof_ctx *c, void *dst, const void *src, size_t bytes, int mem) {
+    HIPCHK(c, hipMemcpyAsync(dst, src, bytes, mem == LMTOF_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LMTOF_OK;
+}
+
+bool valid_mem(int mem) { return mem == LMTOF_MEM_HOST || mem == LMTOF_MEM_DEVICE; }
+
+int check_geometry(lmtof_ctx *c, const lmtof_geometry &g) {
+    auto fin = [](double v) { return std::isfinite(v); };
+    if (g.nx < 1 || g.ny < 1 || g.nz < 1) return fail(c, LMTOF_EINVAL, "grid size must be >= 1 per axis");
+    if ((int64_t)g.nx * g.ny * g.nz > 0x7fffffffLL) return fail(c, LMTOF_EINVAL, "grid has more than 2^31-1 voxels");
+    if (g.reserved0 != 0) return fail(c, LMTOF_EINVAL, "reserved0 must be 0");
+    if (!(g.vx > 0 && g.vy > 0 && g.vz > 0 && fin(g.vx) && fin(g.vy) && fin(g.vz)))
+        return fail(c, LMTOF_EINVAL, "voxel sizes must be finite and > 0");
+    if (!(fin(g.x0) && fin(g.y0) && fin(g.z0))) return fail(c, LMTOF_EINVAL, "grid corner must be finite");
+    if (!(g.scanner_radius > 0 && g.scanner_half_length > 0 && fin(g.scanner_radius) && fin(g.scanner_half_length)))
+        return fail(c, LMTOF_EINVAL, "scanner radius and half length must be finite and > 0");
+    if (!(g.max_axial_angle_deg >= 0 && g.max_axial_angle_deg < 90))
+        return fail(c, LMTOF_EINVAL, "max_axial_angle_deg must be in [0, 90)");
+    if (!fin(g.tof_fwhm_ps)) return fail(c, LMTOF_EINVAL, "tof_fwhm_ps must be finite");
+    if (!(g.tof_trunc_sigmas >= 0 && g.tof_trunc_sigmas <= 10))
+        return fail(c, LMTOF_EINVAL, "tof_trunc_sigmas must be in [0, 10] (0 = default 3)");
+    if (!(g.c_mm_per_ps >= 0 && fin(g.c_mm_per_ps))) return fail(c, LMTOF_EINVAL, "c_mm_per_ps must be >= 0");
+    // grid inside the scanner cylinder
+    const double R = g.scanner_radius, H = g.scanner_half_length;
+    const double xs[2] = {g.x0, g.x0 + g.nx * g.vx}, ys[2] = {g.y0, g.y0 + g.ny * g.vy};
+    for (double x : xs)
+        for (double y : ys)
+            if (std::hypot(x, y) > R * (1 + 1e-12))
+                return fail(c, LMTOF_EINVAL, "grid corner (%g, %g) lies outside the scanner radius %g", x, y, R);
+    if (g.z0 < -H * (1 + 1e-12) || g.z0 + g.nz * g.vz > H * (1 + 1e-12))
+        return fail(c, LMTOF_EINVAL, "grid z range lies outside the scanner (|z| <= %g)", H);
+    return LMTOF_OK;
+}
+
+KeyGeom key_geom(const lmtof_ctx *c, bool sort) {
+    const lmtof_geometry &g = c->g;
+    KeyGeom k{};
+    double cell = c->opt_cell_mm;
+    k.ox = (float)g.x0;
+    k.oy = (float)g.y0;
+    k.oz = (float)g.z0;
+    k.n_phi = 8;
+    k.n_lam = 4;
+    k.sort = sort ? 1 : 0;
+    k.tof = g.tof_fwhm_ps > 0;
+    k.half_c = (float)(g.c_mm_per_ps / 2.0);
+    // coarsen cells until the key space stays modest
+    for (;;) {
+        k.ncx = (int)std::ceil(g.nx * g.vx / cell);
+        k.ncy = (int)std::ceil(g.ny * g.vy / cell);
+        k.ncz = (int)std::ceil(g.nz * g.vz / cell);
+        if ((double)k.ncx * k.ncy * k.ncz * k.n_phi * k.n_lam * std::max<size_t>(1, c->regions.size()) <= (1 << 26))
+            break;
+        cell *= 1.25;
+    }
+    k.cell_inv = (float)(1.0 / cell);
+    k.n_regions = (int)c->regions.size();
+    for (size_t r = 0; r < c->regions.size(); ++r) k.region_z[r] = (float)(g.z0 + c->regions[r].core_lo * g.vz);
+    if (!c->regions.empty()) k.region_z[c->regions.size()] = (float)(g.z0 + c->regions.back().core_hi * g.vz);
+    return k;
+}
+
+}  // namespace
+
+// =====================================================================  C ABI
+extern "C" {
+
+int lmtof_create(lmtof_ctx **out, int hip_device, void *hip_stream) {
+    if (!out) {
+        g_create_err = "out is NULL";
+        return LMTOF_EINVAL;
+    }
+    *out = nullptr;
+    try {
+        int ndev = 0;
+        hipError_t e = hipGetDeviceCount(&ndev);
+        if (e != hipSuccess || ndev < 1) {
+            g_create_err = std::string("no HIP device: ") + hipGetErrorString(e);
+            return LMTOF_EHIP;
+        }
+        if (hip_device < 0 || hip_device >= ndev) {
+            g_create_err = "hip_device out of range";
+            return LMTOF_EINVAL;
+        }
+        e = hipSetDevice(hip_device);
+        if (e != hipSuccess) {
+            g_create_err = std::string("hipSetDevice: ") + hipGetErrorString(e);
+            return LMTOF_EHIP;
+        }
+        lmtof_ctx *c = new lmtof_ctx();
+        c->device = hip_device;
+        if (hip_stream) {
+            c->stream = (hipStream_t)hip_stream;
+        } else {
+            e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+            if (e != hipSuccess) {
+                delete c;
+                g_create_err = std::string("hipStreamCreate: ") + hipGetErrorString(e);
+                return LMTOF_EHIP;
+            }
+            c->own_stream = true;
+        }
+        *out = c;
+        g_create_err.clear();
+        return LMTOF_OK;
+    } catch (...) {
+        g_create_err = "host allocation failed";
+        return LMTOF_ENOMEM;
+    }
+}
+
+int lmtof_destroy(lmtof_ctx *c) {
+    if (!c) return LMTOF_OK;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    drop_events(c);
+    dev_free(c->d_s);
+    dev_free(c->d_x);
+    dev_free(c->d_b);
+    dev_free(c->d_probs);
+    dev_free(c->d_part_neff);
+    dev_free(c->d_part_ll);
+    dev_free(c->d_part_old);
+    dev_free(c->d_part_new);
+    dev_free(c->d_stats);
+    dev_free(c->d_scratch);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return LMTOF_OK;
+}
+
+const char *lmtof_last_error(const lmtof_ctx *c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+int lmtof_check_geometry(const lmtof_geometry *gin, char *msg, int64_t msg_len) {
+    lmtof_ctx tmp;
+    int rc = LMTOF_EINVAL;
+    if (!gin) {
+        tmp.err = "geometry is NULL";
+    } else {
+        lmtof_geometry g = *gin;
+        if (g.tof_trunc_sigmas == 0) g.tof_trunc_sigmas = 3.0;
+        if (g.c_mm_per_ps == 0) g.c_mm_per_ps = kDefaultC;
+        rc = check_geometry(&tmp, g);
+    }
+    if (msg && msg_len > 0) {
+        const std::string &m = rc == LMTOF_OK ? std::string() : tmp.err;
+        const size_t k = std::min<size_t>(m.size(), (size_t)msg_len - 1);
+        memcpy(msg, m.data(), k);
+        msg[k] = 0;
+    }
+    return rc;
+}
+
+int lmtof_set_option(lmtof_ctx *c, int key, int64_t v) {
+    if (!c) return LMTOF_EINVAL;
+    c->err.clear();
+    switch (key) {
+    case LMTOF_OPT_STORAGE:
+        if (v != 0 && v != 1) return fail(c, LMTOF_EINVAL, "storage must be 0 (plain) or 1 (packed)");
+        c->opt_storage = (int)v;
+        return LMTOF_OK;
+    case LMTOF_OPT_SORT:
+        if (v != 0 && v != 1) return fail(c, LMTOF_EINVAL, "sort must be 0 or 1");
+        c->opt_sort = (int)v;
+        return LMTOF_OK;
+    case LMTOF_OPT_SENS_NPHI:
+        if (v < 4 || v > 4096) return fail(c, LMTOF_EINVAL, "sensitivity azimuth nodes must be in [4, 4096]");
+        c->opt_nphi = (int)v;
+        return LMTOF_OK;
+    case LMTOF_OPT_BLOCK:
+        if (v != 0 && (v < 64 || v > 1024 || v % 64)) return fail(c, LMTOF_EINVAL, "block must be 0 or 64..1024, x64");
+        c->opt_block = (int)v;
+        c->probs_dirty = true;
+        return LMTOF_OK;
+    case LMTOF_OPT_EVENTS_PER_THREAD:
+        if (v < 0 || v > 16) return fail(c, LMTOF_EINVAL, "events per thread must be in [0, 16]");
+        c->opt_ept = (int)v;
+        c->probs_dirty = true;
+        return LMTOF_OK;
+    case LMTOF_OPT_SORT_CELL_MM:
+        if (v < 1 || v > 10000) return fail(c, LMTOF_EINVAL, "sort cell must be in [1, 10000] mm");
+        c->opt_cell_mm = (double)v;
+        return LMTOF_OK;
+    default:
+        return fail(c, LMTOF_EINVAL, "unknown option %d", key);
+    }
+}
+
+int lmtof_get_option(const lmtof_ctx *c, int key, int64_t *v) {
+    if (!c || !v) return LMTOF_EINVAL;
+    switch (key) {
+    case LMTOF_OPT_STORAGE: *v = c->opt_storage; return LMTOF_OK;
+    case LMTOF_OPT_SORT: *v = c->opt_sort; return LMTOF_OK;
+    case LMTOF_OPT_SENS_NPHI: *v = c->opt_nphi; return LMTOF_OK;
+    case LMTOF_OPT_BLOCK: *v = c->opt_block > 0 ? c->opt_block : kDefaultBlock; return LMTOF_OK;
+    case LMTOF_OPT_EVENTS_PER_THREAD: *v = c->opt_ept > 0 ? c->opt_ept : kDefaultEpt; return LMTOF_OK;
+    case LMTOF_OPT_SORT_CELL_MM: *v = (int64_t)c->opt_cell_mm; return LMTOF_OK;
+    default: return LMTOF_EINVAL;
+    }
+}
+
+int lmtof_set_geometry(lmtof_ctx *c, const lmtof_geometry *gin) {
+    if (!c) return LMTOF_EINVAL;
+    if (!gin) return fail(c, LMTOF_EINVAL, "geometry is NULL");
+    c->err.clear();
+    lmtof_geometry g = *gin;
+    if (g.tof_trunc_sigmas == 0) g.tof_trunc_sigmas = 3.0;
+    if (g.c_mm_per_ps == 0) g.c_mm_per_ps = kDefaultC;
+    int rc = check_geometry(c, g);
+    if (rc) return rc;
+    HIPCHK(c, hipSetDevice(c->device));
+    try {
+        const int64_t V = (int64_t)g.nx * g.ny * g.nz;
+        float *s = nullptr, *x = nullptr, *b = nullptr;
+        if ((rc = dev_alloc(c, &s, V))) return rc;
+        if ((rc = dev_alloc(c, &x, V))) { dev_free(s); return rc; }
+        if ((rc = dev_alloc(c, &b, V))) { dev_free(s); dev_free(x); return rc; }
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        drop_events(c);
+        dev_free(c->d_s);
+        dev_free(c->d_x);
+        dev_free(c->d_b);
+        c->d_s = s;
+        c->d_x = x;
+        c->d_b = b;
+        c->g = g;
+        c->V = V;
+        c->has_geom = true;
+        c->has_sens = false;
+        c->has_image = false;
+        c->probs_dirty = true;
+        Launch L;
+        L.stream = c->stream;
+        HIPCHK(c, launch_fill(L, c->d_b, V, 0.0f));
+        HIPCHK(c, launch_fill(L, c->d_x, V, 0.0f));
+        HIPCHK(c, launch_fill(L, c->d_s, V, 0.0f));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        return LMTOF_OK;
+    } catch (...) {
+        return fail(c, LMTOF_ENOMEM, "host allocation failed");
+    }
+}
+
+int lmtof_load_events(lmtof_ctx *c, const void *ev, int64_t n, int format, int mem) {
+    if (!c) return LMTOF_EINVAL;
+    c->err.clear();
+    if (!c->has_geom) return fail(c, LMTOF_ESTATE, "set the geometry before loading events");
+    if (!ev) return fail(c, LMTOF_EINVAL, "events pointer is NULL");
+    if (n < 1 || n > (int64_t)0xffffffffLL) return fail(c, LMTOF_EINVAL, "event count must be in [1, 2^32-1]");
+    if (format != LMTOF_FMT_F32X7 && format != LMTOF_FMT_PACKED16) return fail(c, LMTOF_EINVAL, "unknown format %d", format);
+    if (!valid_mem(mem)) return fail(c, LMTOF_EINVAL, "unknown memory kind %d", mem);
+    HIPCHK(c, hipSetDevice(c->device));
+    const size_t raw_sz = format == LMTOF_FMT_F32X7 ? 28 : 16;
+    const int packed = c->opt_storage;
+    const size_t st_sz = packed ? 16 : 32;
+    Launch L;
+    L.stream = c->stream;
+    int rc;
+    void *raw = nullptr;
+    void *store = nullptr;
+    int64_t *perm = nullptr;
+    uint32_t *keys = nullptr, *hist = nullptr, *tmp = nullptr, *err = nullptr;
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(c->stream);
+        if (mem == LMTOF_MEM_HOST) dev_free(raw);
+        dev_free(store);
+        dev_free(perm);
+        dev_free(keys);
+        dev_free(hist);
+        dev_free(tmp);
+        dev_free(err);
+    };
+    if (mem == LMTOF_MEM_HOST) {
+        if ((rc = dev_alloc(c, (char **)&raw, raw_sz * n))) return rc;
+        if ((rc = copy_in(c, raw, ev, raw_sz * n, LMTOF_MEM_HOST))) { cleanup(); return rc; }
+    } else {
+        raw = const_cast<void *>(ev);
+    }
+    if ((rc = dev_alloc(c, (char **)&store, st_sz * n)) || (rc = dev_alloc(c, &perm, n)) ||
+        (rc = dev_alloc(c, &err, 1))) {
+        cleanup();
+        return rc;
+    }
+    hipError_t he = hipMemsetAsync(err, 0, sizeof(uint32_t), c->stream);
+    const bool sort = c->opt_sort != 0;
+    // events are loaded unsplit; lmtof_set_regions re-sorts by region
+    std::vector<Region> saved;
+    saved.swap(c->regions);
+    KeyGeom kg = key_geom(c, sort);
+    saved.swap(c->regions);
+    uint32_t nkeys = key_count(kg);
+    if (he == hipSuccess && sort) {
+        if ((rc = dev_alloc(c, &keys, n)) || (rc = dev_alloc(c, &hist, nkeys)) ||
+            (rc = dev_alloc(c, &tmp, scan_tmp_elems(nkeys)))) {
+            cleanup();
+            return rc;
+        }
+        he = hipMemsetAsync(hist, 0, sizeof(uint32_t) * nkeys, c->stream);
+    }
+    if (he == hipSuccess) he = launch_ingest_keys(L, raw, format, n, kg, packed, sort ? keys : nullptr, hist, err);
+    if (he == hipSuccess && sort) he = launch_exclusive_scan(L, hist, nkeys, tmp);
+    uint32_t herr = 0;
+    if (he == hipSuccess) he = hipMemcpyAsync(&herr, err, sizeof herr, hipMemcpyDeviceToHost, c->stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+    if (he != hipSuccess) {
+        cleanup();
+        return fail(c, LMTOF_EHIP, "event ingest: %s", hipGetErrorString(he));
+    }
+    if (herr) {
+        cleanup();
+        std::string why;
+        if (herr & 1) why += " non-finite value;";
+        if (herr & 2) why += " coincident endpoints;";
+        if (herr & 4) why += " coordinate outside int16 range at 0.1 mm;";
+        if (herr & 8) why += " dt outside the binary16 range;";
+        return fail(c, LMTOF_EINVAL, "invalid events:%s", why.c_str());
+    }
+    he = launch_scatter_events(L, raw, format, n, sort ? keys : nullptr, sort ? hist : nullptr, packed, store, perm);
+    if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+    if (he != hipSuccess) {
+        cleanup();
+        return fail(c, LMTOF_EHIP, "event scatter: %s", hipGetErrorString(he));
+    }
+    drop_events(c);
+    c->d_events = store;
+    c->d_perm = perm;
+    store = nullptr;
+    perm = nullptr;
+    c->n_events = n;
+    c->stored_packed = packed;
+    c->probs_dirty = true;
+    cleanup();
+    return LMTOF_OK;
+}
+
+int lmtof_num_events(const lmtof_ctx *c, int64_t *n) {
+    if (!c || !n) return LMTOF_EINVAL;
+    *n = c->n_events;
+    return LMTOF_OK;
+}
+
+int lmtof_read_packed_events(lmtof_ctx *c, void *out, int64_t n, int mem) {
+    if (!c) return LMTOF_EINVAL;
+    c->err.clear();
+    if (!c->n_events || !c->stored_packed) return fail(c, LMTOF_ESTATE, "no packed events are loaded");
+    if (!out || n != c->n_events || !valid_mem(mem)) return fail(c, LMTOF_EINVAL, "need n = %lld and a buffer", (long long)c->n_events);
+    HIPCHK(c, hipSetDevice(c->device));
+    Launch L;
+    L.stream = c->stream;
+    uint4 *tmp = nullptr;
+    int rc;
+    if (mem == LMTOF_MEM_HOST && (rc = dev_alloc(c, &tmp, n))) return rc;
+    uint4 *dst = mem == LMTOF_MEM_HOST ? tmp : (uint4 *)out;
+    hipError_t he = launch_unpermute_packed(L, (const uint4 *)c->d_events, c->d_perm, n, dst);
+    if (he != hipSuccess) { dev_free(tmp); return fail(c, LMTOF_EHIP, "unpermute: %s", hipGetErrorString(he)); }
+    rc = mem == LMTOF_MEM_HOST ? copy_out(c, out, tmp, 16 * n, LMTOF_MEM_HOST)
+                               : (hipStreamSynchronize(c->stream) == hipSuccess ? LMTOF_OK : LMTOF_EHIP);
+    dev_free(tmp);
+    return rc;
+}
+
+int lmtof_compute_sensitivity(lmtof_ctx *c) {
+    if (!c) return LMTOF_EINVAL;
+    c->err.clear();
+    if (!c->has_geom) return fail(c, LMTOF_ESTATE, "set the geometry first");
+    HIPCHK(c, hipSetDevice(c->device));
+    const lmtof_geometry &g = c->g;
+    SensGeom sg{};
+    sg.nx = g.nx;
+    sg.ny = g.ny;
+    sg.nz = g.nz;
+    sg.n_phi = c->opt_nphi;
+    sg.ox = g.x0;
+    sg.oy = g.y0;
+    sg.oz = g.z0;
+    sg.vx = g.vx;
+    sg.vy = g.vy;
+    sg.vz = g.vz;
+    sg.R = g.scanner_radius;
+    sg.H = g.scanner_half_length;
+    sg.tan_lmax = g.max_axial_angle_deg > 0 ? std::tan(g.max_axial_angle_deg * M_PI / 180.0) : 0.0;
+    Launch L;
+    L.stream = c->stream;
+    HIPCHK(c, launch_sensitivity(L, sg, c->d_s));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->has_sens = true;
+    c->has_image = false;
+    return LMTOF_OK;
+}
+
+int lmtof_read_sensitivity(lmtof_ctx *c, float *out, int64_t n, int mem) {
+    if (!c) return LMTOF_EINVAL;
+    c->err.clear();
+    if (!c->has_sens) return fail(c, LMTOF_ESTATE, "no sensitivity yet");
+    if (!out || n != c->V || !valid_mem(mem)) return fail(c, LMTOF_EINVAL, "need n = %lld floats", (long long)c->V);
+    HIPCHK(c, hipSetDevice(c->device));
+    return copy_out(c, out, c->d_s, sizeof(float) * n, mem);
+}
+
+int lmtof_set_sensitivity(lmtof_ctx *c, const float *s, int64_t n, int mem) {
+    if (!c) return LMTOF_EINVAL;
+    c->err.clear();
+    if (!c->has_geom) return fail(c, LMTOF_ESTATE, "set the geometry first");
+    if (!s || n != c->V || !valid_mem(mem)) return fail(c, LMTOF_EINVAL, "need n = %lld floats", (long long)c->V);
+    if (mem == LMTOF_MEM_HOST)
+        for (int64_t j = 0; j < n; ++j)
+            if (!(s[j] >= 0.0f) || !std::isfinite(s[j])) return fail(c, LMTOF_EINVAL, "sensitivity must be finite and >= 0");
+    HIPCHK(c, hipSetDevice(c->device));
+    int rc = copy_in(c, c->d_s, s, sizeof(float) * n, mem);
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->has_sens = true;
+    c->has_image = false;
+    drop_regions(c);
+    return LMTOF_OK;
+}
+
+int lmtof_set_image(lmtof_ctx *c, const float *x0, int64_t n, int mem) {
+    if (!c) return LMTOF_EINVAL;
+    c->err.clear();
+    if (!c->n_events || !c->has_sens) return fail(c, LMTOF_ESTATE, "load events and compute the sensitivity first");
+    if (x0 && (n != c->V || !valid_mem(mem))) return fail(c, LMTOF_EINVAL, "need n = %lld floats", (long long)c->V);
+    if (x0 && mem == LMTOF_MEM_HOST)
+        for (int64_t j = 0; j < n; ++j)
+            if (!(x0[j] >= 0.0f) || !std::isfinite(x0[j])) return fail(c, LMTOF_EINVAL, "image must be finite and >= 0");
+    HIPCHK(c, hipSetDevice(c->device));
+    int rc = ensure_problems(c);
+    if (rc) return rc;
+    if (!c->d_scratch && (rc = dev_alloc(c, &c->d_scratch, 1025))) return rc;
+    Launch L;
+    L.stream = c->stream;
+    for (size_t p = 0; p < c->probs.size(); ++p) {
+        const Problem &P = c->probs[p];
+        const int64_t Vp = (int64_t)P.nx * P.ny * P.nz;
+        if (x0) {
+            const int z_lo = c->regions.empty() ? 0 : c->regions[p].z_lo;
+            const float *src = x0 + (int64_t)z_lo * P.nx * P.ny;
+            if ((rc = copy_in(c, P.x, src, sizeof(float) * Vp, mem))) return rc;
+        } else {
+            HIPCHK(c, launch_sum_positive(L, P.s, Vp, c->d_scratch, 1024, c->d_scratch + 1024));
+            HIPCHK(c, launch_uniform_image(L, P.s, Vp, c->d_scratch + 1024, (double)P.n_events, P.x));
+        }
+        HIPCHK(c, launch_fill(L, P.b, Vp, 0.0f));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->has_image = true;
+    c->iter_count = 0;
+    return LMTOF_OK;
+}
+
+int lmtof_read_image(lmtof_ctx *c, float *out, int64_t n, int mem) {
+    if (!c) return LMTOF_EINVAL;
+    c->err.clear();
+    if (!c->has_image) return fail(c, LMTOF_ESTATE, "no image yet");
+    if (!out || n != c->V || !valid_mem(mem)) return fail(c, LMTOF_EINVAL, "need n = %lld floats", (long long)c->V);
+    HIPCHK(c, hipSetDevice(c->device));
+    if (c->regions.empty()) return copy_out(c, out, c->d_x, sizeof(float) * n, mem);
+    return fail(c, LMTOF_EUNSUPPORTED, "region images: use lmtof_read_region_image");
+}
+
+int lmtof_iterate(lmtof_ctx *c, int n_iter, lmtof_iter_stats *stats) {
+    if (!c) return LMTOF_EINVAL;
+    c->err.clear();
+    if (!c->has_image) return fail(c, LMTOF_ESTATE, "set the image (lmtof_set_image) first");
+    if (n_iter < 1 || n_iter > 10000) return fail(c, LMTOF_EINVAL, "n_iter must be in [1, 10000]");
+    HIPCHK(c, hipSetDevice(c->device));
+    try {
+        int rc = ensure_problems(c);
+        if (rc) return rc;
+        const int np = (int)c->probs.size();
+        if ((rc = ensure_stats(c, (size_t)n_iter * np))) return rc;
+        auto it = c->graphs.find(n_iter);
+        if (it == c->graphs.end()) {
+            GraphEntry ge;
+            rc = build_graph(c, n_iter, ge);
+            if (rc) {
+                if (ge.exec) (void)hipGraphExecDestroy(ge.exec);
+                if (ge.graph) (void)hipGraphDestroy(ge.graph);
+                for (hipEvent_t e : ge.ev) if (e) (void)hipEventDestroy(e);
+                return rc;
+            }
+            it = c->graphs.emplace(n_iter, ge).first;
+        }
+        HIPCHK(c, hipGraphLaunch(it->second.exec, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        std::vector<DevStats> hs((size_t)n_iter * np);
+        HIPCHK(c, hipMemcpy(hs.data(), c->d_stats, sizeof(DevStats) * hs.size(), hipMemcpyDeviceToHost));
+        if (stats) {
+            for (int k = 0; k < n_iter; ++k) {
+                lmtof_iter_stats &o = stats[k];
+                memset(&o, 0, sizeof o);
+                o.iter = c->iter_count + k;
+                double sx = 0, sxo = 0, slf = 0;
+                int64_t ne = 0;
+                for (int p = 0; p < np; ++p) {
+                    const DevStats &d = hs[(size_t)k * np + p];
+                    ne += d.n_eff;
+                    sx += d.sum_sx;
+                    sxo += d.sum_sx_old;
+                    slf += d.sum_logf;
+                }
+                o.n_eff = ne;
+                o.sum_sx = sx;
+                o.loglik = slf - sxo;
+                if (c->graph_events_ok) {
+                    const auto &ev = it->second.ev;
+                    float a = 0, b = 0;
+                    if (hipEventElapsedTime(&a, ev[3 * k], ev[3 * k + 2]) == hipSuccess) o.ms = a;
+                    if (hipEventElapsedTime(&b, ev[3 * k], ev[3 * k + 1]) == hipSuccess) o.project_ms = b;
+                    (void)hipGetLastError();
+                }
+            }
+        }
+        c->iter_count += n_iter;
+        return LMTOF_OK;
+    } catch (...) {
+        return fail(c, LMTOF_ENOMEM, "host allocation failed");
+    }
+}
+
+int lmtof_forward_project(lmtof_ctx *c, const float *x, int64_t nx_, float *f, int64_t nf, int mem) {
+    if (!c) return LMTOF_EINVAL;
+    c->err.clear();
+    if (!c->n_events) return fail(c, LMTOF_ESTATE, "load events first");
+    if (!x || !f || nx_ != c->V || nf != c->n_events || !valid_mem(mem))
+        return fail(c, LMTOF_EINVAL, "need x of %lld floats and f of %lld floats", (long long)c->V, (long long)c->n_events);
+    HIPCHK(c, hipSetDevice(c->device));
+    Launch L;
+    L.stream = c->stream;
+    float *dx = nullptr, *fs = nullptr, *fc = nullptr;
+    Problem *dp = nullptr;
+    int rc = LMTOF_OK;
+    auto done = [&](int r) {
+        (void)hipStreamSynchronize(c->stream);
+        if (mem == LMTOF_MEM_HOST) { dev_free(dx); dev_free(fc); }
+        dev_free(fs);
+        dev_free(dp);
+        return r;
+    };
+    if (mem == LMTOF_MEM_HOST) {
+        if ((rc = dev_alloc(c, &dx, c->V)) || (rc = dev_alloc(c, &fc, c->n_events))) return done(rc);
+        if ((rc = copy_in(c, dx, x, sizeof(float) * c->V, LMTOF_MEM_HOST))) return done(rc);
+    } else {
+        dx = const_cast<float *>(x);
+        fc = f;
+    }
+    if ((rc = dev_alloc(c, &fs, c->n_events))) return done(rc);
+    std::vector<Problem> ps{make_problem(c, 0, c->g.nz, dx, nullptr, nullptr)};
+    ps[0].events = c->d_events;
+    ps[0].n_events = c->n_events;
+    int block, ept;
+    launch_shape(c, block, ept);
+    int64_t nch, nvch;
+    if ((rc = upload_problems(c, ps, block, ept, &dp, nch, nvch))) return done(rc);
+    hipError_t he = launch_project_forward(L, dp, 1, nch, block, ept, fs);
+    if (he == hipSuccess) he = launch_scatter_by_perm(L, fs, c->d_perm, c->n_events, fc);
+    if (he != hipSuccess) return done(fail(c, LMTOF_EHIP, "forward projection: %s", hipGetErrorString(he)));
+    if (mem == LMTOF_MEM_HOST) rc = copy_out(c, f, fc, sizeof(float) * c->n_events, LMTOF_MEM_HOST);
+    else if (hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(c, LMTOF_EHIP, "forward projection failed");
+    return done(rc);
+}
+
+int lmtof_back_project(lmtof_ctx *c, const float *w, int64_t nw, float *b, int64_t nb, int mem) {
+    if (!c) return LMTOF_EINVAL;
+    c->err.clear();
+    if (!c->n_events) return fail(c, LMTOF_ESTATE, "load events first");
+    if (!w || !b || nw != c->n_events || nb != c->V || !valid_mem(mem))
+        return fail(c, LMTOF_EINVAL, "need w of %lld floats and b of %lld floats", (long long)c->n_events, (long long)c->V);
+    HIPCHK(c, hipSetDevice(c->device));
+    Launch L;
+    L.stream = c->stream;
+    float *dw = nullptr, *ws = nullptr, *db = nullptr;
+    Problem *dp = nullptr;
+    int rc = LMTOF_OK;
+    auto done = [&](int r) {
+        (void)hipStreamSynchronize(c->stream);
+        if (mem == LMTOF_MEM_HOST) { dev_free(dw); dev_free(db); }
+        dev_free(ws);
+        dev_free(dp);
+        return r;
+    };
+    if (mem == LMTOF_MEM_HOST) {
+        if ((rc = dev_alloc(c, &dw, c->n_events)) || (rc = dev_alloc(c, &db, c->V))) return done(rc);
+        if ((rc = copy_in(c, dw, w, sizeof(float) * c->n_events, LMTOF_MEM_HOST))) return done(rc);
+    } else {
+        dw = const_cast<float *>(w);
+        db = b;
+    }
+    if ((rc = dev_alloc(c, &ws, c->n_events))) return done(rc);
+    std::vector<Problem> ps{make_problem(c, 0, c->g.nz, nullptr, db, nullptr)};
+    ps[0].events = c->d_events;
+    ps[0].n_events = c->n_events;
+    int block, ept;
+    launch_shape(c, block, ept);
+    int64_t nch, nvch;
+    if ((rc = upload_problems(c, ps, block, ept, &dp, nch, nvch))) return done(rc);
+    hipError_t he = launch_gather_by_perm(L, dw, c->d_perm, c->n_events, ws);
+    if (he == hipSuccess) he = launch_fill(L, db, c->V, 0.0f);
+    if (he == hipSuccess) he = launch_project_back(L, dp, 1, nch, block, ept, ws);
+    if (he != hipSuccess) return done(fail(c, LMTOF_EHIP, "back projection: %s", hipGetErrorString(he)));
+    if (mem == LMTOF_MEM_HOST) rc = copy_out(c, b, db, sizeof(float) * c->V, LMTOF_MEM_HOST);
+    else if (hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(c, LMTOF_EHIP, "back projection failed");
+    return done(rc);
+}
+
+int lmtof_count_segments(lmtof_ctx *c, int64_t *visited, int64_t *weighted) {
+    if (!c) return LMTOF_EINVAL;
+    c->err.clear();
+    if (!c->n_events) return fail(c, LMTOF_ESTATE, "load events first");
+    if (!visited || !weighted) return fail(c, LMTOF_EINVAL, "output pointers are NULL");
+    HIPCHK(c, hipSetDevice(c->device));
+    Launch L;
+    L.stream = c->stream;
+    Problem *dp = nullptr;
+    unsigned long long *part = nullptr;
+    std::vector<Problem> ps{make_problem(c, 0, c->g.nz, nullptr, nullptr, nullptr)};
+    ps[0].events = c->d_events;
+    ps[0].n_events = c->n_events;
+    int block, ept;
+    launch_shape(c, block, ept);
+    int64_t nch, nvch;
+    int rc = upload_problems(c, ps, block, ept, &dp, nch, nvch);
+    if (!rc) rc = dev_alloc(c, &part, 2 * nch);
+    std::vector<unsigned long long> h;
+    if (!rc) {
+        hipError_t he = launch_count_pieces(L, dp, 1, nch, block, ept, part);
+        if (he == hipSuccess) {
+            h.resize(2 * nch);
+            he = hipMemcpyAsync(h.data(), part, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost,
+                                c->stream);
+        }
+        if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+        if (he != hipSuccess) rc = fail(c, LMTOF_EHIP, "segment count: %s", hipGetErrorString(he));
+    }
+    (void)hipStreamSynchronize(c->stream);
+    dev_free(dp);
+    dev_free(part);
+    if (rc) return rc;
+    unsigned long long a = 0, b = 0;
+    for (int64_t k = 0; k < nch; ++k) {
+        a += h[2 * k];
+        b += h[2 * k + 1];
+    }
+    *visited = (int64_t)a;
+    *weighted = (int64_t)b;
+    return LMTOF_OK;
+}
+
+int lmtof_set_regions(lmtof_ctx *c, const int32_t *, int, int) {
+    if (!c) return LMTOF_EINVAL;
+    return fail(c, LMTOF_EUNSUPPORTED, "regions not built yet");
+}
+int lmtof_region_info(const lmtof_ctx *c, int, int32_t *, int64_t *) { return c ? LMTOF_EUNSUPPORTED : LMTOF_EINVAL; }
+int lmtof_read_region_image(lmtof_ctx *c, int, float *, int64_t, int) {
+    if (!c) return LMTOF_EINVAL;
+    return fail(c, LMTOF_EUNSUPPORTED, "regions not built yet");
+}
+int lmtof_clear_regions(lmtof_ctx *c) {
+    if (!c) return LMTOF_EINVAL;
+    drop_regions(c);
+    return LMTOF_OK;
+}
+
+}  // extern "C"

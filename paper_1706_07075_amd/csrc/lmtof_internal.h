@@ -1,0 +1,136 @@
+// Internal declarations shared by the HIP sources of liblmtof.so.
+// Not part of the public ABI (include/lmtof.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lmtof {
+
+// One MLEM problem as the kernels see it: a voxel grid, its images and a
+// contiguous range of stored events.  A whole-volume reconstruction is one
+// problem; the TOF-assisted data division runs one problem per body region.
+struct Problem {
+    const void *events;   // stored events of this problem (plain: 2 x float4; packed: 1 x uint4)
+    int64_t n_events;
+    int64_t ev_offset;    // stored index of this problem's first event (per-event arrays)
+    int64_t chunk_begin;  // first projector chunk of this problem (chunk ids are global)
+    int64_t vchunk_begin; // first update chunk of this problem
+    float *x;             // image (nx*ny*nz)
+    float *b;             // back-projection accumulator, zero between iterations
+    const float *s;       // sensitivity
+    int32_t packed;
+    int32_t tof;
+    int32_t nx, ny, nz;
+    float ox, oy, oz;     // grid corner (mm)
+    float hx, hy, hz;     // far corner (mm)
+    float vx, vy, vz;     // voxel size (mm)
+    float ivx, ivy, ivz;  // 1 / voxel size
+    float half_c;         // c / 2 (mm/ps): TOF centre shift per ps of dt
+    float inv_sig_sqrt2;  // 1 / (sigma sqrt 2), sigma in mm
+    float k_sigma;        // truncation half-width K sigma (mm)
+    float norm;           // 1 / (2 erf(K / sqrt 2)): makes the full kernel sum to 1
+};
+
+constexpr int kMaxProblems = 64;
+
+// Where a kernel goes: straight onto a stream, or as a node of an explicit
+// HIP graph after `deps` (the new node is written to *node).
+struct Launch {
+    hipStream_t stream = nullptr;
+    hipGraph_t graph = nullptr;
+    const hipGraphNode_t *deps = nullptr;
+    size_t n_deps = 0;
+    hipGraphNode_t *node = nullptr;
+};
+
+inline hipError_t do_launch(const Launch &L, const void *func, dim3 grid, dim3 block, size_t shmem, void **args) {
+    if (grid.x == 0) return hipSuccess;
+    if (!L.graph) {
+        hipError_t e = hipLaunchKernel(func, grid, block, args, shmem, L.stream);
+        return e != hipSuccess ? e : hipGetLastError();
+    }
+    hipKernelNodeParams p{};
+    p.blockDim = block;
+    p.gridDim = grid;
+    p.func = const_cast<void *>(func);
+    p.kernelParams = args;
+    p.sharedMemBytes = (unsigned)shmem;
+    p.extra = nullptr;
+    return hipGraphAddKernelNode(L.node, L.graph, L.deps, L.n_deps, &p);
+}
+
+// ---- projector (project.hip)
+int64_t project_chunk_events(int block, int ept);
+hipError_t launch_project_fused(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int block,
+                                int ept, int *part_neff, double *part_ll);
+hipError_t launch_project_forward(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int block,
+                                  int ept, float *f_out);
+// part[2c] = pieces visited by chunk c, part[2c+1] = pieces with non-zero weight.
+hipError_t launch_count_pieces(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int block,
+                               int ept, unsigned long long *part);
+hipError_t launch_project_back(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int block,
+                               int ept, const float *w_in);
+
+// ---- update and reductions (update.hip)
+int64_t update_chunk_voxels();
+hipError_t launch_update(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_vchunks, double *part_old,
+                         double *part_new);
+
+struct DevStats {
+    int64_t n_eff;
+    double sum_sx;      // sum s x after the update
+    double sum_sx_old;  // sum s x before the update
+    double sum_logf;    // sum over events with f > 0 of log f
+};
+// One block per problem: reduce the projector and update partials into
+// stats[iter * n_probs + p].  n_chunks / n_vchunks: totals over all problems.
+hipError_t launch_finalize(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks,
+                           int64_t n_vchunks, const int *part_neff, const double *part_ll, const double *part_old,
+                           const double *part_new, DevStats *stats, int iter);
+
+hipError_t launch_sum_positive(const Launch &L, const float *s, int64_t n, double *partials, int n_part,
+                               double *out);
+hipError_t launch_uniform_image(const Launch &L, const float *s, int64_t n, const double *sum, double n_events,
+                                float *x);
+hipError_t launch_fill(const Launch &L, float *p, int64_t n, float v);
+// dst[i] = src[z_lo * nx * ny + i] for a z-slab of nzs slices.
+hipError_t launch_copy_slab(const Launch &L, const float *src, int64_t plane, int z_lo, int nzs, float *dst);
+
+// ---- sensitivity (sens.hip)
+struct SensGeom {
+    int32_t nx, ny, nz, n_phi;
+    double ox, oy, oz, vx, vy, vz;
+    double R, H, tan_lmax;  // tan_lmax <= 0: no cut
+};
+hipError_t launch_sensitivity(const Launch &L, const SensGeom &g, float *s);
+
+// ---- event ingest: validation, packing, bucketing sort (events.hip)
+struct KeyGeom {
+    int32_t ncx, ncy, ncz;  // TOF-centre cells per axis
+    int32_t n_phi, n_lam;   // direction bins (azimuth over [0, pi), elevation)
+    int32_t n_regions;      // 0: no region split
+    int32_t sort;           // 0: key = region only (keeps caller order inside a region)
+    int32_t tof;
+    float ox, oy, oz, cell_inv;
+    float half_c;
+    float region_z[kMaxProblems + 1];  // core bounds in mm (n_regions + 1 values)
+};
+uint32_t key_count(const KeyGeom &g);
+// Pass 1: validate raw events, compute keys, histogram them.
+// err bits: 1 non-finite, 2 coincident endpoints, 4 int16 overflow (check_pack), 8 dt beyond binary16.
+hipError_t launch_ingest_keys(const Launch &L, const void *raw, int fmt, int64_t n, const KeyGeom &g,
+                              int check_pack, uint32_t *keys, uint32_t *hist, uint32_t *err);
+// In-place exclusive scan of n counters; tmp needs scan_tmp_elems(n) entries.
+int64_t scan_tmp_elems(int64_t n);
+hipError_t launch_exclusive_scan(const Launch &L, uint32_t *data, int64_t n, uint32_t *tmp);
+// Pass 2: place every event at cursor[key]++ in the stored format; perm[pos] = caller index.
+hipError_t launch_scatter_events(const Launch &L, const void *raw, int fmt, int64_t n, const uint32_t *keys,
+                                 uint32_t *cursor, int store_packed, void *store, int64_t *perm);
+hipError_t launch_gather_by_perm(const Launch &L, const float *src_caller, const int64_t *perm, int64_t n,
+                                 float *dst_stored);
+hipError_t launch_scatter_by_perm(const Launch &L, const float *src_stored, const int64_t *perm, int64_t n,
+                                  float *dst_caller);
+hipError_t launch_unpermute_packed(const Launch &L, const uint4 *store, const int64_t *perm, int64_t n, uint4 *out);
+
+}  // namespace lmtof
