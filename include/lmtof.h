@@ -193,9 +193,10 @@ int lmtof_count_segments(lmtof_ctx *ctx, int64_t *visited, int64_t *weighted);
 
 /* ------------------------------------------------------------- regions */
 /* Section 2.5, TOF-assisted data division: split the field of view into
- * n_regions (1..64) axial core slabs given by n_regions+1 increasing slice
- * indices z_bounds[0] = 0 < ... < z_bounds[n] = nz.  Each event goes to the
- * core holding its TOF centre's z (clamped to the first/last core).  Region
+ * n_regions (1..64) axial core slabs given by n_regions+1 strictly
+ * increasing slice indices 0 <= z_bounds[0] < ... < z_bounds[n] <= nz.
+ * Each event goes to the core holding its TOF centre's z (clamped to the
+ * first/last core).  Needs TOF (EUNSUPPORTED otherwise).  Region
  * k is an independent MLEM problem on the sub-volume core_k widened by
  * margin_slices on both sides (clamped to the grid); a negative margin asks
  * for the default ceil(K sigma sin(lambda_max) / vz) + ceil(6 mm / vz).

@@ -376,7 +376,7 @@ int check_geometry(lmtof_ctx *c, const lmtof_geometry &g) {
     return LMTOF_OK;
 }
 
-KeyGeom key_geom(const lmtof_ctx *c, bool sort) {
+KeyGeom key_geom(const lmtof_ctx *c, bool sort, const std::vector<Region> &regions) {
     const lmtof_geometry &g = c->g;
     KeyGeom k{};
     double cell = c->opt_cell_mm;
@@ -393,14 +393,14 @@ KeyGeom key_geom(const lmtof_ctx *c, bool sort) {
         k.ncx = (int)std::ceil(g.nx * g.vx / cell);
         k.ncy = (int)std::ceil(g.ny * g.vy / cell);
         k.ncz = (int)std::ceil(g.nz * g.vz / cell);
-        if ((double)k.ncx * k.ncy * k.ncz * k.n_phi * k.n_lam * std::max<size_t>(1, c->regions.size()) <= (1 << 26))
+        if ((double)k.ncx * k.ncy * k.ncz * k.n_phi * k.n_lam * std::max<size_t>(1, regions.size()) <= (1 << 26))
             break;
         cell *= 1.25;
     }
     k.cell_inv = (float)(1.0 / cell);
-    k.n_regions = (int)c->regions.size();
-    for (size_t r = 0; r < c->regions.size(); ++r) k.region_z[r] = (float)(g.z0 + c->regions[r].core_lo * g.vz);
-    if (!c->regions.empty()) k.region_z[c->regions.size()] = (float)(g.z0 + c->regions.back().core_hi * g.vz);
+    k.n_regions = (int)regions.size();
+    for (size_t r = 0; r < regions.size(); ++r) k.region_z[r] = (float)(g.z0 + regions[r].core_lo * g.vz);
+    if (!regions.empty()) k.region_z[regions.size()] = (float)(g.z0 + regions.back().core_hi * g.vz);
     return k;
 }
 
@@ -628,10 +628,7 @@ int lmtof_load_events(lmtof_ctx *c, const void *ev, int64_t n, int format, int m
     hipError_t he = hipMemsetAsync(err, 0, sizeof(uint32_t), c->stream);
     const bool sort = c->opt_sort != 0;
     // events are loaded unsplit; lmtof_set_regions re-sorts by region
-    std::vector<Region> saved;
-    saved.swap(c->regions);
-    KeyGeom kg = key_geom(c, sort);
-    saved.swap(c->regions);
+    KeyGeom kg = key_geom(c, sort, std::vector<Region>());
     uint32_t nkeys = key_count(kg);
     if (he == hipSuccess && sort) {
         if ((rc = dev_alloc(c, &keys, n)) || (rc = dev_alloc(c, &hist, nkeys)) ||
@@ -726,6 +723,8 @@ int lmtof_compute_sensitivity(lmtof_ctx *c) {
     Launch L;
     L.stream = c->stream;
     HIPCHK(c, launch_sensitivity(L, sg, c->d_s));
+    const int64_t plane = (int64_t)g.nx * g.ny;
+    for (auto &r : c->regions) HIPCHK(c, launch_copy_slab(L, c->d_s, plane, r.z_lo, r.nz, r.s));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->has_sens = true;
     c->has_image = false;
@@ -799,7 +798,13 @@ int lmtof_read_image(lmtof_ctx *c, float *out, int64_t n, int mem) {
     if (!out || n != c->V || !valid_mem(mem)) return fail(c, LMTOF_EINVAL, "need n = %lld floats", (long long)c->V);
     HIPCHK(c, hipSetDevice(c->device));
     if (c->regions.empty()) return copy_out(c, out, c->d_x, sizeof(float) * n, mem);
-    return fail(c, LMTOF_EUNSUPPORTED, "region images: use lmtof_read_region_image");
+    // Section 2.5: the region images, each at its z offset, are summed into one volume
+    Launch L;
+    L.stream = c->stream;
+    const int64_t plane = (int64_t)c->g.nx * c->g.ny;
+    HIPCHK(c, launch_fill(L, c->d_x, c->V, 0.0f));
+    for (auto &r : c->regions) HIPCHK(c, launch_add_slab(L, r.x, plane, r.z_lo, r.nz, c->d_x));
+    return copy_out(c, out, c->d_x, sizeof(float) * n, mem);
 }
 
 int lmtof_iterate(lmtof_ctx *c, int n_iter, lmtof_iter_stats *stats) {
@@ -990,18 +995,127 @@ int lmtof_count_segments(lmtof_ctx *c, int64_t *visited, int64_t *weighted) {
     return LMTOF_OK;
 }
 
-int lmtof_set_regions(lmtof_ctx *c, const int32_t *, int, int) {
+int lmtof_set_regions(lmtof_ctx *c, const int32_t *zb, int n, int margin) {
     if (!c) return LMTOF_EINVAL;
-    return fail(c, LMTOF_EUNSUPPORTED, "regions not built yet");
+    c->err.clear();
+    if (!c->n_events || !c->has_sens) return fail(c, LMTOF_ESTATE, "load events and compute the sensitivity first");
+    const lmtof_geometry &g = c->g;
+    if (!(g.tof_fwhm_ps > 0)) return fail(c, LMTOF_EUNSUPPORTED, "the TOF-assisted data division needs TOF data");
+    if (!zb || n < 1 || n > kMaxProblems) return fail(c, LMTOF_EINVAL, "n_regions must be in [1, %d]", kMaxProblems);
+    if (zb[0] < 0 || zb[n] > g.nz) return fail(c, LMTOF_EINVAL, "z_bounds must lie within [0, nz = %d]", g.nz);
+    for (int k = 0; k < n; ++k)
+        if (zb[k + 1] <= zb[k]) return fail(c, LMTOF_EINVAL, "z_bounds must be strictly increasing");
+    if (margin < 0) {
+        const double sg = sigma_mm(g);
+        const double sl = g.max_axial_angle_deg > 0 ? std::sin(g.max_axial_angle_deg * M_PI / 180.0) : 1.0;
+        margin = (int)std::ceil(g.tof_trunc_sigmas * sg * sl / g.vz - 1e-9) + (int)std::ceil(6.0 / g.vz - 1e-9);
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+    std::vector<Region> regs(n);
+    for (int k = 0; k < n; ++k) {
+        regs[k].core_lo = zb[k];
+        regs[k].core_hi = zb[k + 1];
+        regs[k].z_lo = std::max(0, zb[k] - margin);
+        regs[k].nz = std::min(g.nz, zb[k + 1] + margin) - regs[k].z_lo;
+    }
+    const int64_t N = c->n_events;
+    const size_t esz = c->stored_packed ? 16 : 32;
+    KeyGeom kg = key_geom(c, c->opt_sort != 0, regs);
+    const uint32_t nkeys = key_count(kg), kpr = nkeys / (uint32_t)n;
+    Launch L;
+    L.stream = c->stream;
+    uint32_t *keys = nullptr, *hist = nullptr, *tmp = nullptr, *err = nullptr;
+    int64_t *inner = nullptr, *perm = nullptr;
+    void *store = nullptr;
+    const int64_t plane = (int64_t)g.nx * g.ny;
+    auto cleanup = [&](int rc) {
+        (void)hipStreamSynchronize(c->stream);
+        dev_free(keys); dev_free(hist); dev_free(tmp); dev_free(err);
+        dev_free(inner); dev_free(perm); dev_free(store);
+        for (auto &r : regs) { dev_free(r.x); dev_free(r.b); dev_free(r.s); }
+        return rc;
+    };
+    int rc;
+    if ((rc = dev_alloc(c, &keys, N)) || (rc = dev_alloc(c, &hist, nkeys)) ||
+        (rc = dev_alloc(c, &tmp, scan_tmp_elems(nkeys))) || (rc = dev_alloc(c, &err, 1)) ||
+        (rc = dev_alloc(c, &inner, N)) || (rc = dev_alloc(c, &perm, N)) ||
+        (rc = dev_alloc(c, (char **)&store, esz * N)))
+        return cleanup(rc);
+    for (auto &r : regs) {
+        const int64_t Vr = plane * r.nz;
+        if ((rc = dev_alloc(c, &r.x, Vr)) || (rc = dev_alloc(c, &r.b, Vr)) || (rc = dev_alloc(c, &r.s, Vr)))
+            return cleanup(rc);
+    }
+    const int fmt = c->stored_packed ? 1 : 2;
+    hipError_t he = hipMemsetAsync(hist, 0, sizeof(uint32_t) * nkeys, c->stream);
+    if (he == hipSuccess) he = hipMemsetAsync(err, 0, sizeof(uint32_t), c->stream);
+    if (he == hipSuccess) he = launch_ingest_keys(L, c->d_events, fmt, N, kg, 0, keys, hist, err);
+    if (he == hipSuccess) he = launch_exclusive_scan(L, hist, nkeys, tmp);
+    std::vector<uint32_t> starts(n, 0);
+    for (int k = 0; k < n && he == hipSuccess; ++k)
+        he = hipMemcpyAsync(&starts[k], hist + (size_t)k * kpr, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream);
+    if (he == hipSuccess)
+        he = launch_scatter_events(L, c->d_events, fmt, N, keys, hist, c->stored_packed, store, inner);
+    if (he == hipSuccess) he = launch_compose_perm(L, c->d_perm, inner, N, perm);
+    for (auto &r : regs) {
+        if (he != hipSuccess) break;
+        he = launch_copy_slab(L, c->d_s, plane, r.z_lo, r.nz, r.s);
+        if (he == hipSuccess) he = launch_fill(L, r.b, plane * r.nz, 0.0f);
+        if (he == hipSuccess) he = launch_fill(L, r.x, plane * r.nz, 0.0f);
+    }
+    if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+    if (he != hipSuccess) return cleanup(fail(c, LMTOF_EHIP, "region split: %s", hipGetErrorString(he)));
+    for (int k = 0; k < n; ++k) {
+        regs[k].ev_offset = starts[k];
+        regs[k].n_events = (k + 1 < n ? (int64_t)starts[k + 1] : N) - (int64_t)starts[k];
+    }
+    // install: new event order, new permutation, region buffers
+    drop_regions(c);
+    drop_graphs(c);
+    std::swap(c->d_events, store);
+    std::swap(c->d_perm, perm);
+    c->regions = regs;
+    for (auto &r : regs) r.x = r.b = r.s = nullptr;  // now owned by the context
+    c->margin_used = margin;
+    c->has_image = false;
+    c->probs_dirty = true;
+    return cleanup(LMTOF_OK);
 }
-int lmtof_region_info(const lmtof_ctx *c, int, int32_t *, int64_t *) { return c ? LMTOF_EUNSUPPORTED : LMTOF_EINVAL; }
-int lmtof_read_region_image(lmtof_ctx *c, int, float *, int64_t, int) {
+
+int lmtof_region_info(const lmtof_ctx *c, int k, int32_t *out4, int64_t *n_events) {
+    if (!c || !out4 || !n_events) return LMTOF_EINVAL;
+    if (k < 0 || k >= (int)c->regions.size()) return LMTOF_EINVAL;
+    const Region &r = c->regions[k];
+    out4[0] = r.z_lo;
+    out4[1] = r.nz;
+    out4[2] = r.core_lo;
+    out4[3] = r.core_hi;
+    *n_events = r.n_events;
+    return LMTOF_OK;
+}
+
+int lmtof_read_region_image(lmtof_ctx *c, int k, float *out, int64_t n, int mem) {
     if (!c) return LMTOF_EINVAL;
-    return fail(c, LMTOF_EUNSUPPORTED, "regions not built yet");
+    c->err.clear();
+    if (c->regions.empty() || !c->has_image) return fail(c, LMTOF_ESTATE, "no region images yet");
+    if (k < 0 || k >= (int)c->regions.size()) return fail(c, LMTOF_EINVAL, "region %d out of range", k);
+    const Region &r = c->regions[k];
+    const int64_t Vr = (int64_t)c->g.nx * c->g.ny * r.nz;
+    if (!out || n != Vr || !valid_mem(mem)) return fail(c, LMTOF_EINVAL, "need n = %lld floats", (long long)Vr);
+    HIPCHK(c, hipSetDevice(c->device));
+    return copy_out(c, out, r.x, sizeof(float) * n, mem);
 }
+
 int lmtof_clear_regions(lmtof_ctx *c) {
     if (!c) return LMTOF_EINVAL;
-    drop_regions(c);
+    c->err.clear();
+    if (!c->regions.empty()) {
+        (void)hipSetDevice(c->device);
+        (void)hipStreamSynchronize(c->stream);
+        drop_regions(c);
+        drop_graphs(c);
+        c->has_image = false;
+    }
     return LMTOF_OK;
 }
 

