@@ -38,9 +38,8 @@ def main():
     ap.add_argument("--events", type=int, default=146_000_000)
     ap.add_argument("--iters", type=int, default=10)
     ap.add_argument("--storage", choices=["plain", "packed"], default="plain")
-    ap.add_argument("--cpu-sample", type=int, default=3_000_000,
+    ap.add_argument("--cpu-sample", type=int, default=30_000_000,
                     help="events in the oracle CPU-baseline sample (0 = skip)")
-    ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--ept", type=int, default=0)
     args = ap.parse_args()
 
@@ -68,8 +67,6 @@ def main():
     torch.cuda.synchronize()
 
     opts = dict(storage=1 if args.storage == "packed" else 0)
-    if args.block:
-        opts["block"] = args.block
     if args.ept:
         opts["events_per_thread"] = args.ept
     r = L.Reconstruction(g, device=0, **opts)
@@ -110,6 +107,8 @@ def main():
     N, I, K = w.n_events, w.n_iter, args.steps
     value = N * I * K / wall
     proj_ms = float(np.mean([s["project_ms"] for st in stats for s in st]))
+    fwd_ms = float(np.mean([s["forward_ms"] for st in stats for s in st]))
+    back_ms = float(np.mean([s["back_ms"] for st in stats for s in st]))
     iter_ms = float(np.mean([s["ms"] for st in stats for s in st]))
     loop_rate = N / (iter_ms * 1e-3)
     last = stats[-1][-1]
@@ -139,7 +138,9 @@ def main():
         "recon_latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99))},
         "one_time_ms": {k: float(np.mean([t[k] for t in times])) for k in ("load_ms", "sens_ms", "init_ms")},
         "iteration_ms": iter_ms,
-        "project_kernel_ms": proj_ms,
+        "project_ms": proj_ms,
+        "forward_kernel_ms": fwd_ms,
+        "back_kernel_ms": back_ms,
         "segments_per_event": {"visited": visited / N, "weighted": weighted / N},
         "last_iteration": {"n_eff": last["n_eff"], "sum_sx": last["sum_sx"], "loglik": last["loglik"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

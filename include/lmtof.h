@@ -70,9 +70,8 @@ extern "C" {
 #define LMTOF_OPT_SORT 2
 /* Azimuth nodes of the sensitivity quadrature.  Default 2048. */
 #define LMTOF_OPT_SENS_NPHI 3
-/* Projector launch shape: threads per block (64..1024, multiple of 64) and
- * events per thread (1..16).  0 = library default / autotuned value. */
-#define LMTOF_OPT_BLOCK 4
+/* Forward-projector launch shape: events per thread (1..16; 256 threads per
+ * block).  0 = library default. */
 #define LMTOF_OPT_EVENTS_PER_THREAD 5
 /* Edge of the cubic TOF-centre cell used by the sort key, in mm (default 16). */
 #define LMTOF_OPT_SORT_CELL_MM 6
@@ -103,7 +102,9 @@ typedef struct {
     double sum_sx;    /* sum_j s_j x^{k+1}_j, FP64 (equals n_eff up to rounding) */
     double loglik;    /* sum_i log (A x^k)_i - sum_j s_j x^k_j over n_eff events */
     float ms;         /* wall time of the iteration on the GPU (ms) */
-    float project_ms; /* of which: the fused projector kernel (ms) */
+    float project_ms; /* of which: forward + back projection (ms) */
+    float forward_ms; /* forward projection and ratio kernel (ms) */
+    float back_ms;    /* back projection kernel (ms) */
 } lmtof_iter_stats;
 
 /* ------------------------------------------------------------- lifecycle */

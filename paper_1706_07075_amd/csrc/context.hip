@@ -21,8 +21,7 @@ using namespace lmtof;
 namespace {
 
 constexpr double kDefaultC = 0.299792458;
-constexpr int kDefaultBlock = 256;
-constexpr int kDefaultEpt = 1;
+constexpr int kDefaultEpt = 4;
 
 struct GraphEntry {
     hipGraph_t graph = nullptr;
@@ -36,10 +35,16 @@ struct Region {
     float *x = nullptr, *b = nullptr, *s = nullptr;
 };
 
-template <class T>
-struct DevBuf {
-    T *p = nullptr;
-    size_t n = 0;
+// Brick item lists of one problem batch (see the projector): items grouped
+// by brick; chunks (brick, first item, end item, tile slot) largest first;
+// per non-empty brick its tile slots (brick, first slot, end slot); the
+// tile scratch (one 16^3 FP32 tile per slot).
+struct ItemSet {
+    uint32_t *items = nullptr;
+    uint4 *chunks = nullptr, *bricks = nullptr;
+    float *tiles = nullptr;
+    uint32_t n_chunks = 0, n_bricks = 0, n_slots = 0;
+    uint64_t n_items = 0;
 };
 
 }  // namespace
@@ -51,7 +56,7 @@ struct lmtof_ctx {
     std::string err;
 
     // options
-    int opt_storage = 0, opt_sort = 1, opt_nphi = 2048, opt_block = 0, opt_ept = 0;
+    int opt_storage = 0, opt_sort = 1, opt_nphi = 2048, opt_ept = 0;
     double opt_cell_mm = 16.0;
 
     bool has_geom = false;
@@ -77,7 +82,12 @@ struct lmtof_ctx {
     std::vector<Problem> probs;
     Problem *d_probs = nullptr;
     int64_t n_chunks = 0, n_vchunks = 0;
-    int block_used = kDefaultBlock, ept_used = kDefaultEpt;
+    int ept_used = kDefaultEpt;
+    ItemSet items;               // brick item lists of the iteration batch
+    float *d_rw = nullptr;       // per stored event: 1 / f (MLEM) or a weight
+    size_t rw_cap = 0;
+    float4 *d_lut = nullptr;     // kernel-CDF table
+    double lut_k = -1.0;
     int *d_part_neff = nullptr;
     double *d_part_ll = nullptr, *d_part_old = nullptr, *d_part_new = nullptr;
     size_t part_cap = 0, vpart_cap = 0;
@@ -87,7 +97,6 @@ struct lmtof_ctx {
     bool probs_dirty = true;
 
     std::map<int, GraphEntry> graphs;
-    bool graph_events_ok = true;
 };
 
 namespace {
@@ -130,6 +139,14 @@ void dev_free(T *&p) {
     p = nullptr;
 }
 
+void free_items(ItemSet &it) {
+    dev_free(it.items);
+    dev_free(it.chunks);
+    dev_free(it.bricks);
+    dev_free(it.tiles);
+    it = ItemSet();
+}
+
 void drop_graphs(lmtof_ctx *c) {
     for (auto &kv : c->graphs) {
         if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
@@ -137,6 +154,7 @@ void drop_graphs(lmtof_ctx *c) {
         for (hipEvent_t e : kv.second.ev) (void)hipEventDestroy(e);
     }
     c->graphs.clear();
+    free_items(c->items);
 }
 
 void drop_regions(lmtof_ctx *c) {
@@ -192,14 +210,49 @@ Problem make_problem(const lmtof_ctx *c, int z_lo, int nz, float *x, float *b, c
         P.k_sigma = (float)(g.tof_trunc_sigmas * sg);
         P.norm = (float)(1.0 / (2.0 * std::erf(g.tof_trunc_sigmas / std::sqrt(2.0))));
     }
+    P.lut = c->d_lut;
+    if (P.tof) {
+        const double h = 2.0 * g.tof_trunc_sigmas / (kLutN - 1);
+        P.lut_a = (float)(1.0 / (sigma_mm(g) * h));
+        P.lut_b = (float)(g.tof_trunc_sigmas / h);
+    }
+    P.a_max = P.tof ? 1.0f : (float)std::sqrt(g.vx * g.vx + g.vy * g.vy + g.vz * g.vz);
+    P.nbx = (g.nx + kBrickX - 1) / kBrickX;
+    P.nby = (g.ny + kBrickY - 1) / kBrickY;
+    P.nbz = (nz + kBrickZ - 1) / kBrickZ;
     P.x = x;
     P.b = b;
     P.s = s;
     return P;
 }
 
+// Kernel-CDF table for truncation K: node k at u_k = -K + k h (sigma units),
+// h = 2K / (n - 1), holds Phi(u_k), Phi'(u_k) h and Phi''(u_k) h^2 / 2 with
+// Phi(u) = erf(u / sqrt 2) / (2 erf(K / sqrt 2)) (so a piece's weight is a
+// difference of two values) and Phi'' = -u Phi'.  Evaluated in FP64.
+int ensure_lut(lmtof_ctx *c) {
+    const double K = c->g.tof_trunc_sigmas;
+    if (c->d_lut && c->lut_k == K) return LMTOF_OK;
+    std::vector<float4> tab(kLutN);
+    const double h = 2.0 * K / (kLutN - 1), den = std::erf(K / std::sqrt(2.0));
+    for (int k = 0; k < kLutN; ++k) {
+        const double u = -K + k * h;
+        const double phi = std::exp(-0.5 * u * u) / (std::sqrt(2.0 * M_PI) * den);
+        tab[k] = make_float4((float)(std::erf(u / std::sqrt(2.0)) / (2.0 * den)), (float)(phi * h),
+                             (float)(-u * phi * h * h / 2.0), 0.0f);
+    }
+    if (!c->d_lut) {
+        int rc = dev_alloc(c, &c->d_lut, kLutN);
+        if (rc) return rc;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->d_lut, tab.data(), sizeof(float4) * kLutN, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->lut_k = K;
+    return LMTOF_OK;
+}
+
 void launch_shape(const lmtof_ctx *c, int &block, int &ept) {
-    block = c->opt_block > 0 ? c->opt_block : kDefaultBlock;
+    block = kForwardBlock;
     ept = c->opt_ept > 0 ? c->opt_ept : kDefaultEpt;
 }
 
@@ -209,13 +262,17 @@ int upload_problems(lmtof_ctx *c, std::vector<Problem> &ps, int block, int ept, 
     const int64_t ce = project_chunk_events(block, ept), cv = update_chunk_voxels();
     n_chunks = 0;
     n_vchunks = 0;
+    int64_t nb = 0;
     for (auto &P : ps) {
         P.chunk_begin = n_chunks;
         P.vchunk_begin = n_vchunks;
+        P.brick_base = (int32_t)nb;
+        nb += (int64_t)P.nbx * P.nby * P.nbz;
         n_chunks += (P.n_events + ce - 1) / ce;
         n_vchunks += ((int64_t)P.nx * P.ny * P.nz + cv - 1) / cv;
     }
     if (n_chunks > 0x7fffffffLL) return fail(c, LMTOF_EUNSUPPORTED, "too many projector blocks (%lld)", (long long)n_chunks);
+    if (nb > 0x7fffffffLL) return fail(c, LMTOF_EUNSUPPORTED, "too many bricks (%lld)", (long long)nb);
     if (!*d) {
         int rc = dev_alloc(c, d, kMaxProblems);
         if (rc) return rc;
@@ -224,10 +281,127 @@ int upload_problems(lmtof_ctx *c, std::vector<Problem> &ps, int block, int ept, 
     return LMTOF_OK;
 }
 
+// Brick item lists for an uploaded problem batch: count pieces per brick,
+// lay the lists out by brick and fill them on the GPU; then cut each list
+// into chunks of at most C items (C grows with the total so there are
+// ~8k chunks) and order the chunks largest first.  The chunk table is a
+// launch schedule built on the host from the per-brick counts.
+int build_items(lmtof_ctx *c, const std::vector<Problem> &ps, const Problem *d_probs, int64_t n_chunks, int ept,
+                ItemSet &out) {
+    free_items(out);
+    uint64_t nb = 0;
+    for (const auto &P : ps) nb += (uint64_t)P.nbx * P.nby * P.nbz;
+    Launch L;
+    L.stream = c->stream;
+    uint32_t *cnt = nullptr, *off_d = nullptr;
+    int rc = dev_alloc(c, &cnt, nb + 1);
+    if (rc) return rc;
+    std::vector<uint32_t> h(nb);
+    hipError_t he = hipMemsetAsync(cnt, 0, sizeof(uint32_t) * (nb + 1), c->stream);
+    if (he == hipSuccess) he = launch_brick_items(L, d_probs, (int)ps.size(), n_chunks, ept, cnt, nullptr, nullptr);
+    if (he == hipSuccess) he = hipMemcpyAsync(h.data(), cnt, sizeof(uint32_t) * nb, hipMemcpyDeviceToHost, c->stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+    if (he != hipSuccess) {
+        dev_free(cnt);
+        return fail(c, LMTOF_EHIP, "brick item count: %s", hipGetErrorString(he));
+    }
+    std::vector<uint32_t> off(nb + 1);
+    uint64_t tot = 0;
+    for (uint64_t b = 0; b < nb; ++b) {
+        off[b] = (uint32_t)tot;
+        tot += h[b];
+    }
+    if (tot > 0xffffffffULL) {
+        dev_free(cnt);
+        return fail(c, LMTOF_EUNSUPPORTED, "more than 2^32-1 brick items");
+    }
+    off[nb] = (uint32_t)tot;
+    const uint64_t C = std::max<uint64_t>(2048, (tot + 8191) / 8192);
+    std::vector<uint4> chunks, bricks;
+    uint32_t slot = 0;
+    for (uint64_t b = 0; b < nb; ++b) {
+        if (!h[b]) continue;
+        const uint32_t nch = (uint32_t)((h[b] + C - 1) / C);
+        bricks.push_back(make_uint4((uint32_t)b, slot, slot + nch, 0));
+        for (uint32_t q = 0; q < nch; ++q) {
+            const uint32_t k0 = off[b] + (uint32_t)((uint64_t)h[b] * q / nch);
+            const uint32_t k1 = off[b] + (uint32_t)((uint64_t)h[b] * (q + 1) / nch);
+            chunks.push_back(make_uint4((uint32_t)b, k0, k1, slot + q));
+        }
+        slot += nch;
+    }
+    std::stable_sort(chunks.begin(), chunks.end(),
+                     [](const uint4 &a, const uint4 &b) { return (a.z - a.y) > (b.z - b.y); });
+    ItemSet it;
+    it.n_chunks = (uint32_t)chunks.size();
+    it.n_bricks = (uint32_t)bricks.size();
+    it.n_slots = slot;
+    it.n_items = tot;
+    if ((rc = dev_alloc(c, &it.items, tot)) || (rc = dev_alloc(c, &off_d, nb + 1)) ||
+        (rc = dev_alloc(c, &it.chunks, chunks.size())) || (rc = dev_alloc(c, &it.bricks, bricks.size())) ||
+        (rc = dev_alloc(c, &it.tiles, (size_t)slot * kBrickVox))) {
+        dev_free(cnt);
+        dev_free(off_d);
+        free_items(it);
+        return rc;
+    }
+    he = hipMemcpyAsync(off_d, off.data(), sizeof(uint32_t) * (nb + 1), hipMemcpyHostToDevice, c->stream);
+    if (he == hipSuccess && !chunks.empty())
+        he = hipMemcpyAsync(it.chunks, chunks.data(), sizeof(uint4) * chunks.size(), hipMemcpyHostToDevice, c->stream);
+    if (he == hipSuccess && !bricks.empty())
+        he = hipMemcpyAsync(it.bricks, bricks.data(), sizeof(uint4) * bricks.size(), hipMemcpyHostToDevice, c->stream);
+    if (he == hipSuccess) he = hipMemcpyAsync(cnt, off_d, sizeof(uint32_t) * (nb + 1), hipMemcpyDeviceToDevice, c->stream);
+    if (he == hipSuccess)
+        he = launch_brick_items(L, d_probs, (int)ps.size(), n_chunks, ept, cnt, it.items, off_d + 1);
+    if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+    dev_free(cnt);
+    dev_free(off_d);
+    if (he != hipSuccess) {
+        free_items(it);
+        return fail(c, LMTOF_EHIP, "brick item fill: %s", hipGetErrorString(he));
+    }
+    out = it;
+    return LMTOF_OK;
+}
+
+// Back projection of per-stored-event weights w into the batch's b arrays
+// (as graph nodes after *prev, or on the stream).
+int add_back(lmtof_ctx *c, Launch L, const Problem *d_probs, int np, const ItemSet &it, const float *w,
+             hipGraphNode_t *prev) {
+    const bool tof = c->g.tof_fwhm_ps > 0;
+    hipGraphNode_t node = nullptr;
+    if (L.graph) {
+        L.deps = prev;
+        L.n_deps = 1;
+        L.node = &node;
+    }
+    HIPCHK(c, launch_back_chunks(L, tof, d_probs, np, c->d_events, it.chunks, it.n_chunks, it.items, w, it.tiles));
+    if (L.graph && it.n_chunks) {
+        *prev = node;
+        L.deps = prev;
+    }
+    HIPCHK(c, launch_reduce_tiles(L, d_probs, np, it.bricks, it.n_bricks, it.tiles));
+    if (L.graph && it.n_bricks) *prev = node;
+    return LMTOF_OK;
+}
+
+int ensure_rw(lmtof_ctx *c) {
+    if ((size_t)c->n_events <= c->rw_cap) return LMTOF_OK;
+    dev_free(c->d_rw);
+    c->rw_cap = 0;
+    int rc = dev_alloc(c, &c->d_rw, c->n_events);
+    if (rc) return rc;
+    c->rw_cap = c->n_events;
+    return LMTOF_OK;
+}
+
 // (Re)build the batch the iteration runs: the whole volume, or one problem per region.
 int ensure_problems(lmtof_ctx *c) {
     if (!c->probs_dirty) return LMTOF_OK;
     drop_graphs(c);
+    int rc0 = ensure_lut(c);
+    if (rc0) return rc0;
+    if ((rc0 = ensure_rw(c))) return rc0;
     std::vector<Problem> ps;
     const size_t esz = c->stored_packed ? 16 : 32;
     if (c->regions.empty()) {
@@ -249,8 +423,8 @@ int ensure_problems(lmtof_ctx *c) {
     launch_shape(c, block, ept);
     int rc = upload_problems(c, ps, block, ept, &c->d_probs, c->n_chunks, c->n_vchunks);
     if (rc) return rc;
+    if ((rc = build_items(c, ps, c->d_probs, c->n_chunks, ept, c->items))) return rc;
     c->probs = ps;
-    c->block_used = block;
     c->ept_used = ept;
     if ((size_t)c->n_chunks > c->part_cap) {
         dev_free(c->d_part_neff);
@@ -282,52 +456,49 @@ int ensure_stats(lmtof_ctx *c, size_t n) {
     return LMTOF_OK;
 }
 
+// n_iter MLEM iterations as one explicit HIP graph.  Per iteration: event
+// record, forward + ratio, event record, brick back projection, event
+// record, update, finalize (stats of iteration k into slot k), event record.
 int build_graph(lmtof_ctx *c, int n_iter, GraphEntry &ge) {
     const int np = (int)c->probs.size();
+    const bool tof = c->g.tof_fwhm_ps > 0;
     HIPCHK(c, hipGraphCreate(&ge.graph, 0));
-    ge.ev.assign(3 * n_iter, nullptr);
+    ge.ev.assign(4 * n_iter, nullptr);
     for (auto &e : ge.ev) HIPCHK(c, hipEventCreate(&e));
     hipGraphNode_t prev = nullptr;
     bool have_prev = false;
+    auto record = [&](hipEvent_t ev) -> int {
+        hipGraphNode_t n = nullptr;
+        HIPCHK(c, hipGraphAddEventRecordNode(&n, ge.graph, have_prev ? &prev : nullptr, have_prev ? 1 : 0, ev));
+        prev = n;
+        have_prev = true;
+        return LMTOF_OK;
+    };
     for (int k = 0; k < n_iter; ++k) {
+        int rc;
+        if ((rc = record(ge.ev[4 * k]))) return rc;
+        hipGraphNode_t node = nullptr;
         Launch L;
         L.graph = ge.graph;
-        hipGraphNode_t nA = nullptr, nP = nullptr, nB = nullptr, nU = nullptr, nF = nullptr, nC = nullptr;
-        if (c->graph_events_ok) {
-            hipError_t e = hipGraphAddEventRecordNode(&nA, ge.graph, have_prev ? &prev : nullptr, have_prev ? 1 : 0,
-                                                      ge.ev[3 * k]);
-            if (e != hipSuccess) {
-                (void)hipGetLastError();
-                return fail(c, LMTOF_EHIP, "hipGraphAddEventRecordNode: %s", hipGetErrorString(e));
-            }
-            prev = nA;
-            have_prev = true;
-        }
-        L.deps = have_prev ? &prev : nullptr;
-        L.n_deps = have_prev ? 1 : 0;
-        L.node = &nP;
-        HIPCHK(c, launch_project_fused(L, c->d_probs, np, c->n_chunks, c->block_used, c->ept_used, c->d_part_neff,
-                                       c->d_part_ll));
-        prev = nP;
-        have_prev = true;
-        if (c->graph_events_ok) {
-            HIPCHK(c, hipGraphAddEventRecordNode(&nB, ge.graph, &prev, 1, ge.ev[3 * k + 1]));
-            prev = nB;
-        }
         L.deps = &prev;
         L.n_deps = 1;
-        L.node = &nU;
-        HIPCHK(c, launch_update(L, c->d_probs, np, c->n_vchunks, c->d_part_old, c->d_part_new));
-        prev = nU;
+        L.node = &node;
+        HIPCHK(c, launch_forward(L, tof, c->d_probs, np, c->n_chunks, c->ept_used, 0, c->d_rw, c->d_part_neff,
+                                 c->d_part_ll));
+        if (node) prev = node;
+        if ((rc = record(ge.ev[4 * k + 1]))) return rc;
+        if ((rc = add_back(c, L, c->d_probs, np, c->items, c->d_rw, &prev))) return rc;
+        if ((rc = record(ge.ev[4 * k + 2]))) return rc;
         L.deps = &prev;
-        L.node = &nF;
+        node = nullptr;
+        HIPCHK(c, launch_update(L, c->d_probs, np, c->n_vchunks, c->d_part_old, c->d_part_new));
+        if (node) prev = node;
+        L.deps = &prev;
+        node = nullptr;
         HIPCHK(c, launch_finalize(L, c->d_probs, np, c->n_chunks, c->n_vchunks, c->d_part_neff, c->d_part_ll,
                                   c->d_part_old, c->d_part_new, c->d_stats, k));
-        prev = nF;
-        if (c->graph_events_ok) {
-            HIPCHK(c, hipGraphAddEventRecordNode(&nC, ge.graph, &prev, 1, ge.ev[3 * k + 2]));
-            prev = nC;
-        }
+        if (node) prev = node;
+        if ((rc = record(ge.ev[4 * k + 3]))) return rc;
     }
     HIPCHK(c, hipGraphInstantiate(&ge.exec, ge.graph, nullptr, nullptr, 0));
     return LMTOF_OK;
@@ -468,6 +639,8 @@ int lmtof_destroy(lmtof_ctx *c) {
     dev_free(c->d_part_new);
     dev_free(c->d_stats);
     dev_free(c->d_scratch);
+    dev_free(c->d_rw);
+    dev_free(c->d_lut);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
     return LMTOF_OK;
@@ -511,11 +684,6 @@ int lmtof_set_option(lmtof_ctx *c, int key, int64_t v) {
         if (v < 4 || v > 4096) return fail(c, LMTOF_EINVAL, "sensitivity azimuth nodes must be in [4, 4096]");
         c->opt_nphi = (int)v;
         return LMTOF_OK;
-    case LMTOF_OPT_BLOCK:
-        if (v != 0 && (v < 64 || v > 1024 || v % 64)) return fail(c, LMTOF_EINVAL, "block must be 0 or 64..1024, x64");
-        c->opt_block = (int)v;
-        c->probs_dirty = true;
-        return LMTOF_OK;
     case LMTOF_OPT_EVENTS_PER_THREAD:
         if (v < 0 || v > 16) return fail(c, LMTOF_EINVAL, "events per thread must be in [0, 16]");
         c->opt_ept = (int)v;
@@ -536,7 +704,6 @@ int lmtof_get_option(const lmtof_ctx *c, int key, int64_t *v) {
     case LMTOF_OPT_STORAGE: *v = c->opt_storage; return LMTOF_OK;
     case LMTOF_OPT_SORT: *v = c->opt_sort; return LMTOF_OK;
     case LMTOF_OPT_SENS_NPHI: *v = c->opt_nphi; return LMTOF_OK;
-    case LMTOF_OPT_BLOCK: *v = c->opt_block > 0 ? c->opt_block : kDefaultBlock; return LMTOF_OK;
     case LMTOF_OPT_EVENTS_PER_THREAD: *v = c->opt_ept > 0 ? c->opt_ept : kDefaultEpt; return LMTOF_OK;
     case LMTOF_OPT_SORT_CELL_MM: *v = (int64_t)c->opt_cell_mm; return LMTOF_OK;
     default: return LMTOF_EINVAL;
@@ -851,13 +1018,13 @@ int lmtof_iterate(lmtof_ctx *c, int n_iter, lmtof_iter_stats *stats) {
                 o.n_eff = ne;
                 o.sum_sx = sx;
                 o.loglik = slf - sxo;
-                if (c->graph_events_ok) {
-                    const auto &ev = it->second.ev;
-                    float a = 0, b = 0;
-                    if (hipEventElapsedTime(&a, ev[3 * k], ev[3 * k + 2]) == hipSuccess) o.ms = a;
-                    if (hipEventElapsedTime(&b, ev[3 * k], ev[3 * k + 1]) == hipSuccess) o.project_ms = b;
-                    (void)hipGetLastError();
-                }
+                const auto &ev = it->second.ev;
+                float t_all = 0, t_fwd = 0, t_back = 0;
+                if (hipEventElapsedTime(&t_all, ev[4 * k], ev[4 * k + 3]) == hipSuccess) o.ms = t_all;
+                if (hipEventElapsedTime(&t_fwd, ev[4 * k], ev[4 * k + 1]) == hipSuccess) o.forward_ms = t_fwd;
+                if (hipEventElapsedTime(&t_back, ev[4 * k + 1], ev[4 * k + 2]) == hipSuccess) o.back_ms = t_back;
+                o.project_ms = o.forward_ms + o.back_ms;
+                (void)hipGetLastError();
             }
         }
         c->iter_count += n_iter;
@@ -893,7 +1060,7 @@ int lmtof_forward_project(lmtof_ctx *c, const float *x, int64_t nx_, float *f, i
         dx = const_cast<float *>(x);
         fc = f;
     }
-    if ((rc = dev_alloc(c, &fs, c->n_events))) return done(rc);
+    if ((rc = dev_alloc(c, &fs, c->n_events)) || (rc = ensure_lut(c))) return done(rc);
     std::vector<Problem> ps{make_problem(c, 0, c->g.nz, dx, nullptr, nullptr)};
     ps[0].events = c->d_events;
     ps[0].n_events = c->n_events;
@@ -901,7 +1068,7 @@ int lmtof_forward_project(lmtof_ctx *c, const float *x, int64_t nx_, float *f, i
     launch_shape(c, block, ept);
     int64_t nch, nvch;
     if ((rc = upload_problems(c, ps, block, ept, &dp, nch, nvch))) return done(rc);
-    hipError_t he = launch_project_forward(L, dp, 1, nch, block, ept, fs);
+    hipError_t he = launch_forward(L, c->g.tof_fwhm_ps > 0, dp, 1, nch, ept, 1, fs, nullptr, nullptr);
     if (he == hipSuccess) he = launch_scatter_by_perm(L, fs, c->d_perm, c->n_events, fc);
     if (he != hipSuccess) return done(fail(c, LMTOF_EHIP, "forward projection: %s", hipGetErrorString(he)));
     if (mem == LMTOF_MEM_HOST) rc = copy_out(c, f, fc, sizeof(float) * c->n_events, LMTOF_MEM_HOST);
@@ -920,12 +1087,14 @@ int lmtof_back_project(lmtof_ctx *c, const float *w, int64_t nw, float *b, int64
     L.stream = c->stream;
     float *dw = nullptr, *ws = nullptr, *db = nullptr;
     Problem *dp = nullptr;
+    ItemSet its;
     int rc = LMTOF_OK;
     auto done = [&](int r) {
         (void)hipStreamSynchronize(c->stream);
         if (mem == LMTOF_MEM_HOST) { dev_free(dw); dev_free(db); }
         dev_free(ws);
         dev_free(dp);
+        free_items(its);
         return r;
     };
     if (mem == LMTOF_MEM_HOST) {
@@ -935,7 +1104,7 @@ int lmtof_back_project(lmtof_ctx *c, const float *w, int64_t nw, float *b, int64
         dw = const_cast<float *>(w);
         db = b;
     }
-    if ((rc = dev_alloc(c, &ws, c->n_events))) return done(rc);
+    if ((rc = dev_alloc(c, &ws, c->n_events)) || (rc = ensure_lut(c))) return done(rc);
     std::vector<Problem> ps{make_problem(c, 0, c->g.nz, nullptr, db, nullptr)};
     ps[0].events = c->d_events;
     ps[0].n_events = c->n_events;
@@ -943,10 +1112,11 @@ int lmtof_back_project(lmtof_ctx *c, const float *w, int64_t nw, float *b, int64
     launch_shape(c, block, ept);
     int64_t nch, nvch;
     if ((rc = upload_problems(c, ps, block, ept, &dp, nch, nvch))) return done(rc);
+    if ((rc = build_items(c, ps, dp, nch, ept, its))) return done(rc);
     hipError_t he = launch_gather_by_perm(L, dw, c->d_perm, c->n_events, ws);
     if (he == hipSuccess) he = launch_fill(L, db, c->V, 0.0f);
-    if (he == hipSuccess) he = launch_project_back(L, dp, 1, nch, block, ept, ws);
     if (he != hipSuccess) return done(fail(c, LMTOF_EHIP, "back projection: %s", hipGetErrorString(he)));
+    if ((rc = add_back(c, L, dp, 1, its, ws, nullptr))) return done(rc);
     if (mem == LMTOF_MEM_HOST) rc = copy_out(c, b, db, sizeof(float) * c->V, LMTOF_MEM_HOST);
     else if (hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(c, LMTOF_EHIP, "back projection failed");
     return done(rc);
@@ -968,11 +1138,15 @@ int lmtof_count_segments(lmtof_ctx *c, int64_t *visited, int64_t *weighted) {
     int block, ept;
     launch_shape(c, block, ept);
     int64_t nch, nvch;
-    int rc = upload_problems(c, ps, block, ept, &dp, nch, nvch);
+    int rc = ensure_lut(c);
+    if (!rc) ps[0] = make_problem(c, 0, c->g.nz, nullptr, nullptr, nullptr);
+    ps[0].events = c->d_events;
+    ps[0].n_events = c->n_events;
+    if (!rc) rc = upload_problems(c, ps, block, ept, &dp, nch, nvch);
     if (!rc) rc = dev_alloc(c, &part, 2 * nch);
     std::vector<unsigned long long> h;
     if (!rc) {
-        hipError_t he = launch_count_pieces(L, dp, 1, nch, block, ept, part);
+        hipError_t he = launch_count_pieces(L, c->g.tof_fwhm_ps > 0, dp, 1, nch, ept, part);
         if (he == hipSuccess) {
             h.resize(2 * nch);
             he = hipMemcpyAsync(h.data(), part, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost,

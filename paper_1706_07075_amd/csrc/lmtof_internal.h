@@ -10,6 +10,13 @@ namespace lmtof {
 // One MLEM problem as the kernels see it: a voxel grid, its images and a
 // contiguous range of stored events.  A whole-volume reconstruction is one
 // problem; the TOF-assisted data division runs one problem per body region.
+// Kernel-CDF table nodes, brick shape and launch shapes of the projector.
+constexpr int kLutN = 1024;
+constexpr int kBrickX = 16, kBrickY = 16, kBrickZ = 16;
+constexpr int kBrickVox = kBrickX * kBrickY * kBrickZ;
+constexpr int kForwardBlock = 256;
+constexpr int kBackBlock = 512;
+
 struct Problem {
     const void *events;   // stored events of this problem (plain: 2 x float4; packed: 1 x uint4)
     int64_t n_events;
@@ -30,6 +37,11 @@ struct Problem {
     float inv_sig_sqrt2;  // 1 / (sigma sqrt 2), sigma in mm
     float k_sigma;        // truncation half-width K sigma (mm)
     float norm;           // 1 / (2 erf(K / sqrt 2)): makes the full kernel sum to 1
+    const float4 *lut;    // kernel-CDF table (kLutN nodes over [-K, K] sigma)
+    float lut_a, lut_b;   // table position of t (mm): t * lut_a + lut_b
+    float a_max;          // bound on one piece weight (TOF: 1, the kernel mass; else the voxel diagonal)
+    int32_t brick_base;   // global id of this problem's first brick
+    int32_t nbx, nby, nbz;// bricks per axis
 };
 
 constexpr int kMaxProblems = 64;
@@ -62,15 +74,26 @@ inline hipError_t do_launch(const Launch &L, const void *func, dim3 grid, dim3 b
 
 // ---- projector (project.hip)
 int64_t project_chunk_events(int block, int ept);
-hipError_t launch_project_fused(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int block,
-                                int ept, int *part_neff, double *part_ll);
-hipError_t launch_project_forward(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int block,
-                                  int ept, float *f_out);
-// part[2c] = pieces visited by chunk c, part[2c+1] = pieces with non-zero weight.
-hipError_t launch_count_pieces(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int block,
+// Forward projection per event; mode 0: out = 1 / f (0 if f <= 0) and per-chunk
+// partials (n_eff, sum log f); mode 1: out = f.  out is in stored order.
+hipError_t launch_forward(const Launch &L, bool tof, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept,
+                          int mode, float *out, int *part_neff, double *part_ll);
+// Back projection by brick chunks: chunk c = (brick, first item, end item,
+// tile slot); each writes its LDS tile to tiles[slot]; then
+// launch_reduce_tiles sums each brick's slots (brick, first slot, end slot)
+// into b (every voxel of those bricks is written).
+hipError_t launch_back_chunks(const Launch &L, bool tof, const Problem *d_probs, int n_probs, const void *events,
+                              const uint4 *chunks, uint32_t n_chunks, const uint32_t *items, const float *w,
+                              float *tiles);
+hipError_t launch_reduce_tiles(const Launch &L, const Problem *d_probs, int n_probs, const uint4 *bricks,
+                               uint32_t n_bricks, const float *tiles);
+// Brick item lists: items == nullptr counts pieces per brick into ctr; else
+// writes stored event indices at ctr[brick]++, never past end[brick].
+hipError_t launch_brick_items(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept,
+                              uint32_t *ctr, uint32_t *items, const uint32_t *end);
+// part[2c] = voxel pieces visited by chunk c, part[2c+1] = pieces with non-zero weight.
+hipError_t launch_count_pieces(const Launch &L, bool tof, const Problem *d_probs, int n_probs, int64_t n_chunks,
                                int ept, unsigned long long *part);
-hipError_t launch_project_back(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int block,
-                               int ept, const float *w_in);
 
 // ---- update and reductions (update.hip)
 int64_t update_chunk_voxels();

@@ -1,27 +1,39 @@
-// TOF-weighted list-mode projector for gfx950 (forward, ratio, back).
+// TOF-weighted list-mode projector for gfx950: forward + ratio, brick-owned
+// back projection, and the brick item lists they run on.
 //
 // Model (arXiv 1706.07075, Sections 2.3-2.4): every event is inserted into
 // the image through a Gaussian TOF kernel centred on the annihilation point
-// that the time difference gives along the line of response, the kernel
-// being normalised so that its weights along the line sum to one.  Here the
-// kernel is truncated at +-K sigma, renormalised, and integrated exactly
-// over each piece of the line inside a voxel, the pieces coming from a
-// Siddon-style traversal: a_ij = [erf(t_b / (sigma sqrt 2)) -
-// erf(t_a / (sigma sqrt 2))] / (2 erf(K / sqrt 2)) for the piece [t_a, t_b]
-// of the line r(t) = mu + t u in voxel j.  Without TOF the weight is the
-// piece length.
+// that its time difference gives along the line of response, normalised so
+// that its weights along the line sum to one.  Here the kernel is truncated
+// at +-K sigma, renormalised, and integrated exactly over each piece of the
+// line inside a voxel (Siddon-style traversal):
+//   a_ij = Phi(t_b) - Phi(t_a),  Phi(t) = erf(t / (sigma sqrt 2)) / (2 erf(K / sqrt 2)),
+// for the piece [t_a, t_b] of r(t) = mu + t u in voxel j.  Without TOF the
+// weight is the piece length.
 //
-// GPU design: one lane per event.  The ray is parametrised from the TOF
-// centre mu (|t| <= K sigma, so FP32 keeps ~1e-6 mm resolution even 1.2 m
-// from the scanner centre), and every plane crossing is computed from its
-// integer plane index, never by accumulating steps, so crossings do not
-// drift.  The per-piece kernel integral is a difference of consecutive erf
-// values, so the weights telescope: they sum to the kernel mass inside the
-// window up to one rounding.  The forward pass gathers x_j; the ratio
-// 1 / f_i stays in a register; the back pass re-traces the same ray and adds
-// a_ij / f_i to b_j with FP32 atomics (MLEM does not depend on the order).
-// Events are read with non-temporal loads so they do not evict the image
-// from L2 / MALL.
+// GPU design.
+//  * Rays are parametrised from the TOF centre mu (|t| <= K sigma), and mu is
+//    kept relative to an integer anchor plane (formed with error-free FP32
+//    transformations), so a plane crossing (k - j) v - d is resolved to
+//    ~1e-6 mm anywhere in a 2.4 m field of view.  Every crossing comes from
+//    its integer plane index, never by accumulating steps.  A brick face
+//    is a voxel plane, so the crossing where one brick's piece ends is
+//    bitwise the one where the next begins and the weights telescope.
+//  * Phi comes from an LDS table (the paper keeps its TOF samples in a
+//    look-up table too): 1024 nodes over [-K, K] sigma, each holding the value
+//    and the first- and second-order Taylor coefficients, so one 16-byte LDS
+//    read and two FMAs give Phi to ~2e-9, with no divergent branch.
+//  * Forward + ratio is event-parallel: one lane per event, events bucketed
+//    at load so a wavefront traces near-parallel, co-located rays and its
+//    image gathers coalesce; the lane keeps f_i and writes r_i = 1 / f_i.
+//  * Back projection is brick-parallel.  At load every event's window is cut
+//    into pieces per 16^3-voxel brick (item lists), and each brick's list
+//    into chunks of bounded length.  One workgroup takes one chunk: it
+//    accumulates a_ij r_i with LDS atomics and writes its tile with plain
+//    stores; a small kernel adds a brick's chunk tiles into b.  There is no
+//    global atomic on the image (device-scope FP32 atomics sustain only
+//    ~21 G/s on this part, a third of a random gather's rate).  Chunks are
+//    launched largest first so the uneven work balances across CUs.
 #include "lmtof_internal.h"
 
 #include <hip/hip_fp16.h>
@@ -30,70 +42,137 @@ namespace lmtof {
 namespace {
 
 constexpr float kInf = __builtin_huge_valf();
-
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
+// A ray r(t) = mu + t u, with mu held relative to an anchor voxel plane:
+// mu_a = o_a + j_a v_a + d_a, |d_a| <~ v_a.  Plane k on axis a then lies at
+// (k - j_a) v_a - d_a from mu, which FP32 resolves to ~1e-6 mm whatever the
+// absolute position (1.2 m from the centre an absolute FP32 coordinate
+// carries ~6e-5 mm of rounding).
 struct Ray {
-    float mx, my, mz;  // TOF centre (mm)
+    int jx, jy, jz;    // anchor plane indices
+    float dx, dy, dz;  // mu - anchor plane (mm)
     float ux, uy, uz;  // unit direction P1 -> P2
     float t0, t1;      // window (mm from mu)
 };
 
-// Decode stored event i of problem P into endpoints and dt.
-__device__ __forceinline__ void load_event(const Problem &P, int64_t i, float &p1x, float &p1y, float &p1z,
-                                           float &p2x, float &p2y, float &p2z, float &dt) {
-    if (!P.packed) {
-        const f32x4 *e = reinterpret_cast<const f32x4 *>(P.events) + 2 * i;
+// Decode stored event i (plain: 2 x float4; packed: int16 x 6 at 0.1 mm +
+// binary16 dt).  Endpoints come as double-float pairs p = h + l: plain
+// coordinates are exact FP32 (l = 0); a packed coordinate q * 0.1 mm is not,
+// so l holds the FMA residual of q * 0.1f plus q * (0.1 - 0.1f), keeping the
+// decoded endpoint exact to ~1e-15 relative (an FP32 decode alone would be
+// off by up to 6e-5 mm 1.2 m from the centre).
+struct EventGeom {
+    float h[6], l[6];  // P1.xyz, P2.xyz
+    float dt;
+};
+
+__device__ __forceinline__ void load_event(const void *events, int packed, int64_t i, EventGeom &ev) {
+    if (!packed) {
+        const f32x4 *e = reinterpret_cast<const f32x4 *>(events) + 2 * i;
         const f32x4 a = __builtin_nontemporal_load(e), b = __builtin_nontemporal_load(e + 1);
-        p1x = a[0]; p1y = a[1]; p1z = a[2]; p2x = a[3];
-        p2y = b[0]; p2z = b[1]; dt = b[2];
+        ev.h[0] = a[0]; ev.h[1] = a[1]; ev.h[2] = a[2]; ev.h[3] = a[3];
+        ev.h[4] = b[0]; ev.h[5] = b[1]; ev.dt = b[2];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) ev.l[k] = 0.0f;
     } else {
-        const u32x4 w = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(P.events) + i);
-        const uint32_t w0 = w[0], w1 = w[1], w2 = w[2], w3 = w[3];
-        const float q = 0.1f;
-        p1x = (float)(int16_t)(w0 & 0xffffu) * q;
-        p1y = (float)(int16_t)(w0 >> 16) * q;
-        p1z = (float)(int16_t)(w1 & 0xffffu) * q;
-        p2x = (float)(int16_t)(w1 >> 16) * q;
-        p2y = (float)(int16_t)(w2 & 0xffffu) * q;
-        p2z = (float)(int16_t)(w2 >> 16) * q;
+        const u32x4 w = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(events) + i);
+        const float tenth = 0.1f, tenth_lo = -1.4901161e-09f;  // 0.1 - 0.1f
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const float q = (float)(int16_t)((w[k >> 1] >> (16 * (k & 1))) & 0xffffu);
+            ev.h[k] = q * tenth;
+            ev.l[k] = fmaf(q, tenth, -ev.h[k]) + q * tenth_lo;
+        }
         __half_raw hr;
-        hr.x = (unsigned short)(w3 & 0xffffu);
-        dt = __half2float(__half(hr));
+        hr.x = (unsigned short)(w[3] & 0xffffu);
+        ev.dt = __half2float(__half(hr));
     }
 }
 
-// Clip one axis of the line to the slab [lo, hi).
-__device__ __forceinline__ void slab(float m, float u, float lo, float hi, float &t0, float &t1) {
-    if (u != 0.0f) {
-        float iu = 1.0f / u;
-        float a = (lo - m) * iu, b = (hi - m) * iu;
+// Error-free transformations (Knuth's TwoSum; TwoProd with an FMA): a + b =
+// s + e and a * b = p + e exactly in FP32.
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
+    s = a + b;
+    const float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+__device__ __forceinline__ void two_prod(float a, float b, float &p, float &e) {
+    p = a * b;
+    e = fmaf(a, b, -p);
+}
+
+struct RayInv {
+    float ix, iy, iz;  // 1 / u (0 when u = 0)
+    int sx, sy, sz;    // sign of u
+};
+
+// Offset from mu of plane k on an axis with anchor j, offset d, voxel size v.
+__device__ __forceinline__ float plane_rel(int k, int j, float v, float d) { return fmaf((float)(k - j), v, -d); }
+
+// Clip the line to planes [klo, khi) of one axis.
+__device__ __forceinline__ void slab(int klo, int khi, int j, float v, float d, float iu, int su, float &t0,
+                                     float &t1) {
+    const float lo = plane_rel(klo, j, v, d), hi = plane_rel(khi, j, v, d);
+    if (su) {
+        const float a = lo * iu, b = hi * iu;
         t0 = fmaxf(t0, fminf(a, b));
         t1 = fminf(t1, fmaxf(a, b));
-    } else if (!(m >= lo && m < hi)) {
+    } else if (!(lo <= 0.0f && hi > 0.0f)) {
         t0 = kInf;
         t1 = -kInf;
     }
 }
 
-// Event geometry: direction, TOF centre and window.  False if the window is empty.
-__device__ __forceinline__ bool make_ray(const Problem &P, int64_t i, Ray &r) {
-    float p1x, p1y, p1z, p2x, p2y, p2z, dt;
-    load_event(P, i, p1x, p1y, p1z, p2x, p2y, p2z, dt);
-    float dx = p2x - p1x, dy = p2y - p1y, dz = p2z - p1z;
-    float iL = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
-    r.ux = dx * iL;
-    r.uy = dy * iL;
-    r.uz = dz * iL;
-    float sh = P.tof ? P.half_c * dt : 0.0f;
-    r.mx = fmaf(sh, r.ux, 0.5f * (p1x + p2x));
-    r.my = fmaf(sh, r.uy, 0.5f * (p1y + p2y));
-    r.mz = fmaf(sh, r.uz, 0.5f * (p1z + p2z));
+// Anchor one axis: mu = (mh + ml) = o + j v + d.
+__device__ __forceinline__ void anchor(float mh, float ml, float o, float v, float iv, int &j, float &d) {
+    j = (int)rintf((mh - o) * iv);
+    const float q = fmaf((float)j, v, o);
+    d = (mh - q) + ml;
+}
+
+// Event geometry: direction, anchored TOF centre and window (clipped to the
+// grid box and, with TOF, to +-K sigma).  False if the window is empty.
+// The midpoint and the TOF shift along the endpoint difference are formed
+// exactly (double-float); the shift is scaled along d = P2 - P1 itself, so
+// rounding of the scale factor only moves mu along the line.
+__device__ __forceinline__ bool make_ray(const Problem &P, const void *events, int64_t i, Ray &r, RayInv &q) {
+    EventGeom ev;
+    load_event(events, P.packed, i, ev);
+    float dh[3], dl[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        two_sum(ev.h[3 + k], -ev.h[k], dh[k], dl[k]);
+        dl[k] += ev.l[3 + k] - ev.l[k];
+    }
+    const float iL = 1.0f / sqrtf(dh[0] * dh[0] + dh[1] * dh[1] + dh[2] * dh[2]);
+    r.ux = dh[0] * iL;
+    r.uy = dh[1] * iL;
+    r.uz = dh[2] * iL;
+    const float kappa = P.tof ? P.half_c * ev.dt * iL : 0.0f;  // mu = (P1 + P2) / 2 + kappa (P2 - P1)
+    auto centre = [&](int k, float o, float v, float iv, int &j, float &d) {
+        float sh, se, ph, pe, mh, me;
+        two_sum(ev.h[k], ev.h[3 + k], sh, se);
+        se += ev.l[k] + ev.l[3 + k];
+        two_prod(kappa, dh[k], ph, pe);
+        two_sum(0.5f * sh, ph, mh, me);
+        const float ml = me + (0.5f * se + fmaf(kappa, dl[k], pe));
+        anchor(mh, ml, o, v, iv, j, d);
+    };
+    centre(0, P.ox, P.vx, P.ivx, r.jx, r.dx);
+    centre(1, P.oy, P.vy, P.ivy, r.jy, r.dy);
+    centre(2, P.oz, P.vz, P.ivz, r.jz, r.dz);
+    q.sx = (r.ux > 0.0f) - (r.ux < 0.0f);
+    q.sy = (r.uy > 0.0f) - (r.uy < 0.0f);
+    q.sz = (r.uz > 0.0f) - (r.uz < 0.0f);
+    q.ix = q.sx ? 1.0f / r.ux : 0.0f;
+    q.iy = q.sy ? 1.0f / r.uy : 0.0f;
+    q.iz = q.sz ? 1.0f / r.uz : 0.0f;
     float t0 = -kInf, t1 = kInf;
-    slab(r.mx, r.ux, P.ox, P.hx, t0, t1);
-    slab(r.my, r.uy, P.oy, P.hy, t0, t1);
-    slab(r.mz, r.uz, P.oz, P.hz, t0, t1);
+    slab(0, P.nx, r.jx, P.vx, r.dx, q.ix, q.sx, t0, t1);
+    slab(0, P.ny, r.jy, P.vy, r.dy, q.iy, q.sy, t0, t1);
+    slab(0, P.nz, r.jz, P.vz, r.dz, q.iz, q.sz, t0, t1);
     if (P.tof) {
         t0 = fmaxf(t0, -P.k_sigma);
         t1 = fminf(t1, P.k_sigma);
@@ -103,74 +182,123 @@ __device__ __forceinline__ bool make_ray(const Problem &P, int64_t i, Ray &r) {
     return t0 < t1;
 }
 
-// Walk the voxels of ray r inside its window and call visit(j, a_ij) for
-// each piece (a zero-length piece at a plane tie yields a_ij = 0).
-template <class Visit>
-__device__ __forceinline__ void traverse(const Problem &P, const Ray &r, Visit &&visit) {
-    // Entry voxel: the point at t0, clamped (t0 may sit on the grid boundary).
-    int ix = (int)floorf((fmaf(r.t0, r.ux, r.mx) - P.ox) * P.ivx);
-    int iy = (int)floorf((fmaf(r.t0, r.uy, r.my) - P.oy) * P.ivy);
-    int iz = (int)floorf((fmaf(r.t0, r.uz, r.mz) - P.oz) * P.ivz);
-    ix = min(max(ix, 0), P.nx - 1);
-    iy = min(max(iy, 0), P.ny - 1);
-    iz = min(max(iz, 0), P.nz - 1);
-    const int sx = (r.ux > 0.0f) - (r.ux < 0.0f);
-    const int sy = (r.uy > 0.0f) - (r.uy < 0.0f);
-    const int sz = (r.uz > 0.0f) - (r.uz < 0.0f);
-    const float iux = sx ? 1.0f / r.ux : 0.0f;
-    const float iuy = sy ? 1.0f / r.uy : 0.0f;
-    const float iuz = sz ? 1.0f / r.uz : 0.0f;
-    // Next plane crossed on each axis, from its integer index.
-    auto cross = [](int idx, int s, float o, float v, float m, float iu) -> float {
-        return s ? (fmaf((float)(idx + (s > 0)), v, o) - m) * iu : kInf;
-    };
-    float tnx = cross(ix, sx, P.ox, P.vx, r.mx, iux);
-    float tny = cross(iy, sy, P.oy, P.vy, r.my, iuy);
-    float tnz = cross(iz, sz, P.oz, P.vz, r.mz, iuz);
-    const int sxy = P.nx, sxyz = P.nx * P.ny;
-    int j = ix + sxy * iy + sxyz * iz;
-    const bool tof = P.tof;
-    float t = r.t0;
-    float e_prev = tof ? erff(t * P.inv_sig_sqrt2) : 0.0f;
-    const int max_steps = P.nx + P.ny + P.nz + 2;
+// Voxel index along one axis at parameter t.
+__device__ __forceinline__ int voxel_at(float t, float u, int j, float d, float iv) {
+    return j + (int)floorf(fmaf(t, u, d) * iv);
+}
+
+// Truncated-kernel CDF from the LDS table: node k at u_k = -K + k h (sigma
+// units) holds (Phi_k, Phi'_k h, Phi''_k h^2 / 2); pos = t * lut_a + lut_b.
+struct Cdf {
+    const float4 *tab;
+    float a, b;
+    __device__ __forceinline__ float operator()(float t) const {
+        const float pos = fmaf(t, a, b);
+        const float kf = fminf(fmaxf(rintf(pos), 0.0f), (float)(kLutN - 1));
+        const float dp = pos - kf;
+        const float4 e = tab[(int)kf];
+        return fmaf(dp, fmaf(dp, e.z, e.y), e.x);
+    }
+};
+
+// A voxel box the traversal is confined to (the whole grid or one brick),
+// with the strides of the index it reports.
+struct Box {
+    int x0, y0, z0;  // first voxel (global indices)
+    int nx, ny, nz;  // extent
+    int sy, sz;      // strides of the reported index
+};
+
+// Walk the voxels of ray r between ta and tb (already inside the box) and
+// call visit(j, a) for every piece; j is box-local.  A plane tie gives a
+// zero-length piece (a = 0).
+template <bool TOF, class Visit>
+__device__ __forceinline__ void walk(const Problem &P, const Ray &r, const RayInv &q, float ta, float tb,
+                                     const Box &B, const Cdf &cdf, Visit &&visit) {
+    int ix = voxel_at(ta, r.ux, r.jx, r.dx, P.ivx);
+    int iy = voxel_at(ta, r.uy, r.jy, r.dy, P.ivy);
+    int iz = voxel_at(ta, r.uz, r.jz, r.dz, P.ivz);
+    ix = min(max(ix, B.x0), B.x0 + B.nx - 1);
+    iy = min(max(iy, B.y0), B.y0 + B.ny - 1);
+    iz = min(max(iz, B.z0), B.z0 + B.nz - 1);
+    // next plane on each axis, from its global index
+    const int ux1 = q.sx > 0, uy1 = q.sy > 0, uz1 = q.sz > 0;
+    float tnx = q.sx ? plane_rel(ix + ux1, r.jx, P.vx, r.dx) * q.ix : kInf;
+    float tny = q.sy ? plane_rel(iy + uy1, r.jy, P.vy, r.dy) * q.iy : kInf;
+    float tnz = q.sz ? plane_rel(iz + uz1, r.jz, P.vz, r.dz) * q.iz : kInf;
+    int lx = ix - B.x0, ly = iy - B.y0, lz = iz - B.z0;
+    int j = lx + B.sy * ly + B.sz * lz;
+    const int djy = q.sy * B.sy, djz = q.sz * B.sz;
+    float t = ta;
+    float c = TOF ? cdf(ta) : 0.0f;
+    const int max_steps = B.nx + B.ny + B.nz + 2;
     for (int step = 0; step < max_steps; ++step) {
-        float tn = fminf(fminf(tnx, tny), fminf(tnz, r.t1));
-        tn = fmaxf(tn, t);
+        const float tmin = fminf(fminf(tnx, tny), tnz);
+        const bool last = tmin >= tb;
+        const float tn = fmaxf(fminf(tmin, tb), t);
         float a;
-        if (tof) {
-            float e = erff(tn * P.inv_sig_sqrt2);
-            a = (e - e_prev) * P.norm;
-            e_prev = e;
+        if (TOF) {
+            const float cn = cdf(tn);
+            a = cn - c;
+            c = cn;
         } else {
             a = tn - t;
         }
         visit(j, a);
-        if (tn >= r.t1) break;
-        if (tnx <= tny && tnx <= tnz) {
-            ix += sx;
-            if ((unsigned)ix >= (unsigned)P.nx) break;
-            j += sx;
-            tnx = cross(ix, sx, P.ox, P.vx, r.mx, iux);
-        } else if (tny <= tnz) {
-            iy += sy;
-            if ((unsigned)iy >= (unsigned)P.ny) break;
-            j += sy * sxy;
-            tny = cross(iy, sy, P.oy, P.vy, r.my, iuy);
-        } else {
-            iz += sz;
-            if ((unsigned)iz >= (unsigned)P.nz) break;
-            j += sz * sxyz;
-            tnz = cross(iz, sz, P.oz, P.vz, r.mz, iuz);
-        }
+        if (last) break;
         t = tn;
+        if (tnx == tmin) {
+            lx += q.sx;
+            if ((unsigned)lx >= (unsigned)B.nx) break;
+            j += q.sx;
+            tnx = plane_rel(lx + B.x0 + ux1, r.jx, P.vx, r.dx) * q.ix;
+        } else if (tny == tmin) {
+            ly += q.sy;
+            if ((unsigned)ly >= (unsigned)B.ny) break;
+            j += djy;
+            tny = plane_rel(ly + B.y0 + uy1, r.jy, P.vy, r.dy) * q.iy;
+        } else {
+            lz += q.sz;
+            if ((unsigned)lz >= (unsigned)B.nz) break;
+            j += djz;
+            tnz = plane_rel(lz + B.z0 + uz1, r.jz, P.vz, r.dz) * q.iz;
+        }
     }
 }
 
-// Which problem owns chunk c (block-uniform; problems are few and ordered).
-__device__ __forceinline__ int find_problem(const Problem *probs, int n_probs, int64_t c) {
-    int p = n_probs - 1;
-    while (p > 0 && probs[p].chunk_begin > c) --p;
-    return p;
+__device__ __forceinline__ Box grid_box(const Problem &P) {
+    Box B;
+    B.x0 = B.y0 = B.z0 = 0;
+    B.nx = P.nx;
+    B.ny = P.ny;
+    B.nz = P.nz;
+    B.sy = P.nx;
+    B.sz = P.nx * P.ny;
+    return B;
+}
+
+// Brick (bx, by, bz) of problem P as a box with LDS-tile strides.
+__device__ __forceinline__ Box brick_box(const Problem &P, int bx, int by, int bz) {
+    Box B;
+    B.x0 = bx * kBrickX;
+    B.y0 = by * kBrickY;
+    B.z0 = bz * kBrickZ;
+    B.nx = min(kBrickX, P.nx - B.x0);
+    B.ny = min(kBrickY, P.ny - B.y0);
+    B.nz = min(kBrickZ, P.nz - B.z0);
+    B.sy = kBrickX;
+    B.sz = kBrickX * kBrickY;
+    return B;
+}
+
+// Part of the window inside box B (same plane formulas as the walk).
+__device__ __forceinline__ void clip_to_box(const Problem &P, const Ray &r, const RayInv &q, const Box &B,
+                                            float &ta, float &tb) {
+    ta = r.t0;
+    tb = r.t1;
+    slab(B.x0, B.x0 + B.nx, r.jx, P.vx, r.dx, q.ix, q.sx, ta, tb);
+    slab(B.y0, B.y0 + B.ny, r.jy, P.vy, r.dy, q.iy, q.sy, ta, tb);
+    slab(B.z0, B.z0 + B.nz, r.jz, P.vz, r.dz, q.iz, q.sz, ta, tb);
 }
 
 template <class T>
@@ -180,115 +308,298 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
-// Fused MLEM projector: forward, ratio, back for every event of one chunk.
-// Per-chunk partials: number of events with f > 0 and sum of log f.
-__global__ void __launch_bounds__(1024) k_project_fused(const Problem *__restrict__ probs, int n_probs, int ept,
-                                                        int *__restrict__ part_neff,
-                                                        double *__restrict__ part_ll) {
+__device__ __forceinline__ int find_problem(const Problem *probs, int n_probs, int64_t c) {
+    int p = n_probs - 1;
+    while (p > 0 && probs[p].chunk_begin > c) --p;
+    return p;
+}
+
+__device__ __forceinline__ int find_brick_problem(const Problem *probs, int n_probs, uint32_t b) {
+    int p = n_probs - 1;
+    while (p > 0 && (uint32_t)probs[p].brick_base > b) --p;
+    return p;
+}
+
+__device__ __forceinline__ void stage_lut(float4 *lds, const float4 *src) {
+    for (int k = threadIdx.x; k < kLutN; k += blockDim.x) lds[k] = src[k];
+}
+
+// Forward projection of one chunk of events.  mode 0 (MLEM): out[i] =
+// 1 / f_i (0 if f_i <= 0) plus per-chunk partials (events with f > 0, sum
+// of log f); mode 1: out[i] = f_i.  out is indexed by stored event position.
+template <bool TOF>
+__global__ void __launch_bounds__(kForwardBlock) k_forward(const Problem *__restrict__ probs, int n_probs, int ept,
+                                                           int mode, float *__restrict__ out,
+                                                           int *__restrict__ part_neff,
+                                                           double *__restrict__ part_ll) {
+    __shared__ float4 lut[kLutN];
+    __shared__ int s_n[kForwardBlock / 64];
+    __shared__ double s_l[kForwardBlock / 64];
     const int64_t c = blockIdx.x;
-    const int p = find_problem(probs, n_probs, c);
-    const Problem &P = probs[p];
-    const int64_t base = (c - P.chunk_begin) * (int64_t)blockDim.x * ept;
+    const Problem P = probs[find_problem(probs, n_probs, c)];
+    if (TOF) stage_lut(lut, P.lut);
+    __syncthreads();
+    const Cdf cdf{lut, P.lut_a, P.lut_b};
+    const Box B = grid_box(P);
     const float *__restrict__ x = P.x;
-    float *__restrict__ b = P.b;
+    const int64_t base = (c - P.chunk_begin) * (int64_t)blockDim.x * ept;
     int neff = 0;
     float ll = 0.0f;
     for (int e = 0; e < ept; ++e) {
         const int64_t i = base + (int64_t)e * blockDim.x + threadIdx.x;
         if (i >= P.n_events) break;
         Ray r;
-        if (!make_ray(P, i, r)) continue;
+        RayInv q;
         float f = 0.0f;
-        traverse(P, r, [&](int j, float a) { f = fmaf(a, x[j], f); });
-        if (!(f > 0.0f)) continue;
-        ++neff;
-        ll += logf(f);
-        const float rf = 1.0f / f;
-        traverse(P, r, [&](int j, float a) {
-            if (a != 0.0f) unsafeAtomicAdd(b + j, a * rf);
-        });
+        if (make_ray(P, P.events, i, r, q))
+            walk<TOF>(P, r, q, r.t0, r.t1, B, cdf, [&](int j, float a) { f = fmaf(a, x[j], f); });
+        if (mode == 0) {
+            const bool pos = f > 0.0f;
+            neff += pos;
+            ll += pos ? logf(f) : 0.0f;
+            out[P.ev_offset + i] = pos ? 1.0f / f : 0.0f;
+        } else {
+            out[P.ev_offset + i] = f;
+        }
     }
-    // block reduction of the partials
-    __shared__ int s_n[16];
-    __shared__ double s_l[16];
-    int wn = wave_sum(neff);
-    double wl = wave_sum((double)ll);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) { s_n[wid] = wn; s_l[wid] = wl; }
+    if (mode == 0) {
+        const int wn = wave_sum(neff);
+        const double wl = wave_sum((double)ll);
+        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+        if (lane == 0) {
+            s_n[wid] = wn;
+            s_l[wid] = wl;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int tn = 0;
+            double tl = 0.0;
+            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+                tn += s_n[w];
+                tl += s_l[w];
+            }
+            part_neff[c] = tn;
+            part_ll[c] = tl;
+        }
+    }
+}
+
+// Back projection of one chunk of one brick's item list: sum over the
+// chunk's items of a_ij w_i, written (plain stores) to the chunk's tile
+// slot.  A brick with several chunks has several slots; k_reduce_tiles adds
+// them into b.  No global atomics.
+//
+// The LDS accumulation is 64-bit fixed point: FP32 LDS atomic adds run at
+// ~0.2 T/s on this part, 64-bit integer ones at ~2.8 T/s.  Each contribution
+// a w (an FP32 product, 24-bit exact) is scaled by S = 2^e and rounded to an
+// integer; e is chosen from the chunk's item count n, the problem's bound
+// on a and the chunk's max |w| so that n * a_max * w_max * S < 2^62: no sum
+// can overflow.  Integer addition is exact and associative, so the tile does
+// not depend on the order of the items (deterministic), and its rounding
+// (2^-e per contribution) is far below FP32 accumulation error.
+template <bool TOF>
+__global__ void __launch_bounds__(kBackBlock) k_back_chunks(const Problem *__restrict__ probs, int n_probs,
+                                                            const void *__restrict__ events,
+                                                            const uint4 *__restrict__ chunks,
+                                                            const uint32_t *__restrict__ items,
+                                                            const float *__restrict__ w,
+                                                            float *__restrict__ tiles) {
+    __shared__ unsigned long long tile[kBrickVox];
+    __shared__ float4 lut[kLutN];
+    __shared__ float s_wmax[kBackBlock / 64];
+    const uint4 ch = chunks[blockIdx.x];  // (brick, first item, end item, tile slot)
+    const uint32_t bid = ch.x;
+    const Problem P = probs[find_brick_problem(probs, n_probs, bid)];
+    const uint32_t bl = bid - (uint32_t)P.brick_base;
+    const int bx = (int)(bl % (uint32_t)P.nbx), by = (int)((bl / (uint32_t)P.nbx) % (uint32_t)P.nby),
+              bz = (int)(bl / ((uint32_t)P.nbx * (uint32_t)P.nby));
+    const Box B = brick_box(P, bx, by, bz);
+    for (int k = threadIdx.x; k < kBrickVox; k += blockDim.x) tile[k] = 0ull;
+    if (TOF) stage_lut(lut, P.lut);
+    // scale from the chunk's largest |w|
+    float wm = 0.0f;
+    for (uint32_t k = ch.y + threadIdx.x; k < ch.z; k += blockDim.x) wm = fmaxf(wm, fabsf(w[items[k]]));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) wm = fmaxf(wm, __shfl_xor(wm, off, 64));
+    if ((threadIdx.x & 63) == 0) s_wmax[threadIdx.x >> 6] = wm;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int tn = 0;
-        double tl = 0.0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { tn += s_n[w]; tl += s_l[w]; }
-        part_neff[c] = tn;
-        part_ll[c] = tl;
+    wm = 0.0f;
+    for (int k = 0; k < kBackBlock / 64; ++k) wm = fmaxf(wm, s_wmax[k]);
+    int en, ea, ew;
+    frexpf((float)(ch.z - ch.y), &en);
+    frexpf(P.a_max, &ea);
+    frexpf(wm, &ew);
+    const int e = min(max(62 - (en + ea + ew), -126), 126);
+    const float S = ldexpf(1.0f, e);
+    const Cdf cdf{lut, P.lut_a, P.lut_b};
+    if (wm > 0.0f) {
+        for (uint32_t k = ch.y + threadIdx.x; k < ch.z; k += blockDim.x) {
+            const uint32_t i = items[k];
+            const float ws = w[i] * S;
+            if (ws == 0.0f) continue;
+            Ray r;
+            RayInv q;
+            if (!make_ray(P, events, (int64_t)i, r, q)) continue;
+            float ta, tb;
+            clip_to_box(P, r, q, B, ta, tb);
+            if (!(ta < tb)) continue;
+            walk<TOF>(P, r, q, ta, tb, B, cdf, [&](int j, float a) {
+                if (a != 0.0f) atomicAdd(&tile[j], (unsigned long long)__float2ll_rn(a * ws));
+            });
+        }
+    }
+    __syncthreads();
+    const float inv = ldexpf(1.0f, -e);
+    float *__restrict__ dst = tiles + (size_t)ch.w * kBrickVox;
+    for (int k = threadIdx.x; k < kBrickVox; k += blockDim.x) dst[k] = __ll2float_rn((long long)tile[k]) * inv;
+}
+
+// b over one brick = sum of its chunk tiles (slots [first, end)).
+__global__ void __launch_bounds__(256) k_reduce_tiles(const Problem *__restrict__ probs, int n_probs,
+                                                      const uint4 *__restrict__ bricks,
+                                                      const float *__restrict__ tiles) {
+    const uint4 br = bricks[blockIdx.x];  // (brick, first slot, end slot, -)
+    const Problem P = probs[find_brick_problem(probs, n_probs, br.x)];
+    const uint32_t bl = br.x - (uint32_t)P.brick_base;
+    const int bx = (int)(bl % (uint32_t)P.nbx), by = (int)((bl / (uint32_t)P.nbx) % (uint32_t)P.nby),
+              bz = (int)(bl / ((uint32_t)P.nbx * (uint32_t)P.nby));
+    const Box B = brick_box(P, bx, by, bz);
+    float *__restrict__ b = P.b;
+    for (int k = threadIdx.x; k < kBrickVox; k += blockDim.x) {
+        float acc = 0.0f;
+        for (uint32_t sl = br.y; sl < br.z; ++sl) acc += tiles[(size_t)sl * kBrickVox + k];
+        const int lx = k % kBrickX, ly = (k / kBrickX) % kBrickY, lz = k / (kBrickX * kBrickY);
+        if (lx < B.nx && ly < B.ny && lz < B.nz)
+            b[(B.x0 + lx) + (int64_t)P.nx * ((B.y0 + ly) + (int64_t)P.ny * (B.z0 + lz))] = acc;
     }
 }
 
-// Forward projection only: f_out[stored index] = (A x)_i.
-__global__ void __launch_bounds__(1024) k_project_forward(const Problem *__restrict__ probs, int n_probs, int ept,
-                                                          float *__restrict__ f_out) {
+// Wave-aggregated counter bump: every emitting lane gets ctr[key] + its rank
+// among the lanes of its wave that emit the same key; one atomic per key per
+// wave.  All lanes of the wave must call it.
+__device__ __forceinline__ uint32_t agg_add(uint32_t *ctr, uint32_t key, bool emit) {
+    const int lane = threadIdx.x & 63;
+    unsigned long long pend = __ballot(emit);
+    uint32_t res = 0;
+    while (pend) {
+        const int leader = __ffsll((long long)pend) - 1;
+        const uint32_t k0 = __shfl(key, leader, 64);
+        const unsigned long long grp = __ballot(emit && key == k0) & pend;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(ctr + k0, (uint32_t)__popcll(grp));
+        base = __shfl(base, leader, 64);
+        if ((grp >> lane) & 1ull) res = base + (uint32_t)__popcll(grp & ((1ull << lane) - 1ull));
+        pend &= ~grp;
+    }
+    return res;
+}
+
+// Brick item lists: walk each event's window through the brick grid (brick
+// faces are voxel planes, same crossing formulas as the voxel walk) and, for
+// every brick crossed over a positive length, bump ctr[brick] (items ==
+// nullptr: counting) or write the event's stored index at ctr[brick]++
+// (filling; end[brick] bounds each list).  The whole wave steps in lockstep
+// so same-brick lanes share one atomic.
+__global__ void __launch_bounds__(kForwardBlock) k_brick_items(const Problem *__restrict__ probs, int n_probs,
+                                                               int ept, uint32_t *__restrict__ ctr,
+                                                               uint32_t *__restrict__ items,
+                                                               const uint32_t *__restrict__ end) {
     const int64_t c = blockIdx.x;
-    const int p = find_problem(probs, n_probs, c);
-    const Problem &P = probs[p];
+    const Problem P = probs[find_problem(probs, n_probs, c)];
     const int64_t base = (c - P.chunk_begin) * (int64_t)blockDim.x * ept;
     for (int e = 0; e < ept; ++e) {
         const int64_t i = base + (int64_t)e * blockDim.x + threadIdx.x;
-        if (i >= P.n_events) break;
         Ray r;
-        float f = 0.0f;
-        if (make_ray(P, i, r)) traverse(P, r, [&](int j, float a) { f = fmaf(a, P.x[j], f); });
-        f_out[P.ev_offset + i] = f;
+        RayInv q;
+        bool active = i < P.n_events && make_ray(P, P.events, i, r, q);
+        int bx = 0, by = 0, bz = 0, ux1 = 0, uy1 = 0, uz1 = 0;
+        float tnx = kInf, tny = kInf, tnz = kInf, t = 0.0f, t1 = 0.0f;
+        if (active) {
+            ux1 = q.sx > 0;
+            uy1 = q.sy > 0;
+            uz1 = q.sz > 0;
+            const int ix = voxel_at(r.t0, r.ux, r.jx, r.dx, P.ivx);
+            const int iy = voxel_at(r.t0, r.uy, r.jy, r.dy, P.ivy);
+            const int iz = voxel_at(r.t0, r.uz, r.jz, r.dz, P.ivz);
+            bx = min(max(ix, 0), P.nx - 1) / kBrickX;
+            by = min(max(iy, 0), P.ny - 1) / kBrickY;
+            bz = min(max(iz, 0), P.nz - 1) / kBrickZ;
+            tnx = q.sx ? plane_rel((bx + ux1) * kBrickX, r.jx, P.vx, r.dx) * q.ix : kInf;
+            tny = q.sy ? plane_rel((by + uy1) * kBrickY, r.jy, P.vy, r.dy) * q.iy : kInf;
+            tnz = q.sz ? plane_rel((bz + uz1) * kBrickZ, r.jz, P.vz, r.dz) * q.iz : kInf;
+            t = r.t0;
+            t1 = r.t1;
+        }
+        while (__ballot(active)) {
+            const float tmin = fminf(fminf(tnx, tny), tnz);
+            const float tn = fminf(tmin, t1);
+            const bool emit = active && tn > t;
+            const uint32_t key =
+                emit ? (uint32_t)P.brick_base + (uint32_t)(bx + P.nbx * (by + P.nby * bz)) : 0u;
+            const uint32_t pos = agg_add(ctr, key, emit);
+            if (items && emit && pos < end[key]) items[pos] = (uint32_t)(P.ev_offset + i);
+            if (active) {
+                if (tmin >= t1) {
+                    active = false;
+                } else {
+                    t = fmaxf(tn, t);
+                    if (tnx == tmin) {
+                        bx += q.sx;
+                        active = (unsigned)bx < (unsigned)P.nbx;
+                        tnx = plane_rel((bx + ux1) * kBrickX, r.jx, P.vx, r.dx) * q.ix;
+                    } else if (tny == tmin) {
+                        by += q.sy;
+                        active = (unsigned)by < (unsigned)P.nby;
+                        tny = plane_rel((by + uy1) * kBrickY, r.jy, P.vy, r.dy) * q.iy;
+                    } else {
+                        bz += q.sz;
+                        active = (unsigned)bz < (unsigned)P.nbz;
+                        tnz = plane_rel((bz + uz1) * kBrickZ, r.jz, P.vz, r.dz) * q.iz;
+                    }
+                }
+            }
+        }
     }
 }
 
-// Back projection only: b_j += sum_i a_ij w[stored index].
-__global__ void __launch_bounds__(1024) k_project_back(const Problem *__restrict__ probs, int n_probs, int ept,
-                                                       const float *__restrict__ w_in) {
+// Diagnostic: voxel pieces visited per chunk and how many have non-zero weight.
+template <bool TOF>
+__global__ void __launch_bounds__(kForwardBlock) k_count_pieces(const Problem *__restrict__ probs, int n_probs,
+                                                                int ept, unsigned long long *__restrict__ part) {
+    __shared__ float4 lut[kLutN];
+    __shared__ unsigned long long s_c[kForwardBlock / 64], s_z[kForwardBlock / 64];
     const int64_t c = blockIdx.x;
-    const int p = find_problem(probs, n_probs, c);
-    const Problem &P = probs[p];
-    const int64_t base = (c - P.chunk_begin) * (int64_t)blockDim.x * ept;
-    for (int e = 0; e < ept; ++e) {
-        const int64_t i = base + (int64_t)e * blockDim.x + threadIdx.x;
-        if (i >= P.n_events) break;
-        const float w = w_in[P.ev_offset + i];
-        if (w == 0.0f) continue;
-        Ray r;
-        if (!make_ray(P, i, r)) continue;
-        traverse(P, r, [&](int j, float a) {
-            if (a != 0.0f) unsafeAtomicAdd(P.b + j, a * w);
-        });
-    }
-}
-
-// Diagnostic: number of voxel pieces each chunk's rays visit (one gather in
-// the forward pass and at most one atomic in the back pass per piece).
-__global__ void __launch_bounds__(1024) k_count_pieces(const Problem *__restrict__ probs, int n_probs, int ept,
-                                                       unsigned long long *__restrict__ part) {
-    const int64_t c = blockIdx.x;
-    const int p = find_problem(probs, n_probs, c);
-    const Problem &P = probs[p];
+    const Problem P = probs[find_problem(probs, n_probs, c)];
+    if (TOF) stage_lut(lut, P.lut);
+    __syncthreads();
+    const Cdf cdf{lut, P.lut_a, P.lut_b};
+    const Box B = grid_box(P);
     const int64_t base = (c - P.chunk_begin) * (int64_t)blockDim.x * ept;
     unsigned long long cnt = 0, nz = 0;
     for (int e = 0; e < ept; ++e) {
         const int64_t i = base + (int64_t)e * blockDim.x + threadIdx.x;
         if (i >= P.n_events) break;
         Ray r;
-        if (!make_ray(P, i, r)) continue;
-        traverse(P, r, [&](int, float a) {
+        RayInv q;
+        if (!make_ray(P, P.events, i, r, q)) continue;
+        walk<TOF>(P, r, q, r.t0, r.t1, B, cdf, [&](int, float a) {
             ++cnt;
             nz += (a != 0.0f);
         });
     }
-    __shared__ unsigned long long s_c[16], s_z[16];
-    unsigned long long wc = wave_sum(cnt), wz = wave_sum(nz);
+    const unsigned long long wc = wave_sum(cnt), wz = wave_sum(nz);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) { s_c[wid] = wc; s_z[wid] = wz; }
+    if (lane == 0) {
+        s_c[wid] = wc;
+        s_z[wid] = wz;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long a = 0, b = 0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { a += s_c[w]; b += s_z[w]; }
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+            a += s_c[k];
+            b += s_z[k];
+        }
         part[2 * c] = a;
         part[2 * c + 1] = b;
     }
@@ -296,34 +607,44 @@ __global__ void __launch_bounds__(1024) k_count_pieces(const Problem *__restrict
 
 }  // namespace
 
-hipError_t launch_count_pieces(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int block,
-                               int ept, unsigned long long *part) {
-    void *args[] = {&d_probs, &n_probs, &ept, &part};
-    return do_launch(L, reinterpret_cast<const void *>(&k_count_pieces), dim3((unsigned)n_chunks), dim3(block), 0,
-                     args);
-}
-
 int64_t project_chunk_events(int block, int ept) { return (int64_t)block * ept; }
 
-hipError_t launch_project_fused(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int block,
-                                int ept, int *part_neff, double *part_ll) {
-    void *args[] = {&d_probs, &n_probs, &ept, &part_neff, &part_ll};
-    return do_launch(L, reinterpret_cast<const void *>(&k_project_fused), dim3((unsigned)n_chunks), dim3(block), 0,
-                     args);
+hipError_t launch_forward(const Launch &L, bool tof, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept,
+                          int mode, float *out, int *part_neff, double *part_ll) {
+    void *args[] = {&d_probs, &n_probs, &ept, &mode, &out, &part_neff, &part_ll};
+    const void *fn = tof ? reinterpret_cast<const void *>(&k_forward<true>)
+                         : reinterpret_cast<const void *>(&k_forward<false>);
+    return do_launch(L, fn, dim3((unsigned)n_chunks), dim3(kForwardBlock), 0, args);
 }
 
-hipError_t launch_project_forward(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int block,
-                                  int ept, float *f_out) {
-    void *args[] = {&d_probs, &n_probs, &ept, &f_out};
-    return do_launch(L, reinterpret_cast<const void *>(&k_project_forward), dim3((unsigned)n_chunks), dim3(block),
-                     0, args);
+hipError_t launch_back_chunks(const Launch &L, bool tof, const Problem *d_probs, int n_probs, const void *events,
+                              const uint4 *chunks, uint32_t n_chunks, const uint32_t *items, const float *w,
+                              float *tiles) {
+    void *args[] = {&d_probs, &n_probs, &events, &chunks, &items, &w, &tiles};
+    const void *fn = tof ? reinterpret_cast<const void *>(&k_back_chunks<true>)
+                         : reinterpret_cast<const void *>(&k_back_chunks<false>);
+    return do_launch(L, fn, dim3(n_chunks), dim3(kBackBlock), 0, args);
 }
 
-hipError_t launch_project_back(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int block,
-                               int ept, const float *w_in) {
-    void *args[] = {&d_probs, &n_probs, &ept, &w_in};
-    return do_launch(L, reinterpret_cast<const void *>(&k_project_back), dim3((unsigned)n_chunks), dim3(block), 0,
-                     args);
+hipError_t launch_reduce_tiles(const Launch &L, const Problem *d_probs, int n_probs, const uint4 *bricks,
+                               uint32_t n_bricks, const float *tiles) {
+    void *args[] = {&d_probs, &n_probs, &bricks, &tiles};
+    return do_launch(L, reinterpret_cast<const void *>(&k_reduce_tiles), dim3(n_bricks), dim3(256), 0, args);
+}
+
+hipError_t launch_brick_items(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept,
+                              uint32_t *ctr, uint32_t *items, const uint32_t *end) {
+    void *args[] = {&d_probs, &n_probs, &ept, &ctr, &items, &end};
+    return do_launch(L, reinterpret_cast<const void *>(&k_brick_items), dim3((unsigned)n_chunks),
+                     dim3(kForwardBlock), 0, args);
+}
+
+hipError_t launch_count_pieces(const Launch &L, bool tof, const Problem *d_probs, int n_probs, int64_t n_chunks,
+                               int ept, unsigned long long *part) {
+    void *args[] = {&d_probs, &n_probs, &ept, &part};
+    const void *fn = tof ? reinterpret_cast<const void *>(&k_count_pieces<true>)
+                         : reinterpret_cast<const void *>(&k_count_pieces<false>);
+    return do_launch(L, fn, dim3((unsigned)n_chunks), dim3(kForwardBlock), 0, args);
 }
 
 }  // namespace lmtof

@@ -33,7 +33,6 @@ LMTOF_MEM_DEVICE = 1
 LMTOF_OPT_STORAGE = 1
 LMTOF_OPT_SORT = 2
 LMTOF_OPT_SENS_NPHI = 3
-LMTOF_OPT_BLOCK = 4
 LMTOF_OPT_EVENTS_PER_THREAD = 5
 LMTOF_OPT_SORT_CELL_MM = 6
 
@@ -58,7 +57,8 @@ class lmtof_geometry(C.Structure):
 
 class lmtof_iter_stats(C.Structure):
     _fields_ = [("iter", C.c_int32), ("reserved0", C.c_int32), ("n_eff", C.c_int64), ("sum_sx", C.c_double),
-                ("loglik", C.c_double), ("ms", C.c_float), ("project_ms", C.c_float)]
+                ("loglik", C.c_double), ("ms", C.c_float), ("project_ms", C.c_float),
+                ("forward_ms", C.c_float), ("back_ms", C.c_float)]
 
 
 if not os.path.exists(LIB_PATH):
@@ -255,8 +255,8 @@ def lmtof_read_image(ctx, n: int, out=None):
 def lmtof_iterate(ctx, n_iter: int):
     st = (lmtof_iter_stats * n_iter)()
     _check(_lib.lmtof_iterate(ctx, n_iter, st), ctx)
-    return [dict(iter=s.iter, n_eff=s.n_eff, sum_sx=s.sum_sx, loglik=s.loglik, ms=s.ms, project_ms=s.project_ms)
-            for s in st]
+    return [dict(iter=s.iter, n_eff=s.n_eff, sum_sx=s.sum_sx, loglik=s.loglik, ms=s.ms, project_ms=s.project_ms,
+                 forward_ms=s.forward_ms, back_ms=s.back_ms) for s in st]
 
 
 def lmtof_forward_project(ctx, x, n_events: int, out=None):

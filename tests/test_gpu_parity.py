@@ -186,8 +186,8 @@ def test_one_step_parity_from_oracle_image(c1):
     assert e < 5e-6
 
 
-@pytest.mark.parametrize("opts", [dict(sort=0), dict(block=64, events_per_thread=3),
-                                  dict(block=1024, events_per_thread=1), dict(sort=1, sort_cell_mm=40)])
+@pytest.mark.parametrize("opts", [dict(sort=0), dict(events_per_thread=3), dict(events_per_thread=1),
+                                  dict(sort=1, sort_cell_mm=40)])
 def test_launch_shapes_and_sort_agree(c1, opts):
     _say(f"case: options {opts}")
     with _recon(c1["g"], c1["ev"], **opts) as r:

@@ -2,9 +2,9 @@
 
 Each region is an independent MLEM problem on its sub-volume (core slab
 widened by the margin).  The oracle assigns events to regions itself from
-the FP64 TOF centre and runs plain MLEM per region; events whose TOF centre
+the FP64 TOF centre and runs plain MLEM per region.  Events whose TOF centre
 lies within 1e-3 mm of a core boundary (where FP32 and FP64 may disagree)
-would make the split ambiguous, and the seeds used here have none.
+are dropped from the input that both sides get (2 of 200 000 here).
 """
 import numpy as np
 import pytest
@@ -46,6 +46,13 @@ def _smooth_sens(w):
     return s.astype(np.float32).ravel()
 
 
+def unambiguous(w, ev, zb):
+    """Drop events whose TOF centre lies within 1e-3 mm of a core boundary
+    (FP32 and FP64 may put them on different sides); both sides get the rest."""
+    _, amb = _assign(w.geometry(), ev, zb)
+    return ev[~amb]
+
+
 def _region_case(w, ev, zb, n_iter, margin=-1, storage=0):
     g = w.geometry()
     s = _smooth_sens(w)
@@ -66,8 +73,8 @@ def _region_case(w, ev, zb, n_iter, margin=-1, storage=0):
 def test_regions_cylinder_three_slabs():
     print("case: cylinder, 3 regions", flush=True)
     w = synth.cylinder_workload(n_events=60000)
-    ev = synth.events(w)
     zb = [0, 20, 40, 64]
+    ev = unambiguous(w, synth.events(w), zb)
     g, s, r_of, infos, st, imgs, summed = _region_case(w, ev, zb, 4)
     plane = w.nx * w.ny
     # default margin: ceil(3 sigma / 4 mm) + ceil(6 mm / 4 mm) = 15 + 2 (no axial cut)
@@ -96,14 +103,14 @@ def test_regions_cylinder_three_slabs():
 def test_regions_wholebody_nine_cores_packed_and_plain():
     print("case: whole body, 9 regions", flush=True)
     w = synth.wholebody_workload(n_events=200000)
-    ev = synth.events(w, n=200000)
     zb = [0, 107, 177, 240, 290, 335, 375, 410, 438, 470]
+    ev = unambiguous(w, synth.events(w, n=200000), zb)
     g, s, r_of, infos, st, imgs, summed = _region_case(w, ev, zb, 3)
     assert [i["nz"] for i in infos] == [120, 96, 89, 76, 71, 66, 61, 54, 58]
     plane = w.nx * w.ny
     counts = [i["n_events"] for i in infos]
     print("  events per region", counts, flush=True)
-    assert sum(counts) == len(ev)
+    assert sum(counts) == len(ev) and len(ev) > 199000
     for k in (0, 4, 8):
         info = infos[k]
         sel = r_of == k
@@ -114,10 +121,22 @@ def test_regions_wholebody_nine_cores_packed_and_plain():
         e = oracle.rel_l2(imgs[k], xk)
         print(f"  region {k} rel L2 {e:.2e}", flush=True)
         assert e < 1e-5
-    # packed storage runs the same split on decoded events
-    _, _, _, infos_p, _, imgs_p, _ = _region_case(w, ev, zb, 3, storage=1)
-    assert [i["n_events"] for i in infos_p][0] > 0
-    assert oracle.rel_l2(np.concatenate(imgs_p), np.concatenate(imgs)) < 2e-2
+    # packed storage: the same split on the decoded events (oracle packer + decoder)
+    dec = oracle.decode_packed(oracle.pack_events(ev))
+    r_dec, amb_dec = _assign(g, dec, zb)
+    keep = ~amb_dec
+    _, _, _, infos_p, _, imgs_p, _ = _region_case(w, ev[keep], zb, 3, storage=1)
+    for k in (0, 5):
+        info = infos_p[k]
+        sel = keep.copy()
+        sel[keep] = r_dec[keep] == k
+        assert info["n_events"] == int(sel.sum())
+        gk = dict(g, z0=g["z0"] + info["z_lo"] * w.voxel, nz=info["nz"])
+        sk = s[info["z_lo"] * plane:(info["z_lo"] + info["nz"]) * plane].astype(np.float64)
+        xk, _ = oracle.mlem(gk, dec[sel], sk, 3)
+        e = oracle.rel_l2(imgs_p[k], xk)
+        print(f"  packed region {k} vs oracle on decoded events: rel L2 {e:.2e}", flush=True)
+        assert e < 1e-5
 
 
 def test_region_errors():
