@@ -38,7 +38,7 @@ def main():
     ap.add_argument("--events", type=int, default=146_000_000)
     ap.add_argument("--iters", type=int, default=10)
     ap.add_argument("--storage", choices=["plain", "packed"], default="plain")
-    ap.add_argument("--cpu-sample", type=int, default=30_000_000,
+    ap.add_argument("--cpu-sample", type=int, default=60_000_000,
                     help="events in the oracle CPU-baseline sample (0 = skip)")
     ap.add_argument("--ept", type=int, default=0)
     args = ap.parse_args()
@@ -106,17 +106,24 @@ def main():
 
     N, I, K = w.n_events, w.n_iter, args.steps
     value = N * I * K / wall
-    proj_ms = float(np.mean([s["project_ms"] for st in stats for s in st]))
-    fwd_ms = float(np.mean([s["forward_ms"] for st in stats for s in st]))
-    back_ms = float(np.mean([s["back_ms"] for st in stats for s in st]))
-    iter_ms = float(np.mean([s["ms"] for st in stats for s in st]))
+    allst = [s for st in stats for s in st]
+    mean = lambda key: float(np.mean([s[key] for s in allst]))  # noqa: E731
+    proj_ms, fwd_ms, back_ms = mean("project_ms"), mean("forward_ms"), mean("back_ms")
+    backk_ms, upd_ms, iter_ms = mean("back_kernel_ms"), mean("update_ms"), mean("ms")
     loop_rate = N / (iter_ms * 1e-3)
     last = stats[-1][-1]
 
+    # Algorithmic bytes (no reuse across events): an event record of E bytes
+    # and one 4-byte ratio per event, one 4-byte image access per voxel piece
+    # (a gather in the forward pass, a scatter-add in the back pass), and a
+    # 20-byte-per-voxel update pass (x, s, b read; x written; b cleared).
     visited, weighted = r.count_segments()
     E = 16 if args.storage == "packed" else 32
-    bytes_launch = N * E + 4 * visited + 4 * weighted
-    achieved = bytes_launch / (proj_ms * 1e-3) / 1e9
+    V = w.n_voxels
+    bytes_back = N * (E + 4) + 4 * weighted
+    bytes_fwd = N * (E + 4) + 4 * visited
+    bytes_iter = N * E + 4 * (visited + weighted) + 20 * V
+    gbs = lambda b, ms: b / (ms * 1e-3) / 1e9  # noqa: E731
     step_ms = [t["step_ms"] for t in times]
 
     out = {
@@ -138,15 +145,20 @@ def main():
         "recon_latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99))},
         "one_time_ms": {k: float(np.mean([t[k] for t in times])) for k in ("load_ms", "sens_ms", "init_ms")},
         "iteration_ms": iter_ms,
-        "project_ms": proj_ms,
-        "forward_kernel_ms": fwd_ms,
-        "back_kernel_ms": back_ms,
+        "kernel_ms": {"project": proj_ms, "k_forward": fwd_ms, "back_stage": back_ms, "k_back_chunks": backk_ms,
+                      "update_stage": upd_ms},
         "segments_per_event": {"visited": visited / N, "weighted": weighted / N},
         "last_iteration": {"n_eff": last["n_eff"], "sum_sx": last["sum_sx"], "loglik": last["loglik"]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_project_fused",
-                     "bytes_per_launch": bytes_launch},
+        "roofline": {"bound": "hbm", "achieved": gbs(bytes_back, backk_ms), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs(bytes_back, backk_ms) / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_back_chunks", "bytes_per_launch": bytes_back},
+        "roofline_forward": {"bound": "hbm", "achieved": gbs(bytes_fwd, fwd_ms), "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": gbs(bytes_fwd, fwd_ms) / HBM_PEAK_GBS,
+                             "kernel": "k_forward", "bytes_per_launch": bytes_fwd},
+        "roofline_iteration": {"bound": "hbm", "achieved": gbs(bytes_iter, iter_ms), "peak": HBM_PEAK_GBS,
+                               "unit": "GB/s", "frac": gbs(bytes_iter, iter_ms) / HBM_PEAK_GBS,
+                               "bytes_per_event_iteration": bytes_iter / N,
+                               "hbm_roofline_event_iterations_per_s": HBM_PEAK_GBS * 1e9 / (bytes_iter / N)},
     }
     r.close()
     del ev_dev

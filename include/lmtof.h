@@ -104,7 +104,9 @@ typedef struct {
     float ms;         /* wall time of the iteration on the GPU (ms) */
     float project_ms; /* of which: forward + back projection (ms) */
     float forward_ms; /* forward projection and ratio kernel (ms) */
-    float back_ms;    /* back projection kernel (ms) */
+    float back_ms;    /* back projection stage: brick scales, brick kernel, tile reduction (ms) */
+    float back_kernel_ms; /* of which the brick back projection kernel alone (ms) */
+    float update_ms;  /* image update and statistics (ms) */
 } lmtof_iter_stats;
 
 /* ------------------------------------------------------------- lifecycle */
@@ -211,6 +213,52 @@ int lmtof_region_info(const lmtof_ctx *ctx, int k, int32_t *out4, int64_t *n_eve
 int lmtof_read_region_image(lmtof_ctx *ctx, int k, float *out, int64_t n, int mem);
 /* Drop the region split (back to one whole-volume problem). */
 int lmtof_clear_regions(lmtof_ctx *ctx);
+
+/* --------------------------------------------------------------- serving */
+/* Continuous-batching reconstruction server on one GPU (not in the paper; it
+ * serves many list-mode reconstructions at once).  A pool admits requests
+ * while their estimated device footprint fits its HBM budget; each step runs
+ * ONE batched MLEM iteration over every active request (each at its own
+ * iteration index, all in the same kernel launches); requests join and
+ * leave at step boundaries, keeping events and images resident meanwhile.
+ * A request's result does not depend on which other requests share its
+ * steps (every kernel is order-independent for a given request). */
+typedef struct lmtof_pool lmtof_pool;
+
+typedef struct {
+    lmtof_geometry geometry;
+    const void *events;  /* n_events records in `format`, in `mem` */
+    int64_t n_events;
+    int32_t format;      /* LMTOF_FMT_* */
+    int32_t mem;         /* LMTOF_MEM_* */
+    int32_t n_iter;      /* MLEM iterations, >= 1 */
+    int32_t storage;     /* 0 plain, 1 packed */
+} lmtof_request;
+
+/* Create a pool on `hip_device` (stream as in lmtof_create) with an HBM
+ * budget in bytes for resident requests (> 0). */
+int lmtof_pool_create(lmtof_pool **out, int hip_device, void *hip_stream, int64_t hbm_budget_bytes);
+int lmtof_pool_destroy(lmtof_pool *pool);
+const char *lmtof_pool_last_error(const lmtof_pool *pool);
+/* Estimated device footprint (bytes) the pool reserves for a request. */
+int lmtof_pool_request_bytes(const lmtof_request *req, int64_t *bytes);
+/* Validate, copy and prepare (ingest, bucketing, sensitivity, start image,
+ * brick lists) a request; *id receives its handle.  LMTOF_EAGAIN (nothing
+ * done) if its footprint does not fit the budget next to the resident
+ * requests now, or if it is TOF and the active requests are not (or the
+ * reverse: a batch is all-TOF or all-non-TOF); LMTOF_ENOMEM if it can
+ * never fit. */
+int lmtof_pool_submit(lmtof_pool *pool, const lmtof_request *req, int64_t *id);
+/* One batched iteration over all active requests; *n_active receives how
+ * many were active (0: nothing to do).  Requests that reach their
+ * iteration count become finished (images kept until polled). */
+int lmtof_pool_step(lmtof_pool *pool, int *n_active);
+/* *done = 1 and the image copied to out (nx*ny*nz floats in `mem`) if
+ * request id has finished; the request is then released.  *done = 0 if it
+ * is still running.  EINVAL for an unknown id. */
+int lmtof_pool_poll(lmtof_pool *pool, int64_t id, int *done, float *out, int64_t n, int mem);
+/* Bytes reserved, budget, active and finished-but-unpolled request counts. */
+int lmtof_pool_info(const lmtof_pool *pool, int64_t *used, int64_t *budget, int *n_active, int *n_finished);
 
 #ifdef __cplusplus
 }

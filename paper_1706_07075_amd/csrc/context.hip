@@ -22,11 +22,14 @@ namespace {
 
 constexpr double kDefaultC = 0.299792458;
 constexpr int kDefaultEpt = 4;
+// Event records per graph-replayed iteration: start, after forward, after
+// brick scales, after brick back projection, after tile reduction, end.
+constexpr int kEventsPerIter = 6;
 
 struct GraphEntry {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    std::vector<hipEvent_t> ev;  // 3 per iteration: start, after projector, after finalize
+    std::vector<hipEvent_t> ev;  // kEventsPerIter per iteration
 };
 
 struct Region {
@@ -42,9 +45,11 @@ struct Region {
 struct ItemSet {
     uint32_t *items = nullptr;
     uint4 *chunks = nullptr, *bricks = nullptr;
-    float *tiles = nullptr;
+    unsigned long long *tiles = nullptr;
+    float *wmax = nullptr;
     uint32_t n_chunks = 0, n_bricks = 0, n_slots = 0;
     uint64_t n_items = 0;
+    std::vector<uint4> h_chunks, h_bricks;  // host copies (batching several problems)
 };
 
 }  // namespace
@@ -144,6 +149,7 @@ void free_items(ItemSet &it) {
     dev_free(it.chunks);
     dev_free(it.bricks);
     dev_free(it.tiles);
+    dev_free(it.wmax);
     it = ItemSet();
 }
 
@@ -286,7 +292,7 @@ int upload_problems(lmtof_ctx *c, std::vector<Problem> &ps, int block, int ept, 
 // into chunks of at most C items (C grows with the total so there are
 // ~8k chunks) and order the chunks largest first.  The chunk table is a
 // launch schedule built on the host from the per-brick counts.
-int build_items(lmtof_ctx *c, const std::vector<Problem> &ps, const Problem *d_probs, int64_t n_chunks, int ept,
+int build_items(lmtof_ctx *c, std::vector<Problem> &ps, Problem *d_probs, int64_t n_chunks, int ept,
                 ItemSet &out) {
     free_items(out);
     uint64_t nb = 0;
@@ -298,7 +304,7 @@ int build_items(lmtof_ctx *c, const std::vector<Problem> &ps, const Problem *d_p
     if (rc) return rc;
     std::vector<uint32_t> h(nb);
     hipError_t he = hipMemsetAsync(cnt, 0, sizeof(uint32_t) * (nb + 1), c->stream);
-    if (he == hipSuccess) he = launch_brick_items(L, d_probs, (int)ps.size(), n_chunks, ept, cnt, nullptr, nullptr);
+    if (he == hipSuccess) he = launch_brick_items(L, d_probs, (int)ps.size(), n_chunks, ept, cnt, nullptr, 0);
     if (he == hipSuccess) he = hipMemcpyAsync(h.data(), cnt, sizeof(uint32_t) * nb, hipMemcpyDeviceToHost, c->stream);
     if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
     if (he != hipSuccess) {
@@ -322,11 +328,12 @@ int build_items(lmtof_ctx *c, const std::vector<Problem> &ps, const Problem *d_p
     for (uint64_t b = 0; b < nb; ++b) {
         if (!h[b]) continue;
         const uint32_t nch = (uint32_t)((h[b] + C - 1) / C);
-        bricks.push_back(make_uint4((uint32_t)b, slot, slot + nch, 0));
+        const uint32_t bi = (uint32_t)bricks.size();
+        bricks.push_back(make_uint4((uint32_t)b, slot, slot + nch, h[b]));
         for (uint32_t q = 0; q < nch; ++q) {
             const uint32_t k0 = off[b] + (uint32_t)((uint64_t)h[b] * q / nch);
             const uint32_t k1 = off[b] + (uint32_t)((uint64_t)h[b] * (q + 1) / nch);
-            chunks.push_back(make_uint4((uint32_t)b, k0, k1, slot + q));
+            chunks.push_back(make_uint4(bi, k0, k1, slot + q));
         }
         slot += nch;
     }
@@ -339,20 +346,26 @@ int build_items(lmtof_ctx *c, const std::vector<Problem> &ps, const Problem *d_p
     it.n_items = tot;
     if ((rc = dev_alloc(c, &it.items, tot)) || (rc = dev_alloc(c, &off_d, nb + 1)) ||
         (rc = dev_alloc(c, &it.chunks, chunks.size())) || (rc = dev_alloc(c, &it.bricks, bricks.size())) ||
-        (rc = dev_alloc(c, &it.tiles, (size_t)slot * kBrickVox))) {
+        (rc = dev_alloc(c, &it.tiles, (size_t)slot * kBrickVox)) || (rc = dev_alloc(c, &it.wmax, slot))) {
         dev_free(cnt);
         dev_free(off_d);
         free_items(it);
         return rc;
     }
-    he = hipMemcpyAsync(off_d, off.data(), sizeof(uint32_t) * (nb + 1), hipMemcpyHostToDevice, c->stream);
+    for (auto &P : ps) {
+        P.items = it.items;
+        P.tiles = it.tiles;
+        P.wmax = it.wmax;
+    }
+    he = hipMemcpyAsync(d_probs, ps.data(), sizeof(Problem) * ps.size(), hipMemcpyHostToDevice, c->stream);
+    if (he == hipSuccess)
+        he = hipMemcpyAsync(off_d, off.data(), sizeof(uint32_t) * (nb + 1), hipMemcpyHostToDevice, c->stream);
     if (he == hipSuccess && !chunks.empty())
         he = hipMemcpyAsync(it.chunks, chunks.data(), sizeof(uint4) * chunks.size(), hipMemcpyHostToDevice, c->stream);
     if (he == hipSuccess && !bricks.empty())
         he = hipMemcpyAsync(it.bricks, bricks.data(), sizeof(uint4) * bricks.size(), hipMemcpyHostToDevice, c->stream);
     if (he == hipSuccess) he = hipMemcpyAsync(cnt, off_d, sizeof(uint32_t) * (nb + 1), hipMemcpyDeviceToDevice, c->stream);
-    if (he == hipSuccess)
-        he = launch_brick_items(L, d_probs, (int)ps.size(), n_chunks, ept, cnt, it.items, off_d + 1);
+    if (he == hipSuccess) he = launch_brick_items(L, d_probs, (int)ps.size(), n_chunks, ept, cnt, off_d + 1, 1);
     if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
     dev_free(cnt);
     dev_free(off_d);
@@ -360,14 +373,17 @@ int build_items(lmtof_ctx *c, const std::vector<Problem> &ps, const Problem *d_p
         free_items(it);
         return fail(c, LMTOF_EHIP, "brick item fill: %s", hipGetErrorString(he));
     }
-    out = it;
+    it.h_chunks = std::move(chunks);
+    it.h_bricks = std::move(bricks);
+    out = std::move(it);
     return LMTOF_OK;
 }
 
-// Back projection of per-stored-event weights w into the batch's b arrays
-// (as graph nodes after *prev, or on the stream).
-int add_back(lmtof_ctx *c, Launch L, const Problem *d_probs, int np, const ItemSet &it, const float *w,
-             hipGraphNode_t *prev) {
+// Back projection of each problem's weights P.rw into its b (as graph nodes
+// after *prev, or on the stream).  In a graph, ev_a and ev_b (if given) are
+// recorded right before and right after the brick kernel, to time it alone.
+int add_back(lmtof_ctx *c, Launch L, const Problem *d_probs, int np, const ItemSet &it, hipGraphNode_t *prev,
+             hipEvent_t ev_a = nullptr, hipEvent_t ev_b = nullptr) {
     const bool tof = c->g.tof_fwhm_ps > 0;
     hipGraphNode_t node = nullptr;
     if (L.graph) {
@@ -375,12 +391,28 @@ int add_back(lmtof_ctx *c, Launch L, const Problem *d_probs, int np, const ItemS
         L.n_deps = 1;
         L.node = &node;
     }
-    HIPCHK(c, launch_back_chunks(L, tof, d_probs, np, c->d_events, it.chunks, it.n_chunks, it.items, w, it.tiles));
+    auto record = [&](hipEvent_t ev) -> int {
+        if (!L.graph || !ev) return LMTOF_OK;
+        hipGraphNode_t n = nullptr;
+        HIPCHK(c, hipGraphAddEventRecordNode(&n, L.graph, prev, 1, ev));
+        *prev = n;
+        L.deps = prev;
+        return LMTOF_OK;
+    };
+    int rc;
+    HIPCHK(c, launch_chunk_wmax(L, d_probs, np, it.chunks, it.n_chunks, it.bricks));
     if (L.graph && it.n_chunks) {
         *prev = node;
         L.deps = prev;
     }
-    HIPCHK(c, launch_reduce_tiles(L, d_probs, np, it.bricks, it.n_bricks, it.tiles));
+    if ((rc = record(ev_a))) return rc;
+    HIPCHK(c, launch_back_chunks(L, tof, d_probs, np, it.chunks, it.n_chunks, it.bricks));
+    if (L.graph && it.n_chunks) {
+        *prev = node;
+        L.deps = prev;
+    }
+    if ((rc = record(ev_b))) return rc;
+    HIPCHK(c, launch_reduce_tiles(L, d_probs, np, it.bricks, it.n_bricks));
     if (L.graph && it.n_bricks) *prev = node;
     return LMTOF_OK;
 }
@@ -409,6 +441,7 @@ int ensure_problems(lmtof_ctx *c) {
         P.events = c->d_events;
         P.n_events = c->n_events;
         P.ev_offset = 0;
+        P.rw = c->d_rw;
         ps.push_back(P);
     } else {
         for (auto &r : c->regions) {
@@ -416,6 +449,7 @@ int ensure_problems(lmtof_ctx *c) {
             P.events = (const char *)c->d_events + esz * r.ev_offset;
             P.n_events = r.n_events;
             P.ev_offset = r.ev_offset;
+            P.rw = c->d_rw + r.ev_offset;
             ps.push_back(P);
         }
     }
@@ -457,13 +491,14 @@ int ensure_stats(lmtof_ctx *c, size_t n) {
 }
 
 // n_iter MLEM iterations as one explicit HIP graph.  Per iteration: event
-// record, forward + ratio, event record, brick back projection, event
-// record, update, finalize (stats of iteration k into slot k), event record.
+// record, forward + ratio, event record, brick scales, event record, brick
+// back projection, event record, tile reduction, event record, update,
+// finalize (stats of iteration k into slot k), event record.
 int build_graph(lmtof_ctx *c, int n_iter, GraphEntry &ge) {
     const int np = (int)c->probs.size();
     const bool tof = c->g.tof_fwhm_ps > 0;
     HIPCHK(c, hipGraphCreate(&ge.graph, 0));
-    ge.ev.assign(4 * n_iter, nullptr);
+    ge.ev.assign(kEventsPerIter * n_iter, nullptr);
     for (auto &e : ge.ev) HIPCHK(c, hipEventCreate(&e));
     hipGraphNode_t prev = nullptr;
     bool have_prev = false;
@@ -476,19 +511,20 @@ int build_graph(lmtof_ctx *c, int n_iter, GraphEntry &ge) {
     };
     for (int k = 0; k < n_iter; ++k) {
         int rc;
-        if ((rc = record(ge.ev[4 * k]))) return rc;
+        if ((rc = record(ge.ev[kEventsPerIter * k]))) return rc;
         hipGraphNode_t node = nullptr;
         Launch L;
         L.graph = ge.graph;
         L.deps = &prev;
         L.n_deps = 1;
         L.node = &node;
-        HIPCHK(c, launch_forward(L, tof, c->d_probs, np, c->n_chunks, c->ept_used, 0, c->d_rw, c->d_part_neff,
-                                 c->d_part_ll));
+        HIPCHK(c, launch_forward(L, tof, c->d_probs, np, c->n_chunks, c->ept_used, 0, c->d_part_neff, c->d_part_ll));
         if (node) prev = node;
-        if ((rc = record(ge.ev[4 * k + 1]))) return rc;
-        if ((rc = add_back(c, L, c->d_probs, np, c->items, c->d_rw, &prev))) return rc;
-        if ((rc = record(ge.ev[4 * k + 2]))) return rc;
+        if ((rc = record(ge.ev[kEventsPerIter * k + 1]))) return rc;
+        if ((rc = add_back(c, L, c->d_probs, np, c->items, &prev, ge.ev[kEventsPerIter * k + 2],
+                           ge.ev[kEventsPerIter * k + 3])))
+            return rc;
+        if ((rc = record(ge.ev[kEventsPerIter * k + 4]))) return rc;
         L.deps = &prev;
         node = nullptr;
         HIPCHK(c, launch_update(L, c->d_probs, np, c->n_vchunks, c->d_part_old, c->d_part_new));
@@ -498,7 +534,7 @@ int build_graph(lmtof_ctx *c, int n_iter, GraphEntry &ge) {
         HIPCHK(c, launch_finalize(L, c->d_probs, np, c->n_chunks, c->n_vchunks, c->d_part_neff, c->d_part_ll,
                                   c->d_part_old, c->d_part_new, c->d_stats, k));
         if (node) prev = node;
-        if ((rc = record(ge.ev[4 * k + 3]))) return rc;
+        if ((rc = record(ge.ev[kEventsPerIter * k + 5]))) return rc;
     }
     HIPCHK(c, hipGraphInstantiate(&ge.exec, ge.graph, nullptr, nullptr, 0));
     return LMTOF_OK;
@@ -573,6 +609,42 @@ KeyGeom key_geom(const lmtof_ctx *c, bool sort, const std::vector<Region> &regio
     for (size_t r = 0; r < regions.size(); ++r) k.region_z[r] = (float)(g.z0 + regions[r].core_lo * g.vz);
     if (!regions.empty()) k.region_z[regions.size()] = (float)(g.z0 + regions.back().core_hi * g.vz);
     return k;
+}
+
+// Device bytes a prepared context holds (events, permutation, per-event
+// weights, brick lists and tiles, images, partials).
+int64_t ctx_device_bytes(const lmtof_ctx *c) {
+    const int64_t esz = c->stored_packed ? 16 : 32;
+    int64_t b = c->n_events * (esz + 8 + 4) + 3 * 4 * c->V;
+    b += (int64_t)c->items.n_items * 4 + (int64_t)c->items.n_slots * (kBrickVox * 8 + 4);
+    b += (int64_t)(c->items.n_chunks + c->items.n_bricks) * 16;
+    b += (int64_t)c->part_cap * 12 + (int64_t)c->vpart_cap * 16 + kLutN * 16;
+    return b;
+}
+
+// Footprint the pool reserves for a request: stored events, permutation,
+// weights, ~ (1 + 1.7 * window / brick edge) brick items per event plus
+// tiles, three images, and the transient ingest buffers (raw copy, keys,
+// sort histogram).
+int64_t request_bytes_estimate(const lmtof_request &q) {
+    const lmtof_geometry &g = q.geometry;
+    const int64_t V = (int64_t)g.nx * g.ny * g.nz;
+    const int64_t N = q.n_events;
+    const double c = g.c_mm_per_ps > 0 ? g.c_mm_per_ps : kDefaultC;
+    const double K = g.tof_trunc_sigmas > 0 ? g.tof_trunc_sigmas : 3.0;
+    const double vmin = std::min(g.vx, std::min(g.vy, g.vz));
+    double win;
+    if (g.tof_fwhm_ps > 0)
+        win = 2.0 * K * (c * g.tof_fwhm_ps / 2.0) / (2.0 * std::sqrt(2.0 * std::log(2.0)));
+    else
+        win = std::sqrt(std::pow(g.nx * g.vx, 2) + std::pow(g.ny * g.vy, 2) + std::pow(g.nz * g.vz, 2));
+    const double ipe = 1.3 * (1.0 + 1.7 * win / (kBrickX * vmin));
+    const int64_t items = (int64_t)(N * ipe);
+    const int64_t esz = q.storage ? 16 : 32;
+    int64_t b = N * (esz + 8 + 4) + items * 4 + 3 * 4 * V;
+    b += (items / 2048 + 1 + V / kBrickVox + 1) * (int64_t)kBrickVox * 8 / 4;  // tiles
+    b += N * (q.mem == LMTOF_MEM_HOST ? 28 : 0) + N * (esz + 8 + 4);       // ingest transients
+    return b + (64 << 20);
 }
 
 }  // namespace
@@ -1019,10 +1091,16 @@ int lmtof_iterate(lmtof_ctx *c, int n_iter, lmtof_iter_stats *stats) {
                 o.sum_sx = sx;
                 o.loglik = slf - sxo;
                 const auto &ev = it->second.ev;
-                float t_all = 0, t_fwd = 0, t_back = 0;
-                if (hipEventElapsedTime(&t_all, ev[4 * k], ev[4 * k + 3]) == hipSuccess) o.ms = t_all;
-                if (hipEventElapsedTime(&t_fwd, ev[4 * k], ev[4 * k + 1]) == hipSuccess) o.forward_ms = t_fwd;
-                if (hipEventElapsedTime(&t_back, ev[4 * k + 1], ev[4 * k + 2]) == hipSuccess) o.back_ms = t_back;
+                const hipEvent_t *e = &ev[(size_t)kEventsPerIter * k];
+                auto span = [&](int a, int b) {
+                    float t = 0;
+                    return hipEventElapsedTime(&t, e[a], e[b]) == hipSuccess ? t : 0.0f;
+                };
+                o.ms = span(0, 5);
+                o.forward_ms = span(0, 1);
+                o.back_ms = span(1, 4);
+                o.back_kernel_ms = span(2, 3);
+                o.update_ms = span(4, 5);
                 o.project_ms = o.forward_ms + o.back_ms;
                 (void)hipGetLastError();
             }
@@ -1064,11 +1142,12 @@ int lmtof_forward_project(lmtof_ctx *c, const float *x, int64_t nx_, float *f, i
     std::vector<Problem> ps{make_problem(c, 0, c->g.nz, dx, nullptr, nullptr)};
     ps[0].events = c->d_events;
     ps[0].n_events = c->n_events;
+    ps[0].rw = fs;
     int block, ept;
     launch_shape(c, block, ept);
     int64_t nch, nvch;
     if ((rc = upload_problems(c, ps, block, ept, &dp, nch, nvch))) return done(rc);
-    hipError_t he = launch_forward(L, c->g.tof_fwhm_ps > 0, dp, 1, nch, ept, 1, fs, nullptr, nullptr);
+    hipError_t he = launch_forward(L, c->g.tof_fwhm_ps > 0, dp, 1, nch, ept, 1, nullptr, nullptr);
     if (he == hipSuccess) he = launch_scatter_by_perm(L, fs, c->d_perm, c->n_events, fc);
     if (he != hipSuccess) return done(fail(c, LMTOF_EHIP, "forward projection: %s", hipGetErrorString(he)));
     if (mem == LMTOF_MEM_HOST) rc = copy_out(c, f, fc, sizeof(float) * c->n_events, LMTOF_MEM_HOST);
@@ -1108,6 +1187,7 @@ int lmtof_back_project(lmtof_ctx *c, const float *w, int64_t nw, float *b, int64
     std::vector<Problem> ps{make_problem(c, 0, c->g.nz, nullptr, db, nullptr)};
     ps[0].events = c->d_events;
     ps[0].n_events = c->n_events;
+    ps[0].rw = ws;
     int block, ept;
     launch_shape(c, block, ept);
     int64_t nch, nvch;
@@ -1116,7 +1196,7 @@ int lmtof_back_project(lmtof_ctx *c, const float *w, int64_t nw, float *b, int64
     hipError_t he = launch_gather_by_perm(L, dw, c->d_perm, c->n_events, ws);
     if (he == hipSuccess) he = launch_fill(L, db, c->V, 0.0f);
     if (he != hipSuccess) return done(fail(c, LMTOF_EHIP, "back projection: %s", hipGetErrorString(he)));
-    if ((rc = add_back(c, L, dp, 1, its, ws, nullptr))) return done(rc);
+    if ((rc = add_back(c, L, dp, 1, its, nullptr))) return done(rc);
     if (mem == LMTOF_MEM_HOST) rc = copy_out(c, b, db, sizeof(float) * c->V, LMTOF_MEM_HOST);
     else if (hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(c, LMTOF_EHIP, "back projection failed");
     return done(rc);
@@ -1290,6 +1370,307 @@ int lmtof_clear_regions(lmtof_ctx *c) {
         drop_graphs(c);
         c->has_image = false;
     }
+    return LMTOF_OK;
+}
+
+}  // extern "C"
+
+// ==================================================================== serving
+
+struct PoolReq {
+    int64_t id = 0;
+    lmtof_ctx *ctx = nullptr;
+    int n_iter = 0, done = 0;
+    int64_t bytes = 0;
+};
+
+struct lmtof_pool {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    int64_t budget = 0, used = 0, next_id = 1;
+    std::vector<PoolReq> active;
+    std::map<int64_t, PoolReq> finished;
+    // current batch
+    bool dirty = true;
+    std::vector<Problem> batch;
+    Problem *d_probs = nullptr;
+    size_t probs_cap = 0;
+    uint4 *d_chunks = nullptr, *d_bricks = nullptr;
+    size_t chunks_cap = 0, bricks_cap = 0;
+    uint32_t n_bchunks = 0, n_bbricks = 0;
+    int64_t n_chunks = 0, n_vchunks = 0;
+    int *part_neff = nullptr;
+    double *part_ll = nullptr, *part_old = nullptr, *part_new = nullptr;
+    size_t part_cap = 0, vpart_cap = 0;
+    DevStats *d_stats = nullptr;
+    size_t stats_cap = 0;
+    int ept = kDefaultEpt;
+};
+
+namespace {
+
+int pfail(lmtof_pool *p, int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (p) p->err = buf;
+    return code;
+}
+
+#define PHIP(p, expr)                                                                                  \
+    do {                                                                                               \
+        hipError_t e__ = (expr);                                                                       \
+        if (e__ != hipSuccess) return pfail((p), LMTOF_EHIP, "%s: %s", #expr, hipGetErrorString(e__)); \
+    } while (0)
+
+template <class T>
+int pool_grow(lmtof_pool *p, T **ptr, size_t &cap, size_t n) {
+    if (n <= cap && *ptr) return LMTOF_OK;
+    dev_free(*ptr);
+    cap = 0;
+    if (hipMalloc((void **)ptr, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) {
+        (void)hipGetLastError();
+        *ptr = nullptr;
+        return pfail(p, LMTOF_ENOMEM, "pool batch allocation failed");
+    }
+    cap = n;
+    return LMTOF_OK;
+}
+
+// Batch = every active request's problem; chunk ids, brick ids and update
+// chunks renumbered across the batch; brick chunks of all requests merged
+// largest first.
+int pool_build_batch(lmtof_pool *p) {
+    p->batch.clear();
+    std::vector<uint4> chunks, bricks;
+    int64_t nch = 0, nvch = 0, nb = 0;
+    const int64_t ce = project_chunk_events(kForwardBlock, p->ept), cv = update_chunk_voxels();
+    for (auto &r : p->active) {
+        Problem P = r.ctx->probs[0];
+        P.chunk_begin = nch;
+        P.vchunk_begin = nvch;
+        P.brick_base = (int32_t)nb;
+        nch += (P.n_events + ce - 1) / ce;
+        nvch += ((int64_t)P.nx * P.ny * P.nz + cv - 1) / cv;
+        const uint32_t bt = (uint32_t)bricks.size();
+        for (uint4 q : r.ctx->items.h_chunks) chunks.push_back(make_uint4(q.x + bt, q.y, q.z, q.w));
+        for (uint4 q : r.ctx->items.h_bricks) bricks.push_back(make_uint4(q.x + (uint32_t)nb, q.y, q.z, q.w));
+        nb += (int64_t)P.nbx * P.nby * P.nbz;
+        p->batch.push_back(P);
+    }
+    if (nch > 0x7fffffffLL || nb > 0x7fffffffLL) return pfail(p, LMTOF_EUNSUPPORTED, "batch too large");
+    std::stable_sort(chunks.begin(), chunks.end(),
+                     [](const uint4 &a, const uint4 &b) { return (a.z - a.y) > (b.z - b.y); });
+    const size_t np = p->batch.size();
+    int rc;
+    if ((rc = pool_grow(p, &p->d_probs, p->probs_cap, np)) || (rc = pool_grow(p, &p->d_chunks, p->chunks_cap, chunks.size())) ||
+        (rc = pool_grow(p, &p->d_bricks, p->bricks_cap, bricks.size())) ||
+        (rc = pool_grow(p, &p->d_stats, p->stats_cap, np)))
+        return rc;
+    if ((size_t)nch > p->part_cap) {
+        size_t c0 = p->part_cap, c1 = p->part_cap;
+        if ((rc = pool_grow(p, &p->part_neff, c0, nch)) || (rc = pool_grow(p, &p->part_ll, c1, nch))) return rc;
+        p->part_cap = nch;
+    }
+    if ((size_t)nvch > p->vpart_cap) {
+        size_t c0 = p->vpart_cap, c1 = p->vpart_cap;
+        if ((rc = pool_grow(p, &p->part_old, c0, nvch)) || (rc = pool_grow(p, &p->part_new, c1, nvch))) return rc;
+        p->vpart_cap = nvch;
+    }
+    PHIP(p, hipMemcpyAsync(p->d_probs, p->batch.data(), sizeof(Problem) * np, hipMemcpyHostToDevice, p->stream));
+    if (!chunks.empty())
+        PHIP(p, hipMemcpyAsync(p->d_chunks, chunks.data(), sizeof(uint4) * chunks.size(), hipMemcpyHostToDevice, p->stream));
+    if (!bricks.empty())
+        PHIP(p, hipMemcpyAsync(p->d_bricks, bricks.data(), sizeof(uint4) * bricks.size(), hipMemcpyHostToDevice, p->stream));
+    PHIP(p, hipStreamSynchronize(p->stream));
+    p->n_bchunks = (uint32_t)chunks.size();
+    p->n_bbricks = (uint32_t)bricks.size();
+    p->n_chunks = nch;
+    p->n_vchunks = nvch;
+    p->dirty = false;
+    return LMTOF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lmtof_pool_create(lmtof_pool **out, int hip_device, void *hip_stream, int64_t budget) {
+    if (!out) return LMTOF_EINVAL;
+    *out = nullptr;
+    if (budget <= 0) {
+        g_create_err = "HBM budget must be > 0";
+        return LMTOF_EINVAL;
+    }
+    try {
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev) {
+            (void)hipGetLastError();
+            g_create_err = "no such HIP device";
+            return ndev < 1 ? LMTOF_EHIP : LMTOF_EINVAL;
+        }
+        if (hipSetDevice(hip_device) != hipSuccess) {
+            g_create_err = "hipSetDevice failed";
+            return LMTOF_EHIP;
+        }
+        lmtof_pool *p = new lmtof_pool();
+        p->device = hip_device;
+        p->budget = budget;
+        if (hip_stream) {
+            p->stream = (hipStream_t)hip_stream;
+        } else {
+            if (hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking) != hipSuccess) {
+                delete p;
+                g_create_err = "hipStreamCreate failed";
+                return LMTOF_EHIP;
+            }
+            p->own_stream = true;
+        }
+        *out = p;
+        return LMTOF_OK;
+    } catch (...) {
+        g_create_err = "host allocation failed";
+        return LMTOF_ENOMEM;
+    }
+}
+
+int lmtof_pool_destroy(lmtof_pool *p) {
+    if (!p) return LMTOF_OK;
+    (void)hipSetDevice(p->device);
+    (void)hipStreamSynchronize(p->stream);
+    for (auto &r : p->active) lmtof_destroy(r.ctx);
+    for (auto &kv : p->finished) lmtof_destroy(kv.second.ctx);
+    dev_free(p->d_probs);
+    dev_free(p->d_chunks);
+    dev_free(p->d_bricks);
+    dev_free(p->part_neff);
+    dev_free(p->part_ll);
+    dev_free(p->part_old);
+    dev_free(p->part_new);
+    dev_free(p->d_stats);
+    if (p->own_stream) (void)hipStreamDestroy(p->stream);
+    delete p;
+    return LMTOF_OK;
+}
+
+const char *lmtof_pool_last_error(const lmtof_pool *p) { return p ? p->err.c_str() : g_create_err.c_str(); }
+
+int lmtof_pool_request_bytes(const lmtof_request *q, int64_t *bytes) {
+    if (!q || !bytes || q->n_events < 1) return LMTOF_EINVAL;
+    *bytes = request_bytes_estimate(*q);
+    return LMTOF_OK;
+}
+
+int lmtof_pool_submit(lmtof_pool *p, const lmtof_request *q, int64_t *id) {
+    if (!p) return LMTOF_EINVAL;
+    p->err.clear();
+    if (!q || !id) return pfail(p, LMTOF_EINVAL, "request or id pointer is NULL");
+    if (q->n_iter < 1 || q->n_iter > 10000) return pfail(p, LMTOF_EINVAL, "n_iter must be in [1, 10000]");
+    if (q->storage != 0 && q->storage != 1) return pfail(p, LMTOF_EINVAL, "storage must be 0 or 1");
+    if (q->n_events < 1) return pfail(p, LMTOF_EINVAL, "n_events must be >= 1");
+    const bool tof = q->geometry.tof_fwhm_ps > 0;
+    for (auto &r : p->active)
+        if ((r.ctx->g.tof_fwhm_ps > 0) != tof)
+            return pfail(p, LMTOF_EAGAIN, "TOF and non-TOF requests are not batched together; retry when drained");
+    const int64_t est = request_bytes_estimate(*q);
+    if (est > p->budget) return pfail(p, LMTOF_ENOMEM, "request needs ~%lld bytes, over the %lld-byte budget",
+                                      (long long)est, (long long)p->budget);
+    if (p->used + est > p->budget)
+        return pfail(p, LMTOF_EAGAIN, "request needs ~%lld bytes, %lld free now", (long long)est,
+                     (long long)(p->budget - p->used));
+    lmtof_ctx *c = nullptr;
+    int rc = lmtof_create(&c, p->device, p->stream);
+    if (rc) return pfail(p, rc, "%s", lmtof_last_error(nullptr));
+    auto bail = [&](int code) {
+        std::string m = lmtof_last_error(c);
+        lmtof_destroy(c);
+        return pfail(p, code, "%s", m.c_str());
+    };
+    if ((rc = lmtof_set_option(c, LMTOF_OPT_STORAGE, q->storage))) return bail(rc);
+    if ((rc = lmtof_set_geometry(c, &q->geometry))) return bail(rc);
+    if ((rc = lmtof_load_events(c, q->events, q->n_events, q->format, q->mem))) return bail(rc);
+    if ((rc = lmtof_compute_sensitivity(c))) return bail(rc);
+    if ((rc = lmtof_set_image(c, nullptr, 0, LMTOF_MEM_HOST))) return bail(rc);
+    PoolReq r;
+    r.id = p->next_id++;
+    r.ctx = c;
+    r.n_iter = q->n_iter;
+    r.bytes = std::max(est, ctx_device_bytes(c));
+    p->used += r.bytes;
+    p->active.push_back(r);
+    p->dirty = true;
+    *id = r.id;
+    return LMTOF_OK;
+}
+
+int lmtof_pool_step(lmtof_pool *p, int *n_active) {
+    if (!p) return LMTOF_EINVAL;
+    p->err.clear();
+    if (n_active) *n_active = (int)p->active.size();
+    if (p->active.empty()) return LMTOF_OK;
+    PHIP(p, hipSetDevice(p->device));
+    int rc;
+    if (p->dirty && (rc = pool_build_batch(p))) return rc;
+    const int np = (int)p->batch.size();
+    const bool tof = p->batch[0].tof != 0;  // submit keeps a batch all-TOF or all-non-TOF
+    Launch L;
+    L.stream = p->stream;
+    PHIP(p, launch_forward(L, tof, p->d_probs, np, p->n_chunks, p->ept, 0, p->part_neff, p->part_ll));
+    PHIP(p, launch_chunk_wmax(L, p->d_probs, np, p->d_chunks, p->n_bchunks, p->d_bricks));
+    PHIP(p, launch_back_chunks(L, tof, p->d_probs, np, p->d_chunks, p->n_bchunks, p->d_bricks));
+    PHIP(p, launch_reduce_tiles(L, p->d_probs, np, p->d_bricks, p->n_bbricks));
+    PHIP(p, launch_update(L, p->d_probs, np, p->n_vchunks, p->part_old, p->part_new));
+    PHIP(p, launch_finalize(L, p->d_probs, np, p->n_chunks, p->n_vchunks, p->part_neff, p->part_ll, p->part_old,
+                            p->part_new, p->d_stats, 0));
+    PHIP(p, hipStreamSynchronize(p->stream));
+    std::vector<PoolReq> still;
+    for (auto &r : p->active) {
+        r.done += 1;
+        r.ctx->iter_count += 1;
+        if (r.done >= r.n_iter) {
+            p->finished[r.id] = r;
+            p->dirty = true;
+        } else {
+            still.push_back(r);
+        }
+    }
+    p->active.swap(still);
+    return LMTOF_OK;
+}
+
+int lmtof_pool_poll(lmtof_pool *p, int64_t id, int *done, float *out, int64_t n, int mem) {
+    if (!p) return LMTOF_EINVAL;
+    p->err.clear();
+    if (!done) return pfail(p, LMTOF_EINVAL, "done pointer is NULL");
+    *done = 0;
+    auto it = p->finished.find(id);
+    if (it == p->finished.end()) {
+        for (auto &r : p->active)
+            if (r.id == id) return LMTOF_OK;
+        return pfail(p, LMTOF_EINVAL, "unknown request id %lld", (long long)id);
+    }
+    lmtof_ctx *c = it->second.ctx;
+    if (out) {
+        int rc = lmtof_read_image(c, out, n, mem);
+        if (rc) return pfail(p, rc, "%s", lmtof_last_error(c));
+    }
+    p->used -= it->second.bytes;
+    lmtof_destroy(c);
+    p->finished.erase(it);
+    *done = 1;
+    return LMTOF_OK;
+}
+
+int lmtof_pool_info(const lmtof_pool *p, int64_t *used, int64_t *budget, int *n_active, int *n_finished) {
+    if (!p) return LMTOF_EINVAL;
+    if (used) *used = p->used;
+    if (budget) *budget = p->budget;
+    if (n_active) *n_active = (int)p->active.size();
+    if (n_finished) *n_finished = (int)p->finished.size();
     return LMTOF_OK;
 }
 

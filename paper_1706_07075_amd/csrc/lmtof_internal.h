@@ -26,6 +26,10 @@ struct Problem {
     float *x;             // image (nx*ny*nz)
     float *b;             // back-projection accumulator, zero between iterations
     const float *s;       // sensitivity
+    float *rw;            // per event of this problem: 1 / f (MLEM) or a back-projection weight
+    const uint32_t *items;// brick item list array (problem-local event indices) the chunks index
+    unsigned long long *tiles;  // 64-bit fixed-point chunk tiles, indexed by tile slot
+    float *wmax;          // per tile slot: largest |w| of the chunk
     int32_t packed;
     int32_t tof;
     int32_t nx, ny, nz;
@@ -74,23 +78,27 @@ inline hipError_t do_launch(const Launch &L, const void *func, dim3 grid, dim3 b
 
 // ---- projector (project.hip)
 int64_t project_chunk_events(int block, int ept);
-// Forward projection per event; mode 0: out = 1 / f (0 if f <= 0) and per-chunk
-// partials (n_eff, sum log f); mode 1: out = f.  out is in stored order.
+// Forward projection per event into P.rw; mode 0: 1 / f (0 if f <= 0) and
+// per-chunk partials (n_eff, sum log f); mode 1: f.
 hipError_t launch_forward(const Launch &L, bool tof, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept,
-                          int mode, float *out, int *part_neff, double *part_ll);
-// Back projection by brick chunks: chunk c = (brick, first item, end item,
-// tile slot); each writes its LDS tile to tiles[slot]; then
-// launch_reduce_tiles sums each brick's slots (brick, first slot, end slot)
-// into b (every voxel of those bricks is written).
-hipError_t launch_back_chunks(const Launch &L, bool tof, const Problem *d_probs, int n_probs, const void *events,
-                              const uint4 *chunks, uint32_t n_chunks, const uint32_t *items, const float *w,
-                              float *tiles);
+                          int mode, int *part_neff, double *part_ll);
+// Back projection by brick chunks.  Brick table entry (global brick id,
+// first tile slot, end tile slot, items in the brick); chunk (brick table
+// index, first item, end item, tile slot) over P.items / P.tiles of the
+// brick's problem with weights P.rw.  launch_chunk_wmax, then
+// launch_back_chunks, then launch_reduce_tiles (which writes every voxel of
+// the listed bricks of P.b).
+hipError_t launch_chunk_wmax(const Launch &L, const Problem *d_probs, int n_probs, const uint4 *chunks,
+                             uint32_t n_chunks, const uint4 *bricks);
+hipError_t launch_back_chunks(const Launch &L, bool tof, const Problem *d_probs, int n_probs, const uint4 *chunks,
+                              uint32_t n_chunks, const uint4 *bricks);
 hipError_t launch_reduce_tiles(const Launch &L, const Problem *d_probs, int n_probs, const uint4 *bricks,
-                               uint32_t n_bricks, const float *tiles);
-// Brick item lists: items == nullptr counts pieces per brick into ctr; else
-// writes stored event indices at ctr[brick]++, never past end[brick].
+                               uint32_t n_bricks);
+// Brick item lists: fill == 0 counts pieces per global brick into ctr; else
+// writes problem-local event indices to P.items at ctr[brick]++, never past
+// end[brick].
 hipError_t launch_brick_items(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept,
-                              uint32_t *ctr, uint32_t *items, const uint32_t *end);
+                              uint32_t *ctr, const uint32_t *end, int fill);
 // part[2c] = voxel pieces visited by chunk c, part[2c+1] = pieces with non-zero weight.
 hipError_t launch_count_pieces(const Launch &L, bool tof, const Problem *d_probs, int n_probs, int64_t n_chunks,
                                int ept, unsigned long long *part);

@@ -329,8 +329,7 @@ __device__ __forceinline__ void stage_lut(float4 *lds, const float4 *src) {
 // of log f); mode 1: out[i] = f_i.  out is indexed by stored event position.
 template <bool TOF>
 __global__ void __launch_bounds__(kForwardBlock) k_forward(const Problem *__restrict__ probs, int n_probs, int ept,
-                                                           int mode, float *__restrict__ out,
-                                                           int *__restrict__ part_neff,
+                                                           int mode, int *__restrict__ part_neff,
                                                            double *__restrict__ part_ll) {
     __shared__ float4 lut[kLutN];
     __shared__ int s_n[kForwardBlock / 64];
@@ -342,6 +341,7 @@ __global__ void __launch_bounds__(kForwardBlock) k_forward(const Problem *__rest
     const Cdf cdf{lut, P.lut_a, P.lut_b};
     const Box B = grid_box(P);
     const float *__restrict__ x = P.x;
+    float *__restrict__ out = P.rw;
     const int64_t base = (c - P.chunk_begin) * (int64_t)blockDim.x * ept;
     int neff = 0;
     float ll = 0.0f;
@@ -357,9 +357,9 @@ __global__ void __launch_bounds__(kForwardBlock) k_forward(const Problem *__rest
             const bool pos = f > 0.0f;
             neff += pos;
             ll += pos ? logf(f) : 0.0f;
-            out[P.ev_offset + i] = pos ? 1.0f / f : 0.0f;
+            out[i] = pos ? 1.0f / f : 0.0f;
         } else {
-            out[P.ev_offset + i] = f;
+            out[i] = f;
         }
     }
     if (mode == 0) {
@@ -384,52 +384,75 @@ __global__ void __launch_bounds__(kForwardBlock) k_forward(const Problem *__rest
     }
 }
 
-// Back projection of one chunk of one brick's item list: sum over the
-// chunk's items of a_ij w_i, written (plain stores) to the chunk's tile
-// slot.  A brick with several chunks has several slots; k_reduce_tiles adds
-// them into b.  No global atomics.
+// Back projection, in three launches over the brick chunks.
 //
 // The LDS accumulation is 64-bit fixed point: FP32 LDS atomic adds run at
-// ~0.2 T/s on this part, 64-bit integer ones at ~2.8 T/s.  Each contribution
-// a w (an FP32 product, 24-bit exact) is scaled by S = 2^e and rounded to an
-// integer; e is chosen from the chunk's item count n, the problem's bound
-// on a and the chunk's max |w| so that n * a_max * w_max * S < 2^62: no sum
-// can overflow.  Integer addition is exact and associative, so the tile does
-// not depend on the order of the items (deterministic), and its rounding
-// (2^-e per contribution) is far below FP32 accumulation error.
+// ~0.2 T/s on this part, 64-bit integer ones at ~2.8 T/s.  A brick's
+// contributions a w (each an FP32 product) are scaled by S = 2^e and
+// rounded to integers, e being chosen per brick from its item count n, the
+// problem's bound a_max on a piece weight and the brick's largest |w|, so
+// that n a_max w_max S < 2^62: no sum can overflow.  Chunk tiles stay 64-bit
+// and are added exactly, so b does not depend on how the brick's items are
+// ordered or cut into chunks: the result is deterministic, and the same
+// for a problem run alone or batched with others.
+//
+// Brick table entry (brick id, first tile slot, end tile slot, items in the
+// brick); chunk (brick table index, first item, end item, tile slot).
+
+// 1. Largest |w| over each chunk's items, per tile slot.
+__global__ void __launch_bounds__(256) k_chunk_wmax(const Problem *__restrict__ probs, int n_probs,
+                                                    const uint4 *__restrict__ chunks,
+                                                    const uint4 *__restrict__ bricks) {
+    __shared__ float s_m[4];
+    const uint4 ch = chunks[blockIdx.x];
+    const uint4 br = bricks[ch.x];
+    const Problem &P = probs[find_brick_problem(probs, n_probs, br.x)];
+    const uint32_t *__restrict__ items = P.items;
+    const float *__restrict__ w = P.rw;
+    float wm = 0.0f;
+    for (uint32_t k = ch.y + threadIdx.x; k < ch.z; k += blockDim.x) wm = fmaxf(wm, fabsf(w[items[k]]));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) wm = fmaxf(wm, __shfl_xor(wm, off, 64));
+    if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = wm;
+    __syncthreads();
+    if (threadIdx.x == 0) P.wmax[ch.w] = fmaxf(fmaxf(s_m[0], s_m[1]), fmaxf(s_m[2], s_m[3]));
+}
+
+// Fixed-point exponent of a brick (same value in every chunk and the reduce).
+__device__ __forceinline__ int brick_exponent(const Problem &P, const uint4 &br, float &wmax) {
+    float wm = 0.0f;
+    for (uint32_t sl = br.y; sl < br.z; ++sl) wm = fmaxf(wm, P.wmax[sl]);
+    wmax = wm;
+    int en, ea, ew;
+    frexpf((float)br.w, &en);
+    frexpf(P.a_max, &ea);
+    frexpf(wm, &ew);
+    return min(max(62 - (en + ea + ew), -126), 126);
+}
+
+// 2. One chunk: sum over its items of round(a_ij w_i 2^e) in an LDS tile,
+//    stored (64-bit) to the chunk's tile slot.
 template <bool TOF>
 __global__ void __launch_bounds__(kBackBlock) k_back_chunks(const Problem *__restrict__ probs, int n_probs,
-                                                            const void *__restrict__ events,
                                                             const uint4 *__restrict__ chunks,
-                                                            const uint32_t *__restrict__ items,
-                                                            const float *__restrict__ w,
-                                                            float *__restrict__ tiles) {
+                                                            const uint4 *__restrict__ bricks) {
     __shared__ unsigned long long tile[kBrickVox];
     __shared__ float4 lut[kLutN];
-    __shared__ float s_wmax[kBackBlock / 64];
-    const uint4 ch = chunks[blockIdx.x];  // (brick, first item, end item, tile slot)
-    const uint32_t bid = ch.x;
+    const uint4 ch = chunks[blockIdx.x];
+    const uint4 br = bricks[ch.x];
+    const uint32_t bid = br.x;
     const Problem P = probs[find_brick_problem(probs, n_probs, bid)];
     const uint32_t bl = bid - (uint32_t)P.brick_base;
     const int bx = (int)(bl % (uint32_t)P.nbx), by = (int)((bl / (uint32_t)P.nbx) % (uint32_t)P.nby),
               bz = (int)(bl / ((uint32_t)P.nbx * (uint32_t)P.nby));
     const Box B = brick_box(P, bx, by, bz);
+    const uint32_t *__restrict__ items = P.items;
+    const float *__restrict__ w = P.rw;
     for (int k = threadIdx.x; k < kBrickVox; k += blockDim.x) tile[k] = 0ull;
     if (TOF) stage_lut(lut, P.lut);
-    // scale from the chunk's largest |w|
-    float wm = 0.0f;
-    for (uint32_t k = ch.y + threadIdx.x; k < ch.z; k += blockDim.x) wm = fmaxf(wm, fabsf(w[items[k]]));
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) wm = fmaxf(wm, __shfl_xor(wm, off, 64));
-    if ((threadIdx.x & 63) == 0) s_wmax[threadIdx.x >> 6] = wm;
     __syncthreads();
-    wm = 0.0f;
-    for (int k = 0; k < kBackBlock / 64; ++k) wm = fmaxf(wm, s_wmax[k]);
-    int en, ea, ew;
-    frexpf((float)(ch.z - ch.y), &en);
-    frexpf(P.a_max, &ea);
-    frexpf(wm, &ew);
-    const int e = min(max(62 - (en + ea + ew), -126), 126);
+    float wm;
+    const int e = brick_exponent(P, br, wm);
     const float S = ldexpf(1.0f, e);
     const Cdf cdf{lut, P.lut_a, P.lut_b};
     if (wm > 0.0f) {
@@ -439,7 +462,7 @@ __global__ void __launch_bounds__(kBackBlock) k_back_chunks(const Problem *__res
             if (ws == 0.0f) continue;
             Ray r;
             RayInv q;
-            if (!make_ray(P, events, (int64_t)i, r, q)) continue;
+            if (!make_ray(P, P.events, (int64_t)i, r, q)) continue;
             float ta, tb;
             clip_to_box(P, r, q, B, ta, tb);
             if (!(ta < tb)) continue;
@@ -449,116 +472,161 @@ __global__ void __launch_bounds__(kBackBlock) k_back_chunks(const Problem *__res
         }
     }
     __syncthreads();
-    const float inv = ldexpf(1.0f, -e);
-    float *__restrict__ dst = tiles + (size_t)ch.w * kBrickVox;
-    for (int k = threadIdx.x; k < kBrickVox; k += blockDim.x) dst[k] = __ll2float_rn((long long)tile[k]) * inv;
+    unsigned long long *__restrict__ dst = P.tiles + (size_t)ch.w * kBrickVox;
+    for (int k = threadIdx.x; k < kBrickVox; k += blockDim.x) dst[k] = tile[k];
 }
 
-// b over one brick = sum of its chunk tiles (slots [first, end)).
+// 3. b over one brick = (exact sum of its chunk tiles) 2^-e.
 __global__ void __launch_bounds__(256) k_reduce_tiles(const Problem *__restrict__ probs, int n_probs,
-                                                      const uint4 *__restrict__ bricks,
-                                                      const float *__restrict__ tiles) {
-    const uint4 br = bricks[blockIdx.x];  // (brick, first slot, end slot, -)
-    const Problem P = probs[find_brick_problem(probs, n_probs, br.x)];
+                                                      const uint4 *__restrict__ bricks) {
+    const uint4 br = bricks[blockIdx.x];
+    const Problem &P = probs[find_brick_problem(probs, n_probs, br.x)];
     const uint32_t bl = br.x - (uint32_t)P.brick_base;
     const int bx = (int)(bl % (uint32_t)P.nbx), by = (int)((bl / (uint32_t)P.nbx) % (uint32_t)P.nby),
               bz = (int)(bl / ((uint32_t)P.nbx * (uint32_t)P.nby));
     const Box B = brick_box(P, bx, by, bz);
+    float wm;
+    const float inv = ldexpf(1.0f, -brick_exponent(P, br, wm));
     float *__restrict__ b = P.b;
+    const unsigned long long *__restrict__ tiles = P.tiles;
     for (int k = threadIdx.x; k < kBrickVox; k += blockDim.x) {
-        float acc = 0.0f;
+        unsigned long long acc = 0ull;
         for (uint32_t sl = br.y; sl < br.z; ++sl) acc += tiles[(size_t)sl * kBrickVox + k];
         const int lx = k % kBrickX, ly = (k / kBrickX) % kBrickY, lz = k / (kBrickX * kBrickY);
         if (lx < B.nx && ly < B.ny && lz < B.nz)
-            b[(B.x0 + lx) + (int64_t)P.nx * ((B.y0 + ly) + (int64_t)P.ny * (B.z0 + lz))] = acc;
+            b[(B.x0 + lx) + (int64_t)P.nx * ((B.y0 + ly) + (int64_t)P.ny * (B.z0 + lz))] =
+                __ll2float_rn((long long)acc) * inv;
     }
 }
 
-// Wave-aggregated counter bump: every emitting lane gets ctr[key] + its rank
-// among the lanes of its wave that emit the same key; one atomic per key per
-// wave.  All lanes of the wave must call it.
-__device__ __forceinline__ uint32_t agg_add(uint32_t *ctr, uint32_t key, bool emit) {
-    const int lane = threadIdx.x & 63;
-    unsigned long long pend = __ballot(emit);
-    uint32_t res = 0;
-    while (pend) {
-        const int leader = __ffsll((long long)pend) - 1;
-        const uint32_t k0 = __shfl(key, leader, 64);
-        const unsigned long long grp = __ballot(emit && key == k0) & pend;
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(ctr + k0, (uint32_t)__popcll(grp));
-        base = __shfl(base, leader, 64);
-        if ((grp >> lane) & 1ull) res = base + (uint32_t)__popcll(grp & ((1ull << lane) - 1ull));
-        pend &= ~grp;
+// Per-block open-addressing table in LDS mapping a brick id to a slot.
+constexpr int kHashSlots = 1024;
+constexpr uint32_t kEmpty = 0xffffffffu;
+
+__device__ __forceinline__ int hash_slot(uint32_t key) { return (int)((key * 2654435761u) >> 22); }
+
+// Slot of key, inserting it if absent; -1 if the table is full.
+__device__ __forceinline__ int hash_insert(uint32_t *keys, uint32_t key) {
+    int h = hash_slot(key);
+    for (int probe = 0; probe < kHashSlots; ++probe) {
+        uint32_t k = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (k == kEmpty) {
+            k = atomicCAS(&keys[h], kEmpty, key);
+            if (k == kEmpty) return h;
+        }
+        if (k == key) return h;
+        h = (h + 1) & (kHashSlots - 1);
     }
-    return res;
+    return -1;
 }
 
-// Brick item lists: walk each event's window through the brick grid (brick
-// faces are voxel planes, same crossing formulas as the voxel walk) and, for
-// every brick crossed over a positive length, bump ctr[brick] (items ==
-// nullptr: counting) or write the event's stored index at ctr[brick]++
-// (filling; end[brick] bounds each list).  The whole wave steps in lockstep
-// so same-brick lanes share one atomic.
+__device__ __forceinline__ int hash_find(const uint32_t *keys, uint32_t key) {
+    int h = hash_slot(key);
+    for (int probe = 0; probe < kHashSlots; ++probe) {
+        const uint32_t k = keys[h];
+        if (k == key) return h;
+        if (k == kEmpty) return -1;
+        h = (h + 1) & (kHashSlots - 1);
+    }
+    return -1;
+}
+
+// Walk one event's window through the brick grid of P and call
+// visit(global brick id) for every brick crossed over a positive length.
+// Brick faces are voxel planes, so this uses the voxel walk's crossing
+// formulas and cuts the window exactly where the brick pieces meet.
+template <class Visit>
+__device__ __forceinline__ void brick_walk(const Problem &P, const Ray &r, const RayInv &q, Visit &&visit) {
+    const int ux1 = q.sx > 0, uy1 = q.sy > 0, uz1 = q.sz > 0;
+    int bx = min(max(voxel_at(r.t0, r.ux, r.jx, r.dx, P.ivx), 0), P.nx - 1) / kBrickX;
+    int by = min(max(voxel_at(r.t0, r.uy, r.jy, r.dy, P.ivy), 0), P.ny - 1) / kBrickY;
+    int bz = min(max(voxel_at(r.t0, r.uz, r.jz, r.dz, P.ivz), 0), P.nz - 1) / kBrickZ;
+    float tnx = q.sx ? plane_rel((bx + ux1) * kBrickX, r.jx, P.vx, r.dx) * q.ix : kInf;
+    float tny = q.sy ? plane_rel((by + uy1) * kBrickY, r.jy, P.vy, r.dy) * q.iy : kInf;
+    float tnz = q.sz ? plane_rel((bz + uz1) * kBrickZ, r.jz, P.vz, r.dz) * q.iz : kInf;
+    float t = r.t0;
+    const int max_steps = P.nbx + P.nby + P.nbz + 2;
+    for (int step = 0; step < max_steps; ++step) {
+        const float tmin = fminf(fminf(tnx, tny), tnz);
+        const float tn = fminf(tmin, r.t1);
+        if (tn > t) visit((uint32_t)P.brick_base + (uint32_t)(bx + P.nbx * (by + P.nby * bz)));
+        if (tmin >= r.t1) break;
+        t = fmaxf(tn, t);
+        if (tnx == tmin) {
+            bx += q.sx;
+            if ((unsigned)bx >= (unsigned)P.nbx) break;
+            tnx = plane_rel((bx + ux1) * kBrickX, r.jx, P.vx, r.dx) * q.ix;
+        } else if (tny == tmin) {
+            by += q.sy;
+            if ((unsigned)by >= (unsigned)P.nby) break;
+            tny = plane_rel((by + uy1) * kBrickY, r.jy, P.vy, r.dy) * q.iy;
+        } else {
+            bz += q.sz;
+            if ((unsigned)bz >= (unsigned)P.nbz) break;
+            tnz = plane_rel((bz + uz1) * kBrickZ, r.jz, P.vz, r.dz) * q.iz;
+        }
+    }
+}
+
+// Brick item lists.  Counting (fill == 0): ctr[brick] += pieces.  Filling:
+// every piece gets a position from ctr[brick]++ (never past end[brick]) and
+// P.items[position] = its problem-local event index.  A block first tallies
+// its pieces per brick in an LDS hash table, then touches each global
+// counter once (bucketed events make whole blocks hit the same few bricks,
+// and same-address global atomics serialise); when filling, the block then
+// re-walks its events and hands out positions from its reserved ranges.
 __global__ void __launch_bounds__(kForwardBlock) k_brick_items(const Problem *__restrict__ probs, int n_probs,
                                                                int ept, uint32_t *__restrict__ ctr,
-                                                               uint32_t *__restrict__ items,
-                                                               const uint32_t *__restrict__ end) {
+                                                               const uint32_t *__restrict__ end, int fill) {
+    __shared__ uint32_t hkey[kHashSlots], hcnt[kHashSlots], hbase[kHashSlots];
+    for (int k = threadIdx.x; k < kHashSlots; k += blockDim.x) {
+        hkey[k] = kEmpty;
+        hcnt[k] = 0;
+    }
+    __syncthreads();
     const int64_t c = blockIdx.x;
     const Problem P = probs[find_problem(probs, n_probs, c)];
     const int64_t base = (c - P.chunk_begin) * (int64_t)blockDim.x * ept;
+    uint32_t *__restrict__ items = const_cast<uint32_t *>(P.items);
     for (int e = 0; e < ept; ++e) {
         const int64_t i = base + (int64_t)e * blockDim.x + threadIdx.x;
         Ray r;
         RayInv q;
-        bool active = i < P.n_events && make_ray(P, P.events, i, r, q);
-        int bx = 0, by = 0, bz = 0, ux1 = 0, uy1 = 0, uz1 = 0;
-        float tnx = kInf, tny = kInf, tnz = kInf, t = 0.0f, t1 = 0.0f;
-        if (active) {
-            ux1 = q.sx > 0;
-            uy1 = q.sy > 0;
-            uz1 = q.sz > 0;
-            const int ix = voxel_at(r.t0, r.ux, r.jx, r.dx, P.ivx);
-            const int iy = voxel_at(r.t0, r.uy, r.jy, r.dy, P.ivy);
-            const int iz = voxel_at(r.t0, r.uz, r.jz, r.dz, P.ivz);
-            bx = min(max(ix, 0), P.nx - 1) / kBrickX;
-            by = min(max(iy, 0), P.ny - 1) / kBrickY;
-            bz = min(max(iz, 0), P.nz - 1) / kBrickZ;
-            tnx = q.sx ? plane_rel((bx + ux1) * kBrickX, r.jx, P.vx, r.dx) * q.ix : kInf;
-            tny = q.sy ? plane_rel((by + uy1) * kBrickY, r.jy, P.vy, r.dy) * q.iy : kInf;
-            tnz = q.sz ? plane_rel((bz + uz1) * kBrickZ, r.jz, P.vz, r.dz) * q.iz : kInf;
-            t = r.t0;
-            t1 = r.t1;
-        }
-        while (__ballot(active)) {
-            const float tmin = fminf(fminf(tnx, tny), tnz);
-            const float tn = fminf(tmin, t1);
-            const bool emit = active && tn > t;
-            const uint32_t key =
-                emit ? (uint32_t)P.brick_base + (uint32_t)(bx + P.nbx * (by + P.nby * bz)) : 0u;
-            const uint32_t pos = agg_add(ctr, key, emit);
-            if (items && emit && pos < end[key]) items[pos] = (uint32_t)(P.ev_offset + i);
-            if (active) {
-                if (tmin >= t1) {
-                    active = false;
-                } else {
-                    t = fmaxf(tn, t);
-                    if (tnx == tmin) {
-                        bx += q.sx;
-                        active = (unsigned)bx < (unsigned)P.nbx;
-                        tnx = plane_rel((bx + ux1) * kBrickX, r.jx, P.vx, r.dx) * q.ix;
-                    } else if (tny == tmin) {
-                        by += q.sy;
-                        active = (unsigned)by < (unsigned)P.nby;
-                        tny = plane_rel((by + uy1) * kBrickY, r.jy, P.vy, r.dy) * q.iy;
-                    } else {
-                        bz += q.sz;
-                        active = (unsigned)bz < (unsigned)P.nbz;
-                        tnz = plane_rel((bz + uz1) * kBrickZ, r.jz, P.vz, r.dz) * q.iz;
-                    }
-                }
+        if (i >= P.n_events || !make_ray(P, P.events, i, r, q)) continue;
+        brick_walk(P, r, q, [&](uint32_t key) {
+            const int h = hash_insert(hkey, key);
+            if (h >= 0) {
+                atomicAdd(&hcnt[h], 1u);
+            } else if (!fill) {
+                atomicAdd(ctr + key, 1u);
+            } else {
+                const uint32_t pos = atomicAdd(ctr + key, 1u);
+                if (pos < end[key]) items[pos] = (uint32_t)i;
             }
+        });
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < kHashSlots; k += blockDim.x) {
+        if (hkey[k] == kEmpty) continue;
+        const uint32_t b = atomicAdd(ctr + hkey[k], hcnt[k]);
+        if (fill) {
+            hbase[k] = b;
+            hcnt[k] = 0;
         }
+    }
+    if (!fill) return;
+    __syncthreads();
+    for (int e = 0; e < ept; ++e) {
+        const int64_t i = base + (int64_t)e * blockDim.x + threadIdx.x;
+        Ray r;
+        RayInv q;
+        if (i >= P.n_events || !make_ray(P, P.events, i, r, q)) continue;
+        brick_walk(P, r, q, [&](uint32_t key) {
+            const int h = hash_find(hkey, key);
+            if (h < 0) return;  // placed directly in the first walk
+            const uint32_t pos = hbase[h] + atomicAdd(&hcnt[h], 1u);
+            if (pos < end[key]) items[pos] = (uint32_t)i;
+        });
     }
 }
 
@@ -610,31 +678,36 @@ __global__ void __launch_bounds__(kForwardBlock) k_count_pieces(const Problem *_
 int64_t project_chunk_events(int block, int ept) { return (int64_t)block * ept; }
 
 hipError_t launch_forward(const Launch &L, bool tof, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept,
-                          int mode, float *out, int *part_neff, double *part_ll) {
-    void *args[] = {&d_probs, &n_probs, &ept, &mode, &out, &part_neff, &part_ll};
+                          int mode, int *part_neff, double *part_ll) {
+    void *args[] = {&d_probs, &n_probs, &ept, &mode, &part_neff, &part_ll};
     const void *fn = tof ? reinterpret_cast<const void *>(&k_forward<true>)
                          : reinterpret_cast<const void *>(&k_forward<false>);
     return do_launch(L, fn, dim3((unsigned)n_chunks), dim3(kForwardBlock), 0, args);
 }
 
-hipError_t launch_back_chunks(const Launch &L, bool tof, const Problem *d_probs, int n_probs, const void *events,
-                              const uint4 *chunks, uint32_t n_chunks, const uint32_t *items, const float *w,
-                              float *tiles) {
-    void *args[] = {&d_probs, &n_probs, &events, &chunks, &items, &w, &tiles};
+hipError_t launch_back_chunks(const Launch &L, bool tof, const Problem *d_probs, int n_probs, const uint4 *chunks,
+                              uint32_t n_chunks, const uint4 *bricks) {
+    void *args[] = {&d_probs, &n_probs, &chunks, &bricks};
     const void *fn = tof ? reinterpret_cast<const void *>(&k_back_chunks<true>)
                          : reinterpret_cast<const void *>(&k_back_chunks<false>);
     return do_launch(L, fn, dim3(n_chunks), dim3(kBackBlock), 0, args);
 }
 
+hipError_t launch_chunk_wmax(const Launch &L, const Problem *d_probs, int n_probs, const uint4 *chunks,
+                             uint32_t n_chunks, const uint4 *bricks) {
+    void *args[] = {&d_probs, &n_probs, &chunks, &bricks};
+    return do_launch(L, reinterpret_cast<const void *>(&k_chunk_wmax), dim3(n_chunks), dim3(256), 0, args);
+}
+
 hipError_t launch_reduce_tiles(const Launch &L, const Problem *d_probs, int n_probs, const uint4 *bricks,
-                               uint32_t n_bricks, const float *tiles) {
-    void *args[] = {&d_probs, &n_probs, &bricks, &tiles};
+                               uint32_t n_bricks) {
+    void *args[] = {&d_probs, &n_probs, &bricks};
     return do_launch(L, reinterpret_cast<const void *>(&k_reduce_tiles), dim3(n_bricks), dim3(256), 0, args);
 }
 
 hipError_t launch_brick_items(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept,
-                              uint32_t *ctr, uint32_t *items, const uint32_t *end) {
-    void *args[] = {&d_probs, &n_probs, &ept, &ctr, &items, &end};
+                              uint32_t *ctr, const uint32_t *end, int fill) {
+    void *args[] = {&d_probs, &n_probs, &ept, &ctr, &end, &fill};
     return do_launch(L, reinterpret_cast<const void *>(&k_brick_items), dim3((unsigned)n_chunks),
                      dim3(kForwardBlock), 0, args);
 }

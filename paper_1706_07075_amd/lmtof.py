@@ -58,7 +58,13 @@ class lmtof_geometry(C.Structure):
 class lmtof_iter_stats(C.Structure):
     _fields_ = [("iter", C.c_int32), ("reserved0", C.c_int32), ("n_eff", C.c_int64), ("sum_sx", C.c_double),
                 ("loglik", C.c_double), ("ms", C.c_float), ("project_ms", C.c_float),
-                ("forward_ms", C.c_float), ("back_ms", C.c_float)]
+                ("forward_ms", C.c_float), ("back_ms", C.c_float), ("back_kernel_ms", C.c_float),
+                ("update_ms", C.c_float)]
+
+
+class lmtof_request(C.Structure):
+    _fields_ = [("geometry", lmtof_geometry), ("events", C.c_void_p), ("n_events", C.c_int64),
+                ("format", C.c_int32), ("mem", C.c_int32), ("n_iter", C.c_int32), ("storage", C.c_int32)]
 
 
 if not os.path.exists(LIB_PATH):
@@ -102,6 +108,14 @@ _sig = {
     "lmtof_region_info": ([_P, C.c_int, C.POINTER(C.c_int32), C.POINTER(_i64)], C.c_int),
     "lmtof_read_region_image": ([_P, C.c_int, _P, _i64, C.c_int], C.c_int),
     "lmtof_clear_regions": ([_P], C.c_int),
+    "lmtof_pool_create": ([C.POINTER(_P), C.c_int, _P, _i64], C.c_int),
+    "lmtof_pool_destroy": ([_P], C.c_int),
+    "lmtof_pool_last_error": ([_P], C.c_char_p),
+    "lmtof_pool_request_bytes": ([C.POINTER(lmtof_request), C.POINTER(_i64)], C.c_int),
+    "lmtof_pool_submit": ([_P, C.POINTER(lmtof_request), C.POINTER(_i64)], C.c_int),
+    "lmtof_pool_step": ([_P, C.POINTER(C.c_int)], C.c_int),
+    "lmtof_pool_poll": ([_P, _i64, C.POINTER(C.c_int), _P, _i64, C.c_int], C.c_int),
+    "lmtof_pool_info": ([_P, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
 }
 for _name, (_args, _res) in _sig.items():
     _f = getattr(_lib, _name)
@@ -256,7 +270,8 @@ def lmtof_iterate(ctx, n_iter: int):
     st = (lmtof_iter_stats * n_iter)()
     _check(_lib.lmtof_iterate(ctx, n_iter, st), ctx)
     return [dict(iter=s.iter, n_eff=s.n_eff, sum_sx=s.sum_sx, loglik=s.loglik, ms=s.ms, project_ms=s.project_ms,
-                 forward_ms=s.forward_ms, back_ms=s.back_ms) for s in st]
+                 forward_ms=s.forward_ms, back_ms=s.back_ms, back_kernel_ms=s.back_kernel_ms,
+                 update_ms=s.update_ms) for s in st]
 
 
 def lmtof_forward_project(ctx, x, n_events: int, out=None):
@@ -310,6 +325,80 @@ def lmtof_read_region_image(ctx, k: int, n: int, out=None):
 
 def lmtof_clear_regions(ctx) -> None:
     _check(_lib.lmtof_clear_regions(ctx), ctx)
+
+
+# ---------------------------------------------------------------- serving
+def lmtof_pool_last_error(pool) -> str:
+    m = _lib.lmtof_pool_last_error(pool)
+    return m.decode() if m else ""
+
+
+def _pcheck(rc: int, pool) -> None:
+    if rc != LMTOF_OK:
+        raise LmtofError(rc, lmtof_pool_last_error(pool))
+
+
+def lmtof_pool_create(hbm_budget_bytes: int, hip_device: int = 0, hip_stream: Optional[int] = None):
+    h = C.c_void_p()
+    rc = _lib.lmtof_pool_create(C.byref(h), hip_device, C.c_void_p(hip_stream) if hip_stream else None,
+                                int(hbm_budget_bytes))
+    _pcheck(rc, None)
+    return h
+
+
+def lmtof_pool_destroy(pool) -> None:
+    _pcheck(_lib.lmtof_pool_destroy(pool), None)
+
+
+def make_request(geometry, ev, n_iter: int, storage: int = 0, fmt: Optional[int] = None):
+    """(lmtof_request, keep-alive) for events ev (NumPy or GPU tensor)."""
+    if fmt is None:
+        fmt = LMTOF_FMT_PACKED16 if "int16" in str(ev.dtype) else LMTOF_FMT_F32X7
+    per = 7 if fmt == LMTOF_FMT_F32X7 else 8
+    p, mem, keep = _in(ev, np.float32 if fmt == LMTOF_FMT_F32X7 else np.int16)
+    q = lmtof_request()
+    q.geometry = geometry if isinstance(geometry, lmtof_geometry) else geometry_struct(geometry)
+    q.events = p
+    q.n_events = int(np.prod(ev.shape)) // per
+    q.format = fmt
+    q.mem = mem
+    q.n_iter = int(n_iter)
+    q.storage = int(storage)
+    return q, keep
+
+
+def lmtof_pool_request_bytes(req) -> int:
+    v = C.c_int64()
+    _pcheck(_lib.lmtof_pool_request_bytes(C.byref(req), C.byref(v)), None)
+    return v.value
+
+
+def lmtof_pool_submit(pool, req) -> int:
+    """Request id; raises LmtofError (code LMTOF_EAGAIN when it does not fit now)."""
+    v = C.c_int64()
+    _pcheck(_lib.lmtof_pool_submit(pool, C.byref(req), C.byref(v)), pool)
+    return v.value
+
+
+def lmtof_pool_step(pool) -> int:
+    n = C.c_int()
+    _pcheck(_lib.lmtof_pool_step(pool, C.byref(n)), pool)
+    return n.value
+
+
+def lmtof_pool_poll(pool, rid: int, n_voxels: int, out=None):
+    """Image (and release) if request rid finished, else None."""
+    o, p, mem = _out(out, n_voxels, np.float32)
+    done = C.c_int()
+    _pcheck(_lib.lmtof_pool_poll(pool, rid, C.byref(done), p, n_voxels, mem), pool)
+    return o if done.value else None
+
+
+def lmtof_pool_info(pool):
+    used, budget = C.c_int64(), C.c_int64()
+    na, nf = C.c_int(), C.c_int()
+    _pcheck(_lib.lmtof_pool_info(pool, C.byref(used), C.byref(budget), C.byref(na), C.byref(nf)), pool)
+    return dict(used=used.value, budget=budget.value, active=na.value, finished=nf.value)
 
 
 def exported_symbols():
