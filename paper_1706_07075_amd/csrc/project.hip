@@ -45,45 +45,69 @@ constexpr float kInf = __builtin_huge_valf();
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
+// Device-memory views: pointers read from the problem table are generic;
+// casting them to the global address space lets loads and stores use the
+// global (not flat) instructions.
+template <class T>
+using gptr = __attribute__((address_space(1))) T *;
+template <class T>
+__device__ __forceinline__ gptr<T> global(T *p) {
+    return (gptr<T>)p;
+}
+
 // A ray r(t) = mu + t u, with mu held relative to an anchor voxel plane:
-// mu_a = o_a + j_a v_a + d_a, |d_a| <~ v_a.  Plane k on axis a then lies at
-// (k - j_a) v_a - d_a from mu, which FP32 resolves to ~1e-6 mm whatever the
-// absolute position (1.2 m from the centre an absolute FP32 coordinate
-// carries ~6e-5 mm of rounding).
+// mu_a = o_a + j_a v_a + d_a, |d_a| <~ v_a.  Plane k on axis a is crossed at
+//   T_a(k) = (k - j_a) A_a + B_a,  A_a = v_a / u_a,  B_a = -d_a / u_a
+// (one FMA on an exactly represented small integer), which FP32 resolves to
+// ~1e-6 mm of the TOF window whatever the absolute position (1.2 m from the
+// centre an absolute FP32 coordinate carries ~6e-5 mm of rounding).  Every
+// kernel gets every crossing from this one formula, so a piece boundary on
+// a brick face is bitwise the same on both sides of it.  An axis with
+// u_a = 0 is never crossed: A_a = 0, B_a = +inf.
 struct Ray {
     int jx, jy, jz;    // anchor plane indices
     float dx, dy, dz;  // mu - anchor plane (mm)
     float ux, uy, uz;  // unit direction P1 -> P2
+    float ax, ay, az;  // A: t per plane
+    float bx, by, bz;  // B: crossing time of the anchor plane
     float t0, t1;      // window (mm from mu)
 };
 
+__device__ __forceinline__ float cross(int k, int j, float a, float b) { return fmaf((float)(k - j), a, b); }
+
 // Decode stored event i (plain: 2 x float4; packed: int16 x 6 at 0.1 mm +
 // binary16 dt).  Endpoints come as double-float pairs p = h + l: plain
-// coordinates are exact FP32 (l = 0); a packed coordinate q * 0.1 mm is not,
-// so l holds the FMA residual of q * 0.1f plus q * (0.1 - 0.1f), keeping the
-// decoded endpoint exact to ~1e-15 relative (an FP32 decode alone would be
-// off by up to 6e-5 mm 1.2 m from the centre).
+// coordinates are exact FP32 (l = 0).  A packed coordinate q / 10 mm is
+// not: h = fl(q * 0.1f) and l = (q - 10 h) / 10, where q - 10 h is exact
+// (one FMA), so h + l is q / 10 to ~1e-8 ulp(h), and exactly q / 10
+// whenever that is an FP32 number (a coordinate on a voxel plane stays on
+// it; an FP32 decode alone would be off by up to 6e-5 mm 1.2 m from the
+// centre).
 struct EventGeom {
     float h[6], l[6];  // P1.xyz, P2.xyz
     float dt;
 };
 
-__device__ __forceinline__ void load_event(const void *events, int packed, int64_t i, EventGeom &ev) {
-    if (!packed) {
-        const f32x4 *e = reinterpret_cast<const f32x4 *>(events) + 2 * i;
+template <bool PACKED>
+__device__ __forceinline__ void load_event(const void *events, int64_t i, EventGeom &ev) {
+    // No contraction: h must be the rounded product that l corrects, also
+    // where h later feeds an addition (a fused q * 0.1f + h' would double
+    // count the residual held in l).
+#pragma clang fp contract(off)
+    if (!PACKED) {
+        const gptr<const f32x4> e = global(reinterpret_cast<const f32x4 *>(events)) + 2 * i;
         const f32x4 a = __builtin_nontemporal_load(e), b = __builtin_nontemporal_load(e + 1);
         ev.h[0] = a[0]; ev.h[1] = a[1]; ev.h[2] = a[2]; ev.h[3] = a[3];
         ev.h[4] = b[0]; ev.h[5] = b[1]; ev.dt = b[2];
 #pragma unroll
         for (int k = 0; k < 6; ++k) ev.l[k] = 0.0f;
     } else {
-        const u32x4 w = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(events) + i);
-        const float tenth = 0.1f, tenth_lo = -1.4901161e-09f;  // 0.1 - 0.1f
+        const u32x4 w = __builtin_nontemporal_load(global(reinterpret_cast<const u32x4 *>(events)) + i);
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             const float q = (float)(int16_t)((w[k >> 1] >> (16 * (k & 1))) & 0xffffu);
-            ev.h[k] = q * tenth;
-            ev.l[k] = fmaf(q, tenth, -ev.h[k]) + q * tenth_lo;
+            ev.h[k] = q * 0.1f;
+            ev.l[k] = fmaf(-10.0f, ev.h[k], q) * 0.1f;  // (q - 10 h) exactly, over 10
         }
         __half_raw hr;
         hr.x = (unsigned short)(w[3] & 0xffffu);
@@ -92,44 +116,46 @@ __device__ __forceinline__ void load_event(const void *events, int packed, int64
 }
 
 // Error-free transformations (Knuth's TwoSum; TwoProd with an FMA): a + b =
-// s + e and a * b = p + e exactly in FP32.
+// s + e and a * b = p + e exactly in FP32.  Contraction is off so that no
+// operation here is fused with the product that formed an input.
 __device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
+#pragma clang fp contract(off)
     s = a + b;
     const float bb = s - a;
     e = (a - (s - bb)) + (b - bb);
 }
 __device__ __forceinline__ void two_prod(float a, float b, float &p, float &e) {
+#pragma clang fp contract(off)
     p = a * b;
     e = fmaf(a, b, -p);
 }
-
-struct RayInv {
-    float ix, iy, iz;  // 1 / u (0 when u = 0)
-    int sx, sy, sz;    // sign of u
-};
 
 // Offset from mu of plane k on an axis with anchor j, offset d, voxel size v.
 __device__ __forceinline__ float plane_rel(int k, int j, float v, float d) { return fmaf((float)(k - j), v, -d); }
 
 // Clip the line to planes [klo, khi) of one axis.
-__device__ __forceinline__ void slab(int klo, int khi, int j, float v, float d, float iu, int su, float &t0,
+__device__ __forceinline__ void slab(int klo, int khi, int j, float v, float d, float u, float a, float b, float &t0,
                                      float &t1) {
-    const float lo = plane_rel(klo, j, v, d), hi = plane_rel(khi, j, v, d);
-    if (su) {
-        const float a = lo * iu, b = hi * iu;
-        t0 = fmaxf(t0, fminf(a, b));
-        t1 = fminf(t1, fmaxf(a, b));
-    } else if (!(lo <= 0.0f && hi > 0.0f)) {
+    if (u != 0.0f) {
+        const float lo = cross(klo, j, a, b), hi = cross(khi, j, a, b);
+        t0 = fmaxf(t0, fminf(lo, hi));
+        t1 = fminf(t1, fmaxf(lo, hi));
+    } else if (!(plane_rel(klo, j, v, d) <= 0.0f && plane_rel(khi, j, v, d) > 0.0f)) {
         t0 = kInf;
         t1 = -kInf;
     }
 }
 
-// Anchor one axis: mu = (mh + ml) = o + j v + d.
-__device__ __forceinline__ void anchor(float mh, float ml, float o, float v, float iv, int &j, float &d) {
+// Anchor one axis: mu = (mh + ml) = o + j v + d; crossing coefficients A, B.
+__device__ __forceinline__ void anchor(float mh, float ml, float o, float v, float iv, float u, int &j, float &d,
+                                       float &a, float &b) {
+#pragma clang fp contract(off)
     j = (int)rintf((mh - o) * iv);
     const float q = fmaf((float)j, v, o);
     d = (mh - q) + ml;
+    const float iu = __builtin_amdgcn_rcpf(u);
+    a = u != 0.0f ? v * iu : 0.0f;
+    b = u != 0.0f ? -d * iu : kInf;
 }
 
 // Event geometry: direction, anchored TOF centre and window (clipped to the
@@ -137,42 +163,40 @@ __device__ __forceinline__ void anchor(float mh, float ml, float o, float v, flo
 // The midpoint and the TOF shift along the endpoint difference are formed
 // exactly (double-float); the shift is scaled along d = P2 - P1 itself, so
 // rounding of the scale factor only moves mu along the line.
-__device__ __forceinline__ bool make_ray(const Problem &P, const void *events, int64_t i, Ray &r, RayInv &q) {
+template <bool PACKED>
+__device__ __forceinline__ bool make_ray(const Problem &P, int64_t i, Ray &r) {
+    // Contraction off: every kernel that inlines this must derive bitwise
+    // the same ray from an event (brick lists, forward and back passes).
+#pragma clang fp contract(off)
     EventGeom ev;
-    load_event(events, P.packed, i, ev);
+    load_event<PACKED>(P.events, i, ev);
     float dh[3], dl[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         two_sum(ev.h[3 + k], -ev.h[k], dh[k], dl[k]);
         dl[k] += ev.l[3 + k] - ev.l[k];
     }
-    const float iL = 1.0f / sqrtf(dh[0] * dh[0] + dh[1] * dh[1] + dh[2] * dh[2]);
+    const float iL = __builtin_amdgcn_rsqf(dh[0] * dh[0] + dh[1] * dh[1] + dh[2] * dh[2]);
     r.ux = dh[0] * iL;
     r.uy = dh[1] * iL;
     r.uz = dh[2] * iL;
     const float kappa = P.tof ? P.half_c * ev.dt * iL : 0.0f;  // mu = (P1 + P2) / 2 + kappa (P2 - P1)
-    auto centre = [&](int k, float o, float v, float iv, int &j, float &d) {
+    auto centre = [&](int k, float o, float v, float iv, float u, int &j, float &d, float &a, float &b) {
         float sh, se, ph, pe, mh, me;
         two_sum(ev.h[k], ev.h[3 + k], sh, se);
         se += ev.l[k] + ev.l[3 + k];
         two_prod(kappa, dh[k], ph, pe);
         two_sum(0.5f * sh, ph, mh, me);
         const float ml = me + (0.5f * se + fmaf(kappa, dl[k], pe));
-        anchor(mh, ml, o, v, iv, j, d);
+        anchor(mh, ml, o, v, iv, u, j, d, a, b);
     };
-    centre(0, P.ox, P.vx, P.ivx, r.jx, r.dx);
-    centre(1, P.oy, P.vy, P.ivy, r.jy, r.dy);
-    centre(2, P.oz, P.vz, P.ivz, r.jz, r.dz);
-    q.sx = (r.ux > 0.0f) - (r.ux < 0.0f);
-    q.sy = (r.uy > 0.0f) - (r.uy < 0.0f);
-    q.sz = (r.uz > 0.0f) - (r.uz < 0.0f);
-    q.ix = q.sx ? 1.0f / r.ux : 0.0f;
-    q.iy = q.sy ? 1.0f / r.uy : 0.0f;
-    q.iz = q.sz ? 1.0f / r.uz : 0.0f;
+    centre(0, P.ox, P.vx, P.ivx, r.ux, r.jx, r.dx, r.ax, r.bx);
+    centre(1, P.oy, P.vy, P.ivy, r.uy, r.jy, r.dy, r.ay, r.by);
+    centre(2, P.oz, P.vz, P.ivz, r.uz, r.jz, r.dz, r.az, r.bz);
     float t0 = -kInf, t1 = kInf;
-    slab(0, P.nx, r.jx, P.vx, r.dx, q.ix, q.sx, t0, t1);
-    slab(0, P.ny, r.jy, P.vy, r.dy, q.iy, q.sy, t0, t1);
-    slab(0, P.nz, r.jz, P.vz, r.dz, q.iz, q.sz, t0, t1);
+    slab(0, P.nx, r.jx, P.vx, r.dx, r.ux, r.ax, r.bx, t0, t1);
+    slab(0, P.ny, r.jy, P.vy, r.dy, r.uy, r.ay, r.by, t0, t1);
+    slab(0, P.nz, r.jz, P.vz, r.dz, r.uz, r.az, r.bz, t0, t1);
     if (P.tof) {
         t0 = fmaxf(t0, -P.k_sigma);
         t1 = fminf(t1, P.k_sigma);
@@ -184,6 +208,7 @@ __device__ __forceinline__ bool make_ray(const Problem &P, const void *events, i
 
 // Voxel index along one axis at parameter t.
 __device__ __forceinline__ int voxel_at(float t, float u, int j, float d, float iv) {
+#pragma clang fp contract(off)
     return j + (int)floorf(fmaf(t, u, d) * iv);
 }
 
@@ -194,7 +219,7 @@ struct Cdf {
     float a, b;
     __device__ __forceinline__ float operator()(float t) const {
         const float pos = fmaf(t, a, b);
-        const float kf = fminf(fmaxf(rintf(pos), 0.0f), (float)(kLutN - 1));
+        const float kf = __builtin_amdgcn_fmed3f(rintf(pos), 0.0f, (float)(kLutN - 1));
         const float dp = pos - kf;
         const float4 e = tab[(int)kf];
         return fmaf(dp, fmaf(dp, e.z, e.y), e.x);
@@ -209,33 +234,69 @@ struct Box {
     int sy, sz;      // strides of the reported index
 };
 
-// Walk the voxels of ray r between ta and tb (already inside the box) and
-// call visit(j, a) for every piece; j is box-local.  A plane tie gives a
-// zero-length piece (a = 0).
+// Voxel-by-voxel traversal of a ray inside a box, without divergent
+// branches: each step advances the axis whose next plane is crossed first
+// (ties go x, then y, then z; the tied axes follow with zero-length pieces).
+// Crossing times come from the plane index (never by adding up steps).
+struct Stepper {
+    float kx, ky, kz;  // next plane on each axis, minus the anchor index
+    float tx, ty, tz;  // its crossing time
+    float sx, sy, sz;  // +-1: plane index step
+    int j;             // current voxel, box-local index
+    int djx, djy, djz; // index step per axis
+    int max_steps;
+
+    // Start in the voxel holding r(ta), clamped into B.
+    __device__ __forceinline__ Stepper(const Problem &P, const Ray &r, float ta, const Box &B) {
+        int ix = min(max(voxel_at(ta, r.ux, r.jx, r.dx, P.ivx), B.x0), B.x0 + B.nx - 1);
+        int iy = min(max(voxel_at(ta, r.uy, r.jy, r.dy, P.ivy), B.y0), B.y0 + B.ny - 1);
+        int iz = min(max(voxel_at(ta, r.uz, r.jz, r.dz, P.ivz), B.z0), B.z0 + B.nz - 1);
+        const bool px = r.ux > 0.0f, py = r.uy > 0.0f, pz = r.uz > 0.0f;
+        sx = px ? 1.0f : -1.0f;
+        sy = py ? 1.0f : -1.0f;
+        sz = pz ? 1.0f : -1.0f;
+        kx = (float)(ix + px - r.jx);
+        ky = (float)(iy + py - r.jy);
+        kz = (float)(iz + pz - r.jz);
+        tx = fmaf(kx, r.ax, r.bx);
+        ty = fmaf(ky, r.ay, r.by);
+        tz = fmaf(kz, r.az, r.bz);
+        j = (ix - B.x0) + B.sy * (iy - B.y0) + B.sz * (iz - B.z0);
+        djx = px ? 1 : -1;
+        djy = py ? B.sy : -B.sy;
+        djz = pz ? B.sz : -B.sz;
+        max_steps = B.nx + B.ny + B.nz + 2;
+    }
+    __device__ __forceinline__ float next() const { return fminf(fminf(tx, ty), tz); }
+    __device__ __forceinline__ void advance(const Ray &r, float tmin) {
+        const bool mx = tx == tmin;
+        const bool my = !mx && ty == tmin;
+        const bool mz = !mx && !my;
+        kx += mx ? sx : 0.0f;
+        ky += my ? sy : 0.0f;
+        kz += mz ? sz : 0.0f;
+        tx = fmaf(kx, r.ax, r.bx);
+        ty = fmaf(ky, r.ay, r.by);
+        tz = fmaf(kz, r.az, r.bz);
+        // (a sum of masked terms: a select between two members would be
+        // folded into a load through a selected address, off registers)
+        j += (mx ? djx : 0) + (my ? djy : 0) + (mz ? djz : 0);
+    }
+};
+
+// Walk the voxels of ray r between ta and tb (already inside box B) and call
+// visit(j, a) for every piece, j box-local.  A plane tie gives a
+// zero-length piece (a = 0).  The piece [t, t'] ends at the next crossing
+// clamped into [t, tb].
 template <bool TOF, class Visit>
-__device__ __forceinline__ void walk(const Problem &P, const Ray &r, const RayInv &q, float ta, float tb,
-                                     const Box &B, const Cdf &cdf, Visit &&visit) {
-    int ix = voxel_at(ta, r.ux, r.jx, r.dx, P.ivx);
-    int iy = voxel_at(ta, r.uy, r.jy, r.dy, P.ivy);
-    int iz = voxel_at(ta, r.uz, r.jz, r.dz, P.ivz);
-    ix = min(max(ix, B.x0), B.x0 + B.nx - 1);
-    iy = min(max(iy, B.y0), B.y0 + B.ny - 1);
-    iz = min(max(iz, B.z0), B.z0 + B.nz - 1);
-    // next plane on each axis, from its global index
-    const int ux1 = q.sx > 0, uy1 = q.sy > 0, uz1 = q.sz > 0;
-    float tnx = q.sx ? plane_rel(ix + ux1, r.jx, P.vx, r.dx) * q.ix : kInf;
-    float tny = q.sy ? plane_rel(iy + uy1, r.jy, P.vy, r.dy) * q.iy : kInf;
-    float tnz = q.sz ? plane_rel(iz + uz1, r.jz, P.vz, r.dz) * q.iz : kInf;
-    int lx = ix - B.x0, ly = iy - B.y0, lz = iz - B.z0;
-    int j = lx + B.sy * ly + B.sz * lz;
-    const int djy = q.sy * B.sy, djz = q.sz * B.sz;
+__device__ __forceinline__ void walk(const Problem &P, const Ray &r, float ta, float tb, const Box &B,
+                                     const Cdf &cdf, Visit &&visit) {
+    Stepper s(P, r, ta, B);
     float t = ta;
     float c = TOF ? cdf(ta) : 0.0f;
-    const int max_steps = B.nx + B.ny + B.nz + 2;
-    for (int step = 0; step < max_steps; ++step) {
-        const float tmin = fminf(fminf(tnx, tny), tnz);
-        const bool last = tmin >= tb;
-        const float tn = fmaxf(fminf(tmin, tb), t);
+    for (int step = 0; step < s.max_steps; ++step) {
+        const float tmin = s.next();
+        const float tn = __builtin_amdgcn_fmed3f(tmin, t, tb);
         float a;
         if (TOF) {
             const float cn = cdf(tn);
@@ -244,25 +305,10 @@ __device__ __forceinline__ void walk(const Problem &P, const Ray &r, const RayIn
         } else {
             a = tn - t;
         }
-        visit(j, a);
-        if (last) break;
         t = tn;
-        if (tnx == tmin) {
-            lx += q.sx;
-            if ((unsigned)lx >= (unsigned)B.nx) break;
-            j += q.sx;
-            tnx = plane_rel(lx + B.x0 + ux1, r.jx, P.vx, r.dx) * q.ix;
-        } else if (tny == tmin) {
-            ly += q.sy;
-            if ((unsigned)ly >= (unsigned)B.ny) break;
-            j += djy;
-            tny = plane_rel(ly + B.y0 + uy1, r.jy, P.vy, r.dy) * q.iy;
-        } else {
-            lz += q.sz;
-            if ((unsigned)lz >= (unsigned)B.nz) break;
-            j += djz;
-            tnz = plane_rel(lz + B.z0 + uz1, r.jz, P.vz, r.dz) * q.iz;
-        }
+        visit(s.j, a);
+        if (tmin >= tb) break;
+        s.advance(r, tmin);
     }
 }
 
@@ -291,14 +337,13 @@ __device__ __forceinline__ Box brick_box(const Problem &P, int bx, int by, int b
     return B;
 }
 
-// Part of the window inside box B (same plane formulas as the walk).
-__device__ __forceinline__ void clip_to_box(const Problem &P, const Ray &r, const RayInv &q, const Box &B,
-                                            float &ta, float &tb) {
+// Part of the window inside box B (same crossing formula as the walk).
+__device__ __forceinline__ void clip_to_box(const Problem &P, const Ray &r, const Box &B, float &ta, float &tb) {
     ta = r.t0;
     tb = r.t1;
-    slab(B.x0, B.x0 + B.nx, r.jx, P.vx, r.dx, q.ix, q.sx, ta, tb);
-    slab(B.y0, B.y0 + B.ny, r.jy, P.vy, r.dy, q.iy, q.sy, ta, tb);
-    slab(B.z0, B.z0 + B.nz, r.jz, P.vz, r.dz, q.iz, q.sz, ta, tb);
+    slab(B.x0, B.x0 + B.nx, r.jx, P.vx, r.dx, r.ux, r.ax, r.bx, ta, tb);
+    slab(B.y0, B.y0 + B.ny, r.jy, P.vy, r.dy, r.uy, r.ay, r.by, ta, tb);
+    slab(B.z0, B.z0 + B.nz, r.jz, P.vz, r.dz, r.uz, r.az, r.bz, ta, tb);
 }
 
 template <class T>
@@ -324,9 +369,64 @@ __device__ __forceinline__ void stage_lut(float4 *lds, const float4 *src) {
     for (int k = threadIdx.x; k < kLutN; k += blockDim.x) lds[k] = src[k];
 }
 
+// f_i = sum_j a_ij x_j over the window of ray r.  The image value of the
+// next voxel is fetched one piece ahead, so its latency overlaps the weight
+// computation of the current piece.
+template <bool TOF>
+__device__ __forceinline__ float forward_ray(const Problem &P, const Ray &r, const Box &B, const Cdf &cdf,
+                                             gptr<const float> x, uint32_t last_voxel) {
+    Stepper s(P, r, r.t0, B);
+    const float tb = r.t1;
+    float t = r.t0;
+    float c = TOF ? cdf(t) : 0.0f;
+    float f = 0.0f;
+    float xj = x[min((uint32_t)s.j, last_voxel)];
+    for (int step = 0; step < s.max_steps; ++step) {
+        const float tmin = s.next();
+        const float tn = __builtin_amdgcn_fmed3f(tmin, t, tb);
+        float a;
+        if (TOF) {
+            const float cn = cdf(tn);
+            a = cn - c;
+            c = cn;
+        } else {
+            a = tn - t;
+        }
+        t = tn;
+        f = fmaf(a, xj, f);
+        if (tmin >= tb) break;
+        s.advance(r, tmin);
+        xj = x[min((uint32_t)s.j, last_voxel)];
+    }
+    return f;
+}
+
 // Forward projection of one chunk of events.  mode 0 (MLEM): out[i] =
 // 1 / f_i (0 if f_i <= 0) plus per-chunk partials (events with f > 0, sum
 // of log f); mode 1: out[i] = f_i.  out is indexed by stored event position.
+template <bool TOF, bool PACKED>
+__device__ __forceinline__ void forward_chunk(const Problem &P, int64_t base, int ept, int mode, const Cdf &cdf,
+                                              int &neff, float &ll) {
+    const Box B = grid_box(P);
+    const gptr<const float> x = global(P.x);
+    const gptr<float> out = global(P.rw);
+    const uint32_t last_voxel = (uint32_t)P.nx * (uint32_t)P.ny * (uint32_t)P.nz - 1u;
+    for (int e = 0; e < ept; ++e) {
+        const int64_t i = base + (int64_t)e * blockDim.x + threadIdx.x;
+        if (i >= P.n_events) break;
+        Ray r;
+        const float f = make_ray<PACKED>(P, i, r) ? forward_ray<TOF>(P, r, B, cdf, x, last_voxel) : 0.0f;
+        if (mode == 0) {
+            const bool pos = f > 0.0f;
+            neff += pos;
+            ll += pos ? logf(f) : 0.0f;
+            out[i] = pos ? 1.0f / f : 0.0f;
+        } else {
+            out[i] = f;
+        }
+    }
+}
+
 template <bool TOF>
 __global__ void __launch_bounds__(kForwardBlock) k_forward(const Problem *__restrict__ probs, int n_probs, int ept,
                                                            int mode, int *__restrict__ part_neff,
@@ -339,29 +439,13 @@ __global__ void __launch_bounds__(kForwardBlock) k_forward(const Problem *__rest
     if (TOF) stage_lut(lut, P.lut);
     __syncthreads();
     const Cdf cdf{lut, P.lut_a, P.lut_b};
-    const Box B = grid_box(P);
-    const float *__restrict__ x = P.x;
-    float *__restrict__ out = P.rw;
     const int64_t base = (c - P.chunk_begin) * (int64_t)blockDim.x * ept;
     int neff = 0;
     float ll = 0.0f;
-    for (int e = 0; e < ept; ++e) {
-        const int64_t i = base + (int64_t)e * blockDim.x + threadIdx.x;
-        if (i >= P.n_events) break;
-        Ray r;
-        RayInv q;
-        float f = 0.0f;
-        if (make_ray(P, P.events, i, r, q))
-            walk<TOF>(P, r, q, r.t0, r.t1, B, cdf, [&](int j, float a) { f = fmaf(a, x[j], f); });
-        if (mode == 0) {
-            const bool pos = f > 0.0f;
-            neff += pos;
-            ll += pos ? logf(f) : 0.0f;
-            out[i] = pos ? 1.0f / f : 0.0f;
-        } else {
-            out[i] = f;
-        }
-    }
+    if (P.packed)
+        forward_chunk<TOF, true>(P, base, ept, mode, cdf, neff, ll);
+    else
+        forward_chunk<TOF, false>(P, base, ept, mode, cdf, neff, ll);
     if (mode == 0) {
         const int wn = wave_sum(neff);
         const double wl = wave_sum((double)ll);
@@ -430,6 +514,49 @@ __device__ __forceinline__ int brick_exponent(const Problem &P, const uint4 &br,
     return min(max(62 - (en + ea + ew), -126), 126);
 }
 
+// round(v) as a 64-bit two's-complement integer, for 0 <= v < 2^62: the
+// high word is floor(v 2^-32); the low word v - hi 2^32 is exact in FP32
+// (it is the low part of v's significand), then rounded.
+__device__ __forceinline__ unsigned long long fixed_nonneg(float v) {
+    const float hi = floorf(v * 0x1p-32f);
+    const float lo = rintf(fmaf(hi, -0x1p32f, v));
+    return ((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+// One item's pieces in brick box B, added to the tile as round(a |ws|),
+// subtracted when ws < 0.  A weight a is clamped at 0 (the interpolated
+// CDF may dip by ~1e-10 between nodes).
+template <bool TOF, bool PACKED>
+__device__ __forceinline__ void back_item(const Problem &P, uint32_t i, float ws, const Box &B, const Cdf &cdf,
+                                          unsigned long long *tile) {
+    Ray r;
+    if (!make_ray<PACKED>(P, (int64_t)i, r)) return;
+    float ta, tb;
+    clip_to_box(P, r, B, ta, tb);
+    if (!(ta < tb)) return;
+    if (ws > 0.0f) {
+        walk<TOF>(P, r, ta, tb, B, cdf, [&](int j, float a) {
+            atomicAdd(&tile[j & (kBrickVox - 1)], fixed_nonneg(fmaxf(a, 0.0f) * ws));
+        });
+    } else {
+        walk<TOF>(P, r, ta, tb, B, cdf, [&](int j, float a) {
+            atomicSub(&tile[j & (kBrickVox - 1)], fixed_nonneg(fmaxf(a, 0.0f) * -ws));
+        });
+    }
+}
+
+template <bool TOF, bool PACKED>
+__device__ __forceinline__ void back_chunk_items(const Problem &P, const uint4 &ch, float S, const Box &B,
+                                                 const Cdf &cdf, unsigned long long *tile) {
+    const gptr<const uint32_t> items = global(P.items);
+    const gptr<const float> w = global(P.rw);
+    for (uint32_t k = ch.y + threadIdx.x; k < ch.z; k += blockDim.x) {
+        const uint32_t i = items[k];
+        const float ws = w[i] * S;
+        if (ws != 0.0f) back_item<TOF, PACKED>(P, i, ws, B, cdf, tile);
+    }
+}
+
 // 2. One chunk: sum over its items of round(a_ij w_i 2^e) in an LDS tile,
 //    stored (64-bit) to the chunk's tile slot.
 template <bool TOF>
@@ -446,8 +573,6 @@ __global__ void __launch_bounds__(kBackBlock) k_back_chunks(const Problem *__res
     const int bx = (int)(bl % (uint32_t)P.nbx), by = (int)((bl / (uint32_t)P.nbx) % (uint32_t)P.nby),
               bz = (int)(bl / ((uint32_t)P.nbx * (uint32_t)P.nby));
     const Box B = brick_box(P, bx, by, bz);
-    const uint32_t *__restrict__ items = P.items;
-    const float *__restrict__ w = P.rw;
     for (int k = threadIdx.x; k < kBrickVox; k += blockDim.x) tile[k] = 0ull;
     if (TOF) stage_lut(lut, P.lut);
     __syncthreads();
@@ -456,23 +581,13 @@ __global__ void __launch_bounds__(kBackBlock) k_back_chunks(const Problem *__res
     const float S = ldexpf(1.0f, e);
     const Cdf cdf{lut, P.lut_a, P.lut_b};
     if (wm > 0.0f) {
-        for (uint32_t k = ch.y + threadIdx.x; k < ch.z; k += blockDim.x) {
-            const uint32_t i = items[k];
-            const float ws = w[i] * S;
-            if (ws == 0.0f) continue;
-            Ray r;
-            RayInv q;
-            if (!make_ray(P, P.events, (int64_t)i, r, q)) continue;
-            float ta, tb;
-            clip_to_box(P, r, q, B, ta, tb);
-            if (!(ta < tb)) continue;
-            walk<TOF>(P, r, q, ta, tb, B, cdf, [&](int j, float a) {
-                if (a != 0.0f) atomicAdd(&tile[j], (unsigned long long)__float2ll_rn(a * ws));
-            });
-        }
+        if (P.packed)
+            back_chunk_items<TOF, true>(P, ch, S, B, cdf, tile);
+        else
+            back_chunk_items<TOF, false>(P, ch, S, B, cdf, tile);
     }
     __syncthreads();
-    unsigned long long *__restrict__ dst = P.tiles + (size_t)ch.w * kBrickVox;
+    const gptr<unsigned long long> dst = global(P.tiles) + (size_t)ch.w * kBrickVox;
     for (int k = threadIdx.x; k < kBrickVox; k += blockDim.x) dst[k] = tile[k];
 }
 
@@ -536,14 +651,15 @@ __device__ __forceinline__ int hash_find(const uint32_t *keys, uint32_t key) {
 // Brick faces are voxel planes, so this uses the voxel walk's crossing
 // formulas and cuts the window exactly where the brick pieces meet.
 template <class Visit>
-__device__ __forceinline__ void brick_walk(const Problem &P, const Ray &r, const RayInv &q, Visit &&visit) {
-    const int ux1 = q.sx > 0, uy1 = q.sy > 0, uz1 = q.sz > 0;
+__device__ __forceinline__ void brick_walk(const Problem &P, const Ray &r, Visit &&visit) {
+    const bool px = r.ux > 0.0f, py = r.uy > 0.0f, pz = r.uz > 0.0f;
     int bx = min(max(voxel_at(r.t0, r.ux, r.jx, r.dx, P.ivx), 0), P.nx - 1) / kBrickX;
     int by = min(max(voxel_at(r.t0, r.uy, r.jy, r.dy, P.ivy), 0), P.ny - 1) / kBrickY;
     int bz = min(max(voxel_at(r.t0, r.uz, r.jz, r.dz, P.ivz), 0), P.nz - 1) / kBrickZ;
-    float tnx = q.sx ? plane_rel((bx + ux1) * kBrickX, r.jx, P.vx, r.dx) * q.ix : kInf;
-    float tny = q.sy ? plane_rel((by + uy1) * kBrickY, r.jy, P.vy, r.dy) * q.iy : kInf;
-    float tnz = q.sz ? plane_rel((bz + uz1) * kBrickZ, r.jz, P.vz, r.dz) * q.iz : kInf;
+    const int sx = px ? 1 : -1, sy = py ? 1 : -1, sz = pz ? 1 : -1;
+    float tnx = cross((bx + px) * kBrickX, r.jx, r.ax, r.bx);
+    float tny = cross((by + py) * kBrickY, r.jy, r.ay, r.by);
+    float tnz = cross((bz + pz) * kBrickZ, r.jz, r.az, r.bz);
     float t = r.t0;
     const int max_steps = P.nbx + P.nby + P.nbz + 2;
     for (int step = 0; step < max_steps; ++step) {
@@ -553,17 +669,17 @@ __device__ __forceinline__ void brick_walk(const Problem &P, const Ray &r, const
         if (tmin >= r.t1) break;
         t = fmaxf(tn, t);
         if (tnx == tmin) {
-            bx += q.sx;
+            bx += sx;
             if ((unsigned)bx >= (unsigned)P.nbx) break;
-            tnx = plane_rel((bx + ux1) * kBrickX, r.jx, P.vx, r.dx) * q.ix;
+            tnx = cross((bx + px) * kBrickX, r.jx, r.ax, r.bx);
         } else if (tny == tmin) {
-            by += q.sy;
+            by += sy;
             if ((unsigned)by >= (unsigned)P.nby) break;
-            tny = plane_rel((by + uy1) * kBrickY, r.jy, P.vy, r.dy) * q.iy;
+            tny = cross((by + py) * kBrickY, r.jy, r.ay, r.by);
         } else {
-            bz += q.sz;
+            bz += sz;
             if ((unsigned)bz >= (unsigned)P.nbz) break;
-            tnz = plane_rel((bz + uz1) * kBrickZ, r.jz, P.vz, r.dz) * q.iz;
+            tnz = cross((bz + pz) * kBrickZ, r.jz, r.az, r.bz);
         }
     }
 }
@@ -575,25 +691,16 @@ __device__ __forceinline__ void brick_walk(const Problem &P, const Ray &r, const
 // counter once (bucketed events make whole blocks hit the same few bricks,
 // and same-address global atomics serialise); when filling, the block then
 // re-walks its events and hands out positions from its reserved ranges.
-__global__ void __launch_bounds__(kForwardBlock) k_brick_items(const Problem *__restrict__ probs, int n_probs,
-                                                               int ept, uint32_t *__restrict__ ctr,
-                                                               const uint32_t *__restrict__ end, int fill) {
-    __shared__ uint32_t hkey[kHashSlots], hcnt[kHashSlots], hbase[kHashSlots];
-    for (int k = threadIdx.x; k < kHashSlots; k += blockDim.x) {
-        hkey[k] = kEmpty;
-        hcnt[k] = 0;
-    }
-    __syncthreads();
-    const int64_t c = blockIdx.x;
-    const Problem P = probs[find_problem(probs, n_probs, c)];
-    const int64_t base = (c - P.chunk_begin) * (int64_t)blockDim.x * ept;
-    uint32_t *__restrict__ items = const_cast<uint32_t *>(P.items);
+template <bool PACKED>
+__device__ __forceinline__ void brick_items_pass(const Problem &P, int64_t base, int ept, uint32_t *__restrict__ ctr,
+                                                 const uint32_t *__restrict__ end, int fill, uint32_t *hkey,
+                                                 uint32_t *hcnt, uint32_t *hbase) {
+    const gptr<uint32_t> items = global(const_cast<uint32_t *>(P.items));
     for (int e = 0; e < ept; ++e) {
         const int64_t i = base + (int64_t)e * blockDim.x + threadIdx.x;
         Ray r;
-        RayInv q;
-        if (i >= P.n_events || !make_ray(P, P.events, i, r, q)) continue;
-        brick_walk(P, r, q, [&](uint32_t key) {
+        if (i >= P.n_events || !make_ray<PACKED>(P, i, r)) continue;
+        brick_walk(P, r, [&](uint32_t key) {
             const int h = hash_insert(hkey, key);
             if (h >= 0) {
                 atomicAdd(&hcnt[h], 1u);
@@ -619,15 +726,32 @@ __global__ void __launch_bounds__(kForwardBlock) k_brick_items(const Problem *__
     for (int e = 0; e < ept; ++e) {
         const int64_t i = base + (int64_t)e * blockDim.x + threadIdx.x;
         Ray r;
-        RayInv q;
-        if (i >= P.n_events || !make_ray(P, P.events, i, r, q)) continue;
-        brick_walk(P, r, q, [&](uint32_t key) {
+        if (i >= P.n_events || !make_ray<PACKED>(P, i, r)) continue;
+        brick_walk(P, r, [&](uint32_t key) {
             const int h = hash_find(hkey, key);
             if (h < 0) return;  // placed directly in the first walk
             const uint32_t pos = hbase[h] + atomicAdd(&hcnt[h], 1u);
             if (pos < end[key]) items[pos] = (uint32_t)i;
         });
     }
+}
+
+__global__ void __launch_bounds__(kForwardBlock) k_brick_items(const Problem *__restrict__ probs, int n_probs,
+                                                               int ept, uint32_t *__restrict__ ctr,
+                                                               const uint32_t *__restrict__ end, int fill) {
+    __shared__ uint32_t hkey[kHashSlots], hcnt[kHashSlots], hbase[kHashSlots];
+    for (int k = threadIdx.x; k < kHashSlots; k += blockDim.x) {
+        hkey[k] = kEmpty;
+        hcnt[k] = 0;
+    }
+    __syncthreads();
+    const int64_t c = blockIdx.x;
+    const Problem P = probs[find_problem(probs, n_probs, c)];
+    const int64_t base = (c - P.chunk_begin) * (int64_t)blockDim.x * ept;
+    if (P.packed)
+        brick_items_pass<true>(P, base, ept, ctr, end, fill, hkey, hcnt, hbase);
+    else
+        brick_items_pass<false>(P, base, ept, ctr, end, fill, hkey, hcnt, hbase);
 }
 
 // Diagnostic: voxel pieces visited per chunk and how many have non-zero weight.
@@ -648,9 +772,8 @@ __global__ void __launch_bounds__(kForwardBlock) k_count_pieces(const Problem *_
         const int64_t i = base + (int64_t)e * blockDim.x + threadIdx.x;
         if (i >= P.n_events) break;
         Ray r;
-        RayInv q;
-        if (!make_ray(P, P.events, i, r, q)) continue;
-        walk<TOF>(P, r, q, r.t0, r.t1, B, cdf, [&](int, float a) {
+        if (!(P.packed ? make_ray<true>(P, i, r) : make_ray<false>(P, i, r))) continue;
+        walk<TOF>(P, r, r.t0, r.t1, B, cdf, [&](int, float a) {
             ++cnt;
             nz += (a != 0.0f);
         });

@@ -22,7 +22,7 @@ import numpy as np
 from . import lmtof as L
 
 
-@dataclass
+@dataclass(eq=False)  # identity: requests hold arrays
 class Request:
     geometry: Dict[str, Any]
     events: Any                 # float32 (n, 7) NumPy array or GPU tensor

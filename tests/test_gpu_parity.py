@@ -358,6 +358,43 @@ def test_packed_storage_bit_exact_and_parity(c1):
     assert e_orig < 6e-2
 
 
+def test_packed_rays_in_voxel_planes(c1):
+    """Packed endpoints sit on a 0.1 mm lattice, so a ray can lie exactly in
+    a voxel plane (both ends at z = -64 mm, a plane of the 4 mm grid; or
+    x = const on a plane).  The half-open voxel convention puts it in the
+    voxel above the plane; the decoded position must be exact for that
+    (a decode that is off by an ulp below the plane picks the other row)."""
+    _say("case: packed rays lying in voxel planes")
+    g = c1["g"]
+    rng = np.random.default_rng(11)
+    n = 4000
+    phi1 = rng.uniform(0, 2 * np.pi, n)
+    phi2 = phi1 + np.pi + rng.uniform(-0.6, 0.6, n)
+    R = g["scanner_radius"]
+    ev = np.zeros((n, 7), np.float64)
+    ev[:, 0], ev[:, 1] = R * np.cos(phi1), R * np.sin(phi1)
+    ev[:, 3], ev[:, 4] = R * np.cos(phi2), R * np.sin(phi2)
+    planes = g["z0"] + g["vz"] * rng.integers(1, g["nz"], n)
+    ev[:, 2] = ev[:, 5] = planes
+    # a quarter lie in an x plane instead (x1 = x2 on a plane, z free)
+    q = n // 4
+    xp = g["x0"] + g["vx"] * rng.integers(1, g["nx"], q)
+    ev[:q, 0] = ev[:q, 3] = xp
+    ev[:q, 1], ev[:q, 4] = -np.sqrt(R * R - xp * xp), np.sqrt(R * R - xp * xp)
+    ev[:q, 2], ev[:q, 5] = rng.uniform(-100, 100, q), rng.uniform(-100, 100, q)
+    ev[:, 6] = rng.normal(0, 300, n)
+    ev = ev.astype(np.float32)
+    dec = oracle.decode_packed(oracle.pack_events(ev))
+    x = rng.uniform(0.2, 2.0, c1["w"].n_voxels).astype(np.float32)
+    with _recon(g, ev, storage=1) as r:
+        f = r.forward_project(x)
+    ref = oracle.forward(g, dec, x.astype(np.float64))
+    rel = np.abs(f - ref) / np.maximum(ref, 1e-30)
+    _say(f"  rel L2 {oracle.rel_l2(f, ref):.2e}, max rel {rel[ref > 0].max():.2e}")
+    assert oracle.rel_l2(f, ref) < 2e-6
+    assert rel[ref > 1e-3 * ref.max()].max() < 1e-4
+
+
 def test_packed_input_format(c1):
     _say("case: packed input")
     p = oracle.pack_events(c1["ev"][:5000])
