@@ -41,6 +41,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=60_000_000,
                     help="events in the oracle CPU-baseline sample (0 = skip)")
     ap.add_argument("--ept", type=int, default=0)
+    ap.add_argument("--copy-ref-mib", type=int, default=0,
+                    help="first copy this many MiB device-to-device (a reference for HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -56,6 +58,15 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+
+    if args.copy_ref_mib > 0:
+        src = torch.ones(args.copy_ref_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy reference: {args.copy_ref_mib} MiB read + {args.copy_ref_mib} MiB written")
+        del src, dst
 
     w = synth.wholebody_workload(n_events=args.events, n_iter=args.iters)
     g = w.geometry()

@@ -65,15 +65,18 @@ extern "C" {
  * (16 B/event: int16 endpoints at 0.1 mm, binary16 dt; float32 input is
  * rounded half-to-even on the GPU).  Takes effect at the next load.  Default 0. */
 #define LMTOF_OPT_STORAGE 1
-/* Reorder events at load by (TOF-centre cell, direction bin) so that
- * neighbouring GPU lanes trace nearby, near-parallel rays.  0/1, default 1. */
+/* Reorder events at load by (16^3-voxel brick holding the TOF centre,
+ * direction bin, sub-cell of the brick) so that neighbouring GPU lanes trace
+ * nearby, near-parallel rays and each brick's events form a few long runs.
+ * 0/1, default 1. */
 #define LMTOF_OPT_SORT 2
 /* Azimuth nodes of the sensitivity quadrature.  Default 2048. */
 #define LMTOF_OPT_SENS_NPHI 3
 /* Forward-projector launch shape: events per thread (1..16; 256 threads per
  * block).  0 = library default. */
 #define LMTOF_OPT_EVENTS_PER_THREAD 5
-/* Edge of the cubic TOF-centre cell used by the sort key, in mm (default 16). */
+/* Approximate edge of the sort key's sub-cells inside a brick, in mm
+ * (default 16: 4 x 4 x 4 sub-cells of a brick of 4 mm voxels). */
 #define LMTOF_OPT_SORT_CELL_MM 6
 
 /* ------------------------------------------------------------------ types */

@@ -47,8 +47,9 @@ struct ItemSet {
     uint4 *chunks = nullptr, *bricks = nullptr;
     unsigned long long *tiles = nullptr;
     float *wmax = nullptr;
+    uint32_t *pairs = nullptr, *pair_off = nullptr;  // (forward chunk) lists per brick
     uint32_t n_chunks = 0, n_bricks = 0, n_slots = 0;
-    uint64_t n_items = 0;
+    uint64_t n_items = 0, n_pairs = 0;
     std::vector<uint4> h_chunks, h_bricks;  // host copies (batching several problems)
 };
 
@@ -95,6 +96,7 @@ struct lmtof_ctx {
     double lut_k = -1.0;
     int *d_part_neff = nullptr;
     double *d_part_ll = nullptr, *d_part_old = nullptr, *d_part_new = nullptr;
+    float *d_part_wmax = nullptr;
     size_t part_cap = 0, vpart_cap = 0;
     DevStats *d_stats = nullptr;
     size_t stats_cap = 0;
@@ -150,6 +152,8 @@ void free_items(ItemSet &it) {
     dev_free(it.bricks);
     dev_free(it.tiles);
     dev_free(it.wmax);
+    dev_free(it.pairs);
+    dev_free(it.pair_off);
     it = ItemSet();
 }
 
@@ -297,30 +301,56 @@ int build_items(lmtof_ctx *c, std::vector<Problem> &ps, Problem *d_probs, int64_
     free_items(out);
     uint64_t nb = 0;
     for (const auto &P : ps) nb += (uint64_t)P.nbx * P.nby * P.nbz;
+    const uint64_t nk = nb * kItemClasses;  // (brick, item class) keys
     Launch L;
     L.stream = c->stream;
-    uint32_t *cnt = nullptr, *off_d = nullptr;
-    int rc = dev_alloc(c, &cnt, nb + 1);
-    if (rc) return rc;
-    std::vector<uint32_t> h(nb);
-    hipError_t he = hipMemsetAsync(cnt, 0, sizeof(uint32_t) * (nb + 1), c->stream);
-    if (he == hipSuccess) he = launch_brick_items(L, d_probs, (int)ps.size(), n_chunks, ept, cnt, nullptr, 0);
-    if (he == hipSuccess) he = hipMemcpyAsync(h.data(), cnt, sizeof(uint32_t) * nb, hipMemcpyDeviceToHost, c->stream);
+    uint32_t *cnt = nullptr, *off_d = nullptr, *pcnt = nullptr;
+    auto free_tmp = [&]() {
+        dev_free(cnt);
+        dev_free(off_d);
+        dev_free(pcnt);
+    };
+    int rc = dev_alloc(c, &cnt, nk + 1);
+    if (!rc) rc = dev_alloc(c, &pcnt, nb + 1);
+    if (rc) {
+        free_tmp();
+        return rc;
+    }
+    std::vector<uint32_t> hk(nk), hp(nb);
+    hipError_t he = hipMemsetAsync(cnt, 0, sizeof(uint32_t) * (nk + 1), c->stream);
+    if (he == hipSuccess) he = hipMemsetAsync(pcnt, 0, sizeof(uint32_t) * (nb + 1), c->stream);
+    if (he == hipSuccess) he = launch_brick_items(L, d_probs, (int)ps.size(), n_chunks, ept, cnt, nullptr, pcnt, 0);
+    if (he == hipSuccess) he = hipMemcpyAsync(hk.data(), cnt, sizeof(uint32_t) * nk, hipMemcpyDeviceToHost, c->stream);
+    if (he == hipSuccess) he = hipMemcpyAsync(hp.data(), pcnt, sizeof(uint32_t) * nb, hipMemcpyDeviceToHost, c->stream);
     if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
     if (he != hipSuccess) {
-        dev_free(cnt);
+        free_tmp();
         return fail(c, LMTOF_EHIP, "brick item count: %s", hipGetErrorString(he));
     }
-    std::vector<uint32_t> off(nb + 1);
-    uint64_t tot = 0;
+    std::vector<uint32_t> poff(nb + 1);
+    uint64_t ptot = 0;
     for (uint64_t b = 0; b < nb; ++b) {
-        off[b] = (uint32_t)tot;
-        tot += h[b];
+        poff[b] = (uint32_t)std::min<uint64_t>(ptot, 0xffffffffULL);
+        ptot += hp[b];
     }
-    if (tot > 0xffffffffULL) {
-        dev_free(cnt);
+    // a brick's items are its class ranges back to back
+    std::vector<uint32_t> offk(nk + 1), h(nb), off(nb + 1);
+    uint64_t tot = 0;
+    for (uint64_t k = 0; k < nk; ++k) {
+        if (k % kItemClasses == 0) {
+            off[k / kItemClasses] = (uint32_t)std::min<uint64_t>(tot, 0xffffffffULL);
+            h[k / kItemClasses] = 0;
+        }
+        offk[k] = (uint32_t)std::min<uint64_t>(tot, 0xffffffffULL);
+        tot += hk[k];
+        h[k / kItemClasses] += hk[k];
+    }
+    if (tot > 0xffffffffULL || ptot > 0xffffffffULL) {
+        free_tmp();
         return fail(c, LMTOF_EUNSUPPORTED, "more than 2^32-1 brick items");
     }
+    poff[nb] = (uint32_t)ptot;
+    offk[nk] = (uint32_t)tot;
     off[nb] = (uint32_t)tot;
     const uint64_t C = std::max<uint64_t>(2048, (tot + 8191) / 8192);
     std::vector<uint4> chunks, bricks;
@@ -344,11 +374,12 @@ int build_items(lmtof_ctx *c, std::vector<Problem> &ps, Problem *d_probs, int64_
     it.n_bricks = (uint32_t)bricks.size();
     it.n_slots = slot;
     it.n_items = tot;
-    if ((rc = dev_alloc(c, &it.items, tot)) || (rc = dev_alloc(c, &off_d, nb + 1)) ||
+    it.n_pairs = ptot;
+    if ((rc = dev_alloc(c, &it.items, tot)) || (rc = dev_alloc(c, &off_d, nk + 1)) ||
         (rc = dev_alloc(c, &it.chunks, chunks.size())) || (rc = dev_alloc(c, &it.bricks, bricks.size())) ||
-        (rc = dev_alloc(c, &it.tiles, (size_t)slot * kBrickVox)) || (rc = dev_alloc(c, &it.wmax, slot))) {
-        dev_free(cnt);
-        dev_free(off_d);
+        (rc = dev_alloc(c, &it.tiles, (size_t)slot * kBrickVox)) || (rc = dev_alloc(c, &it.wmax, slot)) ||
+        (rc = dev_alloc(c, &it.pairs, ptot)) || (rc = dev_alloc(c, &it.pair_off, nb + 1))) {
+        free_tmp();
         free_items(it);
         return rc;
     }
@@ -356,19 +387,24 @@ int build_items(lmtof_ctx *c, std::vector<Problem> &ps, Problem *d_probs, int64_
         P.items = it.items;
         P.tiles = it.tiles;
         P.wmax = it.wmax;
+        P.pairs = it.pairs;
+        P.pair_off = it.pair_off + P.brick_base;
     }
     he = hipMemcpyAsync(d_probs, ps.data(), sizeof(Problem) * ps.size(), hipMemcpyHostToDevice, c->stream);
     if (he == hipSuccess)
-        he = hipMemcpyAsync(off_d, off.data(), sizeof(uint32_t) * (nb + 1), hipMemcpyHostToDevice, c->stream);
+        he = hipMemcpyAsync(off_d, offk.data(), sizeof(uint32_t) * (nk + 1), hipMemcpyHostToDevice, c->stream);
     if (he == hipSuccess && !chunks.empty())
         he = hipMemcpyAsync(it.chunks, chunks.data(), sizeof(uint4) * chunks.size(), hipMemcpyHostToDevice, c->stream);
     if (he == hipSuccess && !bricks.empty())
         he = hipMemcpyAsync(it.bricks, bricks.data(), sizeof(uint4) * bricks.size(), hipMemcpyHostToDevice, c->stream);
-    if (he == hipSuccess) he = hipMemcpyAsync(cnt, off_d, sizeof(uint32_t) * (nb + 1), hipMemcpyDeviceToDevice, c->stream);
-    if (he == hipSuccess) he = launch_brick_items(L, d_probs, (int)ps.size(), n_chunks, ept, cnt, off_d + 1, 1);
+    if (he == hipSuccess) he = hipMemcpyAsync(cnt, off_d, sizeof(uint32_t) * (nk + 1), hipMemcpyDeviceToDevice, c->stream);
+    if (he == hipSuccess)
+        he = hipMemcpyAsync(it.pair_off, poff.data(), sizeof(uint32_t) * (nb + 1), hipMemcpyHostToDevice, c->stream);
+    if (he == hipSuccess)
+        he = hipMemcpyAsync(pcnt, it.pair_off, sizeof(uint32_t) * (nb + 1), hipMemcpyDeviceToDevice, c->stream);
+    if (he == hipSuccess) he = launch_brick_items(L, d_probs, (int)ps.size(), n_chunks, ept, cnt, off_d + 1, pcnt, 1);
     if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
-    dev_free(cnt);
-    dev_free(off_d);
+    free_tmp();
     if (he != hipSuccess) {
         free_items(it);
         return fail(c, LMTOF_EHIP, "brick item fill: %s", hipGetErrorString(he));
@@ -382,8 +418,8 @@ int build_items(lmtof_ctx *c, std::vector<Problem> &ps, Problem *d_probs, int64_
 // Back projection of each problem's weights P.rw into its b (as graph nodes
 // after *prev, or on the stream).  In a graph, ev_a and ev_b (if given) are
 // recorded right before and right after the brick kernel, to time it alone.
-int add_back(lmtof_ctx *c, Launch L, const Problem *d_probs, int np, const ItemSet &it, hipGraphNode_t *prev,
-             hipEvent_t ev_a = nullptr, hipEvent_t ev_b = nullptr) {
+int add_back(lmtof_ctx *c, Launch L, const Problem *d_probs, int np, const ItemSet &it, const float *part_wmax,
+             hipGraphNode_t *prev, hipEvent_t ev_a = nullptr, hipEvent_t ev_b = nullptr) {
     const bool tof = c->g.tof_fwhm_ps > 0;
     hipGraphNode_t node = nullptr;
     if (L.graph) {
@@ -400,8 +436,8 @@ int add_back(lmtof_ctx *c, Launch L, const Problem *d_probs, int np, const ItemS
         return LMTOF_OK;
     };
     int rc;
-    HIPCHK(c, launch_chunk_wmax(L, d_probs, np, it.chunks, it.n_chunks, it.bricks));
-    if (L.graph && it.n_chunks) {
+    HIPCHK(c, launch_brick_wmax(L, d_probs, np, it.bricks, it.n_bricks, part_wmax));
+    if (L.graph && it.n_bricks) {
         *prev = node;
         L.deps = prev;
     }
@@ -463,9 +499,11 @@ int ensure_problems(lmtof_ctx *c) {
     if ((size_t)c->n_chunks > c->part_cap) {
         dev_free(c->d_part_neff);
         dev_free(c->d_part_ll);
+        dev_free(c->d_part_wmax);
         c->part_cap = 0;
         if ((rc = dev_alloc(c, &c->d_part_neff, c->n_chunks))) return rc;
         if ((rc = dev_alloc(c, &c->d_part_ll, c->n_chunks))) return rc;
+        if ((rc = dev_alloc(c, &c->d_part_wmax, c->n_chunks))) return rc;
         c->part_cap = c->n_chunks;
     }
     if ((size_t)c->n_vchunks > c->vpart_cap) {
@@ -518,10 +556,11 @@ int build_graph(lmtof_ctx *c, int n_iter, GraphEntry &ge) {
         L.deps = &prev;
         L.n_deps = 1;
         L.node = &node;
-        HIPCHK(c, launch_forward(L, tof, c->d_probs, np, c->n_chunks, c->ept_used, 0, c->d_part_neff, c->d_part_ll));
+        HIPCHK(c, launch_forward(L, tof, c->d_probs, np, c->n_chunks, c->ept_used, 0, c->d_part_neff, c->d_part_ll,
+                                 c->d_part_wmax));
         if (node) prev = node;
         if ((rc = record(ge.ev[kEventsPerIter * k + 1]))) return rc;
-        if ((rc = add_back(c, L, c->d_probs, np, c->items, &prev, ge.ev[kEventsPerIter * k + 2],
+        if ((rc = add_back(c, L, c->d_probs, np, c->items, c->d_part_wmax, &prev, ge.ev[kEventsPerIter * k + 2],
                            ge.ev[kEventsPerIter * k + 3])))
             return rc;
         if ((rc = record(ge.ev[kEventsPerIter * k + 4]))) return rc;
@@ -586,7 +625,6 @@ int check_geometry(lmtof_ctx *c, const lmtof_geometry &g) {
 KeyGeom key_geom(const lmtof_ctx *c, bool sort, const std::vector<Region> &regions) {
     const lmtof_geometry &g = c->g;
     KeyGeom k{};
-    double cell = c->opt_cell_mm;
     k.ox = (float)g.x0;
     k.oy = (float)g.y0;
     k.oz = (float)g.z0;
@@ -595,18 +633,39 @@ KeyGeom key_geom(const lmtof_ctx *c, bool sort, const std::vector<Region> &regio
     k.sort = sort ? 1 : 0;
     k.tof = g.tof_fwhm_ps > 0;
     k.half_c = (float)(g.c_mm_per_ps / 2.0);
-    // coarsen cells until the key space stays modest
-    for (;;) {
-        k.ncx = (int)std::ceil(g.nx * g.vx / cell);
-        k.ncy = (int)std::ceil(g.ny * g.vy / cell);
-        k.ncz = (int)std::ceil(g.nz * g.vz / cell);
-        if ((double)k.ncx * k.ncy * k.ncz * k.n_phi * k.n_lam * std::max<size_t>(1, regions.size()) <= (1 << 26))
-            break;
-        cell *= 1.25;
+    k.bx_inv = (float)(1.0 / (kBrickX * g.vx));
+    k.by_inv = (float)(1.0 / (kBrickY * g.vy));
+    k.bz_inv = (float)(1.0 / (kBrickZ * g.vz));
+    k.ncx = (g.nx + kBrickX - 1) / kBrickX;
+    k.ncy = (g.ny + kBrickY - 1) / kBrickY;
+    int nzb = g.nz;
+    if (!regions.empty()) {
+        nzb = 0;
+        for (const auto &r : regions) nzb = std::max(nzb, r.nz);
     }
-    k.cell_inv = (float)(1.0 / cell);
+    k.ncz = (nzb + kBrickZ - 1) / kBrickZ;
+    // sub-cells of about the requested cell size, fewer if the key space grows too large
+    auto nsub = [&](double brick_mm) { return std::max(1, std::min(16, (int)std::lround(brick_mm / c->opt_cell_mm))); };
+    k.nsx = nsub(kBrickX * g.vx);
+    k.nsy = nsub(kBrickY * g.vy);
+    k.nsz = nsub(kBrickZ * g.vz);
+    const double nr = std::max<size_t>(1, regions.size());
+    while ((double)k.ncx * k.ncy * k.ncz * k.n_phi * k.n_lam * k.nsx * k.nsy * k.nsz * nr > (double)(1 << 26)) {
+        if (k.nsx * k.nsy * k.nsz > 1) {
+            k.nsx = std::max(1, k.nsx / 2);
+            k.nsy = std::max(1, k.nsy / 2);
+            k.nsz = std::max(1, k.nsz / 2);
+        } else {
+            k.n_phi = std::max(1, k.n_phi / 2);
+            k.n_lam = std::max(1, k.n_lam / 2);
+            if (k.n_phi == 1 && k.n_lam == 1) break;
+        }
+    }
     k.n_regions = (int)regions.size();
-    for (size_t r = 0; r < regions.size(); ++r) k.region_z[r] = (float)(g.z0 + regions[r].core_lo * g.vz);
+    for (size_t r = 0; r < regions.size(); ++r) {
+        k.region_z[r] = (float)(g.z0 + regions[r].core_lo * g.vz);
+        k.region_z0[r] = (float)(g.z0 + regions[r].z_lo * g.vz);
+    }
     if (!regions.empty()) k.region_z[regions.size()] = (float)(g.z0 + regions.back().core_hi * g.vz);
     return k;
 }
@@ -617,6 +676,7 @@ int64_t ctx_device_bytes(const lmtof_ctx *c) {
     const int64_t esz = c->stored_packed ? 16 : 32;
     int64_t b = c->n_events * (esz + 8 + 4) + 3 * 4 * c->V;
     b += (int64_t)c->items.n_items * 4 + (int64_t)c->items.n_slots * (kBrickVox * 8 + 4);
+    b += (int64_t)c->items.n_pairs * 4 + (int64_t)(c->V / kBrickVox + 64) * 4;
     b += (int64_t)(c->items.n_chunks + c->items.n_bricks) * 16;
     b += (int64_t)c->part_cap * 12 + (int64_t)c->vpart_cap * 16 + kLutN * 16;
     return b;
@@ -643,6 +703,7 @@ int64_t request_bytes_estimate(const lmtof_request &q) {
     const int64_t esz = q.storage ? 16 : 32;
     int64_t b = N * (esz + 8 + 4) + items * 4 + 3 * 4 * V;
     b += (items / 2048 + 1 + V / kBrickVox + 1) * (int64_t)kBrickVox * 8 / 4;  // tiles
+    b += items;  // (forward chunk, brick) pairs: at most one per item, ~1 in 10 in practice
     b += N * (q.mem == LMTOF_MEM_HOST ? 28 : 0) + N * (esz + 8 + 4);       // ingest transients
     return b + (64 << 20);
 }
@@ -706,6 +767,7 @@ int lmtof_destroy(lmtof_ctx *c) {
     dev_free(c->d_b);
     dev_free(c->d_probs);
     dev_free(c->d_part_neff);
+    dev_free(c->d_part_wmax);
     dev_free(c->d_part_ll);
     dev_free(c->d_part_old);
     dev_free(c->d_part_new);
@@ -1147,7 +1209,7 @@ int lmtof_forward_project(lmtof_ctx *c, const float *x, int64_t nx_, float *f, i
     launch_shape(c, block, ept);
     int64_t nch, nvch;
     if ((rc = upload_problems(c, ps, block, ept, &dp, nch, nvch))) return done(rc);
-    hipError_t he = launch_forward(L, c->g.tof_fwhm_ps > 0, dp, 1, nch, ept, 1, nullptr, nullptr);
+    hipError_t he = launch_forward(L, c->g.tof_fwhm_ps > 0, dp, 1, nch, ept, 1, nullptr, nullptr, nullptr);
     if (he == hipSuccess) he = launch_scatter_by_perm(L, fs, c->d_perm, c->n_events, fc);
     if (he != hipSuccess) return done(fail(c, LMTOF_EHIP, "forward projection: %s", hipGetErrorString(he)));
     if (mem == LMTOF_MEM_HOST) rc = copy_out(c, f, fc, sizeof(float) * c->n_events, LMTOF_MEM_HOST);
@@ -1164,7 +1226,7 @@ int lmtof_back_project(lmtof_ctx *c, const float *w, int64_t nw, float *b, int64
     HIPCHK(c, hipSetDevice(c->device));
     Launch L;
     L.stream = c->stream;
-    float *dw = nullptr, *ws = nullptr, *db = nullptr;
+    float *dw = nullptr, *ws = nullptr, *db = nullptr, *pw = nullptr;
     Problem *dp = nullptr;
     ItemSet its;
     int rc = LMTOF_OK;
@@ -1172,6 +1234,7 @@ int lmtof_back_project(lmtof_ctx *c, const float *w, int64_t nw, float *b, int64
         (void)hipStreamSynchronize(c->stream);
         if (mem == LMTOF_MEM_HOST) { dev_free(dw); dev_free(db); }
         dev_free(ws);
+        dev_free(pw);
         dev_free(dp);
         free_items(its);
         return r;
@@ -1192,11 +1255,12 @@ int lmtof_back_project(lmtof_ctx *c, const float *w, int64_t nw, float *b, int64
     launch_shape(c, block, ept);
     int64_t nch, nvch;
     if ((rc = upload_problems(c, ps, block, ept, &dp, nch, nvch))) return done(rc);
-    if ((rc = build_items(c, ps, dp, nch, ept, its))) return done(rc);
+    if ((rc = build_items(c, ps, dp, nch, ept, its)) || (rc = dev_alloc(c, &pw, nch))) return done(rc);
     hipError_t he = launch_gather_by_perm(L, dw, c->d_perm, c->n_events, ws);
     if (he == hipSuccess) he = launch_fill(L, db, c->V, 0.0f);
+    if (he == hipSuccess) he = launch_chunk_absmax(L, dp, 1, nch, ept, pw);
     if (he != hipSuccess) return done(fail(c, LMTOF_EHIP, "back projection: %s", hipGetErrorString(he)));
-    if ((rc = add_back(c, L, dp, 1, its, nullptr))) return done(rc);
+    if ((rc = add_back(c, L, dp, 1, its, pw, nullptr))) return done(rc);
     if (mem == LMTOF_MEM_HOST) rc = copy_out(c, b, db, sizeof(float) * c->V, LMTOF_MEM_HOST);
     else if (hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(c, LMTOF_EHIP, "back projection failed");
     return done(rc);
@@ -1403,6 +1467,7 @@ struct lmtof_pool {
     int64_t n_chunks = 0, n_vchunks = 0;
     int *part_neff = nullptr;
     double *part_ll = nullptr, *part_old = nullptr, *part_new = nullptr;
+    float *part_wmax = nullptr;
     size_t part_cap = 0, vpart_cap = 0;
     DevStats *d_stats = nullptr;
     size_t stats_cap = 0;
@@ -1472,8 +1537,10 @@ int pool_build_batch(lmtof_pool *p) {
         (rc = pool_grow(p, &p->d_stats, p->stats_cap, np)))
         return rc;
     if ((size_t)nch > p->part_cap) {
-        size_t c0 = p->part_cap, c1 = p->part_cap;
-        if ((rc = pool_grow(p, &p->part_neff, c0, nch)) || (rc = pool_grow(p, &p->part_ll, c1, nch))) return rc;
+        size_t c0 = p->part_cap, c1 = p->part_cap, c2 = p->part_cap;
+        if ((rc = pool_grow(p, &p->part_neff, c0, nch)) || (rc = pool_grow(p, &p->part_ll, c1, nch)) ||
+            (rc = pool_grow(p, &p->part_wmax, c2, nch)))
+            return rc;
         p->part_cap = nch;
     }
     if ((size_t)nvch > p->vpart_cap) {
@@ -1549,6 +1616,7 @@ int lmtof_pool_destroy(lmtof_pool *p) {
     dev_free(p->d_bricks);
     dev_free(p->part_neff);
     dev_free(p->part_ll);
+    dev_free(p->part_wmax);
     dev_free(p->part_old);
     dev_free(p->part_new);
     dev_free(p->d_stats);
@@ -1595,6 +1663,10 @@ int lmtof_pool_submit(lmtof_pool *p, const lmtof_request *q, int64_t *id) {
     if ((rc = lmtof_load_events(c, q->events, q->n_events, q->format, q->mem))) return bail(rc);
     if ((rc = lmtof_compute_sensitivity(c))) return bail(rc);
     if ((rc = lmtof_set_image(c, nullptr, 0, LMTOF_MEM_HOST))) return bail(rc);
+    if (c->ept_used != p->ept) {  // brick pair lists index the forward chunks of this launch shape
+        lmtof_destroy(c);
+        return pfail(p, LMTOF_EUNSUPPORTED, "request prepared with a different launch shape");
+    }
     PoolReq r;
     r.id = p->next_id++;
     r.ctx = c;
@@ -1619,8 +1691,8 @@ int lmtof_pool_step(lmtof_pool *p, int *n_active) {
     const bool tof = p->batch[0].tof != 0;  // submit keeps a batch all-TOF or all-non-TOF
     Launch L;
     L.stream = p->stream;
-    PHIP(p, launch_forward(L, tof, p->d_probs, np, p->n_chunks, p->ept, 0, p->part_neff, p->part_ll));
-    PHIP(p, launch_chunk_wmax(L, p->d_probs, np, p->d_chunks, p->n_bchunks, p->d_bricks));
+    PHIP(p, launch_forward(L, tof, p->d_probs, np, p->n_chunks, p->ept, 0, p->part_neff, p->part_ll, p->part_wmax));
+    PHIP(p, launch_brick_wmax(L, p->d_probs, np, p->d_bricks, p->n_bbricks, p->part_wmax));
     PHIP(p, launch_back_chunks(L, tof, p->d_probs, np, p->d_chunks, p->n_bchunks, p->d_bricks));
     PHIP(p, launch_reduce_tiles(L, p->d_probs, np, p->d_bricks, p->n_bbricks));
     PHIP(p, launch_update(L, p->d_probs, np, p->n_vchunks, p->part_old, p->part_new));

@@ -6,14 +6,21 @@
 // distinct endpoints, and for packed storage int16 range at 0.1 mm and a
 // binary16-representable dt), optionally packed to 16 bytes, and reordered
 // by a counting sort on an integer key:
-//   key = ((region * ncz + cz) * ncy + cy) * ncx + cx) * n_dir + dir,
-// where (cx, cy, cz) is the cubic cell holding the TOF centre and dir bins
-// the undirected line direction (azimuth over [0, pi), elevation).  Events
-// sharing a key trace near-parallel, co-located rays, so a wavefront of them
-// gathers and scatters over the same few cache lines.  MLEM itself does not
-// depend on event order; the permutation is kept so per-event inputs and
-// outputs stay in the caller's order.  The region index (TOF-assisted data
-// division, Section 2.5) is the most significant part of the key, so each
+//   key = ((((region * ncz + bz) * ncy + by) * ncx + bx) * n_dir + dir) * n_sub + sub,
+// where (bx, by, bz) is the 16^3-voxel brick holding the TOF centre, dir
+// bins the undirected line direction (azimuth over [0, pi), elevation) and
+// sub is the sub-cell of the brick holding the centre.  A wavefront of
+// consecutive events then traces near-parallel, co-located rays (its image
+// gathers share cache lines), and the events whose windows cross a given
+// brick - those centred in it and, from each neighbour, the few direction
+// bins pointing at it - form a few long runs of the stored order, so the
+// brick-parallel back projection reads them nearly contiguously.  MLEM
+// itself does not depend on event order; the permutation is kept so
+// per-event inputs and outputs stay in the caller's order.  The region
+// index (TOF-assisted data division, Section 2.5) is the most significant
+// part of the key, and bricks are counted from each region sub-volume's
+// first plane, so each region's events are contiguous and its bricks
+// align with the ones its back projection uses.  The
 // region's events end up contiguous.
 #include "lmtof_internal.h"
 
@@ -66,19 +73,22 @@ __device__ __forceinline__ uint32_t event_key(const KeyGeom &g, const float p[7]
     float my = fmaf(sh, uy, 0.5f * (p[1] + p[4]));
     float mz = fmaf(sh, uz, 0.5f * (p[2] + p[5]));
     uint32_t region = 0;
+    float z0 = g.oz;
     if (g.n_regions > 1) {
         int r = 0;
         for (int k = 1; k < g.n_regions; ++k)
             if (mz >= g.region_z[k]) r = k;
         region = (uint32_t)r;
+        z0 = g.region_z0[r];
     }
     if (!g.sort) return region;
-    int cx = (int)floorf((mx - g.ox) * g.cell_inv);
-    int cy = (int)floorf((my - g.oy) * g.cell_inv);
-    int cz = (int)floorf((mz - g.oz) * g.cell_inv);
-    cx = min(max(cx, 0), g.ncx - 1);
-    cy = min(max(cy, 0), g.ncy - 1);
-    cz = min(max(cz, 0), g.ncz - 1);
+    const float fx = (mx - g.ox) * g.bx_inv, fy = (my - g.oy) * g.by_inv, fz = (mz - z0) * g.bz_inv;
+    const int bx = min(max((int)floorf(fx), 0), g.ncx - 1);
+    const int by = min(max((int)floorf(fy), 0), g.ncy - 1);
+    const int bz = min(max((int)floorf(fz), 0), g.ncz - 1);
+    const int sx = min(max((int)floorf((fx - (float)bx) * (float)g.nsx), 0), g.nsx - 1);
+    const int sy = min(max((int)floorf((fy - (float)by) * (float)g.nsy), 0), g.nsy - 1);
+    const int sz = min(max((int)floorf((fz - (float)bz) * (float)g.nsz), 0), g.nsz - 1);
     // undirected line: canonical direction has uy > 0 (or uy = 0, ux >= 0)
     if (uy < 0.0f || (uy == 0.0f && ux < 0.0f)) {
         ux = -ux;
@@ -90,8 +100,10 @@ __device__ __forceinline__ uint32_t event_key(const KeyGeom &g, const float p[7]
     int bl = (int)((uz + 1.0f) * 0.5f * (float)g.n_lam);
     bp = min(max(bp, 0), g.n_phi - 1);
     bl = min(max(bl, 0), g.n_lam - 1);
-    const uint32_t cell = ((region * (uint32_t)g.ncz + cz) * (uint32_t)g.ncy + cy) * (uint32_t)g.ncx + cx;
-    return cell * (uint32_t)(g.n_phi * g.n_lam) + (uint32_t)(bp * g.n_lam + bl);
+    const uint32_t brick = ((region * (uint32_t)g.ncz + bz) * (uint32_t)g.ncy + by) * (uint32_t)g.ncx + bx;
+    const uint32_t dir = (uint32_t)(bp * g.n_lam + bl);
+    const uint32_t sub = (uint32_t)((sz * g.nsy + sy) * g.nsx + sx);
+    return (brick * (uint32_t)(g.n_phi * g.n_lam) + dir) * (uint32_t)(g.nsx * g.nsy * g.nsz) + sub;
 }
 
 __global__ void __launch_bounds__(kBlock) k_ingest_keys(const void *__restrict__ raw, int fmt, int64_t n, KeyGeom g,
@@ -263,7 +275,7 @@ dim3 grid1(int64_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); }
 uint32_t key_count(const KeyGeom &g) {
     const uint64_t nr = g.n_regions > 1 ? (uint64_t)g.n_regions : 1u;
     if (!g.sort) return (uint32_t)nr;
-    return (uint32_t)(nr * g.ncx * g.ncy * g.ncz * g.n_phi * g.n_lam);
+    return (uint32_t)(nr * g.ncx * g.ncy * g.ncz * g.n_phi * g.n_lam * g.nsx * g.nsy * g.nsz);
 }
 
 hipError_t launch_ingest_keys(const Launch &L, const void *raw, int fmt, int64_t n, const KeyGeom &g,

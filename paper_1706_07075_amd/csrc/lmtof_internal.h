@@ -14,6 +14,9 @@ namespace lmtof {
 constexpr int kLutN = 1024;
 constexpr int kBrickX = 16, kBrickY = 16, kBrickZ = 16;
 constexpr int kBrickVox = kBrickX * kBrickY * kBrickZ;
+// Brick items are grouped by an estimate of their voxel pieces in the brick
+// (longest first), so that a wavefront's lanes walk similar lengths.
+constexpr int kItemClasses = 4;
 constexpr int kForwardBlock = 256;
 constexpr int kBackBlock = 512;
 
@@ -29,7 +32,9 @@ struct Problem {
     float *rw;            // per event of this problem: 1 / f (MLEM) or a back-projection weight
     const uint32_t *items;// brick item list array (problem-local event indices) the chunks index
     unsigned long long *tiles;  // 64-bit fixed-point chunk tiles, indexed by tile slot
-    float *wmax;          // per tile slot: largest |w| of the chunk
+    float *wmax;          // per brick, at its first tile slot: bound on |w| over its items
+    const uint32_t *pairs;    // per brick: the problem-local forward chunks holding its items
+    const uint32_t *pair_off; // brick (problem-local id) -> range in pairs; nbx*nby*nbz + 1 entries
     int32_t packed;
     int32_t tof;
     int32_t nx, ny, nz;
@@ -79,26 +84,33 @@ inline hipError_t do_launch(const Launch &L, const void *func, dim3 grid, dim3 b
 // ---- projector (project.hip)
 int64_t project_chunk_events(int block, int ept);
 // Forward projection per event into P.rw; mode 0: 1 / f (0 if f <= 0) and
-// per-chunk partials (n_eff, sum log f); mode 1: f.
+// per-chunk partials (n_eff, sum log f, largest 1 / f); mode 1: f.
 hipError_t launch_forward(const Launch &L, bool tof, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept,
-                          int mode, int *part_neff, double *part_ll);
+                          int mode, int *part_neff, double *part_ll, float *part_wmax);
 // Back projection by brick chunks.  Brick table entry (global brick id,
 // first tile slot, end tile slot, items in the brick); chunk (brick table
 // index, first item, end item, tile slot) over P.items / P.tiles of the
-// brick's problem with weights P.rw.  launch_chunk_wmax, then
+// brick's problem with weights P.rw.  launch_brick_wmax (per-brick bound
+// on |w| from the forward chunks' maxima part_wmax), then
 // launch_back_chunks, then launch_reduce_tiles (which writes every voxel of
 // the listed bricks of P.b).
-hipError_t launch_chunk_wmax(const Launch &L, const Problem *d_probs, int n_probs, const uint4 *chunks,
-                             uint32_t n_chunks, const uint4 *bricks);
+hipError_t launch_brick_wmax(const Launch &L, const Problem *d_probs, int n_probs, const uint4 *bricks,
+                             uint32_t n_bricks, const float *part_wmax);
+// part_wmax[c] = largest |P.rw| over forward chunk c's events.
+hipError_t launch_chunk_absmax(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept,
+                               float *part_wmax);
 hipError_t launch_back_chunks(const Launch &L, bool tof, const Problem *d_probs, int n_probs, const uint4 *chunks,
                               uint32_t n_chunks, const uint4 *bricks);
 hipError_t launch_reduce_tiles(const Launch &L, const Problem *d_probs, int n_probs, const uint4 *bricks,
                                uint32_t n_bricks);
-// Brick item lists: fill == 0 counts pieces per global brick into ctr; else
-// writes problem-local event indices to P.items at ctr[brick]++, never past
-// end[brick].
+// Brick item lists, keyed by global brick * kItemClasses + item class.
+// fill == 0 counts pieces per key into ctr and (forward chunk, brick) pairs
+// per global brick into pctr; else writes problem-local event indices to
+// P.items at ctr[key]++ (never past end[key]) and problem-local forward
+// chunk indices to P.pairs at pctr[brick]++.  Same launch shape as the
+// forward pass (its chunks are the pairs' chunks).
 hipError_t launch_brick_items(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept,
-                              uint32_t *ctr, const uint32_t *end, int fill);
+                              uint32_t *ctr, const uint32_t *end, uint32_t *pctr, int fill);
 // part[2c] = voxel pieces visited by chunk c, part[2c+1] = pieces with non-zero weight.
 hipError_t launch_count_pieces(const Launch &L, bool tof, const Problem *d_probs, int n_probs, int64_t n_chunks,
                                int ept, unsigned long long *part);
@@ -140,14 +152,17 @@ hipError_t launch_sensitivity(const Launch &L, const SensGeom &g, float *s);
 
 // ---- event ingest: validation, packing, bucketing sort (events.hip)
 struct KeyGeom {
-    int32_t ncx, ncy, ncz;  // TOF-centre cells per axis
+    int32_t ncx, ncy, ncz;  // bricks per axis holding TOF centres
+    int32_t nsx, nsy, nsz;  // sub-cells per brick and axis
     int32_t n_phi, n_lam;   // direction bins (azimuth over [0, pi), elevation)
     int32_t n_regions;      // 0: no region split
     int32_t sort;           // 0: key = region only (keeps caller order inside a region)
     int32_t tof;
-    float ox, oy, oz, cell_inv;
+    float ox, oy, oz;       // grid corner (mm)
+    float bx_inv, by_inv, bz_inv;  // 1 / brick edge (mm)
     float half_c;
-    float region_z[kMaxProblems + 1];  // core bounds in mm (n_regions + 1 values)
+    float region_z[kMaxProblems + 1];   // core bounds in mm (n_regions + 1 values)
+    float region_z0[kMaxProblems];      // z of each region sub-volume's first plane (mm)
 };
 uint32_t key_count(const KeyGeom &g);
 // Pass 1: validate raw events, compute keys, histogram them.

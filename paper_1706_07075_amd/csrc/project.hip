@@ -353,6 +353,12 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
 __device__ __forceinline__ int find_problem(const Problem *probs, int n_probs, int64_t c) {
     int p = n_probs - 1;
     while (p > 0 && probs[p].chunk_begin > c) --p;
@@ -369,34 +375,54 @@ __device__ __forceinline__ void stage_lut(float4 *lds, const float4 *src) {
     for (int k = threadIdx.x; k < kLutN; k += blockDim.x) lds[k] = src[k];
 }
 
-// f_i = sum_j a_ij x_j over the window of ray r.  The image value of the
-// next voxel is fetched one piece ahead, so its latency overlaps the weight
-// computation of the current piece.
+// f_i = sum_j a_ij x_j over the window of ray r.  The traversal runs two
+// pieces ahead of the accumulation, so two image gathers are in flight per
+// lane while earlier pieces are weighted.  A finished traversal pads the
+// queue with empty pieces at tb (weight exactly 0); the piece that ends at
+// tb is always the last real one.
 template <bool TOF>
 __device__ __forceinline__ float forward_ray(const Problem &P, const Ray &r, const Box &B, const Cdf &cdf,
                                              gptr<const float> x, uint32_t last_voxel) {
     Stepper s(P, r, r.t0, B);
     const float tb = r.t1;
+    float tp = r.t0;  // start of the next piece to produce
+    bool done = false;
+    auto produce = [&](float &te, float &xv) {
+        if (done) {
+            te = tb;
+            xv = 0.0f;
+            return;
+        }
+        const float tmin = s.next();
+        te = __builtin_amdgcn_fmed3f(tmin, tp, tb);
+        xv = x[min((uint32_t)s.j, last_voxel)];
+        tp = te;
+        if (tmin >= tb)
+            done = true;
+        else
+            s.advance(r, tmin);
+    };
+    float te0, x0, te1, x1;
+    produce(te0, x0);
+    produce(te1, x1);
     float t = r.t0;
     float c = TOF ? cdf(t) : 0.0f;
     float f = 0.0f;
-    float xj = x[min((uint32_t)s.j, last_voxel)];
     for (int step = 0; step < s.max_steps; ++step) {
-        const float tmin = s.next();
-        const float tn = __builtin_amdgcn_fmed3f(tmin, t, tb);
         float a;
         if (TOF) {
-            const float cn = cdf(tn);
+            const float cn = cdf(te0);
             a = cn - c;
             c = cn;
         } else {
-            a = tn - t;
+            a = te0 - t;
         }
-        t = tn;
-        f = fmaf(a, xj, f);
-        if (tmin >= tb) break;
-        s.advance(r, tmin);
-        xj = x[min((uint32_t)s.j, last_voxel)];
+        t = te0;
+        f = fmaf(a, x0, f);
+        if (te0 >= tb) break;
+        te0 = te1;
+        x0 = x1;
+        produce(te1, x1);
     }
     return f;
 }
@@ -406,7 +432,7 @@ __device__ __forceinline__ float forward_ray(const Problem &P, const Ray &r, con
 // of log f); mode 1: out[i] = f_i.  out is indexed by stored event position.
 template <bool TOF, bool PACKED>
 __device__ __forceinline__ void forward_chunk(const Problem &P, int64_t base, int ept, int mode, const Cdf &cdf,
-                                              int &neff, float &ll) {
+                                              int &neff, float &ll, float &wmax) {
     const Box B = grid_box(P);
     const gptr<const float> x = global(P.x);
     const gptr<float> out = global(P.rw);
@@ -418,9 +444,11 @@ __device__ __forceinline__ void forward_chunk(const Problem &P, int64_t base, in
         const float f = make_ray<PACKED>(P, i, r) ? forward_ray<TOF>(P, r, B, cdf, x, last_voxel) : 0.0f;
         if (mode == 0) {
             const bool pos = f > 0.0f;
+            const float w = pos ? 1.0f / f : 0.0f;
             neff += pos;
             ll += pos ? logf(f) : 0.0f;
-            out[i] = pos ? 1.0f / f : 0.0f;
+            wmax = fmaxf(wmax, w);
+            out[i] = w;
         } else {
             out[i] = f;
         }
@@ -430,10 +458,12 @@ __device__ __forceinline__ void forward_chunk(const Problem &P, int64_t base, in
 template <bool TOF>
 __global__ void __launch_bounds__(kForwardBlock) k_forward(const Problem *__restrict__ probs, int n_probs, int ept,
                                                            int mode, int *__restrict__ part_neff,
-                                                           double *__restrict__ part_ll) {
+                                                           double *__restrict__ part_ll,
+                                                           float *__restrict__ part_wmax) {
     __shared__ float4 lut[kLutN];
     __shared__ int s_n[kForwardBlock / 64];
     __shared__ double s_l[kForwardBlock / 64];
+    __shared__ float s_w[kForwardBlock / 64];
     const int64_t c = blockIdx.x;
     const Problem P = probs[find_problem(probs, n_probs, c)];
     if (TOF) stage_lut(lut, P.lut);
@@ -441,29 +471,34 @@ __global__ void __launch_bounds__(kForwardBlock) k_forward(const Problem *__rest
     const Cdf cdf{lut, P.lut_a, P.lut_b};
     const int64_t base = (c - P.chunk_begin) * (int64_t)blockDim.x * ept;
     int neff = 0;
-    float ll = 0.0f;
+    float ll = 0.0f, wmax = 0.0f;
     if (P.packed)
-        forward_chunk<TOF, true>(P, base, ept, mode, cdf, neff, ll);
+        forward_chunk<TOF, true>(P, base, ept, mode, cdf, neff, ll, wmax);
     else
-        forward_chunk<TOF, false>(P, base, ept, mode, cdf, neff, ll);
+        forward_chunk<TOF, false>(P, base, ept, mode, cdf, neff, ll, wmax);
     if (mode == 0) {
         const int wn = wave_sum(neff);
         const double wl = wave_sum((double)ll);
+        const float ww = wave_max(wmax);
         const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
         if (lane == 0) {
             s_n[wid] = wn;
             s_l[wid] = wl;
+            s_w[wid] = ww;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
             int tn = 0;
             double tl = 0.0;
+            float tw = 0.0f;
             for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
                 tn += s_n[w];
                 tl += s_l[w];
+                tw = fmaxf(tw, s_w[w]);
             }
             part_neff[c] = tn;
             part_ll[c] = tl;
+            part_wmax[c] = tw;
         }
     }
 }
@@ -483,29 +518,49 @@ __global__ void __launch_bounds__(kForwardBlock) k_forward(const Problem *__rest
 // Brick table entry (brick id, first tile slot, end tile slot, items in the
 // brick); chunk (brick table index, first item, end item, tile slot).
 
-// 1. Largest |w| over each chunk's items, per tile slot.
-__global__ void __launch_bounds__(256) k_chunk_wmax(const Problem *__restrict__ probs, int n_probs,
-                                                    const uint4 *__restrict__ chunks,
-                                                    const uint4 *__restrict__ bricks) {
-    __shared__ float s_m[4];
-    const uint4 ch = chunks[blockIdx.x];
-    const uint4 br = bricks[ch.x];
+// 1. Bound on |w| over each brick's items: the largest of the forward
+//    chunk maxima over the chunks holding its events (one wave per brick).
+//    w >= 0 here (MLEM ratios), so the forward pass's max of w is max |w|.
+__global__ void __launch_bounds__(64) k_brick_wmax(const Problem *__restrict__ probs, int n_probs,
+                                                   const uint4 *__restrict__ bricks,
+                                                   const float *__restrict__ part_wmax) {
+    const uint4 br = bricks[blockIdx.x];
     const Problem &P = probs[find_brick_problem(probs, n_probs, br.x)];
-    const uint32_t *__restrict__ items = P.items;
-    const float *__restrict__ w = P.rw;
+    const uint32_t bl = br.x - (uint32_t)P.brick_base;
+    const gptr<const uint32_t> pairs = global(P.pairs);
+    const uint32_t k0 = P.pair_off[bl], k1 = P.pair_off[bl + 1];
     float wm = 0.0f;
-    for (uint32_t k = ch.y + threadIdx.x; k < ch.z; k += blockDim.x) wm = fmaxf(wm, fabsf(w[items[k]]));
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) wm = fmaxf(wm, __shfl_xor(wm, off, 64));
-    if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = wm;
+    for (uint32_t k = k0 + threadIdx.x; k < k1; k += 64) wm = fmaxf(wm, part_wmax[P.chunk_begin + pairs[k]]);
+    wm = wave_max(wm);
+    if (threadIdx.x == 0) global(P.wmax)[br.y] = wm;
+}
+
+// Largest |w| over each forward chunk's events (for weights that do not
+// come from the forward pass, e.g. a caller's back-projection weights).
+__global__ void __launch_bounds__(kForwardBlock) k_chunk_absmax(const Problem *__restrict__ probs, int n_probs,
+                                                                int ept, float *__restrict__ part_wmax) {
+    __shared__ float s_w[kForwardBlock / 64];
+    const int64_t c = blockIdx.x;
+    const Problem &P = probs[find_problem(probs, n_probs, c)];
+    const int64_t base = (c - P.chunk_begin) * (int64_t)blockDim.x * ept;
+    float wm = 0.0f;
+    for (int e = 0; e < ept; ++e) {
+        const int64_t i = base + (int64_t)e * blockDim.x + threadIdx.x;
+        if (i < P.n_events) wm = fmaxf(wm, fabsf(P.rw[i]));
+    }
+    wm = wave_max(wm);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = wm;
     __syncthreads();
-    if (threadIdx.x == 0) P.wmax[ch.w] = fmaxf(fmaxf(s_m[0], s_m[1]), fmaxf(s_m[2], s_m[3]));
+    if (threadIdx.x == 0) {
+        float tw = 0.0f;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tw = fmaxf(tw, s_w[w]);
+        part_wmax[c] = tw;
+    }
 }
 
 // Fixed-point exponent of a brick (same value in every chunk and the reduce).
 __device__ __forceinline__ int brick_exponent(const Problem &P, const uint4 &br, float &wmax) {
-    float wm = 0.0f;
-    for (uint32_t sl = br.y; sl < br.z; ++sl) wm = fmaxf(wm, P.wmax[sl]);
+    const float wm = P.wmax[br.y];
     wmax = wm;
     int en, ea, ew;
     frexpf((float)br.w, &en);
@@ -647,7 +702,8 @@ __device__ __forceinline__ int hash_find(const uint32_t *keys, uint32_t key) {
 }
 
 // Walk one event's window through the brick grid of P and call
-// visit(global brick id) for every brick crossed over a positive length.
+// visit(global brick id, t_in, t_out) for every brick crossed over a
+// positive length [t_in, t_out].
 // Brick faces are voxel planes, so this uses the voxel walk's crossing
 // formulas and cuts the window exactly where the brick pieces meet.
 template <class Visit>
@@ -665,7 +721,7 @@ __device__ __forceinline__ void brick_walk(const Problem &P, const Ray &r, Visit
     for (int step = 0; step < max_steps; ++step) {
         const float tmin = fminf(fminf(tnx, tny), tnz);
         const float tn = fminf(tmin, r.t1);
-        if (tn > t) visit((uint32_t)P.brick_base + (uint32_t)(bx + P.nbx * (by + P.nby * bz)));
+        if (tn > t) visit((uint32_t)P.brick_base + (uint32_t)(bx + P.nbx * (by + P.nby * bz)), t, tn);
         if (tmin >= r.t1) break;
         t = fmaxf(tn, t);
         if (tnx == tmin) {
@@ -684,31 +740,50 @@ __device__ __forceinline__ void brick_walk(const Problem &P, const Ray &r, Visit
     }
 }
 
-// Brick item lists.  Counting (fill == 0): ctr[brick] += pieces.  Filling:
-// every piece gets a position from ctr[brick]++ (never past end[brick]) and
-// P.items[position] = its problem-local event index.  A block first tallies
+// Brick item lists, counted and filled per (brick, item class) key =
+// brick * kItemClasses + class.  Counting (fill == 0): ctr[key] += pieces.
+// Filling: every piece gets a position from ctr[key]++ (never past
+// end[key]) and P.items[position] = its problem-local event index.  A block first tallies
 // its pieces per brick in an LDS hash table, then touches each global
 // counter once (bucketed events make whole blocks hit the same few bricks,
 // and same-address global atomics serialise); when filling, the block then
 // re-walks its events and hands out positions from its reserved ranges.
+// Item class of a brick piece [t0, t1] of ray r: 0 for the longest walks
+// (estimated plane crossings (t1 - t0) sum_a |u_a| / v_a of 16 or more),
+// then 9-15, 4-8, and 3 or fewer.
+__device__ __forceinline__ uint32_t item_class(const Problem &P, const Ray &r, float t0, float t1) {
+    const float m = (t1 - t0) * (fabsf(r.ux) * P.ivx + fabsf(r.uy) * P.ivy + fabsf(r.uz) * P.ivz);
+    return m >= 16.0f ? 0u : m >= 9.0f ? 1u : m >= 4.0f ? 2u : 3u;
+}
+
 template <bool PACKED>
-__device__ __forceinline__ void brick_items_pass(const Problem &P, int64_t base, int ept, uint32_t *__restrict__ ctr,
-                                                 const uint32_t *__restrict__ end, int fill, uint32_t *hkey,
+__device__ __forceinline__ void brick_items_pass(const Problem &P, int64_t base, uint32_t chunk, int ept,
+                                                 uint32_t *__restrict__ ctr, const uint32_t *__restrict__ end,
+                                                 uint32_t *__restrict__ pctr, int fill, uint32_t *hkey,
                                                  uint32_t *hcnt, uint32_t *hbase) {
     const gptr<uint32_t> items = global(const_cast<uint32_t *>(P.items));
+    const gptr<uint32_t> pairs = global(const_cast<uint32_t *>(P.pairs));
+    // one (chunk, brick) pair per distinct key of this block (a brick may
+    // appear once per item class: duplicates only repeat a max operand)
+    auto pair = [&](uint32_t key) {
+        const uint32_t brick = key / kItemClasses;
+        const uint32_t pos = atomicAdd(pctr + brick, 1u);
+        if (fill) pairs[pos] = chunk;
+    };
     for (int e = 0; e < ept; ++e) {
         const int64_t i = base + (int64_t)e * blockDim.x + threadIdx.x;
         Ray r;
         if (i >= P.n_events || !make_ray<PACKED>(P, i, r)) continue;
-        brick_walk(P, r, [&](uint32_t key) {
+        brick_walk(P, r, [&](uint32_t brick, float t0, float t1) {
+            const uint32_t key = brick * kItemClasses + item_class(P, r, t0, t1);
             const int h = hash_insert(hkey, key);
             if (h >= 0) {
                 atomicAdd(&hcnt[h], 1u);
-            } else if (!fill) {
-                atomicAdd(ctr + key, 1u);
             } else {
+                // table full: place the piece (and a pair for it) directly
                 const uint32_t pos = atomicAdd(ctr + key, 1u);
-                if (pos < end[key]) items[pos] = (uint32_t)i;
+                if (fill && pos < end[key]) items[pos] = (uint32_t)i;
+                pair(key);
             }
         });
     }
@@ -716,6 +791,7 @@ __device__ __forceinline__ void brick_items_pass(const Problem &P, int64_t base,
     for (int k = threadIdx.x; k < kHashSlots; k += blockDim.x) {
         if (hkey[k] == kEmpty) continue;
         const uint32_t b = atomicAdd(ctr + hkey[k], hcnt[k]);
+        pair(hkey[k]);
         if (fill) {
             hbase[k] = b;
             hcnt[k] = 0;
@@ -727,7 +803,8 @@ __device__ __forceinline__ void brick_items_pass(const Problem &P, int64_t base,
         const int64_t i = base + (int64_t)e * blockDim.x + threadIdx.x;
         Ray r;
         if (i >= P.n_events || !make_ray<PACKED>(P, i, r)) continue;
-        brick_walk(P, r, [&](uint32_t key) {
+        brick_walk(P, r, [&](uint32_t brick, float t0, float t1) {
+            const uint32_t key = brick * kItemClasses + item_class(P, r, t0, t1);
             const int h = hash_find(hkey, key);
             if (h < 0) return;  // placed directly in the first walk
             const uint32_t pos = hbase[h] + atomicAdd(&hcnt[h], 1u);
@@ -738,7 +815,8 @@ __device__ __forceinline__ void brick_items_pass(const Problem &P, int64_t base,
 
 __global__ void __launch_bounds__(kForwardBlock) k_brick_items(const Problem *__restrict__ probs, int n_probs,
                                                                int ept, uint32_t *__restrict__ ctr,
-                                                               const uint32_t *__restrict__ end, int fill) {
+                                                               const uint32_t *__restrict__ end,
+                                                               uint32_t *__restrict__ pctr, int fill) {
     __shared__ uint32_t hkey[kHashSlots], hcnt[kHashSlots], hbase[kHashSlots];
     for (int k = threadIdx.x; k < kHashSlots; k += blockDim.x) {
         hkey[k] = kEmpty;
@@ -748,10 +826,11 @@ __global__ void __launch_bounds__(kForwardBlock) k_brick_items(const Problem *__
     const int64_t c = blockIdx.x;
     const Problem P = probs[find_problem(probs, n_probs, c)];
     const int64_t base = (c - P.chunk_begin) * (int64_t)blockDim.x * ept;
+    const uint32_t chunk = (uint32_t)(c - P.chunk_begin);
     if (P.packed)
-        brick_items_pass<true>(P, base, ept, ctr, end, fill, hkey, hcnt, hbase);
+        brick_items_pass<true>(P, base, chunk, ept, ctr, end, pctr, fill, hkey, hcnt, hbase);
     else
-        brick_items_pass<false>(P, base, ept, ctr, end, fill, hkey, hcnt, hbase);
+        brick_items_pass<false>(P, base, chunk, ept, ctr, end, pctr, fill, hkey, hcnt, hbase);
 }
 
 // Diagnostic: voxel pieces visited per chunk and how many have non-zero weight.
@@ -801,8 +880,8 @@ __global__ void __launch_bounds__(kForwardBlock) k_count_pieces(const Problem *_
 int64_t project_chunk_events(int block, int ept) { return (int64_t)block * ept; }
 
 hipError_t launch_forward(const Launch &L, bool tof, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept,
-                          int mode, int *part_neff, double *part_ll) {
-    void *args[] = {&d_probs, &n_probs, &ept, &mode, &part_neff, &part_ll};
+                          int mode, int *part_neff, double *part_ll, float *part_wmax) {
+    void *args[] = {&d_probs, &n_probs, &ept, &mode, &part_neff, &part_ll, &part_wmax};
     const void *fn = tof ? reinterpret_cast<const void *>(&k_forward<true>)
                          : reinterpret_cast<const void *>(&k_forward<false>);
     return do_launch(L, fn, dim3((unsigned)n_chunks), dim3(kForwardBlock), 0, args);
@@ -816,10 +895,17 @@ hipError_t launch_back_chunks(const Launch &L, bool tof, const Problem *d_probs,
     return do_launch(L, fn, dim3(n_chunks), dim3(kBackBlock), 0, args);
 }
 
-hipError_t launch_chunk_wmax(const Launch &L, const Problem *d_probs, int n_probs, const uint4 *chunks,
-                             uint32_t n_chunks, const uint4 *bricks) {
-    void *args[] = {&d_probs, &n_probs, &chunks, &bricks};
-    return do_launch(L, reinterpret_cast<const void *>(&k_chunk_wmax), dim3(n_chunks), dim3(256), 0, args);
+hipError_t launch_chunk_absmax(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept,
+                               float *part_wmax) {
+    void *args[] = {&d_probs, &n_probs, &ept, &part_wmax};
+    return do_launch(L, reinterpret_cast<const void *>(&k_chunk_absmax), dim3((unsigned)n_chunks),
+                     dim3(kForwardBlock), 0, args);
+}
+
+hipError_t launch_brick_wmax(const Launch &L, const Problem *d_probs, int n_probs, const uint4 *bricks,
+                             uint32_t n_bricks, const float *part_wmax) {
+    void *args[] = {&d_probs, &n_probs, &bricks, &part_wmax};
+    return do_launch(L, reinterpret_cast<const void *>(&k_brick_wmax), dim3(n_bricks), dim3(64), 0, args);
 }
 
 hipError_t launch_reduce_tiles(const Launch &L, const Problem *d_probs, int n_probs, const uint4 *bricks,
@@ -829,8 +915,8 @@ hipError_t launch_reduce_tiles(const Launch &L, const Problem *d_probs, int n_pr
 }
 
 hipError_t launch_brick_items(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept,
-                              uint32_t *ctr, const uint32_t *end, int fill) {
-    void *args[] = {&d_probs, &n_probs, &ept, &ctr, &end, &fill};
+                              uint32_t *ctr, const uint32_t *end, uint32_t *pctr, int fill) {
+    void *args[] = {&d_probs, &n_probs, &ept, &ctr, &end, &pctr, &fill};
     return do_launch(L, reinterpret_cast<const void *>(&k_brick_items), dim3((unsigned)n_chunks),
                      dim3(kForwardBlock), 0, args);
 }
