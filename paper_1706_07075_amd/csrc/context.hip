@@ -48,6 +48,10 @@ struct ItemSet {
     unsigned long long *tiles = nullptr;
     float *wmax = nullptr;
     uint32_t *pairs = nullptr, *pair_off = nullptr;  // (forward chunk) lists per brick
+    char *item_events = nullptr;                      // event record copies in item order
+    size_t item_bytes = 0;
+    // capacities of the large arrays, kept across rebuilds of the lists
+    size_t items_cap = 0, item_events_cap = 0, tiles_cap = 0, pairs_cap = 0;
     uint32_t n_chunks = 0, n_bricks = 0, n_slots = 0;
     uint64_t n_items = 0, n_pairs = 0;
     std::vector<uint4> h_chunks, h_bricks;  // host copies (batching several problems)
@@ -154,6 +158,7 @@ void free_items(ItemSet &it) {
     dev_free(it.wmax);
     dev_free(it.pairs);
     dev_free(it.pair_off);
+    dev_free(it.item_events);
     it = ItemSet();
 }
 
@@ -296,8 +301,30 @@ int upload_problems(lmtof_ctx *c, std::vector<Problem> &ps, int block, int ept, 
 // into chunks of at most C items (C grows with the total so there are
 // ~8k chunks) and order the chunks largest first.  The chunk table is a
 // launch schedule built on the host from the per-brick counts.
+// Keep *p if it holds n elements already, else reallocate it.
+template <class T>
+int reserve(lmtof_ctx *c, T **p, size_t &cap, size_t n) {
+    if (*p && cap >= n) return LMTOF_OK;
+    dev_free(*p);
+    cap = 0;
+    int rc = dev_alloc(c, p, n);
+    if (!rc) cap = std::max<size_t>(n, 1);
+    return rc;
+}
+
 int build_items(lmtof_ctx *c, std::vector<Problem> &ps, Problem *d_probs, int64_t n_chunks, int ept,
                 ItemSet &out) {
+    // the large arrays are reused when they are big enough (reloading events
+    // of a similar size then allocates nothing large)
+    ItemSet keep;
+    std::swap(keep.items, out.items);
+    std::swap(keep.item_events, out.item_events);
+    std::swap(keep.tiles, out.tiles);
+    std::swap(keep.pairs, out.pairs);
+    keep.items_cap = out.items_cap;
+    keep.item_events_cap = out.item_events_cap;
+    keep.tiles_cap = out.tiles_cap;
+    keep.pairs_cap = out.pairs_cap;
     free_items(out);
     uint64_t nb = 0;
     for (const auto &P : ps) nb += (uint64_t)P.nbx * P.nby * P.nbz;
@@ -314,6 +341,7 @@ int build_items(lmtof_ctx *c, std::vector<Problem> &ps, Problem *d_probs, int64_
     if (!rc) rc = dev_alloc(c, &pcnt, nb + 1);
     if (rc) {
         free_tmp();
+        free_items(keep);
         return rc;
     }
     std::vector<uint32_t> hk(nk), hp(nb);
@@ -325,6 +353,7 @@ int build_items(lmtof_ctx *c, std::vector<Problem> &ps, Problem *d_probs, int64_
     if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
     if (he != hipSuccess) {
         free_tmp();
+        free_items(keep);
         return fail(c, LMTOF_EHIP, "brick item count: %s", hipGetErrorString(he));
     }
     std::vector<uint32_t> poff(nb + 1);
@@ -347,6 +376,7 @@ int build_items(lmtof_ctx *c, std::vector<Problem> &ps, Problem *d_probs, int64_
     }
     if (tot > 0xffffffffULL || ptot > 0xffffffffULL) {
         free_tmp();
+        free_items(keep);
         return fail(c, LMTOF_EUNSUPPORTED, "more than 2^32-1 brick items");
     }
     poff[nb] = (uint32_t)ptot;
@@ -369,16 +399,17 @@ int build_items(lmtof_ctx *c, std::vector<Problem> &ps, Problem *d_probs, int64_
     }
     std::stable_sort(chunks.begin(), chunks.end(),
                      [](const uint4 &a, const uint4 &b) { return (a.z - a.y) > (b.z - b.y); });
-    ItemSet it;
+    ItemSet it = std::move(keep);
     it.n_chunks = (uint32_t)chunks.size();
     it.n_bricks = (uint32_t)bricks.size();
     it.n_slots = slot;
     it.n_items = tot;
     it.n_pairs = ptot;
-    if ((rc = dev_alloc(c, &it.items, tot)) || (rc = dev_alloc(c, &off_d, nk + 1)) ||
+    if ((rc = reserve(c, &it.items, it.items_cap, tot)) || (rc = dev_alloc(c, &off_d, nk + 1)) ||
         (rc = dev_alloc(c, &it.chunks, chunks.size())) || (rc = dev_alloc(c, &it.bricks, bricks.size())) ||
-        (rc = dev_alloc(c, &it.tiles, (size_t)slot * kBrickVox)) || (rc = dev_alloc(c, &it.wmax, slot)) ||
-        (rc = dev_alloc(c, &it.pairs, ptot)) || (rc = dev_alloc(c, &it.pair_off, nb + 1))) {
+        (rc = reserve(c, &it.tiles, it.tiles_cap, (size_t)slot * kBrickVox)) || (rc = dev_alloc(c, &it.wmax, slot)) ||
+        (rc = reserve(c, &it.pairs, it.pairs_cap, ptot)) || (rc = dev_alloc(c, &it.pair_off, nb + 1)) ||
+        (rc = reserve(c, &it.item_events, it.item_events_cap, tot * (c->stored_packed ? 16 : 32)))) {
         free_tmp();
         free_items(it);
         return rc;
@@ -389,7 +420,9 @@ int build_items(lmtof_ctx *c, std::vector<Problem> &ps, Problem *d_probs, int64_
         P.wmax = it.wmax;
         P.pairs = it.pairs;
         P.pair_off = it.pair_off + P.brick_base;
+        P.item_events = it.item_events;
     }
+    it.item_bytes = (size_t)tot * (c->stored_packed ? 16 : 32);
     he = hipMemcpyAsync(d_probs, ps.data(), sizeof(Problem) * ps.size(), hipMemcpyHostToDevice, c->stream);
     if (he == hipSuccess)
         he = hipMemcpyAsync(off_d, offk.data(), sizeof(uint32_t) * (nk + 1), hipMemcpyHostToDevice, c->stream);
@@ -676,16 +709,18 @@ int64_t ctx_device_bytes(const lmtof_ctx *c) {
     const int64_t esz = c->stored_packed ? 16 : 32;
     int64_t b = c->n_events * (esz + 8 + 4) + 3 * 4 * c->V;
     b += (int64_t)c->items.n_items * 4 + (int64_t)c->items.n_slots * (kBrickVox * 8 + 4);
-    b += (int64_t)c->items.n_pairs * 4 + (int64_t)(c->V / kBrickVox + 64) * 4;
+    b += (int64_t)c->items.pairs_cap * 4 + (int64_t)(c->V / kBrickVox + 64) * 4 + (int64_t)c->items.item_events_cap;
+    b += (int64_t)(c->items.items_cap - std::min<size_t>(c->items.items_cap, c->items.n_items)) * 4;
+    b += (int64_t)(c->items.tiles_cap - std::min<size_t>(c->items.tiles_cap, (size_t)c->items.n_slots * kBrickVox)) * 8;
     b += (int64_t)(c->items.n_chunks + c->items.n_bricks) * 16;
     b += (int64_t)c->part_cap * 12 + (int64_t)c->vpart_cap * 16 + kLutN * 16;
     return b;
 }
 
 // Footprint the pool reserves for a request: stored events, permutation,
-// weights, ~ (1 + 1.7 * window / brick edge) brick items per event plus
-// tiles, three images, and the transient ingest buffers (raw copy, keys,
-// sort histogram).
+// weights, ~ (1 + 1.7 * window / brick edge) brick items per event (index
+// and event record copy) plus tiles, three images, and the transient ingest
+// buffers (raw copy, keys, sort histogram).
 int64_t request_bytes_estimate(const lmtof_request &q) {
     const lmtof_geometry &g = q.geometry;
     const int64_t V = (int64_t)g.nx * g.ny * g.nz;
@@ -701,7 +736,7 @@ int64_t request_bytes_estimate(const lmtof_request &q) {
     const double ipe = 1.3 * (1.0 + 1.7 * win / (kBrickX * vmin));
     const int64_t items = (int64_t)(N * ipe);
     const int64_t esz = q.storage ? 16 : 32;
-    int64_t b = N * (esz + 8 + 4) + items * 4 + 3 * 4 * V;
+    int64_t b = N * (esz + 8 + 4) + items * (4 + esz) + 3 * 4 * V;
     b += (items / 2048 + 1 + V / kBrickVox + 1) * (int64_t)kBrickVox * 8 / 4;  // tiles
     b += items;  // (forward chunk, brick) pairs: at most one per item, ~1 in 10 in practice
     b += N * (q.mem == LMTOF_MEM_HOST ? 28 : 0) + N * (esz + 8 + 4);       // ingest transients

@@ -31,6 +31,7 @@ struct Problem {
     const float *s;       // sensitivity
     float *rw;            // per event of this problem: 1 / f (MLEM) or a back-projection weight
     const uint32_t *items;// brick item list array (problem-local event indices) the chunks index
+    const void *item_events;  // per item: a copy of its stored event record (read contiguously by chunks)
     unsigned long long *tiles;  // 64-bit fixed-point chunk tiles, indexed by tile slot
     float *wmax;          // per brick, at its first tile slot: bound on |w| over its items
     const uint32_t *pairs;    // per brick: the problem-local forward chunks holding its items

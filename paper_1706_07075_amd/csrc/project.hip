@@ -164,12 +164,12 @@ __device__ __forceinline__ void anchor(float mh, float ml, float o, float v, flo
 // exactly (double-float); the shift is scaled along d = P2 - P1 itself, so
 // rounding of the scale factor only moves mu along the line.
 template <bool PACKED>
-__device__ __forceinline__ bool make_ray(const Problem &P, int64_t i, Ray &r) {
+__device__ __forceinline__ bool make_ray_from(const Problem &P, const void *records, int64_t i, Ray &r) {
     // Contraction off: every kernel that inlines this must derive bitwise
     // the same ray from an event (brick lists, forward and back passes).
 #pragma clang fp contract(off)
     EventGeom ev;
-    load_event<PACKED>(P.events, i, ev);
+    load_event<PACKED>(records, i, ev);
     float dh[3], dl[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -204,6 +204,25 @@ __device__ __forceinline__ bool make_ray(const Problem &P, int64_t i, Ray &r) {
     r.t0 = t0;
     r.t1 = t1;
     return t0 < t1;
+}
+
+// Ray of stored event i of problem P.
+template <bool PACKED>
+__device__ __forceinline__ bool make_ray(const Problem &P, int64_t i, Ray &r) {
+    return make_ray_from<PACKED>(P, P.events, i, r);
+}
+
+// Copy stored event record i to slot k of an item record array.
+template <bool PACKED>
+__device__ __forceinline__ void copy_record(const void *events, int64_t i, void *dst, uint32_t k) {
+    if (PACKED) {
+        global(reinterpret_cast<u32x4 *>(dst))[k] = global(reinterpret_cast<const u32x4 *>(events))[i];
+    } else {
+        const gptr<const f32x4> e = global(reinterpret_cast<const f32x4 *>(events)) + 2 * i;
+        const gptr<f32x4> d = global(reinterpret_cast<f32x4 *>(dst)) + 2 * (size_t)k;
+        d[0] = e[0];
+        d[1] = e[1];
+    }
 }
 
 // Voxel index along one axis at parameter t.
@@ -375,54 +394,34 @@ __device__ __forceinline__ void stage_lut(float4 *lds, const float4 *src) {
     for (int k = threadIdx.x; k < kLutN; k += blockDim.x) lds[k] = src[k];
 }
 
-// f_i = sum_j a_ij x_j over the window of ray r.  The traversal runs two
-// pieces ahead of the accumulation, so two image gathers are in flight per
-// lane while earlier pieces are weighted.  A finished traversal pads the
-// queue with empty pieces at tb (weight exactly 0); the piece that ends at
-// tb is always the last real one.
+// f_i = sum_j a_ij x_j over the window of ray r.  The image value of the
+// next voxel is fetched one piece ahead, so its latency overlaps the weight
+// computation of the current piece.
 template <bool TOF>
 __device__ __forceinline__ float forward_ray(const Problem &P, const Ray &r, const Box &B, const Cdf &cdf,
                                              gptr<const float> x, uint32_t last_voxel) {
     Stepper s(P, r, r.t0, B);
     const float tb = r.t1;
-    float tp = r.t0;  // start of the next piece to produce
-    bool done = false;
-    auto produce = [&](float &te, float &xv) {
-        if (done) {
-            te = tb;
-            xv = 0.0f;
-            return;
-        }
-        const float tmin = s.next();
-        te = __builtin_amdgcn_fmed3f(tmin, tp, tb);
-        xv = x[min((uint32_t)s.j, last_voxel)];
-        tp = te;
-        if (tmin >= tb)
-            done = true;
-        else
-            s.advance(r, tmin);
-    };
-    float te0, x0, te1, x1;
-    produce(te0, x0);
-    produce(te1, x1);
     float t = r.t0;
     float c = TOF ? cdf(t) : 0.0f;
     float f = 0.0f;
+    float xj = x[min((uint32_t)s.j, last_voxel)];
     for (int step = 0; step < s.max_steps; ++step) {
+        const float tmin = s.next();
+        const float tn = __builtin_amdgcn_fmed3f(tmin, t, tb);
         float a;
         if (TOF) {
-            const float cn = cdf(te0);
+            const float cn = cdf(tn);
             a = cn - c;
             c = cn;
         } else {
-            a = te0 - t;
+            a = tn - t;
         }
-        t = te0;
-        f = fmaf(a, x0, f);
-        if (te0 >= tb) break;
-        te0 = te1;
-        x0 = x1;
-        produce(te1, x1);
+        t = tn;
+        f = fmaf(a, xj, f);
+        if (tmin >= tb) break;
+        s.advance(r, tmin);
+        xj = x[min((uint32_t)s.j, last_voxel)];
     }
     return f;
 }
@@ -582,10 +581,10 @@ __device__ __forceinline__ unsigned long long fixed_nonneg(float v) {
 // subtracted when ws < 0.  A weight a is clamped at 0 (the interpolated
 // CDF may dip by ~1e-10 between nodes).
 template <bool TOF, bool PACKED>
-__device__ __forceinline__ void back_item(const Problem &P, uint32_t i, float ws, const Box &B, const Cdf &cdf,
+__device__ __forceinline__ void back_item(const Problem &P, uint32_t k, float ws, const Box &B, const Cdf &cdf,
                                           unsigned long long *tile) {
     Ray r;
-    if (!make_ray<PACKED>(P, (int64_t)i, r)) return;
+    if (!make_ray_from<PACKED>(P, P.item_events, (int64_t)k, r)) return;
     float ta, tb;
     clip_to_box(P, r, B, ta, tb);
     if (!(ta < tb)) return;
@@ -606,9 +605,8 @@ __device__ __forceinline__ void back_chunk_items(const Problem &P, const uint4 &
     const gptr<const uint32_t> items = global(P.items);
     const gptr<const float> w = global(P.rw);
     for (uint32_t k = ch.y + threadIdx.x; k < ch.z; k += blockDim.x) {
-        const uint32_t i = items[k];
-        const float ws = w[i] * S;
-        if (ws != 0.0f) back_item<TOF, PACKED>(P, i, ws, B, cdf, tile);
+        const float ws = w[items[k]] * S;
+        if (ws != 0.0f) back_item<TOF, PACKED>(P, k, ws, B, cdf, tile);
     }
 }
 
@@ -743,7 +741,10 @@ __device__ __forceinline__ void brick_walk(const Problem &P, const Ray &r, Visit
 // Brick item lists, counted and filled per (brick, item class) key =
 // brick * kItemClasses + class.  Counting (fill == 0): ctr[key] += pieces.
 // Filling: every piece gets a position from ctr[key]++ (never past
-// end[key]) and P.items[position] = its problem-local event index.  A block first tallies
+// end[key]); P.items[position] = its problem-local event index and
+// P.item_events[position] = a copy of the event record, so that the back
+// projection streams a chunk's events instead of gathering them (each
+// event is read once per brick it crosses).  A block first tallies
 // its pieces per brick in an LDS hash table, then touches each global
 // counter once (bucketed events make whole blocks hit the same few bricks,
 // and same-address global atomics serialise); when filling, the block then
@@ -782,7 +783,10 @@ __device__ __forceinline__ void brick_items_pass(const Problem &P, int64_t base,
             } else {
                 // table full: place the piece (and a pair for it) directly
                 const uint32_t pos = atomicAdd(ctr + key, 1u);
-                if (fill && pos < end[key]) items[pos] = (uint32_t)i;
+                if (fill && pos < end[key]) {
+                    items[pos] = (uint32_t)i;
+                    copy_record<PACKED>(P.events, i, const_cast<void *>(P.item_events), pos);
+                }
                 pair(key);
             }
         });
@@ -808,7 +812,10 @@ __device__ __forceinline__ void brick_items_pass(const Problem &P, int64_t base,
             const int h = hash_find(hkey, key);
             if (h < 0) return;  // placed directly in the first walk
             const uint32_t pos = hbase[h] + atomicAdd(&hcnt[h], 1u);
-            if (pos < end[key]) items[pos] = (uint32_t)i;
+            if (pos < end[key]) {
+                items[pos] = (uint32_t)i;
+                copy_record<PACKED>(P.events, i, const_cast<void *>(P.item_events), pos);
+            }
         });
     }
 }
