@@ -24,6 +24,26 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+# TOF-assisted division of the whole-body grid: nine core slabs (z slices),
+# feet to head
+REGION_CORES = [0, 107, 177, 240, 290, 335, 375, 410, 438, 470]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_back_chunks_wholebody_146M.json")
+PROJECTOR_SRC = os.path.join(ROOT, "paper_1706_07075_amd", "csrc", "project.hip")
+
+
+def measured_traffic(storage):
+    """HBM bytes per launch of the brick kernel from committed rocprofv3
+    counter runs, if they were taken on the current projector source."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+        src = hashlib.sha256(open(PROJECTOR_SRC, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    m = rec.get(storage)
+    if not m or rec.get("source_sha256") != src:
+        return None
+    return 1024.0 * (m["fetch_kib"] * rec["fetch_scale"] + m["write_kib"] * rec["write_scale"])
 
 
 def log(msg):
@@ -41,6 +61,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=60_000_000,
                     help="events in the oracle CPU-baseline sample (0 = skip)")
     ap.add_argument("--ept", type=int, default=0)
+    ap.add_argument("--regions", action="store_true",
+                    help="TOF-assisted 9-region division of the same events (one batched launch per kernel)")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device (a reference for HBM byte counters)")
     args = ap.parse_args()
@@ -91,12 +114,25 @@ def main():
         r.compute_sensitivity()
         t["sens_ms"] = (time.perf_counter() - a) * 1e3
         a = time.perf_counter()
+        if args.regions:
+            r.set_regions(REGION_CORES)
         r.set_image()
         t["init_ms"] = (time.perf_counter() - a) * 1e3
         a = time.perf_counter()
         st = r.iterate(w.n_iter)
         t["iter_ms"] = (time.perf_counter() - a) * 1e3
         return t, st
+
+    tuned = None
+    if not args.no_autotune:
+        r.load_events(ev_dev)
+        r.compute_sensitivity()
+        if args.regions:
+            r.set_regions(REGION_CORES)
+        r.set_image()
+        chosen, pass_ms = r.autotune()
+        tuned = {"events_per_thread": chosen, "pass_ms": pass_ms}
+        log(f"autotune: {tuned}")
 
     for k in range(args.warmup):
         t, st = one_step()
@@ -151,7 +187,9 @@ def main():
         "dtype": "f32" if args.storage == "plain" else "i16/f16 events, f32 compute",
         "data": "synthetic",
         "config": {"workload": w.name, "events": N, "iterations": I, "tof_fwhm_ps": w.tof_fwhm_ps,
-                   "storage": args.storage, "step": "ingest+sort+sensitivity+init+10 graph-replayed iterations"},
+                   "storage": args.storage, "regions": REGION_CORES if args.regions else None,
+                   "step": "ingest+sort+sensitivity+init+10 graph-replayed iterations"},
+        "autotune": tuned,
         "iter_loop_event_iterations_per_s": loop_rate,
         "recon_latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99))},
         "one_time_ms": {k: float(np.mean([t[k] for t in times])) for k in ("load_ms", "sens_ms", "init_ms")},
@@ -161,7 +199,8 @@ def main():
         "segments_per_event": {"visited": visited / N, "weighted": weighted / N},
         "last_iteration": {"n_eff": last["n_eff"], "sum_sx": last["sum_sx"], "loglik": last["loglik"]},
         "roofline": {"bound": "hbm", "achieved": gbs(bytes_back, backk_ms), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs(bytes_back, backk_ms) / HBM_PEAK_GBS, "traffic": None,
+                     "frac": gbs(bytes_back, backk_ms) / HBM_PEAK_GBS,
+                     "traffic": None if args.regions else measured_traffic(args.storage),
                      "kernel": "k_back_chunks", "bytes_per_launch": bytes_back},
         "roofline_forward": {"bound": "hbm", "achieved": gbs(bytes_fwd, fwd_ms), "peak": HBM_PEAK_GBS,
                              "unit": "GB/s", "frac": gbs(bytes_fwd, fwd_ms) / HBM_PEAK_GBS,

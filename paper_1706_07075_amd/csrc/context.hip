@@ -1301,6 +1301,69 @@ int lmtof_back_project(lmtof_ctx *c, const float *w, int64_t nw, float *b, int64
     return done(rc);
 }
 
+int lmtof_autotune(lmtof_ctx *c, int64_t *chosen, float *ms) {
+    if (!c) return LMTOF_EINVAL;
+    c->err.clear();
+    if (!c->has_image) return fail(c, LMTOF_ESTATE, "set the image (lmtof_set_image) first");
+    HIPCHK(c, hipSetDevice(c->device));
+    static const int cand[4] = {1, 2, 4, 8};
+    const int saved = c->opt_ept;
+    const bool tof = c->g.tof_fwhm_ps > 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&](int rc) {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        return rc;
+    };
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return cleanup(fail(c, LMTOF_EHIP, "event creation failed"));
+    float best_ms = 0.0f;
+    int best = -1;
+    for (int k = 0; k < 4; ++k) {
+        c->opt_ept = cand[k];
+        c->probs_dirty = true;
+        int rc = ensure_problems(c);
+        if (rc) {
+            c->opt_ept = saved;
+            c->probs_dirty = true;
+            return cleanup(rc);
+        }
+        const int np = (int)c->probs.size();
+        Launch L;
+        L.stream = c->stream;
+        float t = 0.0f;
+        for (int rep = 0; rep < 2; ++rep) {  // the first pass warms caches and code
+            hipError_t he = hipEventRecord(e0, c->stream);
+            if (he == hipSuccess)
+                he = launch_forward(L, tof, c->d_probs, np, c->n_chunks, c->ept_used, 0, c->d_part_neff,
+                                    c->d_part_ll, c->d_part_wmax);
+            if (he != hipSuccess) return cleanup(fail(c, LMTOF_EHIP, "autotune: %s", hipGetErrorString(he)));
+            if ((rc = add_back(c, L, c->d_probs, np, c->items, c->d_part_wmax, nullptr))) return cleanup(rc);
+            if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&t, e0, e1) != hipSuccess)
+                return cleanup(fail(c, LMTOF_EHIP, "autotune timing failed"));
+        }
+        if (ms) ms[k] = t;
+        if (best < 0 || t < best_ms) {
+            best_ms = t;
+            best = cand[k];
+        }
+    }
+    c->opt_ept = best;
+    c->probs_dirty = true;
+    int rc = ensure_problems(c);
+    if (rc) return cleanup(rc);
+    // the passes above wrote back projections into b: clear it for the next iteration
+    Launch L;
+    L.stream = c->stream;
+    for (const auto &P : c->probs)
+        if (launch_fill(L, P.b, (int64_t)P.nx * P.ny * P.nz, 0.0f) != hipSuccess)
+            return cleanup(fail(c, LMTOF_EHIP, "autotune: clearing b failed"));
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return cleanup(fail(c, LMTOF_EHIP, "autotune failed"));
+    if (chosen) *chosen = best;
+    return cleanup(LMTOF_OK);
+}
+
 int lmtof_count_segments(lmtof_ctx *c, int64_t *visited, int64_t *weighted) {
     if (!c) return LMTOF_EINVAL;
     c->err.clear();

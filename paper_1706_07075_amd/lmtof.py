@@ -104,6 +104,7 @@ _sig = {
     "lmtof_forward_project": ([_P, _P, _i64, _P, _i64, C.c_int], C.c_int),
     "lmtof_back_project": ([_P, _P, _i64, _P, _i64, C.c_int], C.c_int),
     "lmtof_count_segments": ([_P, C.POINTER(_i64), C.POINTER(_i64)], C.c_int),
+    "lmtof_autotune": ([_P, C.POINTER(_i64), C.POINTER(C.c_float)], C.c_int),
     "lmtof_set_regions": ([_P, C.POINTER(C.c_int32), C.c_int, C.c_int], C.c_int),
     "lmtof_region_info": ([_P, C.c_int, C.POINTER(C.c_int32), C.POINTER(_i64)], C.c_int),
     "lmtof_read_region_image": ([_P, C.c_int, _P, _i64, C.c_int], C.c_int),
@@ -305,6 +306,15 @@ def lmtof_count_segments(ctx):
     return a.value, b.value
 
 
+def lmtof_autotune(ctx):
+    """Pick the events-per-thread launch shape by timing one projector pass
+    per candidate (1, 2, 4, 8).  Returns (chosen, {candidate: ms})."""
+    chosen = C.c_int64()
+    ms = (C.c_float * 4)()
+    _check(_lib.lmtof_autotune(ctx, C.byref(chosen), ms), ctx)
+    return chosen.value, dict(zip((1, 2, 4, 8), [float(v) for v in ms]))
+
+
 def lmtof_set_regions(ctx, z_bounds, margin_slices: int = -1) -> None:
     zb = np.ascontiguousarray(z_bounds, dtype=np.int32)
     _check(_lib.lmtof_set_regions(ctx, zb.ctypes.data_as(C.POINTER(C.c_int32)), len(zb) - 1, margin_slices), ctx)
@@ -474,6 +484,9 @@ class Reconstruction:
 
     def count_segments(self):
         return lmtof_count_segments(self.ctx)
+
+    def autotune(self):
+        return lmtof_autotune(self.ctx)
 
     def read_packed_events(self, out=None):
         return lmtof_read_packed_events(self.ctx, out)

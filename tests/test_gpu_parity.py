@@ -395,6 +395,25 @@ def test_packed_rays_in_voxel_planes(c1):
     assert rel[ref > 1e-3 * ref.max()].max() < 1e-4
 
 
+def test_autotune_keeps_image_and_parity(c1):
+    _say("case: autotune")
+    with _recon(c1["g"], c1["ev"]) as r:
+        r.compute_sensitivity()
+        r.set_image()
+        x0 = r.read_image()
+        chosen, times = r.autotune()
+        _say(f"  chose {chosen} events per thread; pass ms {times}")
+        assert chosen in (1, 2, 4, 8) and all(t > 0 for t in times.values())
+        assert np.array_equal(r.read_image(), x0)
+        assert L.lmtof_get_option(r.ctx, L.LMTOF_OPT_EVENTS_PER_THREAD) == chosen
+        st = r.iterate(c1["w"].n_iter)
+        x = r.read_image()
+    e = oracle.rel_l2(x, c1["hist"][-1])
+    _say(f"  after autotune: rel L2 {e:.2e}")
+    assert e < 1e-5
+    assert abs(st[0]["sum_sx"] - st[0]["n_eff"]) < 1e-6 * st[0]["n_eff"]
+
+
 def test_packed_input_format(c1):
     _say("case: packed input")
     p = oracle.pack_events(c1["ev"][:5000])
