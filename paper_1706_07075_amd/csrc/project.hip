@@ -645,9 +645,11 @@ __global__ void __launch_bounds__(kBackBlock) k_back_chunks(const Problem *__res
 }
 
 // 3. b over one brick = (exact sum of its chunk tiles) 2^-e.
+//    Four blocks per brick, each a quarter of its voxels.
 __global__ void __launch_bounds__(256) k_reduce_tiles(const Problem *__restrict__ probs, int n_probs,
                                                       const uint4 *__restrict__ bricks) {
-    const uint4 br = bricks[blockIdx.x];
+    const uint4 br = bricks[blockIdx.x >> 2];
+    const int k0 = (int)(blockIdx.x & 3u) * (kBrickVox / 4);
     const Problem &P = probs[find_brick_problem(probs, n_probs, br.x)];
     const uint32_t bl = br.x - (uint32_t)P.brick_base;
     const int bx = (int)(bl % (uint32_t)P.nbx), by = (int)((bl / (uint32_t)P.nbx) % (uint32_t)P.nby),
@@ -657,7 +659,7 @@ __global__ void __launch_bounds__(256) k_reduce_tiles(const Problem *__restrict_
     const float inv = ldexpf(1.0f, -brick_exponent(P, br, wm));
     float *__restrict__ b = P.b;
     const unsigned long long *__restrict__ tiles = P.tiles;
-    for (int k = threadIdx.x; k < kBrickVox; k += blockDim.x) {
+    for (int k = k0 + threadIdx.x; k < k0 + kBrickVox / 4; k += blockDim.x) {
         unsigned long long acc = 0ull;
         for (uint32_t sl = br.y; sl < br.z; ++sl) acc += tiles[(size_t)sl * kBrickVox + k];
         const int lx = k % kBrickX, ly = (k / kBrickX) % kBrickY, lz = k / (kBrickX * kBrickY);
@@ -918,7 +920,7 @@ hipError_t launch_brick_wmax(const Launch &L, const Problem *d_probs, int n_prob
 hipError_t launch_reduce_tiles(const Launch &L, const Problem *d_probs, int n_probs, const uint4 *bricks,
                                uint32_t n_bricks) {
     void *args[] = {&d_probs, &n_probs, &bricks};
-    return do_launch(L, reinterpret_cast<const void *>(&k_reduce_tiles), dim3(n_bricks), dim3(256), 0, args);
+    return do_launch(L, reinterpret_cast<const void *>(&k_reduce_tiles), dim3(4 * n_bricks), dim3(256), 0, args);
 }
 
 hipError_t launch_brick_items(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept,

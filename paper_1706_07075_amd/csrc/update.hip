@@ -73,15 +73,17 @@ __global__ void __launch_bounds__(kUpdBlock) k_update(const Problem *__restrict_
     }
 }
 
-__global__ void __launch_bounds__(256) k_finalize(const Problem *__restrict__ probs, int n_probs,
+constexpr int kFinBlock = 1024;
+
+__global__ void __launch_bounds__(kFinBlock) k_finalize(const Problem *__restrict__ probs, int n_probs,
                                                   int64_t n_chunks, int64_t n_vchunks,
                                                   const int *__restrict__ part_neff,
                                                   const double *__restrict__ part_ll,
                                                   const double *__restrict__ part_old,
                                                   const double *__restrict__ part_new, DevStats *__restrict__ stats,
                                                   int iter) {
-    __shared__ double smd[4];
-    __shared__ int64_t smi[4];
+    __shared__ double smd[kFinBlock / 64];
+    __shared__ int64_t smi[kFinBlock / 64];
     const int p = blockIdx.x;
     const Problem &P = probs[p];
     const int64_t c0 = P.chunk_begin, c1 = (p + 1 < n_probs) ? probs[p + 1].chunk_begin : n_chunks;
@@ -175,7 +177,8 @@ hipError_t launch_finalize(const Launch &L, const Problem *d_probs, int n_probs,
                            const double *part_new, DevStats *stats, int iter) {
     void *args[] = {&d_probs, &n_probs, &n_chunks, &n_vchunks, &part_neff, &part_ll,
                     &part_old, &part_new, &stats, &iter};
-    return do_launch(L, reinterpret_cast<const void *>(&k_finalize), dim3((unsigned)n_probs), dim3(256), 0, args);
+    return do_launch(L, reinterpret_cast<const void *>(&k_finalize), dim3((unsigned)n_probs), dim3(kFinBlock), 0,
+                     args);
 }
 
 hipError_t launch_sum_positive(const Launch &L, const float *s, int64_t n, double *partials, int n_part,
