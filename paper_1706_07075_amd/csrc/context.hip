@@ -91,7 +91,9 @@ struct lmtof_ctx {
     // batch of problems the iteration runs
     std::vector<Problem> probs;
     Problem *d_probs = nullptr;
-    int64_t n_chunks = 0, n_vchunks = 0;
+    int64_t n_chunks = 0, n_vchunks = 0, n_xblk = 0;
+    float *d_xb = nullptr;  // blocked image copies the forward pass gathers from
+    size_t xb_cap = 0;
     int ept_used = kDefaultEpt;
     ItemSet items;               // brick item lists of the iteration batch
     float *d_rw = nullptr;       // per stored event: 1 / f (MLEM) or a weight
@@ -235,6 +237,9 @@ Problem make_problem(const lmtof_ctx *c, int z_lo, int nz, float *x, float *b, c
     P.nbx = (g.nx + kBrickX - 1) / kBrickX;
     P.nby = (g.ny + kBrickY - 1) / kBrickY;
     P.nbz = (nz + kBrickZ - 1) / kBrickZ;
+    P.nbx4 = (g.nx + 3) / 4;
+    P.nby4 = (g.ny + 3) / 4;
+    P.nbz4 = (nz + 3) / 4;
     P.x = x;
     P.b = b;
     P.s = s;
@@ -272,6 +277,18 @@ void launch_shape(const lmtof_ctx *c, int &block, int &ept) {
 }
 
 // Upload a problem table (assigning chunk ranges) to *d (reallocated as needed).
+// Lay out the problems' blocked image copies back to back in xb (n_xblk
+// 4^3 blocks of 64 floats in total; xb may be NULL to only count them).
+int64_t assign_xblocks(std::vector<Problem> &ps, float *xb) {
+    int64_t n = 0;
+    for (auto &P : ps) {
+        P.xblk_begin = n;
+        P.xb = xb ? xb + 64 * n : nullptr;
+        n += (int64_t)P.nbx4 * P.nby4 * P.nbz4;
+    }
+    return n;
+}
+
 int upload_problems(lmtof_ctx *c, std::vector<Problem> &ps, int block, int ept, Problem **d, int64_t &n_chunks,
                     int64_t &n_vchunks) {
     const int64_t ce = project_chunk_events(block, ept), cv = update_chunk_voxels();
@@ -524,8 +541,11 @@ int ensure_problems(lmtof_ctx *c) {
     }
     int block, ept;
     launch_shape(c, block, ept);
-    int rc = upload_problems(c, ps, block, ept, &c->d_probs, c->n_chunks, c->n_vchunks);
+    const int64_t nxb = assign_xblocks(ps, nullptr);
+    int rc = reserve(c, &c->d_xb, c->xb_cap, (size_t)nxb * 64);
     if (rc) return rc;
+    c->n_xblk = assign_xblocks(ps, c->d_xb);
+    if ((rc = upload_problems(c, ps, block, ept, &c->d_probs, c->n_chunks, c->n_vchunks))) return rc;
     if ((rc = build_items(c, ps, c->d_probs, c->n_chunks, ept, c->items))) return rc;
     c->probs = ps;
     c->ept_used = ept;
@@ -589,6 +609,10 @@ int build_graph(lmtof_ctx *c, int n_iter, GraphEntry &ge) {
         L.deps = &prev;
         L.n_deps = 1;
         L.node = &node;
+        HIPCHK(c, launch_block_image(L, c->d_probs, np, c->n_xblk));
+        if (node) prev = node;
+        L.deps = &prev;
+        node = nullptr;
         HIPCHK(c, launch_forward(L, tof, c->d_probs, np, c->n_chunks, c->ept_used, 0, c->d_part_neff, c->d_part_ll,
                                  c->d_part_wmax));
         if (node) prev = node;
@@ -713,7 +737,7 @@ int64_t ctx_device_bytes(const lmtof_ctx *c) {
     b += (int64_t)(c->items.items_cap - std::min<size_t>(c->items.items_cap, c->items.n_items)) * 4;
     b += (int64_t)(c->items.tiles_cap - std::min<size_t>(c->items.tiles_cap, (size_t)c->items.n_slots * kBrickVox)) * 8;
     b += (int64_t)(c->items.n_chunks + c->items.n_bricks) * 16;
-    b += (int64_t)c->part_cap * 12 + (int64_t)c->vpart_cap * 16 + kLutN * 16;
+    b += (int64_t)c->part_cap * 12 + (int64_t)c->vpart_cap * 16 + kLutN * 16 + (int64_t)c->xb_cap * 4;
     return b;
 }
 
@@ -736,7 +760,7 @@ int64_t request_bytes_estimate(const lmtof_request &q) {
     const double ipe = 1.3 * (1.0 + 1.7 * win / (kBrickX * vmin));
     const int64_t items = (int64_t)(N * ipe);
     const int64_t esz = q.storage ? 16 : 32;
-    int64_t b = N * (esz + 8 + 4) + items * (4 + esz) + 3 * 4 * V;
+    int64_t b = N * (esz + 8 + 4) + items * (4 + esz) + 4 * 4 * V;  // x, b, s and the blocked copy of x
     b += (items / 2048 + 1 + V / kBrickVox + 1) * (int64_t)kBrickVox * 8 / 4;  // tiles
     b += items;  // (forward chunk, brick) pairs: at most one per item, ~1 in 10 in practice
     b += N * (q.mem == LMTOF_MEM_HOST ? 28 : 0) + N * (esz + 8 + 4);       // ingest transients
@@ -800,6 +824,7 @@ int lmtof_destroy(lmtof_ctx *c) {
     dev_free(c->d_s);
     dev_free(c->d_x);
     dev_free(c->d_b);
+    dev_free(c->d_xb);
     dev_free(c->d_probs);
     dev_free(c->d_part_neff);
     dev_free(c->d_part_wmax);
@@ -1218,13 +1243,14 @@ int lmtof_forward_project(lmtof_ctx *c, const float *x, int64_t nx_, float *f, i
     HIPCHK(c, hipSetDevice(c->device));
     Launch L;
     L.stream = c->stream;
-    float *dx = nullptr, *fs = nullptr, *fc = nullptr;
+    float *dx = nullptr, *fs = nullptr, *fc = nullptr, *xb = nullptr;
     Problem *dp = nullptr;
     int rc = LMTOF_OK;
     auto done = [&](int r) {
         (void)hipStreamSynchronize(c->stream);
         if (mem == LMTOF_MEM_HOST) { dev_free(dx); dev_free(fc); }
         dev_free(fs);
+        dev_free(xb);
         dev_free(dp);
         return r;
     };
@@ -1243,8 +1269,12 @@ int lmtof_forward_project(lmtof_ctx *c, const float *x, int64_t nx_, float *f, i
     int block, ept;
     launch_shape(c, block, ept);
     int64_t nch, nvch;
+    const int64_t nxb = assign_xblocks(ps, nullptr);
+    if ((rc = dev_alloc(c, &xb, nxb * 64))) return done(rc);
+    assign_xblocks(ps, xb);
     if ((rc = upload_problems(c, ps, block, ept, &dp, nch, nvch))) return done(rc);
-    hipError_t he = launch_forward(L, c->g.tof_fwhm_ps > 0, dp, 1, nch, ept, 1, nullptr, nullptr, nullptr);
+    hipError_t he = launch_block_image(L, dp, 1, nxb);
+    if (he == hipSuccess) he = launch_forward(L, c->g.tof_fwhm_ps > 0, dp, 1, nch, ept, 1, nullptr, nullptr, nullptr);
     if (he == hipSuccess) he = launch_scatter_by_perm(L, fs, c->d_perm, c->n_events, fc);
     if (he != hipSuccess) return done(fail(c, LMTOF_EHIP, "forward projection: %s", hipGetErrorString(he)));
     if (mem == LMTOF_MEM_HOST) rc = copy_out(c, f, fc, sizeof(float) * c->n_events, LMTOF_MEM_HOST);
@@ -1331,6 +1361,8 @@ int lmtof_autotune(lmtof_ctx *c, int64_t *chosen, float *ms) {
         const int np = (int)c->probs.size();
         Launch L;
         L.stream = c->stream;
+        if (launch_block_image(L, c->d_probs, np, c->n_xblk) != hipSuccess)
+            return cleanup(fail(c, LMTOF_EHIP, "autotune: image relayout failed"));
         float t = 0.0f;
         for (int rep = 0; rep < 2; ++rep) {  // the first pass warms caches and code
             hipError_t he = hipEventRecord(e0, c->stream);
@@ -1566,6 +1598,7 @@ struct lmtof_pool {
     int *part_neff = nullptr;
     double *part_ll = nullptr, *part_old = nullptr, *part_new = nullptr;
     float *part_wmax = nullptr;
+    int64_t n_xblk = 0;
     size_t part_cap = 0, vpart_cap = 0;
     DevStats *d_stats = nullptr;
     size_t stats_cap = 0;
@@ -1610,13 +1643,15 @@ int pool_grow(lmtof_pool *p, T **ptr, size_t &cap, size_t n) {
 int pool_build_batch(lmtof_pool *p) {
     p->batch.clear();
     std::vector<uint4> chunks, bricks;
-    int64_t nch = 0, nvch = 0, nb = 0;
+    int64_t nch = 0, nvch = 0, nb = 0, nxb = 0;
     const int64_t ce = project_chunk_events(kForwardBlock, p->ept), cv = update_chunk_voxels();
     for (auto &r : p->active) {
-        Problem P = r.ctx->probs[0];
+        Problem P = r.ctx->probs[0];  // its blocked image copy stays the request's own (P.xb)
         P.chunk_begin = nch;
         P.vchunk_begin = nvch;
         P.brick_base = (int32_t)nb;
+        P.xblk_begin = nxb;
+        nxb += (int64_t)P.nbx4 * P.nby4 * P.nbz4;
         nch += (P.n_events + ce - 1) / ce;
         nvch += ((int64_t)P.nx * P.ny * P.nz + cv - 1) / cv;
         const uint32_t bt = (uint32_t)bricks.size();
@@ -1656,6 +1691,7 @@ int pool_build_batch(lmtof_pool *p) {
     p->n_bbricks = (uint32_t)bricks.size();
     p->n_chunks = nch;
     p->n_vchunks = nvch;
+    p->n_xblk = nxb;
     p->dirty = false;
     return LMTOF_OK;
 }
@@ -1789,6 +1825,7 @@ int lmtof_pool_step(lmtof_pool *p, int *n_active) {
     const bool tof = p->batch[0].tof != 0;  // submit keeps a batch all-TOF or all-non-TOF
     Launch L;
     L.stream = p->stream;
+    PHIP(p, launch_block_image(L, p->d_probs, np, p->n_xblk));
     PHIP(p, launch_forward(L, tof, p->d_probs, np, p->n_chunks, p->ept, 0, p->part_neff, p->part_ll, p->part_wmax));
     PHIP(p, launch_brick_wmax(L, p->d_probs, np, p->d_bricks, p->n_bbricks, p->part_wmax));
     PHIP(p, launch_back_chunks(L, tof, p->d_probs, np, p->d_chunks, p->n_bchunks, p->d_bricks));

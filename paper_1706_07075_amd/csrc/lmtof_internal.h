@@ -52,6 +52,12 @@ struct Problem {
     float a_max;          // bound on one piece weight (TOF: 1, the kernel mass; else the voxel diagonal)
     int32_t brick_base;   // global id of this problem's first brick
     int32_t nbx, nby, nbz;// bricks per axis
+    // Forward-pass copy of x in 4x4x4-voxel blocks (x fastest inside a
+    // block, blocks x fastest): the gathers of a wavefront's near-parallel
+    // rays then fall on a few 64-byte sectors.
+    float *xb;
+    int64_t xblk_begin;   // first 4^3 block of this problem in the relayout launch
+    int32_t nbx4, nby4, nbz4;  // 4^3 blocks per axis
 };
 
 constexpr int kMaxProblems = 64;
@@ -115,6 +121,9 @@ hipError_t launch_brick_items(const Launch &L, const Problem *d_probs, int n_pro
 // part[2c] = voxel pieces visited by chunk c, part[2c+1] = pieces with non-zero weight.
 hipError_t launch_count_pieces(const Launch &L, bool tof, const Problem *d_probs, int n_probs, int64_t n_chunks,
                                int ept, unsigned long long *part);
+
+// xb <- x in 4^3 blocks for every problem (n_xblk blocks in total).
+hipError_t launch_block_image(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_xblk);
 
 // ---- update and reductions (update.hip)
 int64_t update_chunk_voxels();

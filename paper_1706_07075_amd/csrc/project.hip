@@ -303,6 +303,55 @@ struct Stepper {
     }
 };
 
+// The same traversal over the whole grid, reporting the voxel's index in
+// the 4^3-blocked copy of the image (the forward pass gathers from it).
+struct StepperB {
+    float kx, ky, kz, tx, ty, tz, sx, sy, sz;
+    int ix, iy, iz;     // current voxel
+    int dix, diy, diz;  // +-1
+    int max_steps;
+
+    __device__ __forceinline__ StepperB(const Problem &P, const Ray &r, float ta) {
+        ix = min(max(voxel_at(ta, r.ux, r.jx, r.dx, P.ivx), 0), P.nx - 1);
+        iy = min(max(voxel_at(ta, r.uy, r.jy, r.dy, P.ivy), 0), P.ny - 1);
+        iz = min(max(voxel_at(ta, r.uz, r.jz, r.dz, P.ivz), 0), P.nz - 1);
+        const bool px = r.ux > 0.0f, py = r.uy > 0.0f, pz = r.uz > 0.0f;
+        sx = px ? 1.0f : -1.0f;
+        sy = py ? 1.0f : -1.0f;
+        sz = pz ? 1.0f : -1.0f;
+        dix = px ? 1 : -1;
+        diy = py ? 1 : -1;
+        diz = pz ? 1 : -1;
+        kx = (float)(ix + px - r.jx);
+        ky = (float)(iy + py - r.jy);
+        kz = (float)(iz + pz - r.jz);
+        tx = fmaf(kx, r.ax, r.bx);
+        ty = fmaf(ky, r.ay, r.by);
+        tz = fmaf(kz, r.az, r.bz);
+        max_steps = P.nx + P.ny + P.nz + 2;
+    }
+    __device__ __forceinline__ float next() const { return fminf(fminf(tx, ty), tz); }
+    __device__ __forceinline__ void advance(const Ray &r, float tmin) {
+        const bool mx = tx == tmin;
+        const bool my = !mx && ty == tmin;
+        const bool mz = !mx && !my;
+        kx += mx ? sx : 0.0f;
+        ky += my ? sy : 0.0f;
+        kz += mz ? sz : 0.0f;
+        tx = fmaf(kx, r.ax, r.bx);
+        ty = fmaf(ky, r.ay, r.by);
+        tz = fmaf(kz, r.az, r.bz);
+        ix += mx ? dix : 0;
+        iy += my ? diy : 0;
+        iz += mz ? diz : 0;
+    }
+    __device__ __forceinline__ uint32_t index(const Problem &P) const {
+        const uint32_t blk = ((uint32_t)(iz >> 2) * (uint32_t)P.nby4 + (uint32_t)(iy >> 2)) * (uint32_t)P.nbx4 +
+                             (uint32_t)(ix >> 2);
+        return (blk << 6) | ((uint32_t)(iz & 3) << 4) | ((uint32_t)(iy & 3) << 2) | (uint32_t)(ix & 3);
+    }
+};
+
 // Walk the voxels of ray r between ta and tb (already inside box B) and call
 // visit(j, a) for every piece, j box-local.  A plane tie gives a
 // zero-length piece (a = 0).  The piece [t, t'] ends at the next crossing
@@ -394,18 +443,18 @@ __device__ __forceinline__ void stage_lut(float4 *lds, const float4 *src) {
     for (int k = threadIdx.x; k < kLutN; k += blockDim.x) lds[k] = src[k];
 }
 
-// f_i = sum_j a_ij x_j over the window of ray r.  The image value of the
-// next voxel is fetched one piece ahead, so its latency overlaps the weight
-// computation of the current piece.
+// f_i = sum_j a_ij x_j over the window of ray r, gathering from the blocked
+// image copy.  The image value of the next voxel is fetched one piece
+// ahead, so its latency overlaps the weight computation of the current piece.
 template <bool TOF>
-__device__ __forceinline__ float forward_ray(const Problem &P, const Ray &r, const Box &B, const Cdf &cdf,
-                                             gptr<const float> x, uint32_t last_voxel) {
-    Stepper s(P, r, r.t0, B);
+__device__ __forceinline__ float forward_ray(const Problem &P, const Ray &r, const Cdf &cdf, gptr<const float> xb,
+                                             uint32_t last_index) {
+    StepperB s(P, r, r.t0);
     const float tb = r.t1;
     float t = r.t0;
     float c = TOF ? cdf(t) : 0.0f;
     float f = 0.0f;
-    float xj = x[min((uint32_t)s.j, last_voxel)];
+    float xj = xb[min(s.index(P), last_index)];
     for (int step = 0; step < s.max_steps; ++step) {
         const float tmin = s.next();
         const float tn = __builtin_amdgcn_fmed3f(tmin, t, tb);
@@ -421,7 +470,7 @@ __device__ __forceinline__ float forward_ray(const Problem &P, const Ray &r, con
         f = fmaf(a, xj, f);
         if (tmin >= tb) break;
         s.advance(r, tmin);
-        xj = x[min((uint32_t)s.j, last_voxel)];
+        xj = xb[min(s.index(P), last_index)];
     }
     return f;
 }
@@ -432,15 +481,14 @@ __device__ __forceinline__ float forward_ray(const Problem &P, const Ray &r, con
 template <bool TOF, bool PACKED>
 __device__ __forceinline__ void forward_chunk(const Problem &P, int64_t base, int ept, int mode, const Cdf &cdf,
                                               int &neff, float &ll, float &wmax) {
-    const Box B = grid_box(P);
-    const gptr<const float> x = global(P.x);
+    const gptr<const float> xb = global(P.xb);
     const gptr<float> out = global(P.rw);
-    const uint32_t last_voxel = (uint32_t)P.nx * (uint32_t)P.ny * (uint32_t)P.nz - 1u;
+    const uint32_t last_index = (uint32_t)P.nbx4 * (uint32_t)P.nby4 * (uint32_t)P.nbz4 * 64u - 1u;
     for (int e = 0; e < ept; ++e) {
         const int64_t i = base + (int64_t)e * blockDim.x + threadIdx.x;
         if (i >= P.n_events) break;
         Ray r;
-        const float f = make_ray<PACKED>(P, i, r) ? forward_ray<TOF>(P, r, B, cdf, x, last_voxel) : 0.0f;
+        const float f = make_ray<PACKED>(P, i, r) ? forward_ray<TOF>(P, r, cdf, xb, last_index) : 0.0f;
         if (mode == 0) {
             const bool pos = f > 0.0f;
             const float w = pos ? 1.0f / f : 0.0f;
@@ -884,9 +932,31 @@ __global__ void __launch_bounds__(kForwardBlock) k_count_pieces(const Problem *_
     }
 }
 
+// xb <- x in 4^3 blocks: four blocks per 256-thread workgroup, one voxel
+// per thread (voxels past the grid edge are 0).
+__global__ void __launch_bounds__(256) k_block_image(const Problem *__restrict__ probs, int n_probs) {
+    const int64_t blk = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    int p = n_probs - 1;
+    while (p > 0 && probs[p].xblk_begin > blk) --p;
+    const Problem &P = probs[p];
+    const int64_t lb = blk - P.xblk_begin;
+    if (lb >= (int64_t)P.nbx4 * P.nby4 * P.nbz4) return;
+    const int bx = (int)(lb % P.nbx4), by = (int)((lb / P.nbx4) % P.nby4), bz = (int)(lb / ((int64_t)P.nbx4 * P.nby4));
+    const int v = threadIdx.x & 63;
+    const int ix = 4 * bx + (v & 3), iy = 4 * by + ((v >> 2) & 3), iz = 4 * bz + (v >> 4);
+    const float val = (ix < P.nx && iy < P.ny && iz < P.nz) ? P.x[ix + (int64_t)P.nx * (iy + (int64_t)P.ny * iz)] : 0.0f;
+    global(P.xb)[lb * 64 + v] = val;
+}
+
 }  // namespace
 
 int64_t project_chunk_events(int block, int ept) { return (int64_t)block * ept; }
+
+hipError_t launch_block_image(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_xblk) {
+    void *args[] = {&d_probs, &n_probs};
+    return do_launch(L, reinterpret_cast<const void *>(&k_block_image), dim3((unsigned)((n_xblk + 3) / 4)),
+                     dim3(256), 0, args);
+}
 
 hipError_t launch_forward(const Launch &L, bool tof, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept,
                           int mode, int *part_neff, double *part_ll, float *part_wmax) {
