@@ -345,9 +345,13 @@ struct StepperB {
         iy += my ? diy : 0;
         iz += mz ? diz : 0;
     }
-    __device__ __forceinline__ uint32_t index(const Problem &P) const {
-        const uint32_t blk = ((uint32_t)(iz >> 2) * (uint32_t)P.nby4 + (uint32_t)(iy >> 2)) * (uint32_t)P.nbx4 +
-                             (uint32_t)(ix >> 2);
+    // Block coordinates as 14-bit fields and strides masked to 24 bits let
+    // the compiler use full-rate 24-bit multiply-adds.
+    __device__ __forceinline__ uint32_t index(uint32_t stride_y, uint32_t stride_z) const {
+        const uint32_t bx = __builtin_amdgcn_ubfe((uint32_t)ix, 2, 14);
+        const uint32_t by = __builtin_amdgcn_ubfe((uint32_t)iy, 2, 14);
+        const uint32_t bz = __builtin_amdgcn_ubfe((uint32_t)iz, 2, 14);
+        const uint32_t blk = bz * stride_z + (by * stride_y + bx);
         return (blk << 6) | ((uint32_t)(iz & 3) << 4) | ((uint32_t)(iy & 3) << 2) | (uint32_t)(ix & 3);
     }
 };
@@ -450,11 +454,12 @@ template <bool TOF>
 __device__ __forceinline__ float forward_ray(const Problem &P, const Ray &r, const Cdf &cdf, gptr<const float> xb,
                                              uint32_t last_index) {
     StepperB s(P, r, r.t0);
+    const uint32_t sy = (uint32_t)P.nbx4 & 0xffffffu, sz = ((uint32_t)P.nbx4 * (uint32_t)P.nby4) & 0xffffffu;
     const float tb = r.t1;
     float t = r.t0;
     float c = TOF ? cdf(t) : 0.0f;
     float f = 0.0f;
-    float xj = xb[min(s.index(P), last_index)];
+    float xj = xb[min(s.index(sy, sz), last_index)];
     for (int step = 0; step < s.max_steps; ++step) {
         const float tmin = s.next();
         const float tn = __builtin_amdgcn_fmed3f(tmin, t, tb);
@@ -470,7 +475,7 @@ __device__ __forceinline__ float forward_ray(const Problem &P, const Ray &r, con
         f = fmaf(a, xj, f);
         if (tmin >= tb) break;
         s.advance(r, tmin);
-        xj = xb[min(s.index(P), last_index)];
+        xj = xb[min(s.index(sy, sz), last_index)];
     }
     return f;
 }
