@@ -157,6 +157,9 @@ struct SensGeom {
     int32_t nx, ny, nz, n_phi;
     double ox, oy, oz, vx, vy, vz;
     double R, H, tan_lmax;  // tan_lmax <= 0: no cut
+    // symmetries of the voxel-centre lattice that the acceptance shares
+    // (set by the launcher): mirror in x, in y, in z, and the x <-> y swap
+    int32_t sym_x, sym_y, sym_z, sym_xy;
 };
 hipError_t launch_sensitivity(const Launch &L, const SensGeom &g, float *s);
 

@@ -16,7 +16,15 @@
 // thread owns one (x, y) column and a run of z voxels and reuses the two
 // roots for all of them.  The integrand is FP32 (stable root formulas, no
 // cancellation); each voxel's quadrature sum is accumulated in FP64.
+// The acceptance is invariant under x -> -x, y -> -y, x <-> y (rotations
+// and reflections of the barrel) and z -> -z, and so is the midpoint rule
+// on n_phi nodes (n_phi a multiple of 4 for the swap).  When the voxel
+// lattice is symmetric too, only one representative per orbit is
+// integrated (1/16 of the voxels for a centred square grid) and its value
+// written to every image.
 #include "lmtof_internal.h"
+
+#include <cmath>
 
 namespace lmtof {
 namespace {
@@ -24,6 +32,26 @@ namespace {
 constexpr int kSensBlock = 256;
 constexpr int kSensZ = 16;      // z voxels per thread
 constexpr int kMaxPhi = 4096;   // LDS table capacity (32 KB)
+
+// Representative columns: x offsets [hx, nx) when mirrored in x (hx =
+// nx / 2; an odd centre column maps to itself), else [0, nx); likewise y;
+// with the x <-> y swap only dy <= dx of the (square) quadrant.
+struct SensDomain {
+    int hx, hy, hz, mx, my, mz;  // first representative index and count per axis
+    int64_t ncol;                // representative columns
+};
+
+__host__ __device__ __forceinline__ SensDomain sens_domain(const SensGeom &g) {
+    SensDomain d;
+    d.hx = g.sym_x ? g.nx / 2 : 0;
+    d.hy = g.sym_y ? g.ny / 2 : 0;
+    d.hz = g.sym_z ? g.nz / 2 : 0;
+    d.mx = g.nx - d.hx;
+    d.my = g.ny - d.hy;
+    d.mz = g.nz - d.hz;
+    d.ncol = g.sym_xy ? (int64_t)d.mx * (d.mx + 1) / 2 : (int64_t)d.mx * d.my;
+    return d;
+}
 
 __global__ void __launch_bounds__(kSensBlock) k_sensitivity(SensGeom g, float *__restrict__ s) {
     __shared__ float2 cs[kMaxPhi];
@@ -33,19 +61,29 @@ __global__ void __launch_bounds__(kSensBlock) k_sensitivity(SensGeom g, float *_
         cs[k] = make_float2(cn, sn);
     }
     __syncthreads();
-    const int zblocks = (g.nz + kSensZ - 1) / kSensZ;
+    const SensDomain D = sens_domain(g);
+    const int zblocks = (D.mz + kSensZ - 1) / kSensZ;
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t ncol = (int64_t)g.nx * g.ny;
-    if (tid >= ncol * zblocks) return;
-    const int64_t col = tid % ncol;
-    const int zb = (int)(tid / ncol);
-    const int ix = (int)(col % g.nx), iy = (int)(col / g.nx);
+    if (tid >= D.ncol * zblocks) return;
+    const int64_t col = tid % D.ncol;
+    const int zb = (int)(tid / D.ncol);
+    int dx, dy;
+    if (g.sym_xy) {  // col = dx (dx + 1) / 2 + dy, 0 <= dy <= dx
+        dx = (int)((sqrtf(8.0f * (float)col + 1.0f) - 1.0f) * 0.5f);
+        while ((int64_t)dx * (dx + 1) / 2 > col) --dx;
+        while ((int64_t)(dx + 1) * (dx + 2) / 2 <= col) ++dx;
+        dy = (int)(col - (int64_t)dx * (dx + 1) / 2);
+    } else {
+        dx = (int)(col % D.mx);
+        dy = (int)(col / D.mx);
+    }
+    const int ix = D.hx + dx, iy = D.hy + dy;
     const float px = (float)(g.ox + (ix + 0.5) * g.vx);
     const float py = (float)(g.oy + (iy + 0.5) * g.vy);
     const float R = (float)g.R, H = (float)g.H;
     const float r = sqrtf(px * px + py * py);
     const float c = (R - r) * (R + r);  // R^2 - |p|^2 > 0 inside the barrel
-    const int z0 = zb * kSensZ;
+    const int z0 = D.hz + zb * kSensZ;
     const int nzl = min(kSensZ, g.nz - z0);
     float hm[kSensZ], hp[kSensZ];       // H - z, H + z
     double acc[kSensZ];
@@ -85,9 +123,26 @@ __global__ void __launch_bounds__(kSensBlock) k_sensitivity(SensGeom g, float *_
         }
     }
     const double scale = (2.0 * 3.14159265358979323846 / g.n_phi) / (4.0 * 3.14159265358979323846);
+    // images of (ix, iy) under the x/y mirrors and the swap
+    int cx[8], cy[8];
+    int nc = 0;
+    for (int sw = 0; sw < (g.sym_xy ? 2 : 1); ++sw) {
+        const int ax = sw ? iy : ix, ay = sw ? ix : iy;
+        for (int fx = 0; fx < (g.sym_x ? 2 : 1); ++fx)
+            for (int fy = 0; fy < (g.sym_y ? 2 : 1); ++fy) {
+                cx[nc] = fx ? g.nx - 1 - ax : ax;
+                cy[nc] = fy ? g.ny - 1 - ay : ay;
+                ++nc;
+            }
+    }
+    const int64_t plane = (int64_t)g.nx * g.ny;
     for (int q = 0; q < nzl; ++q) {
-        const int64_t j = col + ncol * (int64_t)(z0 + q);
-        s[j] = (c > 0.0f) ? (float)(acc[q] * scale) : 0.0f;
+        const float v = (c > 0.0f) ? (float)(acc[q] * scale) : 0.0f;
+        const int iz = z0 + q;
+        for (int fz = 0; fz < (g.sym_z ? 2 : 1); ++fz) {
+            const int64_t zo = plane * (fz ? g.nz - 1 - iz : iz);
+            for (int m = 0; m < nc; ++m) s[zo + cx[m] + (int64_t)g.nx * cy[m]] = v;
+        }
     }
 }
 
@@ -95,10 +150,20 @@ __global__ void __launch_bounds__(kSensBlock) k_sensitivity(SensGeom g, float *_
 
 hipError_t launch_sensitivity(const Launch &L, const SensGeom &g, float *s) {
     if (g.n_phi < 1 || g.n_phi > kMaxPhi) return hipErrorInvalidValue;
-    const int64_t ncol = (int64_t)g.nx * g.ny;
-    const int64_t nthreads = ncol * ((g.nz + kSensZ - 1) / kSensZ);
-    const unsigned grid = (unsigned)((nthreads + kSensBlock - 1) / kSensBlock);
     SensGeom gg = g;
+    // a lattice axis is mirror-symmetric when the grid is centred on it (to
+    // a millionth of a voxel; the FP32 centre coordinates then agree to
+    // rounding); the azimuth nodes are symmetric for even n_phi, and under
+    // the swap for n_phi divisible by 4
+    auto centred = [](double o, int n, double v) { return std::fabs(o + 0.5 * n * v) <= 1e-6 * v; };
+    const bool even = g.n_phi % 2 == 0;
+    gg.sym_x = even && centred(g.ox, g.nx, g.vx);
+    gg.sym_y = even && centred(g.oy, g.ny, g.vy);
+    gg.sym_z = centred(g.oz, g.nz, g.vz);
+    gg.sym_xy = gg.sym_x && gg.sym_y && g.n_phi % 4 == 0 && g.nx == g.ny && g.vx == g.vy;
+    const SensDomain D = sens_domain(gg);
+    const int64_t nthreads = D.ncol * ((D.mz + kSensZ - 1) / kSensZ);
+    const unsigned grid = (unsigned)((nthreads + kSensBlock - 1) / kSensBlock);
     void *args[] = {&gg, &s};
     return do_launch(L, reinterpret_cast<const void *>(&k_sensitivity), dim3(grid), dim3(kSensBlock), 0, args);
 }

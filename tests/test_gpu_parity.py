@@ -59,6 +59,30 @@ def test_sensitivity_cylinder_full_grid(c1):
     assert rel.max() < 1e-5
 
 
+@pytest.mark.parametrize("shape", [
+    # centred, odd sizes: the centre row, column and slice map to themselves
+    dict(nx=9, ny=9, nz=7, vx=5.0, vy=5.0, vz=6.0, x0=-22.5, y0=-22.5, z0=-21.0),
+    # centred in x and z only, non-square: no y mirror, no x <-> y swap
+    dict(nx=10, ny=7, nz=8, vx=4.0, vy=4.0, vz=5.0, x0=-20.0, y0=-11.0, z0=-20.0),
+    # nothing centred
+    dict(nx=6, ny=5, nz=5, vx=4.0, vy=3.0, vz=5.0, x0=-9.0, y0=-7.0, z0=-13.0),
+])
+def test_sensitivity_symmetry_cases(shape):
+    """The kernel integrates one voxel per symmetry orbit of the lattice and
+    copies it to the others; check every branch against the oracle."""
+    _say(f"case: sensitivity symmetry {shape}")
+    g = dict(shape, scanner_radius=60.0, scanner_half_length=40.0, max_axial_angle_deg=45.0,
+             tof_fwhm_ps=300.0, tof_trunc_sigmas=3.0, c_mm_per_ps=0.299792458)
+    ev = synth.random_events_in_box(10, 5, 60.0, 40.0, tof_sigma_ps=60.0, box=8.0).astype(np.float32)
+    with _recon(g, ev) as r:
+        r.compute_sensitivity()
+        s = r.read_sensitivity()
+    ref = oracle.sensitivity(g)
+    rel = np.abs(s - ref) / ref.max()
+    _say(f"  max rel err {rel.max():.2e}")
+    assert rel.max() < 1e-5
+
+
 def test_sensitivity_wholebody_sampled_voxels():
     _say("case: sensitivity 150x150x600 sampled")
     w = synth.wholebody_workload(n_events=1000)
