@@ -48,10 +48,10 @@ struct ItemSet {
     unsigned long long *tiles = nullptr;
     float *wmax = nullptr;
     uint32_t *pairs = nullptr, *pair_off = nullptr;  // (forward chunk) lists per brick
-    char *item_events = nullptr;                      // event record copies in item order
+    char *item_recs = nullptr;                        // walk records in item order (40 B each)
     size_t item_bytes = 0;
     // capacities of the large arrays, kept across rebuilds of the lists
-    size_t items_cap = 0, item_events_cap = 0, tiles_cap = 0, pairs_cap = 0;
+    size_t items_cap = 0, item_recs_cap = 0, tiles_cap = 0, pairs_cap = 0;
     uint32_t n_chunks = 0, n_bricks = 0, n_slots = 0;
     uint64_t n_items = 0, n_pairs = 0;
     std::vector<uint4> h_chunks, h_bricks;  // host copies (batching several problems)
@@ -160,7 +160,7 @@ void free_items(ItemSet &it) {
     dev_free(it.wmax);
     dev_free(it.pairs);
     dev_free(it.pair_off);
-    dev_free(it.item_events);
+    dev_free(it.item_recs);
     it = ItemSet();
 }
 
@@ -335,11 +335,11 @@ int build_items(lmtof_ctx *c, std::vector<Problem> &ps, Problem *d_probs, int64_
     // of a similar size then allocates nothing large)
     ItemSet keep;
     std::swap(keep.items, out.items);
-    std::swap(keep.item_events, out.item_events);
+    std::swap(keep.item_recs, out.item_recs);
     std::swap(keep.tiles, out.tiles);
     std::swap(keep.pairs, out.pairs);
     keep.items_cap = out.items_cap;
-    keep.item_events_cap = out.item_events_cap;
+    keep.item_recs_cap = out.item_recs_cap;
     keep.tiles_cap = out.tiles_cap;
     keep.pairs_cap = out.pairs_cap;
     free_items(out);
@@ -426,7 +426,7 @@ int build_items(lmtof_ctx *c, std::vector<Problem> &ps, Problem *d_probs, int64_
         (rc = dev_alloc(c, &it.chunks, chunks.size())) || (rc = dev_alloc(c, &it.bricks, bricks.size())) ||
         (rc = reserve(c, &it.tiles, it.tiles_cap, (size_t)slot * kBrickVox)) || (rc = dev_alloc(c, &it.wmax, slot)) ||
         (rc = reserve(c, &it.pairs, it.pairs_cap, ptot)) || (rc = dev_alloc(c, &it.pair_off, nb + 1)) ||
-        (rc = reserve(c, &it.item_events, it.item_events_cap, tot * (c->stored_packed ? 16 : 32)))) {
+        (rc = reserve(c, &it.item_recs, it.item_recs_cap, (size_t)tot * kItemRecBytes))) {
         free_tmp();
         free_items(it);
         return rc;
@@ -437,9 +437,11 @@ int build_items(lmtof_ctx *c, std::vector<Problem> &ps, Problem *d_probs, int64_
         P.wmax = it.wmax;
         P.pairs = it.pairs;
         P.pair_off = it.pair_off + P.brick_base;
-        P.item_events = it.item_events;
+        P.rec_a = reinterpret_cast<const float4 *>(it.item_recs);
+        P.rec_b = reinterpret_cast<const float4 *>(it.item_recs + (size_t)tot * 16);
+        P.rec_k = reinterpret_cast<const uint2 *>(it.item_recs + (size_t)tot * 32);
     }
-    it.item_bytes = (size_t)tot * (c->stored_packed ? 16 : 32);
+    it.item_bytes = (size_t)tot * kItemRecBytes;
     he = hipMemcpyAsync(d_probs, ps.data(), sizeof(Problem) * ps.size(), hipMemcpyHostToDevice, c->stream);
     if (he == hipSuccess)
         he = hipMemcpyAsync(off_d, offk.data(), sizeof(uint32_t) * (nk + 1), hipMemcpyHostToDevice, c->stream);
@@ -733,7 +735,7 @@ int64_t ctx_device_bytes(const lmtof_ctx *c) {
     const int64_t esz = c->stored_packed ? 16 : 32;
     int64_t b = c->n_events * (esz + 8 + 4) + 3 * 4 * c->V;
     b += (int64_t)c->items.n_items * 4 + (int64_t)c->items.n_slots * (kBrickVox * 8 + 4);
-    b += (int64_t)c->items.pairs_cap * 4 + (int64_t)(c->V / kBrickVox + 64) * 4 + (int64_t)c->items.item_events_cap;
+    b += (int64_t)c->items.pairs_cap * 4 + (int64_t)(c->V / kBrickVox + 64) * 4 + (int64_t)c->items.item_recs_cap;
     b += (int64_t)(c->items.items_cap - std::min<size_t>(c->items.items_cap, c->items.n_items)) * 4;
     b += (int64_t)(c->items.tiles_cap - std::min<size_t>(c->items.tiles_cap, (size_t)c->items.n_slots * kBrickVox)) * 8;
     b += (int64_t)(c->items.n_chunks + c->items.n_bricks) * 16;
@@ -743,7 +745,7 @@ int64_t ctx_device_bytes(const lmtof_ctx *c) {
 
 // Footprint the pool reserves for a request: stored events, permutation,
 // weights, ~ (1 + 1.7 * window / brick edge) brick items per event (index
-// and event record copy) plus tiles, three images, and the transient ingest
+// and walk record) plus tiles, three images, and the transient ingest
 // buffers (raw copy, keys, sort histogram).
 int64_t request_bytes_estimate(const lmtof_request &q) {
     const lmtof_geometry &g = q.geometry;
@@ -760,7 +762,7 @@ int64_t request_bytes_estimate(const lmtof_request &q) {
     const double ipe = 1.3 * (1.0 + 1.7 * win / (kBrickX * vmin));
     const int64_t items = (int64_t)(N * ipe);
     const int64_t esz = q.storage ? 16 : 32;
-    int64_t b = N * (esz + 8 + 4) + items * (4 + esz) + 4 * 4 * V;  // x, b, s and the blocked copy of x
+    int64_t b = N * (esz + 8 + 4) + items * (4 + kItemRecBytes) + 4 * 4 * V;  // x, b, s and the blocked copy of x
     b += (items / 2048 + 1 + V / kBrickVox + 1) * (int64_t)kBrickVox * 8 / 4;  // tiles
     b += items;  // (forward chunk, brick) pairs: at most one per item, ~1 in 10 in practice
     b += N * (q.mem == LMTOF_MEM_HOST ? 28 : 0) + N * (esz + 8 + 4);       // ingest transients

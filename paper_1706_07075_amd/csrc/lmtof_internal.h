@@ -17,6 +17,8 @@ constexpr int kBrickVox = kBrickX * kBrickY * kBrickZ;
 // Brick items are grouped by an estimate of their voxel pieces in the brick
 // (longest first), so that a wavefront's lanes walk similar lengths.
 constexpr int kItemClasses = 4;
+// Bytes of one brick item's walk record (two float4 and one uint2).
+constexpr int kItemRecBytes = 40;
 constexpr int kForwardBlock = 256;
 constexpr int kBackBlock = 512;
 
@@ -31,7 +33,12 @@ struct Problem {
     const float *s;       // sensitivity
     float *rw;            // per event of this problem: 1 / f (MLEM) or a back-projection weight
     const uint32_t *items;// brick item list array (problem-local event indices) the chunks index
-    const void *item_events;  // per item: a copy of its stored event record (read contiguously by chunks)
+    // per item, its walk inside the brick, precomputed when the lists are
+    // built: (A_x, A_y, A_z, t_a), (B_x, B_y, B_z, t_b), (k_x | k_y << 16,
+    // k_z | local voxel << 16) with k the first plane index minus the anchor
+    const float4 *rec_a;
+    const float4 *rec_b;
+    const uint2 *rec_k;
     unsigned long long *tiles;  // 64-bit fixed-point chunk tiles, indexed by tile slot
     float *wmax;          // per brick, at its first tile slot: bound on |w| over its items
     const uint32_t *pairs;    // per brick: the problem-local forward chunks holding its items

@@ -44,6 +44,7 @@ namespace {
 constexpr float kInf = __builtin_huge_valf();
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 // Device-memory views: pointers read from the problem table are generic;
 // casting them to the global address space lets loads and stores use the
@@ -212,19 +213,6 @@ __device__ __forceinline__ bool make_ray(const Problem &P, int64_t i, Ray &r) {
     return make_ray_from<PACKED>(P, P.events, i, r);
 }
 
-// Copy stored event record i to slot k of an item record array.
-template <bool PACKED>
-__device__ __forceinline__ void copy_record(const void *events, int64_t i, void *dst, uint32_t k) {
-    if (PACKED) {
-        global(reinterpret_cast<u32x4 *>(dst))[k] = global(reinterpret_cast<const u32x4 *>(events))[i];
-    } else {
-        const gptr<const f32x4> e = global(reinterpret_cast<const f32x4 *>(events)) + 2 * i;
-        const gptr<f32x4> d = global(reinterpret_cast<f32x4 *>(dst)) + 2 * (size_t)k;
-        d[0] = e[0];
-        d[1] = e[1];
-    }
-}
-
 // Voxel index along one axis at parameter t.
 __device__ __forceinline__ int voxel_at(float t, float u, int j, float d, float iv) {
 #pragma clang fp contract(off)
@@ -285,6 +273,24 @@ struct Stepper {
         djy = py ? B.sy : -B.sy;
         djz = pz ? B.sz : -B.sz;
         max_steps = B.nx + B.ny + B.nz + 2;
+    }
+    // Start from a brick item's walk record (brick strides, see the item lists).
+    __device__ __forceinline__ Stepper(const Ray &r, uint2 rk) {
+        const bool px = r.ax > 0.0f, py = r.ay > 0.0f, pz = r.az > 0.0f;  // A has the sign of u
+        sx = px ? 1.0f : -1.0f;
+        sy = py ? 1.0f : -1.0f;
+        sz = pz ? 1.0f : -1.0f;
+        kx = (float)(int16_t)(rk.x & 0xffffu);
+        ky = (float)(int16_t)(rk.x >> 16);
+        kz = (float)(int16_t)(rk.y & 0xffffu);
+        tx = fmaf(kx, r.ax, r.bx);
+        ty = fmaf(ky, r.ay, r.by);
+        tz = fmaf(kz, r.az, r.bz);
+        j = (int)(rk.y >> 16);
+        djx = px ? 1 : -1;
+        djy = py ? kBrickX : -kBrickX;
+        djz = pz ? kBrickX * kBrickY : -kBrickX * kBrickY;
+        max_steps = kBrickX + kBrickY + kBrickZ + 2;
     }
     __device__ __forceinline__ float next() const { return fminf(fminf(tx, ty), tz); }
     __device__ __forceinline__ void advance(const Ray &r, float tmin) {
@@ -361,9 +367,19 @@ struct StepperB {
 // zero-length piece (a = 0).  The piece [t, t'] ends at the next crossing
 // clamped into [t, tb].
 template <bool TOF, class Visit>
+__device__ __forceinline__ void walk_from(Stepper &s, const Ray &r, float ta, float tb, const Cdf &cdf,
+                                          Visit &&visit);
+
+template <bool TOF, class Visit>
 __device__ __forceinline__ void walk(const Problem &P, const Ray &r, float ta, float tb, const Box &B,
                                      const Cdf &cdf, Visit &&visit) {
     Stepper s(P, r, ta, B);
+    walk_from<TOF>(s, r, ta, tb, cdf, visit);
+}
+
+template <bool TOF, class Visit>
+__device__ __forceinline__ void walk_from(Stepper &s, const Ray &r, float ta, float tb, const Cdf &cdf,
+                                          Visit &&visit) {
     float t = ta;
     float c = TOF ? cdf(ta) : 0.0f;
     for (int step = 0; step < s.max_steps; ++step) {
@@ -630,36 +646,43 @@ __device__ __forceinline__ unsigned long long fixed_nonneg(float v) {
     return ((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo;
 }
 
-// One item's pieces in brick box B, added to the tile as round(a |ws|),
-// subtracted when ws < 0.  A weight a is clamped at 0 (the interpolated
-// CDF may dip by ~1e-10 between nodes).
-template <bool TOF, bool PACKED>
-__device__ __forceinline__ void back_item(const Problem &P, uint32_t k, float ws, const Box &B, const Cdf &cdf,
+// One item's pieces in its brick, from its walk record, added to the tile
+// as round(a |ws|), subtracted when ws < 0.  A weight a is clamped at 0
+// (the interpolated CDF may dip by ~1e-10 between nodes).
+template <bool TOF>
+__device__ __forceinline__ void back_item(const Problem &P, uint32_t k, float ws, const Cdf &cdf,
                                           unsigned long long *tile) {
+    const f32x4 ra = global(reinterpret_cast<const f32x4 *>(P.rec_a))[k];
+    const f32x4 rb = global(reinterpret_cast<const f32x4 *>(P.rec_b))[k];
+    const u32x2 rk = global(reinterpret_cast<const u32x2 *>(P.rec_k))[k];
     Ray r;
-    if (!make_ray_from<PACKED>(P, P.item_events, (int64_t)k, r)) return;
-    float ta, tb;
-    clip_to_box(P, r, B, ta, tb);
-    if (!(ta < tb)) return;
+    r.ax = ra[0];
+    r.ay = ra[1];
+    r.az = ra[2];
+    r.bx = rb[0];
+    r.by = rb[1];
+    r.bz = rb[2];
+    Stepper s(r, make_uint2(rk[0], rk[1]));
+    const float ta = ra[3], tb = rb[3];
     if (ws > 0.0f) {
-        walk<TOF>(P, r, ta, tb, B, cdf, [&](int j, float a) {
+        walk_from<TOF>(s, r, ta, tb, cdf, [&](int j, float a) {
             atomicAdd(&tile[j & (kBrickVox - 1)], fixed_nonneg(fmaxf(a, 0.0f) * ws));
         });
     } else {
-        walk<TOF>(P, r, ta, tb, B, cdf, [&](int j, float a) {
+        walk_from<TOF>(s, r, ta, tb, cdf, [&](int j, float a) {
             atomicSub(&tile[j & (kBrickVox - 1)], fixed_nonneg(fmaxf(a, 0.0f) * -ws));
         });
     }
 }
 
-template <bool TOF, bool PACKED>
-__device__ __forceinline__ void back_chunk_items(const Problem &P, const uint4 &ch, float S, const Box &B,
-                                                 const Cdf &cdf, unsigned long long *tile) {
+template <bool TOF>
+__device__ __forceinline__ void back_chunk_items(const Problem &P, const uint4 &ch, float S, const Cdf &cdf,
+                                                 unsigned long long *tile) {
     const gptr<const uint32_t> items = global(P.items);
     const gptr<const float> w = global(P.rw);
     for (uint32_t k = ch.y + threadIdx.x; k < ch.z; k += blockDim.x) {
         const float ws = w[items[k]] * S;
-        if (ws != 0.0f) back_item<TOF, PACKED>(P, k, ws, B, cdf, tile);
+        if (ws != 0.0f) back_item<TOF>(P, k, ws, cdf, tile);
     }
 }
 
@@ -675,10 +698,6 @@ __global__ void __launch_bounds__(kBackBlock) k_back_chunks(const Problem *__res
     const uint4 br = bricks[ch.x];
     const uint32_t bid = br.x;
     const Problem P = probs[find_brick_problem(probs, n_probs, bid)];
-    const uint32_t bl = bid - (uint32_t)P.brick_base;
-    const int bx = (int)(bl % (uint32_t)P.nbx), by = (int)((bl / (uint32_t)P.nbx) % (uint32_t)P.nby),
-              bz = (int)(bl / ((uint32_t)P.nbx * (uint32_t)P.nby));
-    const Box B = brick_box(P, bx, by, bz);
     for (int k = threadIdx.x; k < kBrickVox; k += blockDim.x) tile[k] = 0ull;
     if (TOF) stage_lut(lut, P.lut);
     __syncthreads();
@@ -686,12 +705,7 @@ __global__ void __launch_bounds__(kBackBlock) k_back_chunks(const Problem *__res
     const int e = brick_exponent(P, br, wm);
     const float S = ldexpf(1.0f, e);
     const Cdf cdf{lut, P.lut_a, P.lut_b};
-    if (wm > 0.0f) {
-        if (P.packed)
-            back_chunk_items<TOF, true>(P, ch, S, B, cdf, tile);
-        else
-            back_chunk_items<TOF, false>(P, ch, S, B, cdf, tile);
-    }
+    if (wm > 0.0f) back_chunk_items<TOF>(P, ch, S, cdf, tile);
     __syncthreads();
     const gptr<unsigned long long> dst = global(P.tiles) + (size_t)ch.w * kBrickVox;
     for (int k = threadIdx.x; k < kBrickVox; k += blockDim.x) dst[k] = tile[k];
@@ -796,14 +810,40 @@ __device__ __forceinline__ void brick_walk(const Problem &P, const Ray &r, Visit
 // Brick item lists, counted and filled per (brick, item class) key =
 // brick * kItemClasses + class.  Counting (fill == 0): ctr[key] += pieces.
 // Filling: every piece gets a position from ctr[key]++ (never past
-// end[key]); P.items[position] = its problem-local event index and
-// P.item_events[position] = a copy of the event record, so that the back
-// projection streams a chunk's events instead of gathering them (each
-// event is read once per brick it crosses).  A block first tallies
+// end[key]); P.items[position] = its problem-local event index and the
+// item's walk record (crossing coefficients, its piece of the window, first
+// voxel), so that the back projection streams a chunk's records instead of
+// gathering events and re-deriving rays (each event is walked once per
+// brick it crosses).  A block first tallies
 // its pieces per brick in an LDS hash table, then touches each global
 // counter once (bucketed events make whole blocks hit the same few bricks,
 // and same-address global atomics serialise); when filling, the block then
 // re-walks its events and hands out positions from its reserved ranges.
+// Walk record of a brick item at position pos: the crossing coefficients,
+// the piece [ta, tb] of the window inside the brick (as the brick walk cut
+// it) and the first voxel, as the back projection's walk starts from them.
+__device__ __forceinline__ void write_item_walk(const Problem &P, const Ray &r, uint32_t brick, float ta, float tb,
+                                                uint32_t pos) {
+    const uint32_t bl = brick - (uint32_t)P.brick_base;
+    const int bx = (int)(bl % (uint32_t)P.nbx), by = (int)((bl / (uint32_t)P.nbx) % (uint32_t)P.nby),
+              bz = (int)(bl / ((uint32_t)P.nbx * (uint32_t)P.nby));
+    const Box B = brick_box(P, bx, by, bz);
+    const int ix = min(max(voxel_at(ta, r.ux, r.jx, r.dx, P.ivx), B.x0), B.x0 + B.nx - 1);
+    const int iy = min(max(voxel_at(ta, r.uy, r.jy, r.dy, P.ivy), B.y0), B.y0 + B.ny - 1);
+    const int iz = min(max(voxel_at(ta, r.uz, r.jz, r.dz, P.ivz), B.z0), B.z0 + B.nz - 1);
+    const int kx = ix + (r.ux > 0.0f) - r.jx, ky = iy + (r.uy > 0.0f) - r.jy, kz = iz + (r.uz > 0.0f) - r.jz;
+    const uint32_t j = (uint32_t)((ix - B.x0) + kBrickX * ((iy - B.y0) + kBrickY * (iz - B.z0)));
+    f32x4 a, b;
+    a[0] = r.ax; a[1] = r.ay; a[2] = r.az; a[3] = ta;
+    b[0] = r.bx; b[1] = r.by; b[2] = r.bz; b[3] = tb;
+    u32x2 k;
+    k[0] = ((uint32_t)kx & 0xffffu) | ((uint32_t)ky << 16);
+    k[1] = ((uint32_t)kz & 0xffffu) | (j << 16);
+    global(reinterpret_cast<f32x4 *>(const_cast<float4 *>(P.rec_a)))[pos] = a;
+    global(reinterpret_cast<f32x4 *>(const_cast<float4 *>(P.rec_b)))[pos] = b;
+    global(reinterpret_cast<u32x2 *>(const_cast<uint2 *>(P.rec_k)))[pos] = k;
+}
+
 // Item class of a brick piece [t0, t1] of ray r: 0 for the longest walks
 // (estimated plane crossings (t1 - t0) sum_a |u_a| / v_a of 16 or more),
 // then 9-15, 4-8, and 3 or fewer.
@@ -840,7 +880,7 @@ __device__ __forceinline__ void brick_items_pass(const Problem &P, int64_t base,
                 const uint32_t pos = atomicAdd(ctr + key, 1u);
                 if (fill && pos < end[key]) {
                     items[pos] = (uint32_t)i;
-                    copy_record<PACKED>(P.events, i, const_cast<void *>(P.item_events), pos);
+                    write_item_walk(P, r, brick, t0, t1, pos);
                 }
                 pair(key);
             }
@@ -869,7 +909,7 @@ __device__ __forceinline__ void brick_items_pass(const Problem &P, int64_t base,
             const uint32_t pos = hbase[h] + atomicAdd(&hcnt[h], 1u);
             if (pos < end[key]) {
                 items[pos] = (uint32_t)i;
-                copy_record<PACKED>(P.events, i, const_cast<void *>(P.item_events), pos);
+                write_item_walk(P, r, brick, t0, t1, pos);
             }
         });
     }
