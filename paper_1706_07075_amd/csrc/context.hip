@@ -38,6 +38,12 @@ struct Region {
     float *x = nullptr, *b = nullptr, *s = nullptr;
 };
 
+// A device buffer kept between calls (bytes).
+struct Scratch {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
 // Brick item lists of one problem batch (see the projector): items grouped
 // by brick; chunks (brick, first item, end item, tile slot) largest first;
 // per non-empty brick its tile slots (brick, first slot, end slot); the
@@ -78,6 +84,12 @@ struct lmtof_ctx {
     int stored_packed = 0;
     void *d_events = nullptr;
     int64_t *d_perm = nullptr;  // stored position -> caller index
+    size_t events_cap = 0, perm_cap = 0;  // their allocation sizes (bytes)
+    // buffers kept between loads: the spare event store and permutation a
+    // load or region split writes into (then swapped with the current
+    // ones), and the sort's keys, histogram, scan scratch, error flag and
+    // intermediate permutation
+    Scratch sc_events, sc_perm, sc_keys, sc_hist, sc_tmp, sc_err, sc_inner;
 
     // whole-volume images
     float *d_s = nullptr, *d_x = nullptr, *d_b = nullptr;
@@ -152,6 +164,29 @@ void dev_free(T *&p) {
     p = nullptr;
 }
 
+// (Re)size a reusable buffer: kept when it already holds n elements, so
+// repeated loads of similar size allocate nothing large.
+template <class T>
+int take(lmtof_ctx *c, Scratch &s, T **out, size_t n) {
+    const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+    if (!s.p || s.cap < bytes) {
+        dev_free(s.p);
+        s.cap = 0;
+        char *q = nullptr;
+        int rc = dev_alloc(c, &q, bytes);
+        if (rc) return rc;
+        s.p = q;
+        s.cap = bytes;
+    }
+    *out = static_cast<T *>(s.p);
+    return LMTOF_OK;
+}
+
+void scratch_free(Scratch &s) {
+    dev_free(s.p);
+    s.cap = 0;
+}
+
 void free_items(ItemSet &it) {
     dev_free(it.items);
     dev_free(it.chunks);
@@ -187,11 +222,29 @@ void drop_regions(lmtof_ctx *c) {
 void drop_events(lmtof_ctx *c) {
     dev_free(c->d_events);
     dev_free(c->d_perm);
+    c->events_cap = c->perm_cap = 0;
     c->n_events = 0;
     c->has_image = false;
     drop_regions(c);
     drop_graphs(c);
     c->probs_dirty = true;
+}
+
+// Make (store, perm), taken from the spare buffers, the current events; the
+// previous current buffers become the spares.
+void install_events(lmtof_ctx *c) {
+    std::swap(c->d_events, c->sc_events.p);
+    std::swap(c->events_cap, c->sc_events.cap);
+    void *pp = c->d_perm;
+    c->d_perm = static_cast<int64_t *>(c->sc_perm.p);
+    c->sc_perm.p = pp;
+    std::swap(c->perm_cap, c->sc_perm.cap);
+}
+
+// Free the buffers kept for the next load (a served request loads once).
+void release_load_scratch(lmtof_ctx *c) {
+    for (Scratch *sc : {&c->sc_events, &c->sc_perm, &c->sc_keys, &c->sc_hist, &c->sc_tmp, &c->sc_err, &c->sc_inner})
+        scratch_free(*sc);
 }
 
 double sigma_mm(const lmtof_geometry &g) {
@@ -732,8 +785,10 @@ KeyGeom key_geom(const lmtof_ctx *c, bool sort, const std::vector<Region> &regio
 // Device bytes a prepared context holds (events, permutation, per-event
 // weights, brick lists and tiles, images, partials).
 int64_t ctx_device_bytes(const lmtof_ctx *c) {
-    const int64_t esz = c->stored_packed ? 16 : 32;
-    int64_t b = c->n_events * (esz + 8 + 4) + 3 * 4 * c->V;
+    int64_t b = (int64_t)(c->events_cap + c->perm_cap) + c->n_events * 4 + 3 * 4 * c->V;
+    for (const Scratch *sc : {&c->sc_events, &c->sc_perm, &c->sc_keys, &c->sc_hist, &c->sc_tmp, &c->sc_err,
+                              &c->sc_inner})
+        b += (int64_t)sc->cap;
     b += (int64_t)c->items.n_items * 4 + (int64_t)c->items.n_slots * (kBrickVox * 8 + 4);
     b += (int64_t)c->items.pairs_cap * 4 + (int64_t)(c->V / kBrickVox + 64) * 4 + (int64_t)c->items.item_recs_cap;
     b += (int64_t)(c->items.items_cap - std::min<size_t>(c->items.items_cap, c->items.n_items)) * 4;
@@ -827,6 +882,8 @@ int lmtof_destroy(lmtof_ctx *c) {
     dev_free(c->d_x);
     dev_free(c->d_b);
     dev_free(c->d_xb);
+    for (Scratch *sc : {&c->sc_events, &c->sc_perm, &c->sc_keys, &c->sc_hist, &c->sc_tmp, &c->sc_err, &c->sc_inner})
+        scratch_free(*sc);
     dev_free(c->d_probs);
     dev_free(c->d_part_neff);
     dev_free(c->d_part_wmax);
@@ -964,18 +1021,12 @@ int lmtof_load_events(lmtof_ctx *c, const void *ev, int64_t n, int format, int m
     L.stream = c->stream;
     int rc;
     void *raw = nullptr;
-    void *store = nullptr;
+    char *store = nullptr;
     int64_t *perm = nullptr;
     uint32_t *keys = nullptr, *hist = nullptr, *tmp = nullptr, *err = nullptr;
     auto cleanup = [&]() {
         (void)hipStreamSynchronize(c->stream);
         if (mem == LMTOF_MEM_HOST) dev_free(raw);
-        dev_free(store);
-        dev_free(perm);
-        dev_free(keys);
-        dev_free(hist);
-        dev_free(tmp);
-        dev_free(err);
     };
     if (mem == LMTOF_MEM_HOST) {
         if ((rc = dev_alloc(c, (char **)&raw, raw_sz * n))) return rc;
@@ -983,8 +1034,9 @@ int lmtof_load_events(lmtof_ctx *c, const void *ev, int64_t n, int format, int m
     } else {
         raw = const_cast<void *>(ev);
     }
-    if ((rc = dev_alloc(c, (char **)&store, st_sz * n)) || (rc = dev_alloc(c, &perm, n)) ||
-        (rc = dev_alloc(c, &err, 1))) {
+    // the current events stay valid until the new ones are complete
+    if ((rc = take(c, c->sc_events, &store, st_sz * n)) || (rc = take(c, c->sc_perm, &perm, n)) ||
+        (rc = take(c, c->sc_err, &err, 1))) {
         cleanup();
         return rc;
     }
@@ -994,8 +1046,8 @@ int lmtof_load_events(lmtof_ctx *c, const void *ev, int64_t n, int format, int m
     KeyGeom kg = key_geom(c, sort, std::vector<Region>());
     uint32_t nkeys = key_count(kg);
     if (he == hipSuccess && sort) {
-        if ((rc = dev_alloc(c, &keys, n)) || (rc = dev_alloc(c, &hist, nkeys)) ||
-            (rc = dev_alloc(c, &tmp, scan_tmp_elems(nkeys)))) {
+        if ((rc = take(c, c->sc_keys, &keys, n)) || (rc = take(c, c->sc_hist, &hist, nkeys)) ||
+            (rc = take(c, c->sc_tmp, &tmp, scan_tmp_elems(nkeys)))) {
             cleanup();
             return rc;
         }
@@ -1025,11 +1077,10 @@ int lmtof_load_events(lmtof_ctx *c, const void *ev, int64_t n, int format, int m
         cleanup();
         return fail(c, LMTOF_EHIP, "event scatter: %s", hipGetErrorString(he));
     }
-    drop_events(c);
-    c->d_events = store;
-    c->d_perm = perm;
-    store = nullptr;
-    perm = nullptr;
+    c->has_image = false;
+    drop_regions(c);
+    drop_graphs(c);
+    install_events(c);
     c->n_events = n;
     c->stored_packed = packed;
     c->probs_dirty = true;
@@ -1476,20 +1527,18 @@ int lmtof_set_regions(lmtof_ctx *c, const int32_t *zb, int n, int margin) {
     L.stream = c->stream;
     uint32_t *keys = nullptr, *hist = nullptr, *tmp = nullptr, *err = nullptr;
     int64_t *inner = nullptr, *perm = nullptr;
-    void *store = nullptr;
+    char *store = nullptr;
     const int64_t plane = (int64_t)g.nx * g.ny;
     auto cleanup = [&](int rc) {
         (void)hipStreamSynchronize(c->stream);
-        dev_free(keys); dev_free(hist); dev_free(tmp); dev_free(err);
-        dev_free(inner); dev_free(perm); dev_free(store);
         for (auto &r : regs) { dev_free(r.x); dev_free(r.b); dev_free(r.s); }
         return rc;
     };
     int rc;
-    if ((rc = dev_alloc(c, &keys, N)) || (rc = dev_alloc(c, &hist, nkeys)) ||
-        (rc = dev_alloc(c, &tmp, scan_tmp_elems(nkeys))) || (rc = dev_alloc(c, &err, 1)) ||
-        (rc = dev_alloc(c, &inner, N)) || (rc = dev_alloc(c, &perm, N)) ||
-        (rc = dev_alloc(c, (char **)&store, esz * N)))
+    if ((rc = take(c, c->sc_keys, &keys, N)) || (rc = take(c, c->sc_hist, &hist, nkeys)) ||
+        (rc = take(c, c->sc_tmp, &tmp, scan_tmp_elems(nkeys))) || (rc = take(c, c->sc_err, &err, 1)) ||
+        (rc = take(c, c->sc_inner, &inner, N)) || (rc = take(c, c->sc_perm, &perm, N)) ||
+        (rc = take(c, c->sc_events, &store, esz * N)))
         return cleanup(rc);
     for (auto &r : regs) {
         const int64_t Vr = plane * r.nz;
@@ -1522,8 +1571,7 @@ int lmtof_set_regions(lmtof_ctx *c, const int32_t *zb, int n, int margin) {
     // install: new event order, new permutation, region buffers
     drop_regions(c);
     drop_graphs(c);
-    std::swap(c->d_events, store);
-    std::swap(c->d_perm, perm);
+    install_events(c);
     c->regions = regs;
     for (auto &r : regs) r.x = r.b = r.s = nullptr;  // now owned by the context
     c->margin_used = margin;
@@ -1799,6 +1847,8 @@ int lmtof_pool_submit(lmtof_pool *p, const lmtof_request *q, int64_t *id) {
     if ((rc = lmtof_load_events(c, q->events, q->n_events, q->format, q->mem))) return bail(rc);
     if ((rc = lmtof_compute_sensitivity(c))) return bail(rc);
     if ((rc = lmtof_set_image(c, nullptr, 0, LMTOF_MEM_HOST))) return bail(rc);
+    (void)hipStreamSynchronize(c->stream);
+    release_load_scratch(c);
     if (c->ept_used != p->ept) {  // brick pair lists index the forward chunks of this launch shape
         lmtof_destroy(c);
         return pfail(p, LMTOF_EUNSUPPORTED, "request prepared with a different launch shape");
