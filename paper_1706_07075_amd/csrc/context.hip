@@ -397,7 +397,15 @@ int build_items(lmtof_ctx *c, std::vector<Problem> &ps, Problem *d_probs, int64_
     keep.pairs_cap = out.pairs_cap;
     free_items(out);
     uint64_t nb = 0;
-    for (const auto &P : ps) nb += (uint64_t)P.nbx * P.nby * P.nbz;
+    for (const auto &P : ps) {
+        const uint64_t n = (uint64_t)P.nbx * P.nby * P.nbz;
+        if (n > (uint64_t)kMaxProblemBricks) {
+            free_items(keep);
+            return fail(c, LMTOF_EUNSUPPORTED, "grid of %llu bricks of 16^3 voxels: at most %d per problem",
+                        (unsigned long long)n, kMaxProblemBricks);
+        }
+        nb += n;
+    }
     const uint64_t nk = nb * kItemClasses;  // (brick, item class) keys
     Launch L;
     L.stream = c->stream;
@@ -524,7 +532,7 @@ int build_items(lmtof_ctx *c, std::vector<Problem> &ps, Problem *d_probs, int64_
 // after *prev, or on the stream).  In a graph, ev_a and ev_b (if given) are
 // recorded right before and right after the brick kernel, to time it alone.
 int add_back(lmtof_ctx *c, Launch L, const Problem *d_probs, int np, const ItemSet &it, const float *part_wmax,
-             hipGraphNode_t *prev, hipEvent_t ev_a = nullptr, hipEvent_t ev_b = nullptr) {
+             int64_t n_part, hipGraphNode_t *prev, hipEvent_t ev_a = nullptr, hipEvent_t ev_b = nullptr) {
     const bool tof = c->g.tof_fwhm_ps > 0;
     hipGraphNode_t node = nullptr;
     if (L.graph) {
@@ -541,7 +549,7 @@ int add_back(lmtof_ctx *c, Launch L, const Problem *d_probs, int np, const ItemS
         return LMTOF_OK;
     };
     int rc;
-    HIPCHK(c, launch_brick_wmax(L, d_probs, np, it.bricks, it.n_bricks, part_wmax));
+    HIPCHK(c, launch_brick_wmax(L, d_probs, np, it.bricks, it.n_bricks, part_wmax, n_part));
     if (L.graph && it.n_bricks) {
         *prev = node;
         L.deps = prev;
@@ -672,7 +680,7 @@ int build_graph(lmtof_ctx *c, int n_iter, GraphEntry &ge) {
                                  c->d_part_wmax));
         if (node) prev = node;
         if ((rc = record(ge.ev[kEventsPerIter * k + 1]))) return rc;
-        if ((rc = add_back(c, L, c->d_probs, np, c->items, c->d_part_wmax, &prev, ge.ev[kEventsPerIter * k + 2],
+        if ((rc = add_back(c, L, c->d_probs, np, c->items, c->d_part_wmax, c->n_chunks, &prev, ge.ev[kEventsPerIter * k + 2],
                            ge.ev[kEventsPerIter * k + 3])))
             return rc;
         if ((rc = record(ge.ev[kEventsPerIter * k + 4]))) return rc;
@@ -1378,7 +1386,7 @@ int lmtof_back_project(lmtof_ctx *c, const float *w, int64_t nw, float *b, int64
     if (he == hipSuccess) he = launch_fill(L, db, c->V, 0.0f);
     if (he == hipSuccess) he = launch_chunk_absmax(L, dp, 1, nch, ept, pw);
     if (he != hipSuccess) return done(fail(c, LMTOF_EHIP, "back projection: %s", hipGetErrorString(he)));
-    if ((rc = add_back(c, L, dp, 1, its, pw, nullptr))) return done(rc);
+    if ((rc = add_back(c, L, dp, 1, its, pw, nch, nullptr))) return done(rc);
     if (mem == LMTOF_MEM_HOST) rc = copy_out(c, b, db, sizeof(float) * c->V, LMTOF_MEM_HOST);
     else if (hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(c, LMTOF_EHIP, "back projection failed");
     return done(rc);
@@ -1423,7 +1431,7 @@ int lmtof_autotune(lmtof_ctx *c, int64_t *chosen, float *ms) {
                 he = launch_forward(L, tof, c->d_probs, np, c->n_chunks, c->ept_used, 0, c->d_part_neff,
                                     c->d_part_ll, c->d_part_wmax);
             if (he != hipSuccess) return cleanup(fail(c, LMTOF_EHIP, "autotune: %s", hipGetErrorString(he)));
-            if ((rc = add_back(c, L, c->d_probs, np, c->items, c->d_part_wmax, nullptr))) return cleanup(rc);
+            if ((rc = add_back(c, L, c->d_probs, np, c->items, c->d_part_wmax, c->n_chunks, nullptr))) return cleanup(rc);
             if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                 hipEventElapsedTime(&t, e0, e1) != hipSuccess)
                 return cleanup(fail(c, LMTOF_EHIP, "autotune timing failed"));
@@ -1879,7 +1887,7 @@ int lmtof_pool_step(lmtof_pool *p, int *n_active) {
     L.stream = p->stream;
     PHIP(p, launch_block_image(L, p->d_probs, np, p->n_xblk));
     PHIP(p, launch_forward(L, tof, p->d_probs, np, p->n_chunks, p->ept, 0, p->part_neff, p->part_ll, p->part_wmax));
-    PHIP(p, launch_brick_wmax(L, p->d_probs, np, p->d_bricks, p->n_bbricks, p->part_wmax));
+    PHIP(p, launch_brick_wmax(L, p->d_probs, np, p->d_bricks, p->n_bbricks, p->part_wmax, p->n_chunks));
     PHIP(p, launch_back_chunks(L, tof, p->d_probs, np, p->d_chunks, p->n_bchunks, p->d_bricks));
     PHIP(p, launch_reduce_tiles(L, p->d_probs, np, p->d_bricks, p->n_bbricks));
     PHIP(p, launch_update(L, p->d_probs, np, p->n_vchunks, p->part_old, p->part_new));

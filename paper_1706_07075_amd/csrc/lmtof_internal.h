@@ -16,7 +16,10 @@ constexpr int kBrickX = 16, kBrickY = 16, kBrickZ = 16;
 constexpr int kBrickVox = kBrickX * kBrickY * kBrickZ;
 // Brick items are grouped by an estimate of their voxel pieces in the brick
 // (longest first), so that a wavefront's lanes walk similar lengths.
-constexpr int kItemClasses = 4;
+constexpr int kItemClasses = 8;
+// Largest brick count of one problem (the brick item builder keeps a bitmap
+// of a problem's bricks in LDS).
+constexpr int kMaxProblemBricks = 65536;
 // Bytes of one brick item's walk record (two float4 and one uint2).
 constexpr int kItemRecBytes = 40;
 constexpr int kForwardBlock = 256;
@@ -105,11 +108,11 @@ hipError_t launch_forward(const Launch &L, bool tof, const Problem *d_probs, int
 // first tile slot, end tile slot, items in the brick); chunk (brick table
 // index, first item, end item, tile slot) over P.items / P.tiles of the
 // brick's problem with weights P.rw.  launch_brick_wmax (per-brick bound
-// on |w| from the forward chunks' maxima part_wmax), then
+// on |w| from the forward chunks' maxima part_wmax[0, n_part)), then
 // launch_back_chunks, then launch_reduce_tiles (which writes every voxel of
 // the listed bricks of P.b).
 hipError_t launch_brick_wmax(const Launch &L, const Problem *d_probs, int n_probs, const uint4 *bricks,
-                             uint32_t n_bricks, const float *part_wmax);
+                             uint32_t n_bricks, const float *part_wmax, int64_t n_part);
 // part_wmax[c] = largest |P.rw| over forward chunk c's events.
 hipError_t launch_chunk_absmax(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept,
                                float *part_wmax);
@@ -119,10 +122,12 @@ hipError_t launch_reduce_tiles(const Launch &L, const Problem *d_probs, int n_pr
                                uint32_t n_bricks);
 // Brick item lists, keyed by global brick * kItemClasses + item class.
 // fill == 0 counts pieces per key into ctr and (forward chunk, brick) pairs
-// per global brick into pctr; else writes problem-local event indices to
-// P.items at ctr[key]++ (never past end[key]) and problem-local forward
-// chunk indices to P.pairs at pctr[brick]++.  Same launch shape as the
-// forward pass (its chunks are the pairs' chunks).
+// per global brick into pctr (one per chunk touching the brick); else writes
+// problem-local event indices to P.items at ctr[key]++ (never past end[key])
+// and problem-local forward chunk indices to P.pairs at pctr[brick]++ (never
+// past the brick's P.pair_off end).  Same launch shape as the forward pass
+// (its chunks are the pairs' chunks).  Every problem has at most
+// kMaxProblemBricks bricks.
 hipError_t launch_brick_items(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept,
                               uint32_t *ctr, const uint32_t *end, uint32_t *pctr, int fill);
 // part[2c] = voxel pieces visited by chunk c, part[2c+1] = pieces with non-zero weight.

@@ -591,14 +591,17 @@ __global__ void __launch_bounds__(kForwardBlock) k_forward(const Problem *__rest
 //    w >= 0 here (MLEM ratios), so the forward pass's max of w is max |w|.
 __global__ void __launch_bounds__(64) k_brick_wmax(const Problem *__restrict__ probs, int n_probs,
                                                    const uint4 *__restrict__ bricks,
-                                                   const float *__restrict__ part_wmax) {
+                                                   const float *__restrict__ part_wmax, int64_t n_part) {
     const uint4 br = bricks[blockIdx.x];
     const Problem &P = probs[find_brick_problem(probs, n_probs, br.x)];
     const uint32_t bl = br.x - (uint32_t)P.brick_base;
     const gptr<const uint32_t> pairs = global(P.pairs);
     const uint32_t k0 = P.pair_off[bl], k1 = P.pair_off[bl + 1];
     float wm = 0.0f;
-    for (uint32_t k = k0 + threadIdx.x; k < k1; k += 64) wm = fmaxf(wm, part_wmax[P.chunk_begin + pairs[k]]);
+    for (uint32_t k = k0 + threadIdx.x; k < k1; k += 64) {
+        const int64_t q = P.chunk_begin + pairs[k];
+        if (q < n_part) wm = fmaxf(wm, part_wmax[q]);
+    }
     wm = wave_max(wm);
     if (threadIdx.x == 0) global(P.wmax)[br.y] = wm;
 }
@@ -844,53 +847,63 @@ __device__ __forceinline__ void write_item_walk(const Problem &P, const Ray &r, 
     global(reinterpret_cast<u32x2 *>(const_cast<uint2 *>(P.rec_k)))[pos] = k;
 }
 
-// Item class of a brick piece [t0, t1] of ray r: 0 for the longest walks
-// (estimated plane crossings (t1 - t0) sum_a |u_a| / v_a of 16 or more),
-// then 9-15, 4-8, and 3 or fewer.
+// Item class of a brick piece [t0, t1] of ray r by its estimated plane
+// crossings (t1 - t0) sum_a |u_a| / v_a: 0 for 21 or more, then 16-20,
+// 12-15, 9-11, 6-8, 4-5, 2-3, and 0-1.
 __device__ __forceinline__ uint32_t item_class(const Problem &P, const Ray &r, float t0, float t1) {
     const float m = (t1 - t0) * (fabsf(r.ux) * P.ivx + fabsf(r.uy) * P.ivy + fabsf(r.uz) * P.ivz);
-    return m >= 16.0f ? 0u : m >= 9.0f ? 1u : m >= 4.0f ? 2u : 3u;
+    // class edges in estimated crossings, longest first
+    const float edge[kItemClasses - 1] = {21.0f, 16.0f, 12.0f, 9.0f, 6.0f, 4.0f, 2.0f};
+    uint32_t k = 0;
+#pragma unroll
+    for (int q = 0; q < kItemClasses - 1; ++q) k += m < edge[q];
+    return k;
 }
 
 template <bool PACKED>
 __device__ __forceinline__ void brick_items_pass(const Problem &P, int64_t base, uint32_t chunk, int ept,
                                                  uint32_t *__restrict__ ctr, const uint32_t *__restrict__ end,
                                                  uint32_t *__restrict__ pctr, int fill, uint32_t *hkey,
-                                                 uint32_t *hcnt, uint32_t *hbase) {
+                                                 uint32_t *hcnt, uint32_t *hbase, uint32_t *bmap) {
     const gptr<uint32_t> items = global(const_cast<uint32_t *>(P.items));
     const gptr<uint32_t> pairs = global(const_cast<uint32_t *>(P.pairs));
-    // one (chunk, brick) pair per distinct key of this block (a brick may
-    // appear once per item class: duplicates only repeat a max operand)
-    auto pair = [&](uint32_t key) {
-        const uint32_t brick = key / kItemClasses;
-        const uint32_t pos = atomicAdd(pctr + brick, 1u);
-        if (fill) pairs[pos] = chunk;
-    };
     for (int e = 0; e < ept; ++e) {
         const int64_t i = base + (int64_t)e * blockDim.x + threadIdx.x;
         Ray r;
         if (i >= P.n_events || !make_ray<PACKED>(P, i, r)) continue;
         brick_walk(P, r, [&](uint32_t brick, float t0, float t1) {
+            const uint32_t bl = brick - (uint32_t)P.brick_base;
+            atomicOr(&bmap[bl >> 5], 1u << (bl & 31u));
             const uint32_t key = brick * kItemClasses + item_class(P, r, t0, t1);
             const int h = hash_insert(hkey, key);
             if (h >= 0) {
                 atomicAdd(&hcnt[h], 1u);
             } else {
-                // table full: place the piece (and a pair for it) directly
+                // table full: place the piece directly
                 const uint32_t pos = atomicAdd(ctr + key, 1u);
                 if (fill && pos < end[key]) {
                     items[pos] = (uint32_t)i;
                     write_item_walk(P, r, brick, t0, t1, pos);
                 }
-                pair(key);
             }
         });
     }
     __syncthreads();
+    // One (chunk, brick) pair per brick this block touched.  The set of
+    // bricks does not depend on thread timing (unlike which keys found room
+    // in the table), so both passes emit exactly the same pairs and the fill
+    // pass writes every slot the count pass reserved, once.
+    const uint32_t nb = (uint32_t)P.nbx * (uint32_t)P.nby * (uint32_t)P.nbz;
+    for (uint32_t w = threadIdx.x; w < (nb + 31) / 32; w += blockDim.x) {
+        for (uint32_t bits = bmap[w]; bits; bits &= bits - 1) {
+            const uint32_t bl = w * 32 + (uint32_t)__builtin_ctz(bits);
+            const uint32_t pos = atomicAdd(pctr + P.brick_base + bl, 1u);
+            if (fill && pos < P.pair_off[bl + 1]) pairs[pos] = chunk;
+        }
+    }
     for (int k = threadIdx.x; k < kHashSlots; k += blockDim.x) {
         if (hkey[k] == kEmpty) continue;
         const uint32_t b = atomicAdd(ctr + hkey[k], hcnt[k]);
-        pair(hkey[k]);
         if (fill) {
             hbase[k] = b;
             hcnt[k] = 0;
@@ -920,19 +933,22 @@ __global__ void __launch_bounds__(kForwardBlock) k_brick_items(const Problem *__
                                                                const uint32_t *__restrict__ end,
                                                                uint32_t *__restrict__ pctr, int fill) {
     __shared__ uint32_t hkey[kHashSlots], hcnt[kHashSlots], hbase[kHashSlots];
+    __shared__ uint32_t bmap[kMaxProblemBricks / 32];  // bricks of the problem this block touches
+    const int64_t c = blockIdx.x;
+    const Problem P = probs[find_problem(probs, n_probs, c)];
     for (int k = threadIdx.x; k < kHashSlots; k += blockDim.x) {
         hkey[k] = kEmpty;
         hcnt[k] = 0;
     }
+    const uint32_t nw = ((uint32_t)P.nbx * (uint32_t)P.nby * (uint32_t)P.nbz + 31) / 32;
+    for (uint32_t w = threadIdx.x; w < nw; w += blockDim.x) bmap[w] = 0;
     __syncthreads();
-    const int64_t c = blockIdx.x;
-    const Problem P = probs[find_problem(probs, n_probs, c)];
     const int64_t base = (c - P.chunk_begin) * (int64_t)blockDim.x * ept;
     const uint32_t chunk = (uint32_t)(c - P.chunk_begin);
     if (P.packed)
-        brick_items_pass<true>(P, base, chunk, ept, ctr, end, pctr, fill, hkey, hcnt, hbase);
+        brick_items_pass<true>(P, base, chunk, ept, ctr, end, pctr, fill, hkey, hcnt, hbase, bmap);
     else
-        brick_items_pass<false>(P, base, chunk, ept, ctr, end, pctr, fill, hkey, hcnt, hbase);
+        brick_items_pass<false>(P, base, chunk, ept, ctr, end, pctr, fill, hkey, hcnt, hbase, bmap);
 }
 
 // Diagnostic: voxel pieces visited per chunk and how many have non-zero weight.
@@ -1027,8 +1043,8 @@ hipError_t launch_chunk_absmax(const Launch &L, const Problem *d_probs, int n_pr
 }
 
 hipError_t launch_brick_wmax(const Launch &L, const Problem *d_probs, int n_probs, const uint4 *bricks,
-                             uint32_t n_bricks, const float *part_wmax) {
-    void *args[] = {&d_probs, &n_probs, &bricks, &part_wmax};
+                             uint32_t n_bricks, const float *part_wmax, int64_t n_part) {
+    void *args[] = {&d_probs, &n_probs, &bricks, &part_wmax, &n_part};
     return do_launch(L, reinterpret_cast<const void *>(&k_brick_wmax), dim3(n_bricks), dim3(64), 0, args);
 }
 
