@@ -284,7 +284,7 @@ Problem make_problem(const lmtof_ctx *c, int z_lo, int nz, float *x, float *b, c
     if (P.tof) {
         const double h = 2.0 * g.tof_trunc_sigmas / (kLutN - 1);
         P.lut_a = (float)(1.0 / (sigma_mm(g) * h));
-        P.lut_b = (float)(g.tof_trunc_sigmas / h);
+        P.lut_b = (float)((kLutN - 1) / 2) + 12582912.0f;  // centre node + 1.5 2^23, exact
     }
     P.a_max = P.tof ? 1.0f : (float)std::sqrt(g.vx * g.vx + g.vy * g.vy + g.vz * g.vz);
     P.nbx = (g.nx + kBrickX - 1) / kBrickX;
@@ -293,6 +293,10 @@ Problem make_problem(const lmtof_ctx *c, int z_lo, int nz, float *x, float *b, c
     P.nbx4 = (g.nx + 3) / 4;
     P.nby4 = (g.ny + 3) / 4;
     P.nbz4 = (nz + 3) / 4;
+    P.xfx = 0;
+    while ((1 << P.xfx) < P.nbx4) ++P.xfx;
+    P.xfy = 0;
+    while ((1 << P.xfy) < P.nby4) ++P.xfy;
     P.x = x;
     P.b = b;
     P.s = s;
@@ -302,23 +306,26 @@ Problem make_problem(const lmtof_ctx *c, int z_lo, int nz, float *x, float *b, c
 // Kernel-CDF table for truncation K: node k at u_k = -K + k h (sigma units),
 // h = 2K / (n - 1), holds Phi(u_k), Phi'(u_k) h and Phi''(u_k) h^2 / 2 with
 // Phi(u) = erf(u / sqrt 2) / (2 erf(K / sqrt 2)) (so a piece's weight is a
-// difference of two values) and Phi'' = -u Phi'.  Evaluated in FP64.
+// difference of two values) and Phi'' = -u Phi'.  Evaluated in FP64.  Node
+// k sits at entry k + 1; entries 0 and n + 1 repeat the end values, flat.
 int ensure_lut(lmtof_ctx *c) {
     const double K = c->g.tof_trunc_sigmas;
     if (c->d_lut && c->lut_k == K) return LMTOF_OK;
-    std::vector<float4> tab(kLutN);
+    std::vector<float4> tab(kLutN + 2);
     const double h = 2.0 * K / (kLutN - 1), den = std::erf(K / std::sqrt(2.0));
     for (int k = 0; k < kLutN; ++k) {
         const double u = -K + k * h;
         const double phi = std::exp(-0.5 * u * u) / (std::sqrt(2.0 * M_PI) * den);
-        tab[k] = make_float4((float)(std::erf(u / std::sqrt(2.0)) / (2.0 * den)), (float)(phi * h),
-                             (float)(-u * phi * h * h / 2.0), 0.0f);
+        tab[k + 1] = make_float4((float)(std::erf(u / std::sqrt(2.0)) / (2.0 * den)), (float)(phi * h),
+                                 (float)(-u * phi * h * h / 2.0), 0.0f);
     }
+    tab[0] = make_float4(tab[1].x, 0.0f, 0.0f, 0.0f);
+    tab[kLutN + 1] = make_float4(tab[kLutN].x, 0.0f, 0.0f, 0.0f);
     if (!c->d_lut) {
-        int rc = dev_alloc(c, &c->d_lut, kLutN);
+        int rc = dev_alloc(c, &c->d_lut, kLutN + 2);
         if (rc) return rc;
     }
-    HIPCHK(c, hipMemcpyAsync(c->d_lut, tab.data(), sizeof(float4) * kLutN, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_lut, tab.data(), sizeof(float4) * (kLutN + 2), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->lut_k = K;
     return LMTOF_OK;
@@ -337,7 +344,7 @@ int64_t assign_xblocks(std::vector<Problem> &ps, float *xb) {
     for (auto &P : ps) {
         P.xblk_begin = n;
         P.xb = xb ? xb + 64 * n : nullptr;
-        n += (int64_t)P.nbx4 * P.nby4 * P.nbz4;
+        n += xblocks(P);
     }
     return n;
 }
@@ -349,6 +356,9 @@ int upload_problems(lmtof_ctx *c, std::vector<Problem> &ps, int block, int ept, 
     n_vchunks = 0;
     int64_t nb = 0;
     for (auto &P : ps) {
+        // the forward pass addresses a problem's blocked copy with 32-bit byte offsets
+        if (xblocks(P) * 256 > 0xffffffffLL)
+            return fail(c, LMTOF_EUNSUPPORTED, "grid too large: its blocked image copy exceeds 4 GiB");
         P.chunk_begin = n_chunks;
         P.vchunk_begin = n_vchunks;
         P.brick_base = (int32_t)nb;
@@ -802,7 +812,7 @@ int64_t ctx_device_bytes(const lmtof_ctx *c) {
     b += (int64_t)(c->items.items_cap - std::min<size_t>(c->items.items_cap, c->items.n_items)) * 4;
     b += (int64_t)(c->items.tiles_cap - std::min<size_t>(c->items.tiles_cap, (size_t)c->items.n_slots * kBrickVox)) * 8;
     b += (int64_t)(c->items.n_chunks + c->items.n_bricks) * 16;
-    b += (int64_t)c->part_cap * 12 + (int64_t)c->vpart_cap * 16 + kLutN * 16 + (int64_t)c->xb_cap * 4;
+    b += (int64_t)c->part_cap * 12 + (int64_t)c->vpart_cap * 16 + (kLutN + 2) * 16 + (int64_t)c->xb_cap * 4;
     return b;
 }
 
@@ -825,7 +835,13 @@ int64_t request_bytes_estimate(const lmtof_request &q) {
     const double ipe = 1.3 * (1.0 + 1.7 * win / (kBrickX * vmin));
     const int64_t items = (int64_t)(N * ipe);
     const int64_t esz = q.storage ? 16 : 32;
-    int64_t b = N * (esz + 8 + 4) + items * (4 + kItemRecBytes) + 4 * 4 * V;  // x, b, s and the blocked copy of x
+    auto pow2 = [](int64_t n) {
+        int64_t q2 = 1;
+        while (q2 < n) q2 <<= 1;
+        return q2;
+    };
+    const int64_t xbv = pow2((g.nx + 3) / 4) * pow2((g.ny + 3) / 4) * ((g.nz + 3) / 4) * 64;  // blocked copy of x
+    int64_t b = N * (esz + 8 + 4) + items * (4 + kItemRecBytes) + 3 * 4 * V + 4 * xbv;  // x, b, s, blocked x
     b += (items / 2048 + 1 + V / kBrickVox + 1) * (int64_t)kBrickVox * 8 / 4;  // tiles
     b += items;  // (forward chunk, brick) pairs: at most one per item, ~1 in 10 in practice
     b += N * (q.mem == LMTOF_MEM_HOST ? 28 : 0) + N * (esz + 8 + 4);       // ingest transients
@@ -1709,7 +1725,7 @@ int pool_build_batch(lmtof_pool *p) {
         P.vchunk_begin = nvch;
         P.brick_base = (int32_t)nb;
         P.xblk_begin = nxb;
-        nxb += (int64_t)P.nbx4 * P.nby4 * P.nbz4;
+        nxb += xblocks(P);
         nch += (P.n_events + ce - 1) / ce;
         nvch += ((int64_t)P.nx * P.ny * P.nz + cv - 1) / cv;
         const uint32_t bt = (uint32_t)bricks.size();

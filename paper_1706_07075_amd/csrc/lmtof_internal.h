@@ -11,7 +11,7 @@ namespace lmtof {
 // contiguous range of stored events.  A whole-volume reconstruction is one
 // problem; the TOF-assisted data division runs one problem per body region.
 // Kernel-CDF table nodes, brick shape and launch shapes of the projector.
-constexpr int kLutN = 1024;
+constexpr int kLutN = 1025;  // odd: the centre of the window is a node
 constexpr int kBrickX = 16, kBrickY = 16, kBrickZ = 16;
 constexpr int kBrickVox = kBrickX * kBrickY * kBrickZ;
 // Brick items are grouped by an estimate of their voxel pieces in the brick
@@ -57,18 +57,26 @@ struct Problem {
     float inv_sig_sqrt2;  // 1 / (sigma sqrt 2), sigma in mm
     float k_sigma;        // truncation half-width K sigma (mm)
     float norm;           // 1 / (2 erf(K / sqrt 2)): makes the full kernel sum to 1
-    const float4 *lut;    // kernel-CDF table (kLutN nodes over [-K, K] sigma)
-    float lut_a, lut_b;   // table position of t (mm): t * lut_a + lut_b
+    const float4 *lut;    // kernel-CDF table: a pad entry, kLutN nodes over [-K, K] sigma, a pad entry
+    float lut_a, lut_b;   // node position of t (mm): t * lut_a + (kLutN - 1) / 2; lut_b = (kLutN - 1) / 2 + 1.5 2^23
     float a_max;          // bound on one piece weight (TOF: 1, the kernel mass; else the voxel diagonal)
     int32_t brick_base;   // global id of this problem's first brick
     int32_t nbx, nby, nbz;// bricks per axis
-    // Forward-pass copy of x in 4x4x4-voxel blocks (x fastest inside a
-    // block, blocks x fastest): the gathers of a wavefront's near-parallel
-    // rays then fall on a few 64-byte sectors.
+    // Forward-pass copy of x in 4x4x4-voxel blocks, x fastest inside a
+    // block, so that the gathers of a wavefront's near-parallel rays fall on
+    // a few 64-byte sectors.  Element index = (block << 6) | (iz & 3) << 4 |
+    // (iy & 3) << 2 | (ix & 3), block = bz << (xfx + xfy) | by << xfx | bx:
+    // each block coordinate has a bit field of its own (x and y fields
+    // padded to powers of two; padding blocks hold 0), so a one-voxel step
+    // along an axis is an add within that axis's bits.
     float *xb;
-    int64_t xblk_begin;   // first 4^3 block of this problem in the relayout launch
-    int32_t nbx4, nby4, nbz4;  // 4^3 blocks per axis
+    int64_t xblk_begin;   // first block of this problem in the relayout launch
+    int32_t nbx4, nby4, nbz4;  // 4^3 blocks per axis holding voxels
+    int32_t xfx, xfy;     // widths of the bx and by fields
 };
+
+// Blocks (of 64 floats) of a problem's blocked copy, padding included.
+__host__ __device__ inline int64_t xblocks(const Problem &P) { return (int64_t)P.nbz4 << (P.xfx + P.xfy); }
 
 constexpr int kMaxProblems = 64;
 

@@ -220,16 +220,33 @@ __device__ __forceinline__ int voxel_at(float t, float u, int j, float d, float 
 }
 
 // Truncated-kernel CDF from the LDS table: node k at u_k = -K + k h (sigma
-// units) holds (Phi_k, Phi'_k h, Phi''_k h^2 / 2); pos = t * lut_a + lut_b.
+// units) holds (Phi_k, Phi'_k h, Phi''_k h^2 / 2) at entry k + 1 (entries 0
+// and kLutN + 1 pad the ends).  The node position of t (mm) is t a + c with
+// c = (kLutN - 1) / 2, an integer; b = c + 1.5 2^23, so fma(t, a, b) rounds
+// the position to the nearest node k and returns 1.5 2^23 + k exactly, whose
+// bit pattern is that of 1.5 2^23 plus k: one shift-add gives the entry's
+// byte offset.  |t| <= K sigma keeps k in [0, kLutN - 1].
+constexpr float kLutRound = 12582912.0f;  // 1.5 2^23: the FP32 spacing there is 1
+constexpr uint32_t kLutAddrBias = 16u - (0x4B400000u << 4);  // 16 (k + 1) - (bits(1.5 2^23 + k) << 4)
+
+// One vector-register copy of a uniform value for a loop, instead of a
+// scalar-to-vector move at each use (a vector instruction reads at most one
+// scalar operand here).
+template <class T>
+__device__ __forceinline__ T in_vgpr(T v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
 struct Cdf {
     const float4 *tab;
     float a, b;
     __device__ __forceinline__ float operator()(float t) const {
-        const float pos = fmaf(t, a, b);
-        const float kf = __builtin_amdgcn_fmed3f(rintf(pos), 0.0f, (float)(kLutN - 1));
-        const float dp = pos - kf;
-        const float4 e = tab[(int)kf];
-        return fmaf(dp, fmaf(dp, e.z, e.y), e.x);
+        const float y = fmaf(t, a, b);      // 1.5 2^23 + k
+        const float f = fmaf(t, a, b - y);  // position - k, in [-1/2, 1/2]
+        const float4 e = *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(tab) +
+                                                           ((__float_as_uint(y) << 4) + kLutAddrBias));
+        return fmaf(f, fmaf(f, e.z, e.y), e.x);
     }
 };
 
@@ -274,8 +291,9 @@ struct Stepper {
         djz = pz ? B.sz : -B.sz;
         max_steps = B.nx + B.ny + B.nz + 2;
     }
-    // Start from a brick item's walk record (brick strides, see the item lists).
-    __device__ __forceinline__ Stepper(const Ray &r, uint2 rk) {
+    // Start from a brick item's walk record (see the item lists); j is then
+    // the brick-local voxel index times unit (the caller's bytes per voxel).
+    __device__ __forceinline__ Stepper(const Ray &r, uint2 rk, int unit) {
         const bool px = r.ax > 0.0f, py = r.ay > 0.0f, pz = r.az > 0.0f;  // A has the sign of u
         sx = px ? 1.0f : -1.0f;
         sy = py ? 1.0f : -1.0f;
@@ -286,10 +304,10 @@ struct Stepper {
         tx = fmaf(kx, r.ax, r.bx);
         ty = fmaf(ky, r.ay, r.by);
         tz = fmaf(kz, r.az, r.bz);
-        j = (int)(rk.y >> 16);
-        djx = px ? 1 : -1;
-        djy = py ? kBrickX : -kBrickX;
-        djz = pz ? kBrickX * kBrickY : -kBrickX * kBrickY;
+        j = (int)(rk.y >> 16) * unit;
+        djx = px ? unit : -unit;
+        djy = (py ? kBrickX : -kBrickX) * unit;
+        djz = (pz ? kBrickX * kBrickY : -kBrickX * kBrickY) * unit;
         max_steps = kBrickX + kBrickY + kBrickZ + 2;
     }
     __device__ __forceinline__ float next() const { return fminf(fminf(tx, ty), tz); }
@@ -303,37 +321,49 @@ struct Stepper {
         tx = fmaf(kx, r.ax, r.bx);
         ty = fmaf(ky, r.ay, r.by);
         tz = fmaf(kz, r.az, r.bz);
-        // (a sum of masked terms: a select between two members would be
+        // exactly one axis moves (selects between values held in
+        // registers; selecting between members by reference would be
         // folded into a load through a selected address, off registers)
-        j += (mx ? djx : 0) + (my ? djy : 0) + (mz ? djz : 0);
+        const int dx = djx, dy = djy, dz = djz;
+        j += mx ? dx : (my ? dy : dz);
     }
 };
 
-// The same traversal over the whole grid, reporting the voxel's index in
-// the 4^3-blocked copy of the image (the forward pass gathers from it).
+// The same traversal over the whole grid, reporting the voxel's byte
+// offset in the blocked copy of the image (the forward pass gathers from
+// it).  A step along an axis adds +-1 to that axis's bits of the offset
+// (the sub-block bits and the block field): OR-ing in the other bits
+// carries through them, and the other bits are then put back.
 struct StepperB {
     float kx, ky, kz, tx, ty, tz, sx, sy, sz;
-    int ix, iy, iz;     // current voxel
-    int dix, diy, diz;  // +-1
+    uint32_t off;                 // byte offset of the current voxel
+    uint32_t mx_, my_, mz_;       // each axis's bits of the offset
+    uint32_t dx_, dy_, dz_;       // +1 (lowest bit) or -1 (all bits) within them
     int max_steps;
 
     __device__ __forceinline__ StepperB(const Problem &P, const Ray &r, float ta) {
-        ix = min(max(voxel_at(ta, r.ux, r.jx, r.dx, P.ivx), 0), P.nx - 1);
-        iy = min(max(voxel_at(ta, r.uy, r.jy, r.dy, P.ivy), 0), P.ny - 1);
-        iz = min(max(voxel_at(ta, r.uz, r.jz, r.dz, P.ivz), 0), P.nz - 1);
+        const int ix = min(max(voxel_at(ta, r.ux, r.jx, r.dx, P.ivx), 0), P.nx - 1);
+        const int iy = min(max(voxel_at(ta, r.uy, r.jy, r.dy, P.ivy), 0), P.ny - 1);
+        const int iz = min(max(voxel_at(ta, r.uz, r.jz, r.dz, P.ivz), 0), P.nz - 1);
         const bool px = r.ux > 0.0f, py = r.uy > 0.0f, pz = r.uz > 0.0f;
         sx = px ? 1.0f : -1.0f;
         sy = py ? 1.0f : -1.0f;
         sz = pz ? 1.0f : -1.0f;
-        dix = px ? 1 : -1;
-        diy = py ? 1 : -1;
-        diz = pz ? 1 : -1;
         kx = (float)(ix + px - r.jx);
         ky = (float)(iy + py - r.jy);
         kz = (float)(iz + pz - r.jz);
         tx = fmaf(kx, r.ax, r.bx);
         ty = fmaf(ky, r.ay, r.by);
         tz = fmaf(kz, r.az, r.bz);
+        const uint32_t fx = (uint32_t)P.xfx, fxy = (uint32_t)(P.xfx + P.xfy);
+        const uint32_t blk = ((uint32_t)(iz >> 2) << fxy) | ((uint32_t)(iy >> 2) << fx) | (uint32_t)(ix >> 2);
+        off = ((blk << 6) | ((uint32_t)(iz & 3) << 4) | ((uint32_t)(iy & 3) << 2) | (uint32_t)(ix & 3)) << 2;
+        mx_ = in_vgpr((3u << 2) | (((1u << fx) - 1u) << 8));
+        my_ = in_vgpr((3u << 4) | (((1u << P.xfy) - 1u) << (8 + fx)));
+        mz_ = in_vgpr((3u << 6) | (~0u << (8 + fxy)));
+        dx_ = px ? 4u : mx_;
+        dy_ = py ? 16u : my_;
+        dz_ = pz ? 64u : mz_;
         max_steps = P.nx + P.ny + P.nz + 2;
     }
     __device__ __forceinline__ float next() const { return fminf(fminf(tx, ty), tz); }
@@ -347,18 +377,11 @@ struct StepperB {
         tx = fmaf(kx, r.ax, r.bx);
         ty = fmaf(ky, r.ay, r.by);
         tz = fmaf(kz, r.az, r.bz);
-        ix += mx ? dix : 0;
-        iy += my ? diy : 0;
-        iz += mz ? diz : 0;
-    }
-    // Block coordinates as 14-bit fields and strides masked to 24 bits let
-    // the compiler use full-rate 24-bit multiply-adds.
-    __device__ __forceinline__ uint32_t index(uint32_t stride_y, uint32_t stride_z) const {
-        const uint32_t bx = __builtin_amdgcn_ubfe((uint32_t)ix, 2, 14);
-        const uint32_t by = __builtin_amdgcn_ubfe((uint32_t)iy, 2, 14);
-        const uint32_t bz = __builtin_amdgcn_ubfe((uint32_t)iz, 2, 14);
-        const uint32_t blk = bz * stride_z + (by * stride_y + bx);
-        return (blk << 6) | ((uint32_t)(iz & 3) << 4) | ((uint32_t)(iy & 3) << 2) | (uint32_t)(ix & 3);
+        const uint32_t ax = mx_, ay = my_, az = mz_, ex = dx_, ey = dy_, ez = dz_;
+        const uint32_t m = mx ? ax : (my ? ay : az);
+        const uint32_t d = mx ? ex : (my ? ey : ez);
+        const uint32_t v = (off & m) | ~m;
+        off = ((v + d) & m) | (off & ~m);
     }
 };
 
@@ -460,7 +483,11 @@ __device__ __forceinline__ int find_brick_problem(const Problem *probs, int n_pr
 }
 
 __device__ __forceinline__ void stage_lut(float4 *lds, const float4 *src) {
-    for (int k = threadIdx.x; k < kLutN; k += blockDim.x) lds[k] = src[k];
+    for (int k = threadIdx.x; k < kLutN + 2; k += blockDim.x) lds[k] = src[k];
+}
+
+__device__ __forceinline__ float at_byte(gptr<const float> p, uint32_t off) {
+    return *reinterpret_cast<gptr<const float>>(reinterpret_cast<gptr<const char>>(p) + off);
 }
 
 // f_i = sum_j a_ij x_j over the window of ray r, gathering from the blocked
@@ -468,14 +495,13 @@ __device__ __forceinline__ void stage_lut(float4 *lds, const float4 *src) {
 // ahead, so its latency overlaps the weight computation of the current piece.
 template <bool TOF>
 __device__ __forceinline__ float forward_ray(const Problem &P, const Ray &r, const Cdf &cdf, gptr<const float> xb,
-                                             uint32_t last_index) {
+                                             uint32_t last_off) {
     StepperB s(P, r, r.t0);
-    const uint32_t sy = (uint32_t)P.nbx4 & 0xffffffu, sz = ((uint32_t)P.nbx4 * (uint32_t)P.nby4) & 0xffffffu;
     const float tb = r.t1;
     float t = r.t0;
     float c = TOF ? cdf(t) : 0.0f;
     float f = 0.0f;
-    float xj = xb[min(s.index(sy, sz), last_index)];
+    float xj = at_byte(xb, min(s.off, last_off));
     for (int step = 0; step < s.max_steps; ++step) {
         const float tmin = s.next();
         const float tn = __builtin_amdgcn_fmed3f(tmin, t, tb);
@@ -491,7 +517,7 @@ __device__ __forceinline__ float forward_ray(const Problem &P, const Ray &r, con
         f = fmaf(a, xj, f);
         if (tmin >= tb) break;
         s.advance(r, tmin);
-        xj = xb[min(s.index(sy, sz), last_index)];
+        xj = at_byte(xb, min(s.off, last_off));
     }
     return f;
 }
@@ -504,12 +530,13 @@ __device__ __forceinline__ void forward_chunk(const Problem &P, int64_t base, in
                                               int &neff, float &ll, float &wmax) {
     const gptr<const float> xb = global(P.xb);
     const gptr<float> out = global(P.rw);
-    const uint32_t last_index = (uint32_t)P.nbx4 * (uint32_t)P.nby4 * (uint32_t)P.nbz4 * 64u - 1u;
+    // last float of the copy: steps just past the grid edge stay inside it
+    const uint32_t last_off = (uint32_t)(xblocks(P) * 256 - 4);
     for (int e = 0; e < ept; ++e) {
         const int64_t i = base + (int64_t)e * blockDim.x + threadIdx.x;
         if (i >= P.n_events) break;
         Ray r;
-        const float f = make_ray<PACKED>(P, i, r) ? forward_ray<TOF>(P, r, cdf, xb, last_index) : 0.0f;
+        const float f = make_ray<PACKED>(P, i, r) ? forward_ray<TOF>(P, r, cdf, xb, last_off) : 0.0f;
         if (mode == 0) {
             const bool pos = f > 0.0f;
             const float w = pos ? 1.0f / f : 0.0f;
@@ -528,7 +555,7 @@ __global__ void __launch_bounds__(kForwardBlock) k_forward(const Problem *__rest
                                                            int mode, int *__restrict__ part_neff,
                                                            double *__restrict__ part_ll,
                                                            float *__restrict__ part_wmax) {
-    __shared__ float4 lut[kLutN];
+    __shared__ float4 lut[kLutN + 2];
     __shared__ int s_n[kForwardBlock / 64];
     __shared__ double s_l[kForwardBlock / 64];
     __shared__ float s_w[kForwardBlock / 64];
@@ -536,7 +563,7 @@ __global__ void __launch_bounds__(kForwardBlock) k_forward(const Problem *__rest
     const Problem P = probs[find_problem(probs, n_probs, c)];
     if (TOF) stage_lut(lut, P.lut);
     __syncthreads();
-    const Cdf cdf{lut, P.lut_a, P.lut_b};
+    const Cdf cdf{lut, in_vgpr(P.lut_a), P.lut_b};
     const int64_t base = (c - P.chunk_begin) * (int64_t)blockDim.x * ept;
     int neff = 0;
     float ll = 0.0f, wmax = 0.0f;
@@ -576,7 +603,7 @@ __global__ void __launch_bounds__(kForwardBlock) k_forward(const Problem *__rest
 // The LDS accumulation is 64-bit fixed point: FP32 LDS atomic adds run at
 // ~0.2 T/s on this part, 64-bit integer ones at ~2.8 T/s.  A brick's
 // contributions a w (each an FP32 product) are scaled by S = 2^e and
-// rounded to integers, e being chosen per brick from its item count n, the
+// rounded down to integers, e being chosen per brick from its item count n, the
 // problem's bound a_max on a piece weight and the brick's largest |w|, so
 // that n a_max w_max S < 2^62: no sum can overflow.  Chunk tiles stay 64-bit
 // and are added exactly, so b does not depend on how the brick's items are
@@ -640,18 +667,19 @@ __device__ __forceinline__ int brick_exponent(const Problem &P, const uint4 &br,
     return min(max(62 - (en + ea + ew), -126), 126);
 }
 
-// round(v) as a 64-bit two's-complement integer, for 0 <= v < 2^62: the
-// high word is floor(v 2^-32); the low word v - hi 2^32 is exact in FP32
-// (it is the low part of v's significand), then rounded.
-__device__ __forceinline__ unsigned long long fixed_nonneg(float v) {
+// floor(v) as a 64-bit two's-complement integer, for |v| < 2^62: the high
+// word is floor(v 2^-32) (signed); the low word v - hi 2^32 lies in
+// [0, 2^32) and is exact in FP32 (the low part of v's significand) unless
+// -2^32 < v < 0, where it is within 2^8 of exact; then truncated.
+__device__ __forceinline__ unsigned long long fixed_floor(float v) {
     const float hi = floorf(v * 0x1p-32f);
-    const float lo = rintf(fmaf(hi, -0x1p32f, v));
-    return ((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo;
+    const float lo = fmaf(hi, -0x1p32f, v);
+    return ((unsigned long long)(uint32_t)(int32_t)hi << 32) | (uint32_t)lo;
 }
 
 // One item's pieces in its brick, from its walk record, added to the tile
-// as round(a |ws|), subtracted when ws < 0.  A weight a is clamped at 0
-// (the interpolated CDF may dip by ~1e-10 between nodes).
+// as floor(a ws) (ws may be negative; so may a, by ~1e-10 where the
+// interpolated CDF dips between nodes).
 template <bool TOF>
 __device__ __forceinline__ void back_item(const Problem &P, uint32_t k, float ws, const Cdf &cdf,
                                           unsigned long long *tile) {
@@ -665,17 +693,15 @@ __device__ __forceinline__ void back_item(const Problem &P, uint32_t k, float ws
     r.bx = rb[0];
     r.by = rb[1];
     r.bz = rb[2];
-    Stepper s(r, make_uint2(rk[0], rk[1]));
+    Stepper s(r, make_uint2(rk[0], rk[1]), (int)sizeof(unsigned long long));
     const float ta = ra[3], tb = rb[3];
-    if (ws > 0.0f) {
-        walk_from<TOF>(s, r, ta, tb, cdf, [&](int j, float a) {
-            atomicAdd(&tile[j & (kBrickVox - 1)], fixed_nonneg(fmaxf(a, 0.0f) * ws));
-        });
-    } else {
-        walk_from<TOF>(s, r, ta, tb, cdf, [&](int j, float a) {
-            atomicSub(&tile[j & (kBrickVox - 1)], fixed_nonneg(fmaxf(a, 0.0f) * -ws));
-        });
-    }
+    // j is a byte offset into the tile; the mask keeps a step that rounding
+    // carries past the brick's last plane inside it
+    walk_from<TOF>(s, r, ta, tb, cdf, [&](int j, float a) {
+        atomicAdd(reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(tile) +
+                                                         (j & (kBrickVox * 8 - 8))),
+                  fixed_floor(a * ws));
+    });
 }
 
 template <bool TOF>
@@ -689,14 +715,14 @@ __device__ __forceinline__ void back_chunk_items(const Problem &P, const uint4 &
     }
 }
 
-// 2. One chunk: sum over its items of round(a_ij w_i 2^e) in an LDS tile,
+// 2. One chunk: sum over its items of floor(a_ij w_i 2^e) in an LDS tile,
 //    stored (64-bit) to the chunk's tile slot.
 template <bool TOF>
 __global__ void __launch_bounds__(kBackBlock) k_back_chunks(const Problem *__restrict__ probs, int n_probs,
                                                             const uint4 *__restrict__ chunks,
                                                             const uint4 *__restrict__ bricks) {
     __shared__ unsigned long long tile[kBrickVox];
-    __shared__ float4 lut[kLutN];
+    __shared__ float4 lut[kLutN + 2];
     const uint4 ch = chunks[blockIdx.x];
     const uint4 br = bricks[ch.x];
     const uint32_t bid = br.x;
@@ -707,7 +733,7 @@ __global__ void __launch_bounds__(kBackBlock) k_back_chunks(const Problem *__res
     float wm;
     const int e = brick_exponent(P, br, wm);
     const float S = ldexpf(1.0f, e);
-    const Cdf cdf{lut, P.lut_a, P.lut_b};
+    const Cdf cdf{lut, in_vgpr(P.lut_a), P.lut_b};
     if (wm > 0.0f) back_chunk_items<TOF>(P, ch, S, cdf, tile);
     __syncthreads();
     const gptr<unsigned long long> dst = global(P.tiles) + (size_t)ch.w * kBrickVox;
@@ -955,13 +981,13 @@ __global__ void __launch_bounds__(kForwardBlock) k_brick_items(const Problem *__
 template <bool TOF>
 __global__ void __launch_bounds__(kForwardBlock) k_count_pieces(const Problem *__restrict__ probs, int n_probs,
                                                                 int ept, unsigned long long *__restrict__ part) {
-    __shared__ float4 lut[kLutN];
+    __shared__ float4 lut[kLutN + 2];
     __shared__ unsigned long long s_c[kForwardBlock / 64], s_z[kForwardBlock / 64];
     const int64_t c = blockIdx.x;
     const Problem P = probs[find_problem(probs, n_probs, c)];
     if (TOF) stage_lut(lut, P.lut);
     __syncthreads();
-    const Cdf cdf{lut, P.lut_a, P.lut_b};
+    const Cdf cdf{lut, in_vgpr(P.lut_a), P.lut_b};
     const Box B = grid_box(P);
     const int64_t base = (c - P.chunk_begin) * (int64_t)blockDim.x * ept;
     unsigned long long cnt = 0, nz = 0;
@@ -994,15 +1020,16 @@ __global__ void __launch_bounds__(kForwardBlock) k_count_pieces(const Problem *_
 }
 
 // xb <- x in 4^3 blocks: four blocks per 256-thread workgroup, one voxel
-// per thread (voxels past the grid edge are 0).
+// per thread (voxels past the grid edge and padding blocks are 0).
 __global__ void __launch_bounds__(256) k_block_image(const Problem *__restrict__ probs, int n_probs) {
     const int64_t blk = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     int p = n_probs - 1;
     while (p > 0 && probs[p].xblk_begin > blk) --p;
     const Problem &P = probs[p];
     const int64_t lb = blk - P.xblk_begin;
-    if (lb >= (int64_t)P.nbx4 * P.nby4 * P.nbz4) return;
-    const int bx = (int)(lb % P.nbx4), by = (int)((lb / P.nbx4) % P.nby4), bz = (int)(lb / ((int64_t)P.nbx4 * P.nby4));
+    if (lb >= xblocks(P)) return;
+    const int bx = (int)(lb & ((1 << P.xfx) - 1)), by = (int)((lb >> P.xfx) & ((1 << P.xfy) - 1)),
+              bz = (int)(lb >> (P.xfx + P.xfy));
     const int v = threadIdx.x & 63;
     const int ix = 4 * bx + (v & 3), iy = 4 * by + ((v >> 2) & 3), iz = 4 * bz + (v >> 4);
     const float val = (ix < P.nx && iy < P.ny && iz < P.nz) ? P.x[ix + (int64_t)P.nx * (iy + (int64_t)P.ny * iz)] : 0.0f;
