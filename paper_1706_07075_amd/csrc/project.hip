@@ -258,6 +258,13 @@ struct Box {
     int sy, sz;      // strides of the reported index
 };
 
+// LDS tile of the back projection: a brick's voxels at x + kTileSy y +
+// kTileSz z (8-byte entries).  The odd strides put the neighbours of a
+// voxel along y and z in other LDS banks than the voxel itself, so lanes
+// walking side-by-side rays rarely collide on a bank.
+constexpr int kTileSy = kBrickX + 1, kTileSz = kTileSy * kBrickY + 1;
+constexpr int kTileSlots = (kBrickX - 1) + kTileSy * (kBrickY - 1) + kTileSz * (kBrickZ - 1) + 1;
+
 // Voxel-by-voxel traversal of a ray inside a box, without divergent
 // branches: each step advances the axis whose next plane is crossed first
 // (ties go x, then y, then z; the tied axes follow with zero-length pieces).
@@ -304,10 +311,11 @@ struct Stepper {
         tx = fmaf(kx, r.ax, r.bx);
         ty = fmaf(ky, r.ay, r.by);
         tz = fmaf(kz, r.az, r.bz);
-        j = (int)(rk.y >> 16) * unit;
+        const int v = (int)(rk.y >> 16);  // brick-local voxel, x fastest
+        j = ((v & (kBrickX - 1)) + kTileSy * ((v / kBrickX) & (kBrickY - 1)) + kTileSz * (v / (kBrickX * kBrickY))) * unit;
         djx = px ? unit : -unit;
-        djy = (py ? kBrickX : -kBrickX) * unit;
-        djz = (pz ? kBrickX * kBrickY : -kBrickX * kBrickY) * unit;
+        djy = (py ? kTileSy : -kTileSy) * unit;
+        djz = (pz ? kTileSz : -kTileSz) * unit;
         max_steps = kBrickX + kBrickY + kBrickZ + 2;
     }
     __device__ __forceinline__ float next() const { return fminf(fminf(tx, ty), tz); }
@@ -695,11 +703,11 @@ __device__ __forceinline__ void back_item(const Problem &P, uint32_t k, float ws
     r.bz = rb[2];
     Stepper s(r, make_uint2(rk[0], rk[1]), (int)sizeof(unsigned long long));
     const float ta = ra[3], tb = rb[3];
-    // j is a byte offset into the tile; the mask keeps a step that rounding
-    // carries past the brick's last plane inside it
+    // j is a byte offset into the tile; the clamp keeps a step that rounding
+    // carries past the brick's planes (a piece of ~zero weight) inside it
     walk_from<TOF>(s, r, ta, tb, cdf, [&](int j, float a) {
         atomicAdd(reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(tile) +
-                                                         (j & (kBrickVox * 8 - 8))),
+                                                         min((uint32_t)j, (uint32_t)(kTileSlots - 1) * 8u)),
                   fixed_floor(a * ws));
     });
 }
@@ -721,13 +729,13 @@ template <bool TOF>
 __global__ void __launch_bounds__(kBackBlock) k_back_chunks(const Problem *__restrict__ probs, int n_probs,
                                                             const uint4 *__restrict__ chunks,
                                                             const uint4 *__restrict__ bricks) {
-    __shared__ unsigned long long tile[kBrickVox];
+    __shared__ unsigned long long tile[kTileSlots];
     __shared__ float4 lut[kLutN + 2];
     const uint4 ch = chunks[blockIdx.x];
     const uint4 br = bricks[ch.x];
     const uint32_t bid = br.x;
     const Problem P = probs[find_brick_problem(probs, n_probs, bid)];
-    for (int k = threadIdx.x; k < kBrickVox; k += blockDim.x) tile[k] = 0ull;
+    for (int k = threadIdx.x; k < kTileSlots; k += blockDim.x) tile[k] = 0ull;
     if (TOF) stage_lut(lut, P.lut);
     __syncthreads();
     float wm;
@@ -737,7 +745,8 @@ __global__ void __launch_bounds__(kBackBlock) k_back_chunks(const Problem *__res
     if (wm > 0.0f) back_chunk_items<TOF>(P, ch, S, cdf, tile);
     __syncthreads();
     const gptr<unsigned long long> dst = global(P.tiles) + (size_t)ch.w * kBrickVox;
-    for (int k = threadIdx.x; k < kBrickVox; k += blockDim.x) dst[k] = tile[k];
+    for (int k = threadIdx.x; k < kBrickVox; k += blockDim.x)
+        dst[k] = tile[(k & (kBrickX - 1)) + kTileSy * ((k / kBrickX) & (kBrickY - 1)) + kTileSz * (k / (kBrickX * kBrickY))];
 }
 
 // 3. b over one brick = (exact sum of its chunk tiles) 2^-e.
