@@ -285,6 +285,7 @@ Problem make_problem(const lmtof_ctx *c, int z_lo, int nz, float *x, float *b, c
         const double h = 2.0 * g.tof_trunc_sigmas / (kLutN - 1);
         P.lut_a = (float)(1.0 / (sigma_mm(g) * h));
         P.lut_b = (float)((kLutN - 1) / 2) + 12582912.0f;  // centre node + 1.5 2^23, exact
+        P.lut_h2 = (float)(h * h / 2.0);
     }
     P.a_max = P.tof ? 1.0f : (float)std::sqrt(g.vx * g.vx + g.vy * g.vy + g.vz * g.vz);
     P.nbx = (g.nx + kBrickX - 1) / kBrickX;

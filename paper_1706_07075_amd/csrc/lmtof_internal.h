@@ -59,6 +59,7 @@ struct Problem {
     float norm;           // 1 / (2 erf(K / sqrt 2)): makes the full kernel sum to 1
     const float4 *lut;    // kernel-CDF table: a pad entry, kLutN nodes over [-K, K] sigma, a pad entry
     float lut_a, lut_b;   // node position of t (mm): t * lut_a + (kLutN - 1) / 2; lut_b = (kLutN - 1) / 2 + 1.5 2^23
+    float lut_h2;         // h^2 / 2, h the node spacing in sigma units
     float a_max;          // bound on one piece weight (TOF: 1, the kernel mass; else the voxel diagonal)
     int32_t brick_base;   // global id of this problem's first brick
     int32_t nbx, nby, nbz;// bricks per axis

@@ -250,6 +250,25 @@ struct Cdf {
     }
 };
 
+// The same CDF from (Phi_k, Phi'_k h) pairs, 8 bytes a node (less LDS
+// traffic per lookup): since Phi'' = -u Phi' and u_k = (k - c) h, the
+// curvature term Phi''_k h^2 / 2 is (c - k) (h^2 / 2) Phi'_k h, and c - k is
+// b - y, exactly.
+constexpr uint32_t kLutAddrBias2 = 8u - (0x4B400000u << 3);  // 8 (k + 1) - (bits(1.5 2^23 + k) << 3)
+
+struct Cdf2 {
+    const float2 *tab;
+    float a, b, h2;  // h2 = h^2 / 2, h the node spacing in sigma units
+    __device__ __forceinline__ float operator()(float t) const {
+        const float y = fmaf(t, a, b);      // 1.5 2^23 + k
+        const float ck = b - y;             // c - k
+        const float f = fmaf(t, a, ck);     // position - k, in [-1/2, 1/2]
+        const float2 e = *reinterpret_cast<const float2 *>(reinterpret_cast<const char *>(tab) +
+                                                           ((__float_as_uint(y) << 3) + kLutAddrBias2));
+        return fmaf(f * e.y, fmaf(f * ck, h2, 1.0f), e.x);
+    }
+};
+
 // A voxel box the traversal is confined to (the whole grid or one brick),
 // with the strides of the index it reports.
 struct Box {
@@ -397,19 +416,19 @@ struct StepperB {
 // visit(j, a) for every piece, j box-local.  A plane tie gives a
 // zero-length piece (a = 0).  The piece [t, t'] ends at the next crossing
 // clamped into [t, tb].
-template <bool TOF, class Visit>
-__device__ __forceinline__ void walk_from(Stepper &s, const Ray &r, float ta, float tb, const Cdf &cdf,
+template <bool TOF, class C, class Visit>
+__device__ __forceinline__ void walk_from(Stepper &s, const Ray &r, float ta, float tb, const C &cdf,
                                           Visit &&visit);
 
-template <bool TOF, class Visit>
+template <bool TOF, class C, class Visit>
 __device__ __forceinline__ void walk(const Problem &P, const Ray &r, float ta, float tb, const Box &B,
-                                     const Cdf &cdf, Visit &&visit) {
+                                     const C &cdf, Visit &&visit) {
     Stepper s(P, r, ta, B);
     walk_from<TOF>(s, r, ta, tb, cdf, visit);
 }
 
-template <bool TOF, class Visit>
-__device__ __forceinline__ void walk_from(Stepper &s, const Ray &r, float ta, float tb, const Cdf &cdf,
+template <bool TOF, class C, class Visit>
+__device__ __forceinline__ void walk_from(Stepper &s, const Ray &r, float ta, float tb, const C &cdf,
                                           Visit &&visit) {
     float t = ta;
     float c = TOF ? cdf(ta) : 0.0f;
@@ -689,7 +708,7 @@ __device__ __forceinline__ unsigned long long fixed_floor(float v) {
 // as floor(a ws) (ws may be negative; so may a, by ~1e-10 where the
 // interpolated CDF dips between nodes).
 template <bool TOF>
-__device__ __forceinline__ void back_item(const Problem &P, uint32_t k, float ws, const Cdf &cdf,
+__device__ __forceinline__ void back_item(const Problem &P, uint32_t k, float ws, const Cdf2 &cdf,
                                           unsigned long long *tile) {
     const f32x4 ra = global(reinterpret_cast<const f32x4 *>(P.rec_a))[k];
     const f32x4 rb = global(reinterpret_cast<const f32x4 *>(P.rec_b))[k];
@@ -713,7 +732,7 @@ __device__ __forceinline__ void back_item(const Problem &P, uint32_t k, float ws
 }
 
 template <bool TOF>
-__device__ __forceinline__ void back_chunk_items(const Problem &P, const uint4 &ch, float S, const Cdf &cdf,
+__device__ __forceinline__ void back_chunk_items(const Problem &P, const uint4 &ch, float S, const Cdf2 &cdf,
                                                  unsigned long long *tile) {
     const gptr<const uint32_t> items = global(P.items);
     const gptr<const float> w = global(P.rw);
@@ -730,18 +749,19 @@ __global__ void __launch_bounds__(kBackBlock) k_back_chunks(const Problem *__res
                                                             const uint4 *__restrict__ chunks,
                                                             const uint4 *__restrict__ bricks) {
     __shared__ unsigned long long tile[kTileSlots];
-    __shared__ float4 lut[kLutN + 2];
+    __shared__ float2 lut[kLutN + 2];
     const uint4 ch = chunks[blockIdx.x];
     const uint4 br = bricks[ch.x];
     const uint32_t bid = br.x;
     const Problem P = probs[find_brick_problem(probs, n_probs, bid)];
     for (int k = threadIdx.x; k < kTileSlots; k += blockDim.x) tile[k] = 0ull;
-    if (TOF) stage_lut(lut, P.lut);
+    if (TOF)
+        for (int k = threadIdx.x; k < kLutN + 2; k += blockDim.x) lut[k] = make_float2(P.lut[k].x, P.lut[k].y);
     __syncthreads();
     float wm;
     const int e = brick_exponent(P, br, wm);
     const float S = ldexpf(1.0f, e);
-    const Cdf cdf{lut, in_vgpr(P.lut_a), P.lut_b};
+    const Cdf2 cdf{lut, in_vgpr(P.lut_a), P.lut_b, P.lut_h2};
     if (wm > 0.0f) back_chunk_items<TOF>(P, ch, S, cdf, tile);
     __syncthreads();
     const gptr<unsigned long long> dst = global(P.tiles) + (size_t)ch.w * kBrickVox;
