@@ -14,9 +14,9 @@ namespace lmtof {
 constexpr int kLutN = 1025;  // odd: the centre of the window is a node
 constexpr int kBrickX = 16, kBrickY = 16, kBrickZ = 16;
 constexpr int kBrickVox = kBrickX * kBrickY * kBrickZ;
-// Brick items are grouped by an estimate of their voxel pieces in the brick
+// Brick items are grouped by their voxel-plane crossings in the brick
 // (longest first), so that a wavefront's lanes walk similar lengths.
-constexpr int kItemClasses = 8;
+constexpr int kItemClasses = 16;
 // Largest brick count of one problem (the brick item builder keeps a bitmap
 // of a problem's bricks in LDS).
 constexpr int kMaxProblemBricks = 65536;

@@ -629,10 +629,10 @@ __global__ void __launch_bounds__(kForwardBlock) k_forward(const Problem *__rest
 //
 // The LDS accumulation is 64-bit fixed point: FP32 LDS atomic adds run at
 // ~0.2 T/s on this part, 64-bit integer ones at ~2.8 T/s.  A brick's
-// contributions a w (each an FP32 product) are scaled by S = 2^e and
-// rounded down to integers, e being chosen per brick from its item count n, the
-// problem's bound a_max on a piece weight and the brick's largest |w|, so
-// that n a_max w_max S < 2^62: no sum can overflow.  Chunk tiles stay 64-bit
+// contributions a w are scaled by S = 2^e and rounded to integers, e being
+// chosen per brick from its item count n, the problem's bound a_max on a
+// piece weight and the brick's largest |w|, so that n a_max w_max S < 2^62:
+// no sum can overflow.  Chunk tiles stay 64-bit
 // and are added exactly, so b does not depend on how the brick's items are
 // ordered or cut into chunks: the result is deterministic, and the same
 // for a problem run alone or batched with others.
@@ -691,21 +691,24 @@ __device__ __forceinline__ int brick_exponent(const Problem &P, const uint4 &br,
     frexpf((float)br.w, &en);
     frexpf(P.a_max, &ea);
     frexpf(wm, &ew);
-    return min(max(62 - (en + ea + ew), -126), 126);
+    // n a_max w_max 2^e < 2^62 (no sum overflows) and a_max w_max 2^e < 2^51
+    // (each term is in range of the conversion below)
+    return min(max(min(62 - en, 51) - (ea + ew), -126), 126);
 }
 
-// floor(v) as a 64-bit two's-complement integer, for |v| < 2^62: the high
-// word is floor(v 2^-32) (signed); the low word v - hi 2^32 lies in
-// [0, 2^32) and is exact in FP32 (the low part of v's significand) unless
-// -2^32 < v < 0, where it is within 2^8 of exact; then truncated.
-__device__ __forceinline__ unsigned long long fixed_floor(float v) {
-    const float hi = floorf(v * 0x1p-32f);
-    const float lo = fmaf(hi, -0x1p32f, v);
-    return ((unsigned long long)(uint32_t)(int32_t)hi << 32) | (uint32_t)lo;
+// round(a w) as a 64-bit two's-complement integer, for |a w| < 2^51: the
+// FP64 sum a w + 1.5 2^52 (exact product, one rounding) lies in [2^52,
+// 2^53), where doubles are the integers, so its bit pattern is that of
+// 1.5 2^52 plus round(a w); the constant's low word is 0, so removing it
+// only touches the high word.
+__device__ __forceinline__ unsigned long long fixed_round(float a, double w) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(fma((double)a, w, 0x1.8p52));
+    const uint32_t hi = (uint32_t)(u >> 32) - 0x43380000u;
+    return ((unsigned long long)hi << 32) | (uint32_t)u;
 }
 
 // One item's pieces in its brick, from its walk record, added to the tile
-// as floor(a ws) (ws may be negative; so may a, by ~1e-10 where the
+// as round(a ws) (ws may be negative; so may a, by ~1e-10 where the
 // interpolated CDF dips between nodes).
 template <bool TOF>
 __device__ __forceinline__ void back_item(const Problem &P, uint32_t k, float ws, const Cdf2 &cdf,
@@ -724,10 +727,11 @@ __device__ __forceinline__ void back_item(const Problem &P, uint32_t k, float ws
     const float ta = ra[3], tb = rb[3];
     // j is a byte offset into the tile; the clamp keeps a step that rounding
     // carries past the brick's planes (a piece of ~zero weight) inside it
+    const double wsd = ws;
     walk_from<TOF>(s, r, ta, tb, cdf, [&](int j, float a) {
         atomicAdd(reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(tile) +
                                                          min((uint32_t)j, (uint32_t)(kTileSlots - 1) * 8u)),
-                  fixed_floor(a * ws));
+                  fixed_round(a, wsd));
     });
 }
 
@@ -742,7 +746,7 @@ __device__ __forceinline__ void back_chunk_items(const Problem &P, const uint4 &
     }
 }
 
-// 2. One chunk: sum over its items of floor(a_ij w_i 2^e) in an LDS tile,
+// 2. One chunk: sum over its items of round(a_ij w_i 2^e) in an LDS tile,
 //    stored (64-bit) to the chunk's tile slot.
 template <bool TOF>
 __global__ void __launch_bounds__(kBackBlock) k_back_chunks(const Problem *__restrict__ probs, int n_probs,
@@ -902,16 +906,19 @@ __device__ __forceinline__ void write_item_walk(const Problem &P, const Ray &r, 
     global(reinterpret_cast<u32x2 *>(const_cast<uint2 *>(P.rec_k)))[pos] = k;
 }
 
-// Item class of a brick piece [t0, t1] of ray r by its estimated plane
-// crossings (t1 - t0) sum_a |u_a| / v_a: 0 for 21 or more, then 16-20,
-// 12-15, 9-11, 6-8, 4-5, 2-3, and 0-1.
+// Item class of a brick piece [t0, t1] of ray r by its voxel-plane
+// crossings (the voxel walk's step count): 0 for 30 or more, then 26-29,
+// 23-25, 20-22, 18-19, 16-17, 14-15, 12-13, 10-11, 8-9, 6-7, 5, 4, 3, 2
+// and 0-1.  Items of one class walk nearly the same number of steps, so a
+// wavefront's lanes finish together.
 __device__ __forceinline__ uint32_t item_class(const Problem &P, const Ray &r, float t0, float t1) {
-    const float m = (t1 - t0) * (fabsf(r.ux) * P.ivx + fabsf(r.uy) * P.ivy + fabsf(r.uz) * P.ivz);
-    // class edges in estimated crossings, longest first
-    const float edge[kItemClasses - 1] = {21.0f, 16.0f, 12.0f, 9.0f, 6.0f, 4.0f, 2.0f};
+    const int n = abs(voxel_at(t1, r.ux, r.jx, r.dx, P.ivx) - voxel_at(t0, r.ux, r.jx, r.dx, P.ivx)) +
+                  abs(voxel_at(t1, r.uy, r.jy, r.dy, P.ivy) - voxel_at(t0, r.uy, r.jy, r.dy, P.ivy)) +
+                  abs(voxel_at(t1, r.uz, r.jz, r.dz, P.ivz) - voxel_at(t0, r.uz, r.jz, r.dz, P.ivz));
+    const int edge[kItemClasses - 1] = {30, 26, 23, 20, 18, 16, 14, 12, 10, 8, 6, 5, 4, 3, 2};
     uint32_t k = 0;
 #pragma unroll
-    for (int q = 0; q < kItemClasses - 1; ++q) k += m < edge[q];
+    for (int q = 0; q < kItemClasses - 1; ++q) k += n < edge[q];
     return k;
 }
 
