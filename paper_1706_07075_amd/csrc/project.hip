@@ -711,11 +711,8 @@ __device__ __forceinline__ unsigned long long fixed_round(float a, double w) {
 // as round(a ws) (ws may be negative; so may a, by ~1e-10 where the
 // interpolated CDF dips between nodes).
 template <bool TOF>
-__device__ __forceinline__ void back_item(const Problem &P, uint32_t k, float ws, const Cdf2 &cdf,
+__device__ __forceinline__ void back_item(const f32x4 &ra, const f32x4 &rb, const u32x2 &rk, float ws, const Cdf2 &cdf,
                                           unsigned long long *tile) {
-    const f32x4 ra = global(reinterpret_cast<const f32x4 *>(P.rec_a))[k];
-    const f32x4 rb = global(reinterpret_cast<const f32x4 *>(P.rec_b))[k];
-    const u32x2 rk = global(reinterpret_cast<const u32x2 *>(P.rec_k))[k];
     Ray r;
     r.ax = ra[0];
     r.ay = ra[1];
@@ -740,9 +737,25 @@ __device__ __forceinline__ void back_chunk_items(const Problem &P, const uint4 &
                                                  unsigned long long *tile) {
     const gptr<const uint32_t> items = global(P.items);
     const gptr<const float> w = global(P.rw);
-    for (uint32_t k = ch.y + threadIdx.x; k < ch.z; k += blockDim.x) {
-        const float ws = w[items[k]] * S;
-        if (ws != 0.0f) back_item<TOF>(P, k, ws, cdf, tile);
+    const gptr<const f32x4> rec_a = global(reinterpret_cast<const f32x4 *>(P.rec_a));
+    const gptr<const f32x4> rec_b = global(reinterpret_cast<const f32x4 *>(P.rec_b));
+    const gptr<const u32x2> rec_k = global(reinterpret_cast<const u32x2 *>(P.rec_k));
+    // The next item's event index is loaded (unconditionally, at a clamped
+    // position) while this item is walked, and an item's weight and walk
+    // record are loaded together: one memory round trip per item.
+    const uint32_t last = ch.z - 1;
+    uint32_t k = ch.y + threadIdx.x;
+    uint32_t ev = items[min(k, last)];
+    for (; k < ch.z; k += blockDim.x) {
+        const uint32_t ev_next = items[min(k + blockDim.x, last)];
+        const float wv = w[ev];
+        const f32x4 ra = rec_a[k];
+        const f32x4 rb = rec_b[k];
+        const u32x2 rk = rec_k[k];
+        // (no test for w = 0, which adds zeros: a branch here would let
+        // the compiler move the record loads behind the weight's)
+        back_item<TOF>(ra, rb, rk, wv * S, cdf, tile);
+        ev = ev_next;
     }
 }
 
