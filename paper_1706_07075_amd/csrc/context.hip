@@ -420,14 +420,16 @@ int build_items(lmtof_ctx *c, std::vector<Problem> &ps, Problem *d_probs, int64_
     const uint64_t nk = nb * kItemClasses;  // (brick, item class) keys
     Launch L;
     L.stream = c->stream;
-    uint32_t *cnt = nullptr, *off_d = nullptr, *pcnt = nullptr;
+    uint32_t *cnt = nullptr, *off_d = nullptr, *pcnt = nullptr, *tabs = nullptr;
     auto free_tmp = [&]() {
         dev_free(cnt);
         dev_free(off_d);
         dev_free(pcnt);
+        dev_free(tabs);
     };
     int rc = dev_alloc(c, &cnt, nk + 1);
     if (!rc) rc = dev_alloc(c, &pcnt, nb + 1);
+    if (!rc) rc = dev_alloc(c, &tabs, (size_t)brick_item_tab_words(n_chunks));
     if (rc) {
         free_tmp();
         free_items(keep);
@@ -436,7 +438,7 @@ int build_items(lmtof_ctx *c, std::vector<Problem> &ps, Problem *d_probs, int64_
     std::vector<uint32_t> hk(nk), hp(nb);
     hipError_t he = hipMemsetAsync(cnt, 0, sizeof(uint32_t) * (nk + 1), c->stream);
     if (he == hipSuccess) he = hipMemsetAsync(pcnt, 0, sizeof(uint32_t) * (nb + 1), c->stream);
-    if (he == hipSuccess) he = launch_brick_items(L, d_probs, (int)ps.size(), n_chunks, ept, cnt, nullptr, pcnt, 0);
+    if (he == hipSuccess) he = launch_brick_items(L, d_probs, (int)ps.size(), n_chunks, ept, cnt, nullptr, pcnt, 0, tabs);
     if (he == hipSuccess) he = hipMemcpyAsync(hk.data(), cnt, sizeof(uint32_t) * nk, hipMemcpyDeviceToHost, c->stream);
     if (he == hipSuccess) he = hipMemcpyAsync(hp.data(), pcnt, sizeof(uint32_t) * nb, hipMemcpyDeviceToHost, c->stream);
     if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
@@ -526,7 +528,7 @@ int build_items(lmtof_ctx *c, std::vector<Problem> &ps, Problem *d_probs, int64_
         he = hipMemcpyAsync(it.pair_off, poff.data(), sizeof(uint32_t) * (nb + 1), hipMemcpyHostToDevice, c->stream);
     if (he == hipSuccess)
         he = hipMemcpyAsync(pcnt, it.pair_off, sizeof(uint32_t) * (nb + 1), hipMemcpyDeviceToDevice, c->stream);
-    if (he == hipSuccess) he = launch_brick_items(L, d_probs, (int)ps.size(), n_chunks, ept, cnt, off_d + 1, pcnt, 1);
+    if (he == hipSuccess) he = launch_brick_items(L, d_probs, (int)ps.size(), n_chunks, ept, cnt, off_d + 1, pcnt, 1, tabs);
     if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
     free_tmp();
     if (he != hipSuccess) {
@@ -845,7 +847,9 @@ int64_t request_bytes_estimate(const lmtof_request &q) {
     int64_t b = N * (esz + 8 + 4) + items * (4 + kItemRecBytes) + 3 * 4 * V + 4 * xbv;  // x, b, s, blocked x
     b += (items / 2048 + 1 + V / kBrickVox + 1) * (int64_t)kBrickVox * 8 / 4;  // tiles
     b += items;  // (forward chunk, brick) pairs: at most one per item, ~1 in 10 in practice
-    b += N * (q.mem == LMTOF_MEM_HOST ? 28 : 0) + N * (esz + 8 + 4);       // ingest transients
+    // transients: the ingest's, then (not at the same time) the brick list
+    // builder's key tables, 8 KiB per projector block, at most 32 B an event
+    b += N * (q.mem == LMTOF_MEM_HOST ? 28 : 0) + N * std::max<int64_t>(esz + 8 + 4, 32);
     return b + (64 << 20);
 }
 

@@ -136,9 +136,11 @@ hipError_t launch_reduce_tiles(const Launch &L, const Problem *d_probs, int n_pr
 // and problem-local forward chunk indices to P.pairs at pctr[brick]++ (never
 // past the brick's P.pair_off end).  Same launch shape as the forward pass
 // (its chunks are the pairs' chunks).  Every problem has at most
-// kMaxProblemBricks bricks.
+// kMaxProblemBricks bricks.  tabs (brick_item_tab_words(n_chunks) words)
+// carries each block's key table from the counting launch to the filling one.
 hipError_t launch_brick_items(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept,
-                              uint32_t *ctr, const uint32_t *end, uint32_t *pctr, int fill);
+                              uint32_t *ctr, const uint32_t *end, uint32_t *pctr, int fill, uint32_t *tabs);
+int64_t brick_item_tab_words(int64_t n_chunks);
 // part[2c] = voxel pieces visited by chunk c, part[2c+1] = pieces with non-zero weight.
 hipError_t launch_count_pieces(const Launch &L, bool tof, const Problem *d_probs, int n_probs, int64_t n_chunks,
                                int ept, unsigned long long *part);

@@ -889,11 +889,12 @@ __device__ __forceinline__ void brick_walk(const Problem &P, const Ray &r, Visit
 // item's walk record (crossing coefficients, its piece of the window, first
 // voxel), so that the back projection streams a chunk's records instead of
 // gathering events and re-deriving rays (each event is walked once per
-// brick it crosses).  A block first tallies
-// its pieces per brick in an LDS hash table, then touches each global
+// brick it crosses).  When counting, a block
+// tallies its pieces per key in an LDS hash table, then touches each global
 // counter once (bucketed events make whole blocks hit the same few bricks,
-// and same-address global atomics serialise); when filling, the block then
-// re-walks its events and hands out positions from its reserved ranges.
+// and same-address global atomics serialise) and keeps the table; when
+// filling, the block reloads its table, reserves each key's range, and
+// walks its events once, handing out positions from the reserved ranges.
 // Walk record of a brick item at position pos: the crossing coefficients,
 // the piece [ta, tb] of the window inside the brick (as the brick walk cut
 // it) and the first voxel, as the back projection's walk starts from them.
@@ -935,13 +936,25 @@ __device__ __forceinline__ uint32_t item_class(const Problem &P, const Ray &r, f
     return k;
 }
 
+// Counting (fill == 0): tally the block's pieces per key in the LDS table,
+// add them to ctr, and store the table to tab.  Filling: reload the table,
+// reserve each key's range, then walk the events once.
 template <bool PACKED>
 __device__ __forceinline__ void brick_items_pass(const Problem &P, int64_t base, uint32_t chunk, int ept,
                                                  uint32_t *__restrict__ ctr, const uint32_t *__restrict__ end,
                                                  uint32_t *__restrict__ pctr, int fill, uint32_t *hkey,
-                                                 uint32_t *hcnt, uint32_t *hbase, uint32_t *bmap) {
+                                                 uint32_t *hcnt, uint32_t *hbase, uint32_t *bmap,
+                                                 gptr<uint32_t> tab) {
     const gptr<uint32_t> items = global(const_cast<uint32_t *>(P.items));
     const gptr<uint32_t> pairs = global(const_cast<uint32_t *>(P.pairs));
+    if (fill) {
+        for (int k = threadIdx.x; k < kHashSlots; k += blockDim.x) {
+            if (hkey[k] == kEmpty) continue;
+            hbase[k] = atomicAdd(ctr + hkey[k], hcnt[k]);
+            hcnt[k] = 0;
+        }
+        __syncthreads();
+    }
     for (int e = 0; e < ept; ++e) {
         const int64_t i = base + (int64_t)e * blockDim.x + threadIdx.x;
         Ray r;
@@ -950,16 +963,20 @@ __device__ __forceinline__ void brick_items_pass(const Problem &P, int64_t base,
             const uint32_t bl = brick - (uint32_t)P.brick_base;
             atomicOr(&bmap[bl >> 5], 1u << (bl & 31u));
             const uint32_t key = brick * kItemClasses + item_class(P, r, t0, t1);
-            const int h = hash_insert(hkey, key);
-            if (h >= 0) {
-                atomicAdd(&hcnt[h], 1u);
-            } else {
-                // table full: place the piece directly
-                const uint32_t pos = atomicAdd(ctr + key, 1u);
-                if (fill && pos < end[key]) {
-                    items[pos] = (uint32_t)i;
-                    write_item_walk(P, r, brick, t0, t1, pos);
-                }
+            if (!fill) {
+                const int h = hash_insert(hkey, key);
+                if (h >= 0)
+                    atomicAdd(&hcnt[h], 1u);
+                else
+                    atomicAdd(ctr + key, 1u);  // table full: counted directly
+                return;
+            }
+            // a key is in the table in both passes, or counted directly in both
+            const int h = hash_find(hkey, key);
+            const uint32_t pos = h >= 0 ? hbase[h] + atomicAdd(&hcnt[h], 1u) : atomicAdd(ctr + key, 1u);
+            if (pos < end[key]) {
+                items[pos] = (uint32_t)i;
+                write_item_walk(P, r, brick, t0, t1, pos);
             }
         });
     }
@@ -976,44 +993,27 @@ __device__ __forceinline__ void brick_items_pass(const Problem &P, int64_t base,
             if (fill && pos < P.pair_off[bl + 1]) pairs[pos] = chunk;
         }
     }
+    if (fill) return;
     for (int k = threadIdx.x; k < kHashSlots; k += blockDim.x) {
-        if (hkey[k] == kEmpty) continue;
-        const uint32_t b = atomicAdd(ctr + hkey[k], hcnt[k]);
-        if (fill) {
-            hbase[k] = b;
-            hcnt[k] = 0;
-        }
-    }
-    if (!fill) return;
-    __syncthreads();
-    for (int e = 0; e < ept; ++e) {
-        const int64_t i = base + (int64_t)e * blockDim.x + threadIdx.x;
-        Ray r;
-        if (i >= P.n_events || !make_ray<PACKED>(P, i, r)) continue;
-        brick_walk(P, r, [&](uint32_t brick, float t0, float t1) {
-            const uint32_t key = brick * kItemClasses + item_class(P, r, t0, t1);
-            const int h = hash_find(hkey, key);
-            if (h < 0) return;  // placed directly in the first walk
-            const uint32_t pos = hbase[h] + atomicAdd(&hcnt[h], 1u);
-            if (pos < end[key]) {
-                items[pos] = (uint32_t)i;
-                write_item_walk(P, r, brick, t0, t1, pos);
-            }
-        });
+        if (hkey[k] != kEmpty) atomicAdd(ctr + hkey[k], hcnt[k]);
+        tab[k] = hkey[k];
+        tab[kHashSlots + k] = hcnt[k];
     }
 }
 
 __global__ void __launch_bounds__(kForwardBlock) k_brick_items(const Problem *__restrict__ probs, int n_probs,
                                                                int ept, uint32_t *__restrict__ ctr,
                                                                const uint32_t *__restrict__ end,
-                                                               uint32_t *__restrict__ pctr, int fill) {
+                                                               uint32_t *__restrict__ pctr, int fill,
+                                                               uint32_t *__restrict__ tabs) {
     __shared__ uint32_t hkey[kHashSlots], hcnt[kHashSlots], hbase[kHashSlots];
     __shared__ uint32_t bmap[kMaxProblemBricks / 32];  // bricks of the problem this block touches
     const int64_t c = blockIdx.x;
     const Problem P = probs[find_problem(probs, n_probs, c)];
+    const gptr<uint32_t> tab = global(tabs) + (size_t)c * (2 * kHashSlots);
     for (int k = threadIdx.x; k < kHashSlots; k += blockDim.x) {
-        hkey[k] = kEmpty;
-        hcnt[k] = 0;
+        hkey[k] = fill ? tab[k] : kEmpty;
+        hcnt[k] = fill ? tab[kHashSlots + k] : 0u;
     }
     const uint32_t nw = ((uint32_t)P.nbx * (uint32_t)P.nby * (uint32_t)P.nbz + 31) / 32;
     for (uint32_t w = threadIdx.x; w < nw; w += blockDim.x) bmap[w] = 0;
@@ -1021,9 +1021,9 @@ __global__ void __launch_bounds__(kForwardBlock) k_brick_items(const Problem *__
     const int64_t base = (c - P.chunk_begin) * (int64_t)blockDim.x * ept;
     const uint32_t chunk = (uint32_t)(c - P.chunk_begin);
     if (P.packed)
-        brick_items_pass<true>(P, base, chunk, ept, ctr, end, pctr, fill, hkey, hcnt, hbase, bmap);
+        brick_items_pass<true>(P, base, chunk, ept, ctr, end, pctr, fill, hkey, hcnt, hbase, bmap, tab);
     else
-        brick_items_pass<false>(P, base, chunk, ept, ctr, end, pctr, fill, hkey, hcnt, hbase, bmap);
+        brick_items_pass<false>(P, base, chunk, ept, ctr, end, pctr, fill, hkey, hcnt, hbase, bmap, tab);
 }
 
 // Diagnostic: voxel pieces visited per chunk and how many have non-zero weight.
@@ -1089,6 +1089,8 @@ __global__ void __launch_bounds__(256) k_block_image(const Problem *__restrict__
 
 int64_t project_chunk_events(int block, int ept) { return (int64_t)block * ept; }
 
+int64_t brick_item_tab_words(int64_t n_chunks) { return n_chunks * 2 * kHashSlots; }
+
 hipError_t launch_block_image(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_xblk) {
     void *args[] = {&d_probs, &n_probs};
     return do_launch(L, reinterpret_cast<const void *>(&k_block_image), dim3((unsigned)((n_xblk + 3) / 4)),
@@ -1131,8 +1133,8 @@ hipError_t launch_reduce_tiles(const Launch &L, const Problem *d_probs, int n_pr
 }
 
 hipError_t launch_brick_items(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept,
-                              uint32_t *ctr, const uint32_t *end, uint32_t *pctr, int fill) {
-    void *args[] = {&d_probs, &n_probs, &ept, &ctr, &end, &pctr, &fill};
+                              uint32_t *ctr, const uint32_t *end, uint32_t *pctr, int fill, uint32_t *tabs) {
+    void *args[] = {&d_probs, &n_probs, &ept, &ctr, &end, &pctr, &fill, &tabs};
     return do_launch(L, reinterpret_cast<const void *>(&k_brick_items), dim3((unsigned)n_chunks),
                      dim3(kForwardBlock), 0, args);
 }
