@@ -23,7 +23,7 @@ constexpr int kMaxProblemBricks = 65536;
 // Bytes of one brick item's walk record (two float4 and one uint2).
 constexpr int kItemRecBytes = 40;
 constexpr int kForwardBlock = 256;
-constexpr int kBackBlock = 512;
+constexpr int kBackBlock = 1024;
 
 struct Problem {
     const void *events;   // stored events of this problem (plain: 2 x float4; packed: 1 x uint4)

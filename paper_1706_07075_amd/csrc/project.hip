@@ -844,8 +844,8 @@ __device__ __forceinline__ int hash_find(const uint32_t *keys, uint32_t key) {
 }
 
 // Walk one event's window through the brick grid of P and call
-// visit(global brick id, t_in, t_out) for every brick crossed over a
-// positive length [t_in, t_out].
+// visit(global brick id, bx, by, bz, t_in, t_out) for every brick crossed
+// over a positive length [t_in, t_out].
 // Brick faces are voxel planes, so this uses the voxel walk's crossing
 // formulas and cuts the window exactly where the brick pieces meet.
 template <class Visit>
@@ -863,22 +863,23 @@ __device__ __forceinline__ void brick_walk(const Problem &P, const Ray &r, Visit
     for (int step = 0; step < max_steps; ++step) {
         const float tmin = fminf(fminf(tnx, tny), tnz);
         const float tn = fminf(tmin, r.t1);
-        if (tn > t) visit((uint32_t)P.brick_base + (uint32_t)(bx + P.nbx * (by + P.nby * bz)), t, tn);
+        if (tn > t) visit((uint32_t)P.brick_base + (uint32_t)(bx + P.nbx * (by + P.nby * bz)), bx, by, bz, t, tn);
         if (tmin >= r.t1) break;
         t = fmaxf(tn, t);
-        if (tnx == tmin) {
-            bx += sx;
-            if ((unsigned)bx >= (unsigned)P.nbx) break;
-            tnx = cross((bx + px) * kBrickX, r.jx, r.ax, r.bx);
-        } else if (tny == tmin) {
-            by += sy;
-            if ((unsigned)by >= (unsigned)P.nby) break;
-            tny = cross((by + py) * kBrickY, r.jy, r.ay, r.by);
-        } else {
-            bz += sz;
-            if ((unsigned)bz >= (unsigned)P.nbz) break;
-            tnz = cross((bz + pz) * kBrickZ, r.jz, r.az, r.bz);
-        }
+        // one axis moves (x, then y, then z on ties); masked updates of
+        // values, not a branch per axis (which the compiler may turn into
+        // stores and loads through a selected address, off registers)
+        const bool mx = tnx == tmin;
+        const bool my = !mx && tny == tmin;
+        const bool mz = !mx && !my;
+        bx += mx ? sx : 0;
+        by += my ? sy : 0;
+        bz += mz ? sz : 0;
+        if ((unsigned)bx >= (unsigned)P.nbx || (unsigned)by >= (unsigned)P.nby || (unsigned)bz >= (unsigned)P.nbz)
+            break;
+        tnx = mx ? cross((bx + px) * kBrickX, r.jx, r.ax, r.bx) : tnx;
+        tny = my ? cross((by + py) * kBrickY, r.jy, r.ay, r.by) : tny;
+        tnz = mz ? cross((bz + pz) * kBrickZ, r.jz, r.az, r.bz) : tnz;
     }
 }
 
@@ -898,20 +899,19 @@ __device__ __forceinline__ void brick_walk(const Problem &P, const Ray &r, Visit
 // Walk record of a brick item at position pos: the crossing coefficients,
 // the piece [ta, tb] of the window inside the brick (as the brick walk cut
 // it) and the first voxel, as the back projection's walk starts from them.
-__device__ __forceinline__ void write_item_walk(const Problem &P, const Ray &r, uint32_t brick, float ta, float tb,
-                                                uint32_t pos) {
-    const uint32_t bl = brick - (uint32_t)P.brick_base;
-    const int bx = (int)(bl % (uint32_t)P.nbx), by = (int)((bl / (uint32_t)P.nbx) % (uint32_t)P.nby),
-              bz = (int)(bl / ((uint32_t)P.nbx * (uint32_t)P.nby));
+__device__ __forceinline__ void write_item_walk(const Problem &P, const Ray &r, int bx, int by, int bz, float ta,
+                                                float tb, uint32_t pos) {
     const Box B = brick_box(P, bx, by, bz);
     const int ix = min(max(voxel_at(ta, r.ux, r.jx, r.dx, P.ivx), B.x0), B.x0 + B.nx - 1);
     const int iy = min(max(voxel_at(ta, r.uy, r.jy, r.dy, P.ivy), B.y0), B.y0 + B.ny - 1);
     const int iz = min(max(voxel_at(ta, r.uz, r.jz, r.dz, P.ivz), B.z0), B.z0 + B.nz - 1);
     const int kx = ix + (r.ux > 0.0f) - r.jx, ky = iy + (r.uy > 0.0f) - r.jy, kz = iz + (r.uz > 0.0f) - r.jz;
     const uint32_t j = (uint32_t)((ix - B.x0) + kBrickX * ((iy - B.y0) + kBrickY * (iz - B.z0)));
+    // (register copies: element-wise reads of neighbouring Ray fields would
+    // otherwise be merged into vector loads that keep the ray off registers)
     f32x4 a, b;
-    a[0] = r.ax; a[1] = r.ay; a[2] = r.az; a[3] = ta;
-    b[0] = r.bx; b[1] = r.by; b[2] = r.bz; b[3] = tb;
+    a[0] = in_vgpr(r.ax); a[1] = in_vgpr(r.ay); a[2] = in_vgpr(r.az); a[3] = ta;
+    b[0] = in_vgpr(r.bx); b[1] = in_vgpr(r.by); b[2] = in_vgpr(r.bz); b[3] = tb;
     u32x2 k;
     k[0] = ((uint32_t)kx & 0xffffu) | ((uint32_t)ky << 16);
     k[1] = ((uint32_t)kz & 0xffffu) | (j << 16);
@@ -959,7 +959,7 @@ __device__ __forceinline__ void brick_items_pass(const Problem &P, int64_t base,
         const int64_t i = base + (int64_t)e * blockDim.x + threadIdx.x;
         Ray r;
         if (i >= P.n_events || !make_ray<PACKED>(P, i, r)) continue;
-        brick_walk(P, r, [&](uint32_t brick, float t0, float t1) {
+        brick_walk(P, r, [&](uint32_t brick, int bx, int by, int bz, float t0, float t1) {
             const uint32_t bl = brick - (uint32_t)P.brick_base;
             atomicOr(&bmap[bl >> 5], 1u << (bl & 31u));
             const uint32_t key = brick * kItemClasses + item_class(P, r, t0, t1);
@@ -976,7 +976,7 @@ __device__ __forceinline__ void brick_items_pass(const Problem &P, int64_t base,
             const uint32_t pos = h >= 0 ? hbase[h] + atomicAdd(&hcnt[h], 1u) : atomicAdd(ctr + key, 1u);
             if (pos < end[key]) {
                 items[pos] = (uint32_t)i;
-                write_item_walk(P, r, brick, t0, t1, pos);
+                write_item_walk(P, r, bx, by, bz, t0, t1, pos);
             }
         });
     }
