@@ -1,9 +1,24 @@
-"""Condense a rocprofv3 ``--stats --output-format csv`` kernel table into a
-short Markdown table (kernel, calls, average / total milliseconds, share).
+"""Condense rocprofv3 output into the short summaries kept with the code.
+
+Kernel table (kernel, calls, average / total milliseconds, share) from a
+``--kernel-trace --stats --output-format csv`` run:
 
     python -m paper_1706_07075_amd.profsum <run>_kernel_stats.csv
+
+HBM traffic of one kernel from ``--pmc FETCH_SIZE`` and ``--pmc WRITE_SIZE``
+runs (each its own run, counter values in KiB per dispatch) of a program
+that first copied ``copy_mib`` MiB device to device: each counter is scaled
+by the bytes that copy moved over what the counter read for it.
+
+    python -m paper_1706_07075_amd.profsum traffic KERNEL COPY_MIB SOURCE OUT.json \\
+        plain=<fetch_csv>,<write_csv> [packed=<fetch_csv>,<write_csv>]
+
+(the last 10 dispatches of KERNEL are averaged: one reconstruction's
+iterations, after any autotuner passes).
 """
 import csv
+import hashlib
+import json
 import re
 import sys
 
@@ -24,5 +39,55 @@ def table(path: str) -> str:
     return "\n".join(out)
 
 
+def counter_values(path: str, kernel: str):
+    """Per-dispatch values of the one counter in a counter_collection.csv:
+    (values of `kernel`'s dispatches, values of the device copies)."""
+    with open(path) as fh:
+        rows = list(csv.DictReader(fh))
+    mine, copies = [], []
+    for r in rows:
+        name = short_name(r["Kernel_Name"])
+        if name.split("<")[0] == kernel:
+            mine.append(float(r["Counter_Value"]))
+        elif "copyBuffer" in r["Kernel_Name"]:
+            copies.append(float(r["Counter_Value"]))
+    return mine, copies
+
+
+def traffic(kernel: str, copy_mib: int, source: str, storages: dict, last: int = 10) -> dict:
+    ref_kib = copy_mib * 1024.0
+    rec = {"kernel": kernel, "source_sha256": hashlib.sha256(open(source, "rb").read()).hexdigest(),
+           "copy_reference_mib": copy_mib,
+           "note": f"KiB per dispatch, averaged over the last {last} {kernel} launches of the run (one "
+                   "reconstruction's iterations); a scale is the bytes the device-to-device copy moved over "
+                   "what the counter read for it"}
+    scales = {}
+    for storage, (fetch_csv, write_csv) in storages.items():
+        out = {}
+        for what, path in (("fetch", fetch_csv), ("write", write_csv)):
+            vals, copies = counter_values(path, kernel)
+            vals = vals[-last:]
+            if not vals or not copies:
+                raise SystemExit(f"{path}: no {kernel} dispatch or no copy reference")
+            scales.setdefault(what, []).append(ref_kib / max(copies))
+            out[f"{what}_kib"] = sum(vals) / len(vals)
+            out[f"{what}_dispatches"] = len(vals)
+        rec[storage] = out
+    rec["fetch_scale"] = round(sum(scales["fetch"]) / len(scales["fetch"]), 4)
+    rec["write_scale"] = round(sum(scales["write"]) / len(scales["write"]), 4)
+    return rec
+
+
 if __name__ == "__main__":
-    print(table(sys.argv[1]))
+    if sys.argv[1] == "traffic":
+        kernel, copy_mib, source, out = sys.argv[2], int(sys.argv[3]), sys.argv[4], sys.argv[5]
+        storages = {}
+        for arg in sys.argv[6:]:
+            k, v = arg.split("=", 1)
+            storages[k] = tuple(v.split(","))
+        rec = traffic(kernel, copy_mib, source, storages)
+        with open(out, "w") as fh:
+            json.dump(rec, fh, indent=1)
+        print(json.dumps(rec, indent=1))
+    else:
+        print(table(sys.argv[1]))
