@@ -20,9 +20,10 @@
 //    is a voxel plane, so the crossing where one brick's piece ends is
 //    bitwise the one where the next begins and the weights telescope.
 //  * Phi comes from an LDS table (the paper keeps its TOF samples in a
-//    look-up table too): 1024 nodes over [-K, K] sigma, each holding the value
-//    and the first- and second-order Taylor coefficients, so one 16-byte LDS
-//    read and two FMAs give Phi to ~2e-9, with no divergent branch.
+//    look-up table too): 1025 nodes over [-K, K] sigma, each holding the
+//    value and the first- and second-order Taylor coefficients, so one LDS
+//    read and two FMAs give Phi to ~2e-9, with no divergent branch (the back
+//    projection keeps 8-byte nodes and derives the second-order term).
 //  * Forward + ratio is event-parallel: one lane per event, events bucketed
 //    at load so a wavefront traces near-parallel, co-located rays and its
 //    image gathers coalesce; the lane keeps f_i and writes r_i = 1 / f_i.
@@ -33,7 +34,9 @@
 //    stores; a small kernel adds a brick's chunk tiles into b.  There is no
 //    global atomic on the image (device-scope FP32 atomics sustain only
 //    ~21 G/s on this part, a third of a random gather's rate).  Chunks are
-//    launched largest first so the uneven work balances across CUs.
+//    launched largest first so the uneven work balances across CUs, and a
+//    brick's items are grouped by their step count so a wavefront's lanes
+//    finish together.
 #include "lmtof_internal.h"
 
 #include <hip/hip_fp16.h>
