@@ -804,13 +804,20 @@ __global__ void __launch_bounds__(256) k_reduce_tiles(const Problem *__restrict_
     const float inv = ldexpf(1.0f, -brick_exponent(P, br, wm));
     float *__restrict__ b = P.b;
     const unsigned long long *__restrict__ tiles = P.tiles;
-    for (int k = k0 + threadIdx.x; k < k0 + kBrickVox / 4; k += blockDim.x) {
-        unsigned long long acc = 0ull;
-        for (uint32_t sl = br.y; sl < br.z; ++sl) acc += tiles[(size_t)sl * kBrickVox + k];
+    // each thread sums kReduceVox voxels, their tiles' loads issued together
+    constexpr int kReduceVox = kBrickVox / 4 / 256;
+    unsigned long long acc[kReduceVox] = {};
+    for (uint32_t sl = br.y; sl < br.z; ++sl) {
+#pragma unroll
+        for (int q = 0; q < kReduceVox; ++q) acc[q] += tiles[(size_t)sl * kBrickVox + k0 + threadIdx.x + 256 * q];
+    }
+#pragma unroll
+    for (int q = 0; q < kReduceVox; ++q) {
+        const int k = k0 + (int)threadIdx.x + 256 * q;
         const int lx = k % kBrickX, ly = (k / kBrickX) % kBrickY, lz = k / (kBrickX * kBrickY);
         if (lx < B.nx && ly < B.ny && lz < B.nz)
             b[(B.x0 + lx) + (int64_t)P.nx * ((B.y0 + ly) + (int64_t)P.ny * (B.z0 + lz))] =
-                __ll2float_rn((long long)acc) * inv;
+                __ll2float_rn((long long)acc[q]) * inv;
     }
 }
 
