@@ -620,6 +620,8 @@ int ensure_problems(lmtof_ctx *c) {
     const int64_t nxb = assign_xblocks(ps, nullptr);
     int rc = reserve(c, &c->d_xb, c->xb_cap, (size_t)nxb * 64);
     if (rc) return rc;
+    // padding blocks of the blocked copies stay 0 (the relayout skips them)
+    HIPCHK(c, hipMemsetAsync(c->d_xb, 0, sizeof(float) * 64 * (size_t)nxb, c->stream));
     c->n_xblk = assign_xblocks(ps, c->d_xb);
     if ((rc = upload_problems(c, ps, block, ept, &c->d_probs, c->n_chunks, c->n_vchunks))) return rc;
     if ((rc = build_items(c, ps, c->d_probs, c->n_chunks, ept, c->items))) return rc;
@@ -1355,7 +1357,8 @@ int lmtof_forward_project(lmtof_ctx *c, const float *x, int64_t nx_, float *f, i
     if ((rc = dev_alloc(c, &xb, nxb * 64))) return done(rc);
     assign_xblocks(ps, xb);
     if ((rc = upload_problems(c, ps, block, ept, &dp, nch, nvch))) return done(rc);
-    hipError_t he = launch_block_image(L, dp, 1, nxb);
+    hipError_t he = hipMemsetAsync(xb, 0, sizeof(float) * 64 * (size_t)nxb, c->stream);
+    if (he == hipSuccess) he = launch_block_image(L, dp, 1, nxb);
     if (he == hipSuccess) he = launch_forward(L, c->g.tof_fwhm_ps > 0, dp, 1, nch, ept, 1, nullptr, nullptr, nullptr);
     if (he == hipSuccess) he = launch_scatter_by_perm(L, fs, c->d_perm, c->n_events, fc);
     if (he != hipSuccess) return done(fail(c, LMTOF_EHIP, "forward projection: %s", hipGetErrorString(he)));

@@ -1079,7 +1079,8 @@ __global__ void __launch_bounds__(kForwardBlock) k_count_pieces(const Problem *_
 }
 
 // xb <- x in 4^3 blocks: four blocks per 256-thread workgroup, one voxel
-// per thread (voxels past the grid edge and padding blocks are 0).
+// per thread (voxels past the grid edge are 0; padding blocks are left
+// alone: they are zeroed when the copy is laid out).
 __global__ void __launch_bounds__(256) k_block_image(const Problem *__restrict__ probs, int n_probs) {
     const int64_t blk = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     int p = n_probs - 1;
@@ -1089,6 +1090,7 @@ __global__ void __launch_bounds__(256) k_block_image(const Problem *__restrict__
     if (lb >= xblocks(P)) return;
     const int bx = (int)(lb & ((1 << P.xfx) - 1)), by = (int)((lb >> P.xfx) & ((1 << P.xfy) - 1)),
               bz = (int)(lb >> (P.xfx + P.xfy));
+    if (bx >= P.nbx4 || by >= P.nby4) return;
     const int v = threadIdx.x & 63;
     const int ix = 4 * bx + (v & 3), iy = 4 * by + ((v >> 2) & 3), iz = 4 * bz + (v >> 4);
     const float val = (ix < P.nx && iy < P.ny && iz < P.nz) ? P.x[ix + (int64_t)P.nx * (iy + (int64_t)P.ny * iz)] : 0.0f;
