@@ -106,33 +106,61 @@ __device__ __forceinline__ uint32_t event_key(const KeyGeom &g, const float p[7]
     return (brick * (uint32_t)(g.n_phi * g.n_lam) + dir) * (uint32_t)(g.nsx * g.nsy * g.nsz) + sub;
 }
 
+// Runs of equal keys among a wavefront's lanes (lane order): whether this
+// lane starts a run, the lane that starts its run and the run's length.
+// Every lane of the wavefront must be active; lanes without a key pass a
+// value no key takes, distinct per lane.  Events re-sorted from bucketed
+// order arrive in long runs of one key, whose same-address atomics would
+// serialise; one atomic per run takes their place.
+struct KeyRun {
+    bool head;
+    int start, len;
+};
+__device__ __forceinline__ KeyRun key_run(uint32_t key) {
+    const int lane = (int)(threadIdx.x & 63u);
+    const uint32_t prev = (uint32_t)__shfl_up((int)key, 1, 64);
+    KeyRun r;
+    r.head = lane == 0 || key != prev;
+    const unsigned long long heads = __ballot(r.head);
+    const unsigned long long below = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);  // lanes 0..lane
+    r.start = 63 - __clzll((long long)(heads & below));
+    const unsigned long long above = heads & ~below;
+    r.len = (above ? __ffsll((long long)above) - 1 : 64) - r.start;
+    return r;
+}
+
+// A value no key takes (keys stay below 2^26), distinct per lane.
+__device__ __forceinline__ uint32_t no_key() { return 0xffffff00u | (threadIdx.x & 63u); }
+
 __global__ void __launch_bounds__(kBlock) k_ingest_keys(const void *__restrict__ raw, int fmt, int64_t n, KeyGeom g,
                                                         int check_pack, uint32_t *__restrict__ keys,
                                                         uint32_t *__restrict__ hist, uint32_t *__restrict__ err) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    float p[7];
-    bool fin;
-    read_raw(raw, fmt, i, p, fin);
-    uint32_t e = 0;
-    if (!fin) e |= 1u;
-    if (p[0] == p[3] && p[1] == p[4] && p[2] == p[5]) e |= 2u;
-    if (check_pack && fmt == 0 && fin) {
+    uint32_t key = no_key();
+    if (i < n) {
+        float p[7];
+        bool fin;
+        read_raw(raw, fmt, i, p, fin);
+        uint32_t e = 0;
+        if (!fin) e |= 1u;
+        if (p[0] == p[3] && p[1] == p[4] && p[2] == p[5]) e |= 2u;
+        if (check_pack && fmt == 0 && fin) {
 #pragma unroll
-        for (int k = 0; k < 6; ++k)
-            if (fabsf(rintf(p[k] * 10.0f)) > 32767.0f) e |= 4u;
-        if (fabsf(p[6]) > 65504.0f) e |= 8u;
+            for (int k = 0; k < 6; ++k)
+                if (fabsf(rintf(p[k] * 10.0f)) > 32767.0f) e |= 4u;
+            if (fabsf(p[6]) > 65504.0f) e |= 8u;
+        }
+        if (e) {
+            atomicOr(err, e);
+            if (keys) keys[i] = 0;
+        } else if (keys) {
+            key = event_key(g, p);
+            keys[i] = key;
+        }
     }
-    if (e) {
-        atomicOr(err, e);
-        if (keys) keys[i] = 0;
-        return;
-    }
-    if (keys) {
-        const uint32_t k = event_key(g, p);
-        keys[i] = k;
-        atomicAdd(hist + k, 1u);
-    }
+    if (!keys) return;  // (uniform)
+    const KeyRun run = key_run(key);
+    if (run.head && key != no_key()) atomicAdd(hist + key, (uint32_t)run.len);
 }
 
 // ---- exclusive scan: per-block sums, scan of the sums, per-block scan with offset
@@ -218,8 +246,15 @@ __global__ void __launch_bounds__(kBlock) k_scatter(const void *__restrict__ raw
                                                     int store_packed, void *__restrict__ store,
                                                     int64_t *__restrict__ perm) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t pos = i;
+    if (cursor) {  // (uniform)
+        const uint32_t key = i < n ? keys[i] : no_key();
+        const KeyRun run = key_run(key);
+        uint32_t base = 0;
+        if (run.head && i < n) base = atomicAdd(cursor + key, (uint32_t)run.len);
+        pos = (int64_t)(uint32_t)__shfl((int)base, run.start, 64) + ((int)(threadIdx.x & 63u) - run.start);
+    }
     if (i >= n) return;
-    const int64_t pos = cursor ? (int64_t)atomicAdd(cursor + keys[i], 1u) : i;
     perm[pos] = i;
     if (fmt == 1 && store_packed) {
         reinterpret_cast<uint4 *>(store)[pos] = reinterpret_cast<const uint4 *>(raw)[i];
