@@ -250,6 +250,24 @@ def test_sparse_wholebody_brick_table_overflow(ept):
     assert eb < 2e-6 and ex < 1e-5
 
 
+def test_grid_beyond_brick_limit_is_refused():
+    """A problem may hold at most 65 536 bricks of 16^3 voxels (the brick
+    list builder keeps a bitmap of them per workgroup): a 1024 x 1024 x 288
+    grid (73 728 bricks) is refused with EUNSUPPORTED when the brick lists
+    are built, and the context stays usable."""
+    _say("case: grid beyond the brick limit")
+    g = dict(nx=1024, ny=1024, nz=288, vx=1.0, vy=1.0, vz=1.0, x0=-512.0, y0=-512.0, z0=-144.0,
+             scanner_radius=800.0, scanner_half_length=200.0, max_axial_angle_deg=0.0, tof_fwhm_ps=300.0,
+             tof_trunc_sigmas=3.0, c_mm_per_ps=0.299792458)
+    ev = synth.random_events_in_box(2000, seed=5, radius=800.0, half_length=200.0, tof_sigma_ps=60.0,
+                                    box=100.0).astype(np.float32)
+    with _recon(g, ev) as r:
+        with pytest.raises(L.LmtofError) as e:
+            r.back_project(np.ones(len(ev), np.float32))
+        assert e.value.code == L.LMTOF_EUNSUPPORTED and "bricks" in e.value.msg
+        assert L.lmtof_num_events(r.ctx) == len(ev)
+
+
 @pytest.mark.parametrize("n", [1, 2, 63, 65, 257, 4099])
 def test_ragged_event_counts(n):
     _say(f"case: ragged n={n}")
