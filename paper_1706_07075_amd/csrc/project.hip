@@ -280,12 +280,24 @@ struct Box {
     int sy, sz;      // strides of the reported index
 };
 
-// LDS tile of the back projection: a brick's voxels at x + kTileSy y +
-// kTileSz z (8-byte entries).  The odd strides put the neighbours of a
-// voxel along y and z in other LDS banks than the voxel itself, so lanes
-// walking side-by-side rays rarely collide on a bank.
-constexpr int kTileSy = kBrickX + 1, kTileSz = kTileSy * kBrickY + 1;
-constexpr int kTileSlots = (kBrickX - 1) + kTileSy * (kBrickY - 1) + kTileSz * (kBrickZ - 1) + 1;
+// LDS tile of the back projection: a brick's voxels at kTileBase + x +
+// kTileSy y + kTileSz z (8-byte entries), with a one-voxel margin on every
+// side: x = 16 and y = 16 fall in a row's and a plane's spare slots, and
+// the planes z = -1 and z = 16 and the offset kTileBase hold the rest.  A
+// walk can end one step past the brick on any axes (a crossing that
+// rounding puts just before the exit time: a piece of ~zero weight), and
+// such a piece lands in the margin, which is not copied out.
+//
+// An 8-byte entry spans two of the 32 four-byte LDS banks, so its bank
+// pair is the slot index mod 16.  Steps along x, y and z move the slot by
+// 1, 18 and 310, i.e. by 1, 2 and 6 bank pairs: the voxels that a
+// wavefront's side-by-side rays reach at one step (a patch across the rays'
+// direction) spread over the bank pairs.  With strides 17 and 289 (a step
+// along any axis moving one pair) the brick kernel ran 5 % slower.
+constexpr int kTileSy = kBrickX + 2, kTileSz = kTileSy * (kBrickY + 1) + 4;
+static_assert(kTileSy > kBrickX && kTileSz > kTileSy * kBrickY, "the tile needs its margin");
+constexpr int kTileBase = 1 + kTileSy + kTileSz;
+constexpr int kTileSlots = kTileBase + kBrickX + kTileSy * kBrickY + kTileSz * kBrickZ + 1;
 
 // Voxel-by-voxel traversal of a ray inside a box, without divergent
 // branches: each step advances the axis whose next plane is crossed first
@@ -334,7 +346,9 @@ struct Stepper {
         ty = fmaf(ky, r.ay, r.by);
         tz = fmaf(kz, r.az, r.bz);
         const int v = (int)(rk.y >> 16);  // brick-local voxel, x fastest
-        j = ((v & (kBrickX - 1)) + kTileSy * ((v / kBrickX) & (kBrickY - 1)) + kTileSz * (v / (kBrickX * kBrickY))) * unit;
+        j = (kTileBase + (v & (kBrickX - 1)) + kTileSy * ((v / kBrickX) & (kBrickY - 1)) +
+             kTileSz * (v / (kBrickX * kBrickY))) *
+            unit;
         djx = px ? unit : -unit;
         djy = (py ? kTileSy : -kTileSy) * unit;
         djz = (pz ? kTileSz : -kTileSz) * unit;
@@ -725,13 +739,10 @@ __device__ __forceinline__ void back_item(const f32x4 &ra, const f32x4 &rb, cons
     r.bz = rb[2];
     Stepper s(r, make_uint2(rk[0], rk[1]), (int)sizeof(unsigned long long));
     const float ta = ra[3], tb = rb[3];
-    // j is a byte offset into the tile; the clamp keeps a step that rounding
-    // carries past the brick's planes (a piece of ~zero weight) inside it
+    // j is a byte offset into the tile, inside its margin (see the tile)
     const double wsd = ws;
     walk_from<TOF>(s, r, ta, tb, cdf, [&](int j, float a) {
-        atomicAdd(reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(tile) +
-                                                         min((uint32_t)j, (uint32_t)(kTileSlots - 1) * 8u)),
-                  fixed_round(a, wsd));
+        atomicAdd(reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(tile) + j), fixed_round(a, wsd));
     });
 }
 
@@ -786,7 +797,8 @@ __global__ void __launch_bounds__(kBackBlock) k_back_chunks(const Problem *__res
     __syncthreads();
     const gptr<unsigned long long> dst = global(P.tiles) + (size_t)ch.w * kBrickVox;
     for (int k = threadIdx.x; k < kBrickVox; k += blockDim.x)
-        dst[k] = tile[(k & (kBrickX - 1)) + kTileSy * ((k / kBrickX) & (kBrickY - 1)) + kTileSz * (k / (kBrickX * kBrickY))];
+        dst[k] = tile[kTileBase + (k & (kBrickX - 1)) + kTileSy * ((k / kBrickX) & (kBrickY - 1)) +
+                      kTileSz * (k / (kBrickX * kBrickY))];
 }
 
 // 3. b over one brick = (exact sum of its chunk tiles) 2^-e.
