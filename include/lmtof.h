@@ -185,11 +185,13 @@ int lmtof_iterate(lmtof_ctx *ctx, int n_iter, lmtof_iter_stats *stats);
 /* Launch-shape autotuner (the batched launch of Section 2.5 made to fit the
  * device).  Times one projector pass (forward + ratio, brick back
  * projection) over the loaded events for each candidate events-per-thread
- * value {1, 2, 4, 8}, keeps the fastest as LMTOF_OPT_EVENTS_PER_THREAD and
- * rebuilds the brick lists for it.  The image is not changed; the back
- * projection accumulator is cleared afterwards.  *chosen (may be NULL)
- * receives the value, *ms (may be NULL, 4 floats) the pass time of each
- * candidate in that order.  Needs an image (ESTATE). */
+ * value {1, 2, 4, 8} (the fastest of three passes after a warm-up pass),
+ * keeps the fastest as LMTOF_OPT_EVENTS_PER_THREAD and rebuilds the brick
+ * lists for it; the default (4) stays unless another value beats it by more
+ * than 1 %.  The image is not changed; the back projection accumulator is
+ * cleared afterwards.  *chosen (may be NULL) receives the value, *ms (may be
+ * NULL, 4 floats) the pass time of each candidate in that order.  Needs an
+ * image (ESTATE). */
 int lmtof_autotune(lmtof_ctx *ctx, int64_t *chosen, float *ms);
 
 /* --------------------------------------------------- projector (testing) */

@@ -1432,8 +1432,7 @@ int lmtof_autotune(lmtof_ctx *c, int64_t *chosen, float *ms) {
     };
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return cleanup(fail(c, LMTOF_EHIP, "event creation failed"));
-    float best_ms = 0.0f;
-    int best = -1;
+    float t_cand[4] = {};
     for (int k = 0; k < 4; ++k) {
         c->opt_ept = cand[k];
         c->probs_dirty = true;
@@ -1449,20 +1448,32 @@ int lmtof_autotune(lmtof_ctx *c, int64_t *chosen, float *ms) {
         if (launch_block_image(L, c->d_probs, np, c->n_xblk) != hipSuccess)
             return cleanup(fail(c, LMTOF_EHIP, "autotune: image relayout failed"));
         float t = 0.0f;
-        for (int rep = 0; rep < 2; ++rep) {  // the first pass warms caches and code
+        // the first pass warms caches and code; the fastest of the next three counts
+        for (int rep = 0; rep < 4; ++rep) {
             hipError_t he = hipEventRecord(e0, c->stream);
             if (he == hipSuccess)
                 he = launch_forward(L, tof, c->d_probs, np, c->n_chunks, c->ept_used, 0, c->d_part_neff,
                                     c->d_part_ll, c->d_part_wmax);
             if (he != hipSuccess) return cleanup(fail(c, LMTOF_EHIP, "autotune: %s", hipGetErrorString(he)));
             if ((rc = add_back(c, L, c->d_probs, np, c->items, c->d_part_wmax, c->n_chunks, nullptr))) return cleanup(rc);
+            float tr = 0.0f;
             if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                hipEventElapsedTime(&t, e0, e1) != hipSuccess)
+                hipEventElapsedTime(&tr, e0, e1) != hipSuccess)
                 return cleanup(fail(c, LMTOF_EHIP, "autotune timing failed"));
+            if (rep == 1 || (rep > 1 && tr < t)) t = tr;
         }
+        t_cand[k] = t;
         if (ms) ms[k] = t;
-        if (best < 0 || t < best_ms) {
-            best_ms = t;
+    }
+    // The default shape stays unless another beats it by more than 1 %:
+    // closer passes are within the run-to-run spread of one timing.
+    int best = kDefaultEpt;
+    float best_ms = 0.0f;
+    for (int k = 0; k < 4; ++k)
+        if (cand[k] == kDefaultEpt) best_ms = t_cand[k];
+    for (int k = 0; k < 4; ++k) {
+        if (t_cand[k] < 0.99f * best_ms) {
+            best_ms = t_cand[k];
             best = cand[k];
         }
     }
