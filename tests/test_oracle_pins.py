@@ -325,3 +325,54 @@ def test_packed_codec_roundtrip_and_overflow():
     bad[0, 2] = 3300.0
     with pytest.raises(OverflowError):
         oracle.pack_events(bad)
+
+
+# ---- median sieve between iterations (Section 2.4)
+
+def _median_brute(a, x, y, z):
+    """The 14th smallest of the 27 neighbours of voxel (x, y, z), 0 outside."""
+    nz, ny, nx = a.shape
+    vals = []
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                i, j, k = x + dx, y + dy, z + dz
+                inside = 0 <= i < nx and 0 <= j < ny and 0 <= k < nz
+                vals.append(float(a[k, j, i]) if inside else 0.0)
+    return sorted(vals)[13]
+
+
+@pytest.mark.parametrize("shape", [(5, 4, 3), (1, 1, 1), (2, 1, 3), (6, 5, 4)])
+def test_median3_matches_bruteforce(shape):
+    nx, ny, nz = shape
+    a = np.random.default_rng(7).uniform(0.0, 1.0, (nz, ny, nx)).astype(np.float32)
+    a[a < 0.2] = 0.0  # ties with the zero border
+    got = oracle.median3(a.reshape(-1), nx, ny, nz).reshape(nz, ny, nx)
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                assert got[z, y, x] == _median_brute(a, x, y, z)
+
+
+def test_median3_constant_image_border_counts():
+    """Constant c on 5^3: inside and on faces (18 or 27 neighbours in the grid,
+    at most 9 zeros) the median is c; on edges (12 in the grid) and corners (8)
+    the 15 or 19 zeros win."""
+    c = 2.5
+    m = oracle.median3(np.full(125, c), 5, 5, 5).reshape(5, 5, 5)
+    for z in range(5):
+        for y in range(5):
+            for x in range(5):
+                on = sum(v in (0, 4) for v in (x, y, z))
+                assert m[z, y, x] == (c if on <= 1 else 0.0)
+
+
+def test_median3_removes_impulse_and_keeps_linear_ramp():
+    a = np.zeros((7, 7, 7))
+    a[3, 3, 3] = 100.0
+    assert not oracle.median3(a.reshape(-1), 7, 7, 7).any()
+    # a linear function is symmetric about each interior voxel: the median is the centre value
+    z, y, x = np.meshgrid(np.arange(7), np.arange(7), np.arange(7), indexing="ij")
+    r = (1.0 * x + 3.0 * y + 9.0 * z + 1.0)  # distinct values, odd symmetric neighbourhoods
+    m = oracle.median3(r.reshape(-1), 7, 7, 7).reshape(7, 7, 7)
+    assert np.array_equal(m[1:-1, 1:-1, 1:-1], r[1:-1, 1:-1, 1:-1])
