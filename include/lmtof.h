@@ -78,6 +78,14 @@ extern "C" {
 /* Approximate edge of the sort key's sub-cells inside a brick, in mm
  * (default 16: 4 x 4 x 4 sub-cells of a brick of 4 mm voxels). */
 #define LMTOF_OPT_SORT_CELL_MM 6
+/* Median sieve between iterations (Section 2.4): after each iteration's
+ * update, every image voxel is replaced by the median of its 3 x 3 x 3
+ * neighbourhood, voxels outside the image (the grid, or a region's
+ * sub-volume) counting as 0 (see lmtof_median_filter).  The iteration's
+ * statistics describe the EM step before the sieve, which breaks the EM
+ * normalisation sum_j s_j x_j = n_eff.  0/1, default 0.  Takes effect at the
+ * next lmtof_iterate. */
+#define LMTOF_OPT_MEDIAN_SIEVE 8
 
 /* ------------------------------------------------------------------ types */
 typedef struct lmtof_ctx lmtof_ctx;
@@ -199,6 +207,14 @@ int lmtof_autotune(lmtof_ctx *ctx, int64_t *chosen, float *ms);
  * every loaded event, f in the caller's event order (n_events floats).
  * x and f live in `mem`.  Needs events (ESTATE). */
 int lmtof_forward_project(lmtof_ctx *ctx, const float *x, int64_t nx_, float *f, int64_t nf, int mem);
+/* Median sieve of Section 2.4, applied once: y_j = median of x over the
+ * 3 x 3 x 3 block of voxels around j, voxels outside the grid counting as 0
+ * (the paper gives neither the neighbourhood nor the border rule: this is
+ * the reading used).  With 27 values the median is the 14th smallest, an
+ * element of x: exact.  x and y (nx*ny*nz floats each, x fastest, distinct
+ * arrays) live in `mem`.  Needs a geometry (ESTATE); EINVAL for wrong sizes
+ * or x == y. */
+int lmtof_median_filter(lmtof_ctx *ctx, const float *x, int64_t nx_, float *y, int64_t ny_, int mem);
 /* Back projection b_j = sum_i a_ij w_i of per-event weights w (caller's
  * order, n_events floats) into b (nx*ny*nz floats, overwritten). */
 int lmtof_back_project(lmtof_ctx *ctx, const float *w, int64_t nw, float *b, int64_t nb, int mem);

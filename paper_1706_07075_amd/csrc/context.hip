@@ -72,7 +72,7 @@ struct lmtof_ctx {
     std::string err;
 
     // options
-    int opt_storage = 0, opt_sort = 1, opt_nphi = 2048, opt_ept = 0;
+    int opt_storage = 0, opt_sort = 1, opt_nphi = 2048, opt_ept = 0, opt_median = 0;
     double opt_cell_mm = 16.0;
 
     bool has_geom = false;
@@ -708,6 +708,19 @@ int build_graph(lmtof_ctx *c, int n_iter, GraphEntry &ge) {
         HIPCHK(c, launch_finalize(L, c->d_probs, np, c->n_chunks, c->n_vchunks, c->d_part_neff, c->d_part_ll,
                                   c->d_part_old, c->d_part_new, c->d_stats, k));
         if (node) prev = node;
+        if (c->opt_median) {
+            // median sieve of each problem's image, through its (cleared) b
+            for (const auto &P : c->probs) {
+                L.deps = &prev;
+                node = nullptr;
+                HIPCHK(c, launch_median3(L, P.x, P.b, P.nx, P.ny, P.nz));
+                if (node) prev = node;
+                L.deps = &prev;
+                node = nullptr;
+                HIPCHK(c, launch_take_clear(L, P.x, P.b, (int64_t)P.nx * P.ny * P.nz));
+                if (node) prev = node;
+            }
+        }
         if ((rc = record(ge.ev[kEventsPerIter * k + 5]))) return rc;
     }
     HIPCHK(c, hipGraphInstantiate(&ge.exec, ge.graph, nullptr, nullptr, 0));
@@ -977,6 +990,19 @@ int lmtof_set_option(lmtof_ctx *c, int key, int64_t v) {
         if (v < 1 || v > 10000) return fail(c, LMTOF_EINVAL, "sort cell must be in [1, 10000] mm");
         c->opt_cell_mm = (double)v;
         return LMTOF_OK;
+    case LMTOF_OPT_MEDIAN_SIEVE:
+        if (v != 0 && v != 1) return fail(c, LMTOF_EINVAL, "median sieve must be 0 or 1");
+        if ((int)v != c->opt_median) {
+            // the iteration graphs change; the brick lists stay
+            for (auto &kv : c->graphs) {
+                if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+                if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+                for (hipEvent_t e : kv.second.ev) (void)hipEventDestroy(e);
+            }
+            c->graphs.clear();
+        }
+        c->opt_median = (int)v;
+        return LMTOF_OK;
     default:
         return fail(c, LMTOF_EINVAL, "unknown option %d", key);
     }
@@ -990,6 +1016,7 @@ int lmtof_get_option(const lmtof_ctx *c, int key, int64_t *v) {
     case LMTOF_OPT_SENS_NPHI: *v = c->opt_nphi; return LMTOF_OK;
     case LMTOF_OPT_EVENTS_PER_THREAD: *v = c->opt_ept > 0 ? c->opt_ept : kDefaultEpt; return LMTOF_OK;
     case LMTOF_OPT_SORT_CELL_MM: *v = (int64_t)c->opt_cell_mm; return LMTOF_OK;
+    case LMTOF_OPT_MEDIAN_SIEVE: *v = c->opt_median; return LMTOF_OK;
     default: return LMTOF_EINVAL;
     }
 }
@@ -1364,6 +1391,40 @@ int lmtof_forward_project(lmtof_ctx *c, const float *x, int64_t nx_, float *f, i
     if (he != hipSuccess) return done(fail(c, LMTOF_EHIP, "forward projection: %s", hipGetErrorString(he)));
     if (mem == LMTOF_MEM_HOST) rc = copy_out(c, f, fc, sizeof(float) * c->n_events, LMTOF_MEM_HOST);
     else if (hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(c, LMTOF_EHIP, "forward projection failed");
+    return done(rc);
+}
+
+int lmtof_median_filter(lmtof_ctx *c, const float *x, int64_t nx_, float *y, int64_t ny_, int mem) {
+    if (!c) return LMTOF_EINVAL;
+    c->err.clear();
+    if (!c->has_geom) return fail(c, LMTOF_ESTATE, "set the geometry first");
+    if (!x || !y || nx_ != c->V || ny_ != c->V || !valid_mem(mem))
+        return fail(c, LMTOF_EINVAL, "need x and y of %lld floats", (long long)c->V);
+    if (x == y) return fail(c, LMTOF_EINVAL, "x and y must not be the same array");
+    HIPCHK(c, hipSetDevice(c->device));
+    Launch L;
+    L.stream = c->stream;
+    float *dx = nullptr, *dy = nullptr;
+    int rc = LMTOF_OK;
+    auto done = [&](int r) {
+        (void)hipStreamSynchronize(c->stream);
+        if (mem == LMTOF_MEM_HOST) {
+            dev_free(dx);
+            dev_free(dy);
+        }
+        return r;
+    };
+    if (mem == LMTOF_MEM_HOST) {
+        if ((rc = dev_alloc(c, &dx, c->V)) || (rc = dev_alloc(c, &dy, c->V))) return done(rc);
+        if ((rc = copy_in(c, dx, x, sizeof(float) * c->V, LMTOF_MEM_HOST))) return done(rc);
+    } else {
+        dx = const_cast<float *>(x);
+        dy = y;
+    }
+    const hipError_t he = launch_median3(L, dx, dy, c->g.nx, c->g.ny, c->g.nz);
+    if (he != hipSuccess) return done(fail(c, LMTOF_EHIP, "median filter: %s", hipGetErrorString(he)));
+    if (mem == LMTOF_MEM_HOST) rc = copy_out(c, y, dy, sizeof(float) * c->V, LMTOF_MEM_HOST);
+    else if (hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(c, LMTOF_EHIP, "median filter failed");
     return done(rc);
 }
 

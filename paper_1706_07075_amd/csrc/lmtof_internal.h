@@ -145,6 +145,12 @@ int64_t brick_item_tab_words(int64_t n_chunks);
 hipError_t launch_count_pieces(const Launch &L, bool tof, const Problem *d_probs, int n_probs, int64_t n_chunks,
                                int ept, unsigned long long *part);
 
+// ---- median sieve (median.hip)
+// y = 3x3x3 median of x (nx * ny * nz voxels, x fastest), 0 outside the grid; y != x.
+hipError_t launch_median3(const Launch &L, const float *x, float *y, int nx, int ny, int nz);
+// x <- t, t <- 0 over n voxels.
+hipError_t launch_take_clear(const Launch &L, float *x, float *t, int64_t n);
+
 // xb <- x in 4^3 blocks for every problem (n_xblk blocks in total).
 hipError_t launch_block_image(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_xblk);
 

@@ -35,6 +35,7 @@ LMTOF_OPT_SORT = 2
 LMTOF_OPT_SENS_NPHI = 3
 LMTOF_OPT_EVENTS_PER_THREAD = 5
 LMTOF_OPT_SORT_CELL_MM = 6
+LMTOF_OPT_MEDIAN_SIEVE = 8
 
 ERROR_NAMES = {0: "OK", -1: "EINVAL", -2: "ESTATE", -3: "ENOMEM", -4: "EHIP", -5: "EUNSUPPORTED", -6: "EAGAIN"}
 
@@ -103,6 +104,7 @@ _sig = {
     "lmtof_iterate": ([_P, C.c_int, C.POINTER(lmtof_iter_stats)], C.c_int),
     "lmtof_forward_project": ([_P, _P, _i64, _P, _i64, C.c_int], C.c_int),
     "lmtof_back_project": ([_P, _P, _i64, _P, _i64, C.c_int], C.c_int),
+    "lmtof_median_filter": ([_P, _P, _i64, _P, _i64, C.c_int], C.c_int),
     "lmtof_count_segments": ([_P, C.POINTER(_i64), C.POINTER(_i64)], C.c_int),
     "lmtof_autotune": ([_P, C.POINTER(_i64), C.POINTER(C.c_float)], C.c_int),
     "lmtof_set_regions": ([_P, C.POINTER(C.c_int32), C.c_int, C.c_int], C.c_int),
@@ -299,6 +301,18 @@ def lmtof_back_project(ctx, w, n_voxels: int, out=None):
     return o
 
 
+def lmtof_median_filter(ctx, x, n_voxels: int, out=None):
+    p, mem, keep = _in(x, np.float32)
+    if mem == LMTOF_MEM_DEVICE and out is None:
+        import torch
+        out = torch.empty(n_voxels, dtype=torch.float32, device=x.device)
+    o, po, memo = _out(out, n_voxels, np.float32)
+    if memo != mem:
+        raise ValueError("x and y must both be host or both be device arrays")
+    _check(_lib.lmtof_median_filter(ctx, p, int(np.prod(x.shape)), po, n_voxels, mem), ctx)
+    return o
+
+
 def lmtof_count_segments(ctx):
     """(pieces visited, pieces with non-zero weight) over all loaded events."""
     a, b = C.c_int64(), C.c_int64()
@@ -481,6 +495,9 @@ class Reconstruction:
 
     def back_project(self, w, out=None):
         return lmtof_back_project(self.ctx, w, self.V, out)
+
+    def median_filter(self, x, out=None):
+        return lmtof_median_filter(self.ctx, x, self.V, out)
 
     def count_segments(self):
         return lmtof_count_segments(self.ctx)
