@@ -237,6 +237,63 @@ def median3(x, nx: int, ny: int, nz: int) -> np.ndarray:
     return np.sort(block, axis=0)[13].reshape(-1)
 
 
+TOF_REJECT_Z = 1.959964  # two-sided 95 % quantile of the normal distribution
+
+
+def tof_keep(g: dict, ev, mask, z: float = TOF_REJECT_Z, grow: float = 0.0, min_piece: float = 0.0) -> np.ndarray:
+    """TOF scatter rejection (Section 2.2, Fig. 2): an event is kept when the
+    stretch of its LOR within z sigma of the TOF centre (z = 1.96: the 95 %
+    confidence interval of the annihilation point) passes through the body
+    outline, given as a voxel mask on the reconstruction grid (non-zero =
+    body; x fastest).  The stretch is cut by the grid box and walked voxel by
+    voxel (sorted plane crossings); the event is kept if a piece longer than
+    min_piece lies in a body voxel.  grow widens the stretch by grow mm at
+    both ends (negative: narrows it), which the tests use to bracket events
+    whose decision turns on rounding.  FP64; one event at a time."""
+    e = _ev64(ev)
+    m = np.asarray(mask).reshape(-1) != 0
+    nx, ny, nz = int(g["nx"]), int(g["ny"]), int(g["nz"])
+    v = np.array([g["vx"], g["vy"], g["vz"]], float)
+    o = np.array([g["x0"], g["y0"], g["z0"]], float)
+    n = np.array([nx, ny, nz])
+    c = float(g.get("c_mm_per_ps", 0.0) or 0.299792458)
+    half = z * sigma_mm(float(g["tof_fwhm_ps"]), c) + grow
+    keep = np.zeros(len(e), bool)
+    for i in range(len(e)):
+        p1, p2, dt = e[i, :3], e[i, 3:6], e[i, 6]
+        d = p2 - p1
+        u = d / np.sqrt(d @ d)
+        mu = 0.5 * (p1 + p2) + (c * dt / 2.0) * u
+        t0, t1 = -half, half
+        for k in range(3):  # cut by the grid box (slab method)
+            lo, hi = o[k], o[k] + n[k] * v[k]
+            if u[k] == 0.0:
+                if not lo <= mu[k] < hi:
+                    t0, t1 = 1.0, 0.0
+                continue
+            a, b = (lo - mu[k]) / u[k], (hi - mu[k]) / u[k]
+            t0, t1 = max(t0, min(a, b)), min(t1, max(a, b))
+        if not t0 < t1:
+            continue
+        ts = [t0, t1]
+        for k in range(3):
+            if u[k] == 0.0:
+                continue
+            planes = o[k] + v[k] * np.arange(n[k] + 1)
+            tk = (planes - mu[k]) / u[k]
+            ts.extend(tk[(tk > t0) & (tk < t1)])
+        ts = np.sort(np.array(ts))
+        for a, b in zip(ts[:-1], ts[1:]):
+            if b - a <= min_piece:
+                continue
+            pt = mu + 0.5 * (a + b) * u
+            idx = np.clip(np.floor((pt - o) / v).astype(int), 0, n - 1)
+            if m[(idx[2] * ny + idx[1]) * nx + idx[0]]:
+                keep[i] = True
+                break
+    return keep
+
+
 def rel_l2(a, ref) -> float:
     a = np.asarray(a, np.float64).ravel()
     r = np.asarray(ref, np.float64).ravel()

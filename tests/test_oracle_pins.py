@@ -376,3 +376,74 @@ def test_median3_removes_impulse_and_keeps_linear_ramp():
     r = (1.0 * x + 3.0 * y + 9.0 * z + 1.0)  # distinct values, odd symmetric neighbourhoods
     m = oracle.median3(r.reshape(-1), 7, 7, 7).reshape(7, 7, 7)
     assert np.array_equal(m[1:-1, 1:-1, 1:-1], r[1:-1, 1:-1, 1:-1])
+
+
+# ---- TOF scatter rejection (Section 2.2)
+
+def _box_geom(n=20, v=4.0, fwhm=300.0):
+    return dict(nx=n, ny=n, nz=n, vx=v, vy=v, vz=v, x0=-n * v / 2, y0=-n * v / 2, z0=-n * v / 2,
+                scanner_radius=400.0, scanner_half_length=400.0, max_axial_angle_deg=0.0, tof_fwhm_ps=fwhm,
+                tof_trunc_sigmas=3.0, c_mm_per_ps=0.299792458)
+
+
+def test_tof_keep_axis_ray_threshold_closed_form():
+    """A body of one 4 mm voxel at the grid centre, an x-axis LOR through it,
+    the TOF centre d mm before the voxel's near face: kept iff d < 1.96 sigma
+    (sigma = 19.11 mm at 300 ps: the paper's value)."""
+    g = _box_geom()
+    mask = np.zeros(20 ** 3, np.uint8)
+    mask[(10 * 20 + 10) * 20 + 10] = 1  # voxel [0, 4) mm on every axis
+    sig = oracle.sigma_mm(300.0)
+    c = 0.299792458
+    evs = []
+    for d in (1.959964 * sig - 0.5, 1.959964 * sig + 0.5):
+        xc = 0.0 - d  # centre on the x axis, d before the face x = 0
+        # mu = mid + (c dt / 2) u with u = +x, mid = 0: dt = 2 xc / c
+        evs.append([-400.0, 2.0, 2.0, 400.0, 2.0, 2.0, 2.0 * xc / c])
+    keep = oracle.tof_keep(g, np.array(evs), mask)
+    assert keep.tolist() == [True, False]
+
+
+def test_tof_keep_full_and_empty_masks():
+    g = _box_geom()
+    c = 0.299792458
+    sig = oracle.sigma_mm(300.0)
+    # centres on the x axis at 0 (inside), 40 + 1.9 sigma (interval reaches the box), 40 + 2.1 sigma (misses)
+    xs = [0.0, 40.0 + 1.9 * sig, 40.0 + 2.1 * sig]
+    evs = np.array([[-400.0, 1.0, 1.0, 400.0, 1.0, 1.0, 2.0 * x / c] for x in xs])
+    assert oracle.tof_keep(g, evs, np.ones(20 ** 3)).tolist() == [True, True, False]
+    assert not oracle.tof_keep(g, evs, np.zeros(20 ** 3)).any()
+
+
+def test_tof_keep_matches_dense_sampling():
+    """Against a dense point sampler (0.01 mm steps along the stretch, a
+    different method from the crossing walk) on random LORs and a random
+    blob mask; events whose masked stretch is shorter than 0.05 mm, or that
+    change with the stretch end moved by 0.05 mm, may go either way."""
+    g = _box_geom(n=12)
+    rng = np.random.default_rng(21)
+    mask = (rng.uniform(size=12 ** 3) < 0.08).astype(np.uint8)
+    n = 300
+    a = rng.normal(size=(n, 3))
+    a /= np.linalg.norm(a, axis=1)[:, None]
+    p0 = rng.uniform(-24, 24, size=(n, 3))
+    evs = np.concatenate([p0 - 300 * a, p0 + 300 * a, rng.normal(0, 150, (n, 1))], axis=1)
+    keep = oracle.tof_keep(g, evs, mask)
+    strict = oracle.tof_keep(g, evs, mask, grow=-0.05, min_piece=0.05)
+    loose = oracle.tof_keep(g, evs, mask, grow=0.05)
+    sig = oracle.sigma_mm(300.0)
+    half = oracle.TOF_REJECT_Z * sig
+    c = 0.299792458
+    m = mask.reshape(12, 12, 12)
+    for i in range(n):
+        d = evs[i, 3:6] - evs[i, :3]
+        u = d / np.linalg.norm(d)
+        mu = 0.5 * (evs[i, :3] + evs[i, 3:6]) + c * evs[i, 6] / 2 * u
+        ts = np.arange(-half, half, 0.01)
+        pts = mu + ts[:, None] * u
+        idx = np.floor((pts + 24.0) / 4.0).astype(int)
+        ok = np.all((idx >= 0) & (idx < 12), axis=1)
+        hit = bool(m[idx[ok, 2], idx[ok, 1], idx[ok, 0]].any()) if ok.any() else False
+        assert strict[i] <= hit <= loose[i], i
+        assert strict[i] <= keep[i] <= loose[i], i
+    assert 20 < keep.sum() < n - 20  # both outcomes occur
