@@ -215,6 +215,17 @@ int lmtof_forward_project(lmtof_ctx *ctx, const float *x, int64_t nx_, float *f,
  * arrays) live in `mem`.  Needs a geometry (ESTATE); EINVAL for wrong sizes
  * or x == y. */
 int lmtof_median_filter(lmtof_ctx *ctx, const float *x, int64_t nx_, float *y, int64_t ny_, int mem);
+
+/* TOF scatter rejection of Section 2.2 (a pre-pass: filter the events, then
+ * load the kept ones).  For every loaded event, keep[k] (k the event's index
+ * in the caller's order of the last load) = 1 if the stretch of its LOR
+ * within 1.959964 sigma of its TOF centre (the two-sided 95 % interval of
+ * the annihilation point), cut by the grid box, passes a piece of positive
+ * length through a body voxel, else 0.  The body outline is mask: one byte
+ * per voxel of the grid (x fastest, non-zero = body), e.g. from a CT.  mask
+ * (nx*ny*nz bytes) and keep (n_events bytes) live in `mem`.  Needs loaded
+ * events (ESTATE) and TOF (EUNSUPPORTED otherwise). */
+int lmtof_tof_keep(lmtof_ctx *ctx, const uint8_t *mask, int64_t n_mask, uint8_t *keep, int64_t n_keep, int mem);
 /* Back projection b_j = sum_i a_ij w_i of per-event weights w (caller's
  * order, n_events floats) into b (nx*ny*nz floats, overwritten). */
 int lmtof_back_project(lmtof_ctx *ctx, const float *w, int64_t nw, float *b, int64_t nb, int mem);

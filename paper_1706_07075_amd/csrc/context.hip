@@ -22,6 +22,7 @@ namespace {
 
 constexpr double kDefaultC = 0.299792458;
 constexpr int kDefaultEpt = 4;
+constexpr double kTofRejectZ = 1.959964;  // two-sided 95 % quantile of the normal distribution
 // Event records per graph-replayed iteration: start, after forward, after
 // brick scales, after brick back projection, after tile reduction, end.
 constexpr int kEventsPerIter = 6;
@@ -1425,6 +1426,53 @@ int lmtof_median_filter(lmtof_ctx *c, const float *x, int64_t nx_, float *y, int
     if (he != hipSuccess) return done(fail(c, LMTOF_EHIP, "median filter: %s", hipGetErrorString(he)));
     if (mem == LMTOF_MEM_HOST) rc = copy_out(c, y, dy, sizeof(float) * c->V, LMTOF_MEM_HOST);
     else if (hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(c, LMTOF_EHIP, "median filter failed");
+    return done(rc);
+}
+
+int lmtof_tof_keep(lmtof_ctx *c, const uint8_t *mask, int64_t nmask, uint8_t *keep, int64_t nkeep, int mem) {
+    if (!c) return LMTOF_EINVAL;
+    c->err.clear();
+    if (!c->n_events) return fail(c, LMTOF_ESTATE, "load events first");
+    if (!(c->g.tof_fwhm_ps > 0)) return fail(c, LMTOF_EUNSUPPORTED, "TOF scatter rejection needs TOF events");
+    if (!mask || !keep || nmask != c->V || nkeep != c->n_events || !valid_mem(mem))
+        return fail(c, LMTOF_EINVAL, "need a mask of %lld bytes and keep of %lld bytes", (long long)c->V,
+                    (long long)c->n_events);
+    HIPCHK(c, hipSetDevice(c->device));
+    Launch L;
+    L.stream = c->stream;
+    uint8_t *dm = nullptr, *dk = nullptr;
+    Problem *dp = nullptr;
+    int rc = LMTOF_OK;
+    auto done = [&](int r) {
+        (void)hipStreamSynchronize(c->stream);
+        if (mem == LMTOF_MEM_HOST) {
+            dev_free(dm);
+            dev_free(dk);
+        }
+        dev_free(dp);
+        return r;
+    };
+    if (mem == LMTOF_MEM_HOST) {
+        if ((rc = dev_alloc(c, &dm, c->V)) || (rc = dev_alloc(c, &dk, c->n_events))) return done(rc);
+        if ((rc = copy_in(c, dm, mask, (size_t)c->V, LMTOF_MEM_HOST))) return done(rc);
+    } else {
+        dm = const_cast<uint8_t *>(mask);
+        dk = keep;
+    }
+    // two-sided 95 % interval of the annihilation point along the LOR
+    const double half = kTofRejectZ * sigma_mm(c->g);
+    std::vector<Problem> ps{make_problem(c, 0, c->g.nz, nullptr, nullptr, nullptr)};
+    ps[0].events = c->d_events;
+    ps[0].n_events = c->n_events;
+    ps[0].k_sigma = std::max(ps[0].k_sigma, (float)half * 1.001f);
+    int block, ept;
+    launch_shape(c, block, ept);
+    int64_t nch, nvch;
+    if ((rc = upload_problems(c, ps, block, ept, &dp, nch, nvch))) return done(rc);
+    const hipError_t he = launch_tof_keep(L, dp, c->stored_packed != 0, c->n_events, (float)half, dm, c->d_perm, dk);
+    if (he != hipSuccess) return done(fail(c, LMTOF_EHIP, "TOF scatter rejection: %s", hipGetErrorString(he)));
+    if (mem == LMTOF_MEM_HOST) rc = copy_out(c, keep, dk, (size_t)c->n_events, LMTOF_MEM_HOST);
+    else if (hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(c, LMTOF_EHIP, "TOF scatter rejection failed");
     return done(rc);
 }
 

@@ -145,6 +145,12 @@ int64_t brick_item_tab_words(int64_t n_chunks);
 hipError_t launch_count_pieces(const Launch &L, bool tof, const Problem *d_probs, int n_probs, int64_t n_chunks,
                                int ept, unsigned long long *part);
 
+// TOF scatter rejection of the one problem at d_probs (n_events stored
+// events): keep[perm[i]] = 1 if event i's LOR within half_width mm of its TOF
+// centre passes through a voxel with mask != 0 (P.k_sigma >= half_width).
+hipError_t launch_tof_keep(const Launch &L, const Problem *d_probs, bool packed, int64_t n_events, float half_width,
+                          const uint8_t *mask, const int64_t *perm, uint8_t *keep);
+
 // ---- median sieve (median.hip)
 // y = 3x3x3 median of x (nx * ny * nz voxels, x fastest), 0 outside the grid; y != x.
 hipError_t launch_median3(const Launch &L, const float *x, float *y, int nx, int ny, int nz);

@@ -1109,6 +1109,42 @@ __global__ void __launch_bounds__(256) k_block_image(const Problem *__restrict__
     global(P.xb)[lb * 64 + v] = val;
 }
 
+// TOF scatter rejection (Section 2.2): keep[perm[i]] = 1 if the stretch of
+// stored event i's LOR within half_width mm of its TOF centre (cut by the
+// grid box) has a piece of positive length in a voxel whose mask byte is
+// non-zero, else 0.  One problem: the whole grid (its k_sigma at least
+// half_width).
+template <bool PACKED>
+__global__ void __launch_bounds__(256) k_tof_keep(const Problem *__restrict__ probs, float half_width,
+                                                  const uint8_t *__restrict__ mask,
+                                                  const int64_t *__restrict__ perm, uint8_t *__restrict__ keep) {
+    const Problem &P = probs[0];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P.n_events) return;
+    uint32_t k = 0;
+    Ray r;
+    if (make_ray<PACKED>(P, i, r)) {
+        const float ta = fmaxf(r.t0, -half_width), tb = fminf(r.t1, half_width);
+        if (ta < tb) {
+            // the voxel walk of the projectors, stopping at the first body piece
+            Stepper s(P, r, ta, grid_box(P));
+            float t = ta;
+            for (int step = 0; step < s.max_steps; ++step) {
+                const float tmin = s.next();
+                const float tn = __builtin_amdgcn_fmed3f(tmin, t, tb);
+                if (tn > t && mask[s.j]) {
+                    k = 1;
+                    break;
+                }
+                t = tn;
+                if (tmin >= tb) break;
+                s.advance(r, tmin);
+            }
+        }
+    }
+    keep[perm[i]] = (uint8_t)k;
+}
+
 }  // namespace
 
 int64_t project_chunk_events(int block, int ept) { return (int64_t)block * ept; }
@@ -1169,6 +1205,14 @@ hipError_t launch_count_pieces(const Launch &L, bool tof, const Problem *d_probs
     const void *fn = tof ? reinterpret_cast<const void *>(&k_count_pieces<true>)
                          : reinterpret_cast<const void *>(&k_count_pieces<false>);
     return do_launch(L, fn, dim3((unsigned)n_chunks), dim3(kForwardBlock), 0, args);
+}
+
+hipError_t launch_tof_keep(const Launch &L, const Problem *d_probs, bool packed, int64_t n_events, float half_width,
+                          const uint8_t *mask, const int64_t *perm, uint8_t *keep) {
+    void *args[] = {&d_probs, &half_width, &mask, &perm, &keep};
+    const void *fn = packed ? reinterpret_cast<const void *>(&k_tof_keep<true>)
+                            : reinterpret_cast<const void *>(&k_tof_keep<false>);
+    return do_launch(L, fn, dim3((unsigned)((n_events + 255) / 256)), dim3(256), 0, args);
 }
 
 }  // namespace lmtof

@@ -105,6 +105,7 @@ _sig = {
     "lmtof_forward_project": ([_P, _P, _i64, _P, _i64, C.c_int], C.c_int),
     "lmtof_back_project": ([_P, _P, _i64, _P, _i64, C.c_int], C.c_int),
     "lmtof_median_filter": ([_P, _P, _i64, _P, _i64, C.c_int], C.c_int),
+    "lmtof_tof_keep": ([_P, _P, _i64, _P, _i64, C.c_int], C.c_int),
     "lmtof_count_segments": ([_P, C.POINTER(_i64), C.POINTER(_i64)], C.c_int),
     "lmtof_autotune": ([_P, C.POINTER(_i64), C.POINTER(C.c_float)], C.c_int),
     "lmtof_set_regions": ([_P, C.POINTER(C.c_int32), C.c_int, C.c_int], C.c_int),
@@ -313,6 +314,19 @@ def lmtof_median_filter(ctx, x, n_voxels: int, out=None):
     return o
 
 
+def lmtof_tof_keep(ctx, mask, n_events: int, out=None):
+    """uint8 keep flag per loaded event (caller order) of the TOF scatter rejection."""
+    p, mem, keep_alive = _in(mask, np.uint8)
+    if mem == LMTOF_MEM_DEVICE and out is None:
+        import torch
+        out = torch.empty(n_events, dtype=torch.uint8, device=mask.device)
+    o, po, memo = _out(out, n_events, np.uint8)
+    if memo != mem:
+        raise ValueError("mask and keep must both be host or both be device arrays")
+    _check(_lib.lmtof_tof_keep(ctx, p, int(np.prod(mask.shape)), po, n_events, mem), ctx)
+    return o
+
+
 def lmtof_count_segments(ctx):
     """(pieces visited, pieces with non-zero weight) over all loaded events."""
     a, b = C.c_int64(), C.c_int64()
@@ -498,6 +512,9 @@ class Reconstruction:
 
     def median_filter(self, x, out=None):
         return lmtof_median_filter(self.ctx, x, self.V, out)
+
+    def tof_keep(self, mask, out=None):
+        return lmtof_tof_keep(self.ctx, mask, lmtof_num_events(self.ctx), out)
 
     def count_segments(self):
         return lmtof_count_segments(self.ctx)
