@@ -64,6 +64,8 @@ def main():
     ap.add_argument("--regions", action="store_true",
                     help="TOF-assisted 9-region division of the same events (one batched launch per kernel)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
+    ap.add_argument("--tof-reject", action="store_true",
+                    help="also time the TOF scatter rejection pre-pass (3 calls) against the phantom's body outline")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device (a reference for HBM byte counters)")
     args = ap.parse_args()
@@ -210,6 +212,24 @@ def main():
                                "bytes_per_event_iteration": bytes_iter / N,
                                "hbm_roofline_event_iterations_per_s": HBM_PEAK_GBS * 1e9 / (bytes_iter / N)},
     }
+    if args.tof_reject:
+        gx = g["x0"] + g["vx"] * (np.arange(g["nx"]) + 0.5)
+        gy = g["y0"] + g["vy"] * (np.arange(g["ny"]) + 0.5)
+        gz = g["z0"] + g["vz"] * (np.arange(g["nz"]) + 0.5)
+        zz, yy, xx = np.meshgrid(gz, gy, gx, indexing="ij")
+        pts = np.stack([xx.ravel(), yy.ravel(), zz.ravel()], axis=1)
+        mask = torch.from_numpy((synth.phantom_eval(synth.wholebody_phantom(), pts) > 0).astype(np.uint8)).to(dev)
+        del zz, yy, xx, pts
+        rej_ms = []
+        for k in range(3):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            keep = r.tof_keep(mask)
+            torch.cuda.synchronize()
+            rej_ms.append((time.perf_counter() - a) * 1e3)
+        out["tof_reject"] = {"ms": rej_ms, "kept": int(keep.sum()), "events": N,
+                             "body_voxels": int(mask.sum())}
+        log(f"tof reject: {out['tof_reject']}")
     r.close()
     del ev_dev
     torch.cuda.empty_cache()
