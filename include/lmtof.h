@@ -194,9 +194,10 @@ int lmtof_iterate(lmtof_ctx *ctx, int n_iter, lmtof_iter_stats *stats);
  * device).  Times one projector pass (forward + ratio, brick back
  * projection) over the loaded events for each candidate events-per-thread
  * value {1, 2, 4, 8} (the fastest of three passes after a warm-up pass),
- * keeps the fastest as LMTOF_OPT_EVENTS_PER_THREAD and rebuilds the brick
- * lists for it; the default (4) stays unless another value beats it by more
- * than 1 %.  The image is not changed; the back projection accumulator is
+ * adds a tenth of the time its brick lists took to build (they are built
+ * once per reconstruction of ~10 iterations), keeps the lowest total as
+ * LMTOF_OPT_EVENTS_PER_THREAD and rebuilds the brick lists for it; the
+ * default (4) stays unless another value beats it by more than 1 %.  The image is not changed; the back projection accumulator is
  * cleared afterwards.  *chosen (may be NULL) receives the value, *ms (may be
  * NULL, 4 floats) the pass time of each candidate in that order.  Needs an
  * image (ESTATE). */

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <chrono>
 #include <map>
 #include <new>
 #include <string>
@@ -22,6 +23,7 @@ namespace {
 
 constexpr double kDefaultC = 0.299792458;
 constexpr int kDefaultEpt = 4;
+constexpr float kAutotuneIters = 10.0f;  // iterations a reconstruction is assumed to run
 constexpr double kTofRejectZ = 1.959964;  // two-sided 95 % quantile of the normal distribution
 // Event records per graph-replayed iteration: start, after forward, after
 // brick scales, after brick back projection, after tile reduction, end.
@@ -1541,11 +1543,15 @@ int lmtof_autotune(lmtof_ctx *c, int64_t *chosen, float *ms) {
     };
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return cleanup(fail(c, LMTOF_EHIP, "event creation failed"));
-    float t_cand[4] = {};
+    float t_cand[4] = {}, score[4] = {};
     for (int k = 0; k < 4; ++k) {
         c->opt_ept = cand[k];
         c->probs_dirty = true;
+        const auto b0 = std::chrono::steady_clock::now();
         int rc = ensure_problems(c);
+        if (!rc && hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(c, LMTOF_EHIP, "autotune failed");
+        const float build_ms =
+            std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - b0).count();
         if (rc) {
             c->opt_ept = saved;
             c->probs_dirty = true;
@@ -1572,6 +1578,9 @@ int lmtof_autotune(lmtof_ctx *c, int64_t *chosen, float *ms) {
             if (rep == 1 || (rep > 1 && tr < t)) t = tr;
         }
         t_cand[k] = t;
+        // the brick lists are built once per reconstruction: a tenth of their
+        // build time is charged to each pass (reconstructions run ~10 iterations)
+        score[k] = t + build_ms / kAutotuneIters;
         if (ms) ms[k] = t;
     }
     // The default shape stays unless another beats it by more than 1 %:
@@ -1579,10 +1588,10 @@ int lmtof_autotune(lmtof_ctx *c, int64_t *chosen, float *ms) {
     int best = kDefaultEpt;
     float best_ms = 0.0f;
     for (int k = 0; k < 4; ++k)
-        if (cand[k] == kDefaultEpt) best_ms = t_cand[k];
+        if (cand[k] == kDefaultEpt) best_ms = score[k];
     for (int k = 0; k < 4; ++k) {
-        if (t_cand[k] < 0.99f * best_ms) {
-            best_ms = t_cand[k];
+        if (score[k] < 0.99f * best_ms) {
+            best_ms = score[k];
             best = cand[k];
         }
     }
