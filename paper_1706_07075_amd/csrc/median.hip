@@ -36,8 +36,8 @@ __device__ __forceinline__ void extremes(float (&v)[27]) {
     }
 }
 
-// Round R: the pool is v[R, 15); drop its extremes, then the largest's slot
-// v[14] takes the next value v[15 + R].  After round 11 the pool is v[12, 15).
+// Step R: the pool is v[R, 15); drop its extremes, then the largest's slot
+// v[14] takes the next value v[15 + R].  After step 11 the pool is v[12, 15).
 template <int R>
 struct Forget {
     static __device__ __forceinline__ void run(float (&v)[27]) {
