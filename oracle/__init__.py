@@ -237,6 +237,32 @@ def median3(x, nx: int, ny: int, nz: int) -> np.ndarray:
     return np.sort(block, axis=0)[13].reshape(-1)
 
 
+def attenuation_factors(g: dict, ev, mu) -> np.ndarray:
+    """Attenuation correction factor of every event (Section 2.4): the
+    inverse of the probability that both photons survive, exp(+ line
+    integral of mu along the whole LOR inside the grid), mu in 1/mm per voxel
+    (x fastest).  The line integral is the non-TOF row of A applied to mu."""
+    g0 = dict(g, tof_fwhm_ps=0.0)
+    return np.exp(forward(g0, ev, np.asarray(mu, np.float64)))
+
+
+def mlem_weighted(g: dict, ev, s, n_iter: int, w, x0) -> np.ndarray:
+    """MLEM with a weight per event multiplying its ratio (the paper's
+    attenuation correction on the LOR, Section 2.4): x <- x / s * A^T (w / A x),
+    events with (A x)_i = 0 contributing nothing, voxels with s = 0 held at
+    0.  Written from the definition with the oracle's forward and back
+    projections."""
+    x = np.asarray(x0, np.float64).copy()
+    s = np.asarray(s, np.float64)
+    w = np.asarray(w, np.float64)
+    for _ in range(n_iter):
+        f = forward(g, ev, x)
+        r = np.where(f > 0, w / np.where(f > 0, f, 1.0), 0.0)
+        b = back(g, ev, r)
+        x = np.where(s > 0, x * b / np.where(s > 0, s, 1.0), 0.0)
+    return x
+
+
 TOF_REJECT_Z = 1.959964  # two-sided 95 % quantile of the normal distribution
 
 

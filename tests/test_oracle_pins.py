@@ -447,3 +447,41 @@ def test_tof_keep_matches_dense_sampling():
         assert strict[i] <= hit <= loose[i], i
         assert strict[i] <= keep[i] <= loose[i], i
     assert 20 < keep.sum() < n - 20  # both outcomes occur
+
+
+# ---- attenuation weights on the LOR (Section 2.4)
+
+def test_attenuation_factor_closed_form():
+    """A uniform mu over the grid: the factor is exp(mu x chord length), the
+    chord through the box in closed form for an axis-parallel LOR."""
+    g = _box_geom(n=10, v=4.0)
+    mu = np.full(1000, 0.0096)  # water at 511 keV, 1/mm
+    ev = np.array([[-300.0, 1.0, 2.0, 300.0, 1.0, 2.0, 0.0],     # along x: 40 mm inside
+                   [1.0, 1.0, -300.0, 1.0, 1.0, 300.0, 50.0],    # along z: 40 mm
+                   [-300.0, 30.0, 0.0, 300.0, 30.0, 0.0, 0.0]])  # misses the grid: factor 1
+    acf = oracle.attenuation_factors(g, ev, mu)
+    assert np.allclose(acf, [np.exp(0.0096 * 40), np.exp(0.0096 * 40), 1.0], rtol=1e-12)
+
+
+def test_weighted_mlem_unit_weights_duplicates_and_normalisation():
+    """Unit weights reproduce the plain MLEM; weight 2 on an event equals
+    loading it twice; sum_j s_j x_j after an iteration equals the weight sum
+    over events with (A x)_i > 0."""
+    g = _box_geom(n=6, v=4.0)
+    rng = np.random.default_rng(31)
+    a = rng.normal(size=(40, 3))
+    a /= np.linalg.norm(a, axis=1)[:, None]
+    p0 = rng.uniform(-8, 8, size=(40, 3))
+    ev = np.concatenate([p0 - 300 * a, p0 + 300 * a, rng.normal(0, 40, (40, 1))], axis=1)
+    s = rng.uniform(0.5, 1.5, 216)
+    x0 = np.full(216, 0.3)
+    x1, _ = oracle.mlem(g, ev, s, 2, x0=x0)
+    assert np.allclose(oracle.mlem_weighted(g, ev, s, 2, np.ones(40), x0), x1, rtol=1e-12, atol=0)
+    w = np.ones(40)
+    w[:5] = 2.0
+    xd, _ = oracle.mlem(g, np.concatenate([ev, ev[:5]]), s, 2, x0=x0)
+    assert np.allclose(oracle.mlem_weighted(g, ev, s, 2, w, x0), xd, rtol=1e-12, atol=0)
+    wr = rng.uniform(0.5, 3.0, 40)
+    xw = oracle.mlem_weighted(g, ev, s, 1, wr, x0)
+    f = oracle.forward(g, ev, x0)
+    assert abs((s * xw).sum() - wr[f > 0].sum()) < 1e-10 * wr.sum()
