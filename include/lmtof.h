@@ -227,6 +227,22 @@ int lmtof_median_filter(lmtof_ctx *ctx, const float *x, int64_t nx_, float *y, i
  * (nx*ny*nz bytes) and keep (n_events bytes) live in `mem`.  Needs loaded
  * events (ESTATE) and TOF (EUNSUPPORTED otherwise). */
 int lmtof_tof_keep(lmtof_ctx *ctx, const uint8_t *mask, int64_t n_mask, uint8_t *keep, int64_t n_keep, int mem);
+
+/* Attenuation correction on the LOR (Section 2.4).  The paper weights each
+ * event in the forward model instead of attenuating the sensitivity; its
+ * wording is read as the correction factor 1 / P_survive.
+ * lmtof_attenuation_factors: acf[k] = exp(line integral of mu along event
+ * k's whole LOR inside the grid), k in the caller's order of the last load;
+ * mu (nx*ny*nz floats, 1/mm, x fastest) and acf (n_events floats) live in
+ * `mem`.  Needs loaded events (ESTATE).
+ * lmtof_set_event_weights: w[k] (caller order, n_events floats in `mem`)
+ * multiplies event k's ratio in every following iteration: x <- x / s *
+ * A^T (w / A x).  Then sum_j s_j x_j after an iteration equals the sum of w
+ * over the events with (A x)_i > 0, and the log-likelihood stays
+ * unweighted.  w = NULL drops the weights; loading events drops them too.
+ * Needs loaded events (ESTATE); EINVAL for a wrong count. */
+int lmtof_attenuation_factors(lmtof_ctx *ctx, const float *mu, int64_t n_mu, float *acf, int64_t n_acf, int mem);
+int lmtof_set_event_weights(lmtof_ctx *ctx, const float *w, int64_t n, int mem);
 /* Back projection b_j = sum_i a_ij w_i of per-event weights w (caller's
  * order, n_events floats) into b (nx*ny*nz floats, overwritten). */
 int lmtof_back_project(lmtof_ctx *ctx, const float *w, int64_t nw, float *b, int64_t nb, int mem);

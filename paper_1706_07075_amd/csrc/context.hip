@@ -113,6 +113,11 @@ struct lmtof_ctx {
     ItemSet items;               // brick item lists of the iteration batch
     float *d_rw = nullptr;       // per stored event: 1 / f (MLEM) or a weight
     size_t rw_cap = 0;
+    // per-event ratio weights (attenuation correction on the LOR): caller
+    // order as given, stored order for the iteration
+    bool has_evw = false;
+    float *d_evw_caller = nullptr, *d_evw = nullptr;
+    size_t evw_cap = 0, evw_stored_cap = 0;
     float4 *d_lut = nullptr;     // kernel-CDF table
     double lut_k = -1.0;
     int *d_part_neff = nullptr;
@@ -630,6 +635,12 @@ int ensure_problems(lmtof_ctx *c) {
     if ((rc = build_items(c, ps, c->d_probs, c->n_chunks, ept, c->items))) return rc;
     c->probs = ps;
     c->ept_used = ept;
+    if (c->has_evw) {
+        if ((rc = reserve(c, &c->d_evw, c->evw_stored_cap, (size_t)c->n_events))) return rc;
+        Launch Lw;
+        Lw.stream = c->stream;
+        HIPCHK(c, launch_gather_by_perm(Lw, c->d_evw_caller, c->d_perm, c->n_events, c->d_evw));
+    }
     if ((size_t)c->n_chunks > c->part_cap) {
         dev_free(c->d_part_neff);
         dev_free(c->d_part_ll);
@@ -697,6 +708,17 @@ int build_graph(lmtof_ctx *c, int n_iter, GraphEntry &ge) {
         HIPCHK(c, launch_forward(L, tof, c->d_probs, np, c->n_chunks, c->ept_used, 0, c->d_part_neff, c->d_part_ll,
                                  c->d_part_wmax));
         if (node) prev = node;
+        if (c->has_evw) {
+            // weighted ratios w_i / f_i, and the chunk maxima the brick scales use
+            L.deps = &prev;
+            node = nullptr;
+            HIPCHK(c, launch_mul(L, c->d_rw, c->d_evw, c->n_events));
+            if (node) prev = node;
+            L.deps = &prev;
+            node = nullptr;
+            HIPCHK(c, launch_chunk_absmax(L, c->d_probs, np, c->n_chunks, c->ept_used, c->d_part_wmax));
+            if (node) prev = node;
+        }
         if ((rc = record(ge.ev[kEventsPerIter * k + 1]))) return rc;
         if ((rc = add_back(c, L, c->d_probs, np, c->items, c->d_part_wmax, c->n_chunks, &prev, ge.ev[kEventsPerIter * k + 2],
                            ge.ev[kEventsPerIter * k + 3])))
@@ -940,6 +962,8 @@ int lmtof_destroy(lmtof_ctx *c) {
     dev_free(c->d_stats);
     dev_free(c->d_scratch);
     dev_free(c->d_rw);
+    dev_free(c->d_evw);
+    dev_free(c->d_evw_caller);
     dev_free(c->d_lut);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
@@ -1142,6 +1166,7 @@ int lmtof_load_events(lmtof_ctx *c, const void *ev, int64_t n, int format, int m
     drop_regions(c);
     drop_graphs(c);
     install_events(c);
+    c->has_evw = false;  // weights belong to the previous events
     c->n_events = n;
     c->stored_packed = packed;
     c->probs_dirty = true;
@@ -1348,7 +1373,10 @@ int lmtof_iterate(lmtof_ctx *c, int n_iter, lmtof_iter_stats *stats) {
     }
 }
 
-int lmtof_forward_project(lmtof_ctx *c, const float *x, int64_t nx_, float *f, int64_t nf, int mem) {
+// f (caller order) = A x over the loaded events, with the TOF kernel if tof,
+// else plain chord lengths (the LOR inside the grid); exp(A x) if acf.
+static int forward_events(lmtof_ctx *c, const float *x, int64_t nx_, float *f, int64_t nf, int mem, bool tof,
+                          bool acf) {
     if (!c) return LMTOF_EINVAL;
     c->err.clear();
     if (!c->n_events) return fail(c, LMTOF_ESTATE, "load events first");
@@ -1377,6 +1405,7 @@ int lmtof_forward_project(lmtof_ctx *c, const float *x, int64_t nx_, float *f, i
     }
     if ((rc = dev_alloc(c, &fs, c->n_events)) || (rc = ensure_lut(c))) return done(rc);
     std::vector<Problem> ps{make_problem(c, 0, c->g.nz, dx, nullptr, nullptr)};
+    if (!tof) ps[0].tof = 0;
     ps[0].events = c->d_events;
     ps[0].n_events = c->n_events;
     ps[0].rw = fs;
@@ -1389,12 +1418,44 @@ int lmtof_forward_project(lmtof_ctx *c, const float *x, int64_t nx_, float *f, i
     if ((rc = upload_problems(c, ps, block, ept, &dp, nch, nvch))) return done(rc);
     hipError_t he = hipMemsetAsync(xb, 0, sizeof(float) * 64 * (size_t)nxb, c->stream);
     if (he == hipSuccess) he = launch_block_image(L, dp, 1, nxb);
-    if (he == hipSuccess) he = launch_forward(L, c->g.tof_fwhm_ps > 0, dp, 1, nch, ept, 1, nullptr, nullptr, nullptr);
+    if (he == hipSuccess) he = launch_forward(L, tof, dp, 1, nch, ept, 1, nullptr, nullptr, nullptr);
+    if (he == hipSuccess && acf) he = launch_exp(L, fs, c->n_events);
     if (he == hipSuccess) he = launch_scatter_by_perm(L, fs, c->d_perm, c->n_events, fc);
     if (he != hipSuccess) return done(fail(c, LMTOF_EHIP, "forward projection: %s", hipGetErrorString(he)));
     if (mem == LMTOF_MEM_HOST) rc = copy_out(c, f, fc, sizeof(float) * c->n_events, LMTOF_MEM_HOST);
     else if (hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(c, LMTOF_EHIP, "forward projection failed");
     return done(rc);
+}
+
+int lmtof_forward_project(lmtof_ctx *c, const float *x, int64_t nx_, float *f, int64_t nf, int mem) {
+    if (!c) return LMTOF_EINVAL;
+    return forward_events(c, x, nx_, f, nf, mem, c->g.tof_fwhm_ps > 0, false);
+}
+
+int lmtof_attenuation_factors(lmtof_ctx *c, const float *mu, int64_t n_mu, float *acf, int64_t n_acf, int mem) {
+    if (!c) return LMTOF_EINVAL;
+    return forward_events(c, mu, n_mu, acf, n_acf, mem, false, true);
+}
+
+int lmtof_set_event_weights(lmtof_ctx *c, const float *w, int64_t n, int mem) {
+    if (!c) return LMTOF_EINVAL;
+    c->err.clear();
+    if (!w) {
+        if (c->has_evw) c->probs_dirty = true;
+        c->has_evw = false;
+        return LMTOF_OK;
+    }
+    if (!c->n_events) return fail(c, LMTOF_ESTATE, "load events first");
+    if (n != c->n_events || !valid_mem(mem))
+        return fail(c, LMTOF_EINVAL, "need %lld weights", (long long)c->n_events);
+    HIPCHK(c, hipSetDevice(c->device));
+    int rc = reserve(c, &c->d_evw_caller, c->evw_cap, (size_t)n);
+    if (rc) return rc;
+    if ((rc = copy_in(c, c->d_evw_caller, w, sizeof(float) * (size_t)n, mem))) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->has_evw = true;
+    c->probs_dirty = true;  // stored-order copy and the iteration graph follow
+    return LMTOF_OK;
 }
 
 int lmtof_median_filter(lmtof_ctx *c, const float *x, int64_t nx_, float *y, int64_t ny_, int mem) {

@@ -182,6 +182,9 @@ hipError_t launch_sum_positive(const Launch &L, const float *s, int64_t n, doubl
 hipError_t launch_uniform_image(const Launch &L, const float *s, int64_t n, const double *sum, double n_events,
                                 float *x);
 hipError_t launch_fill(const Launch &L, float *p, int64_t n, float v);
+// a[i] *= w[i]; a[i] = exp(a[i]) (i < n).
+hipError_t launch_mul(const Launch &L, float *a, const float *w, int64_t n);
+hipError_t launch_exp(const Launch &L, float *a, int64_t n);
 // dst[i] = src[z_lo * nx * ny + i] for a z-slab of nzs slices.
 hipError_t launch_copy_slab(const Launch &L, const float *src, int64_t plane, int z_lo, int nzs, float *dst);
 // dst[z_lo * plane + i] += src[i] for i < plane * nzs.

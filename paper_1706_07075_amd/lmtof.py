@@ -106,6 +106,8 @@ _sig = {
     "lmtof_back_project": ([_P, _P, _i64, _P, _i64, C.c_int], C.c_int),
     "lmtof_median_filter": ([_P, _P, _i64, _P, _i64, C.c_int], C.c_int),
     "lmtof_tof_keep": ([_P, _P, _i64, _P, _i64, C.c_int], C.c_int),
+    "lmtof_attenuation_factors": ([_P, _P, _i64, _P, _i64, C.c_int], C.c_int),
+    "lmtof_set_event_weights": ([_P, _P, _i64, C.c_int], C.c_int),
     "lmtof_count_segments": ([_P, C.POINTER(_i64), C.POINTER(_i64)], C.c_int),
     "lmtof_autotune": ([_P, C.POINTER(_i64), C.POINTER(C.c_float)], C.c_int),
     "lmtof_set_regions": ([_P, C.POINTER(C.c_int32), C.c_int, C.c_int], C.c_int),
@@ -327,6 +329,26 @@ def lmtof_tof_keep(ctx, mask, n_events: int, out=None):
     return o
 
 
+def lmtof_attenuation_factors(ctx, mu, n_events: int, out=None):
+    p, mem, keep_alive = _in(mu, np.float32)
+    if mem == LMTOF_MEM_DEVICE and out is None:
+        import torch
+        out = torch.empty(n_events, dtype=torch.float32, device=mu.device)
+    o, po, memo = _out(out, n_events, np.float32)
+    if memo != mem:
+        raise ValueError("mu and acf must both be host or both be device arrays")
+    _check(_lib.lmtof_attenuation_factors(ctx, p, int(np.prod(mu.shape)), po, n_events, mem), ctx)
+    return o
+
+
+def lmtof_set_event_weights(ctx, w) -> None:
+    if w is None:
+        _check(_lib.lmtof_set_event_weights(ctx, None, 0, LMTOF_MEM_HOST), ctx)
+        return
+    p, mem, keep_alive = _in(w, np.float32)
+    _check(_lib.lmtof_set_event_weights(ctx, p, int(np.prod(w.shape)), mem), ctx)
+
+
 def lmtof_count_segments(ctx):
     """(pieces visited, pieces with non-zero weight) over all loaded events."""
     a, b = C.c_int64(), C.c_int64()
@@ -515,6 +537,12 @@ class Reconstruction:
 
     def tof_keep(self, mask, out=None):
         return lmtof_tof_keep(self.ctx, mask, lmtof_num_events(self.ctx), out)
+
+    def attenuation_factors(self, mu, out=None):
+        return lmtof_attenuation_factors(self.ctx, mu, lmtof_num_events(self.ctx), out)
+
+    def set_event_weights(self, w):
+        lmtof_set_event_weights(self.ctx, w)
 
     def count_segments(self):
         return lmtof_count_segments(self.ctx)
