@@ -66,6 +66,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--tof-reject", action="store_true",
                     help="also time the TOF scatter rejection pre-pass (3 calls) against the phantom's body outline")
+    ap.add_argument("--attenuation", action="store_true",
+                    help="also time the attenuation factors of a water map over the body (3 calls) and the "
+                         "iteration loop with them as event weights")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device (a reference for HBM byte counters)")
     args = ap.parse_args()
@@ -212,14 +215,35 @@ def main():
                                "bytes_per_event_iteration": bytes_iter / N,
                                "hbm_roofline_event_iterations_per_s": HBM_PEAK_GBS * 1e9 / (bytes_iter / N)},
     }
-    if args.tof_reject:
+    body = None
+    if args.tof_reject or args.attenuation:
         gx = g["x0"] + g["vx"] * (np.arange(g["nx"]) + 0.5)
         gy = g["y0"] + g["vy"] * (np.arange(g["ny"]) + 0.5)
         gz = g["z0"] + g["vz"] * (np.arange(g["nz"]) + 0.5)
         zz, yy, xx = np.meshgrid(gz, gy, gx, indexing="ij")
         pts = np.stack([xx.ravel(), yy.ravel(), zz.ravel()], axis=1)
-        mask = torch.from_numpy((synth.phantom_eval(synth.wholebody_phantom(), pts) > 0).astype(np.uint8)).to(dev)
+        body = (synth.phantom_eval(synth.wholebody_phantom(), pts) > 0).astype(np.uint8)
         del zz, yy, xx, pts
+    if args.attenuation:
+        mu = torch.from_numpy(body.astype(np.float32) * np.float32(0.0096)).to(dev)  # water at 511 keV, 1/mm
+        acf_ms = []
+        for k in range(3):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            acf = r.attenuation_factors(mu)
+            torch.cuda.synchronize()
+            acf_ms.append((time.perf_counter() - a) * 1e3)
+        r.set_event_weights(acf)
+        r.set_image()
+        st_w = r.iterate(w.n_iter)
+        r.set_event_weights(None)
+        out["attenuation"] = {"factors_ms": acf_ms, "factor_range": [float(acf.min()), float(acf.max())],
+                              "iteration_ms_weighted": float(np.mean([q["ms"] for q in st_w])),
+                              "iteration_ms": iter_ms}
+        log(f"attenuation: {out['attenuation']}")
+        del mu, acf
+    if args.tof_reject:
+        mask = torch.from_numpy(body).to(dev)
         rej_ms = []
         for k in range(3):
             torch.cuda.synchronize()
