@@ -66,6 +66,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--tof-reject", action="store_true",
                     help="also time the TOF scatter rejection pre-pass (3 calls) against the phantom's body outline")
+    ap.add_argument("--sampled", action="store_true",
+                    help="also time the paper's sampled TOF projector (forward and back, 3 calls each)")
     ap.add_argument("--attenuation", action="store_true",
                     help="also time the attenuation factors of a water map over the body (3 calls) and the "
                          "iteration loop with them as event weights")
@@ -215,6 +217,23 @@ def main():
                                "bytes_per_event_iteration": bytes_iter / N,
                                "hbm_roofline_event_iterations_per_s": HBM_PEAK_GBS * 1e9 / (bytes_iter / N)},
     }
+    if args.sampled:
+        xs = torch.ones(w.n_voxels, dtype=torch.float32, device=dev)
+        rs = torch.ones(N, dtype=torch.float32, device=dev)
+        fw_ms, bk_ms = [], []
+        for k in range(3):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            r.sampled_forward_project(xs)
+            torch.cuda.synchronize()
+            fw_ms.append((time.perf_counter() - a) * 1e3)
+            a = time.perf_counter()
+            r.sampled_back_project(rs)
+            torch.cuda.synchronize()
+            bk_ms.append((time.perf_counter() - a) * 1e3)
+        out["sampled_projector"] = {"forward_ms": fw_ms, "back_ms": bk_ms, "samples_per_event": 32}
+        log(f"sampled projector: {out['sampled_projector']}")
+        del xs, rs
     body = None
     if args.tof_reject or args.attenuation:
         gx = g["x0"] + g["vx"] * (np.arange(g["nx"]) + 0.5)

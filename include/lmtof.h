@@ -243,6 +243,19 @@ int lmtof_tof_keep(lmtof_ctx *ctx, const uint8_t *mask, int64_t n_mask, uint8_t 
  * Needs loaded events (ESTATE); EINVAL for a wrong count. */
 int lmtof_attenuation_factors(lmtof_ctx *ctx, const float *mu, int64_t n_mu, float *acf, int64_t n_acf, int mem);
 int lmtof_set_event_weights(lmtof_ctx *ctx, const float *w, int64_t n, int mem);
+
+/* The paper's own TOF projector (Section 2.3), for comparison with the
+ * exact-integral projector above: each loaded event is sampled at 32 points
+ * spaced equally along its LOR over [-K sigma, K sigma] around the TOF
+ * centre (midpoints of 32 equal steps; K = tof_trunc_sigmas), weighted by
+ * the Gaussian density there with the 32 weights summing to 1, each point
+ * reading (forward) or adding into (back) the voxel that holds it; points
+ * outside the grid are dropped.  Forward: f (n_events, caller order) from x
+ * (nx*ny*nz).  Back: b (nx*ny*nz, overwritten) from r (n_events, caller
+ * order); FP32 atomics, so b is not bit-reproducible.  Arrays in `mem`.
+ * Needs loaded TOF events (ESTATE / EUNSUPPORTED). */
+int lmtof_sampled_forward_project(lmtof_ctx *ctx, const float *x, int64_t nx_, float *f, int64_t nf, int mem);
+int lmtof_sampled_back_project(lmtof_ctx *ctx, const float *r, int64_t nr, float *b, int64_t nb, int mem);
 /* Back projection b_j = sum_i a_ij w_i of per-event weights w (caller's
  * order, n_events floats) into b (nx*ny*nz floats, overwritten). */
 int lmtof_back_project(lmtof_ctx *ctx, const float *w, int64_t nw, float *b, int64_t nb, int mem);

@@ -1492,6 +1492,92 @@ int lmtof_median_filter(lmtof_ctx *c, const float *x, int64_t nx_, float *y, int
     return done(rc);
 }
 
+// The sampled projector's geometry: sample positions and Gaussian weights
+// (FP64, normalised to sum 1, then rounded).
+static SampledGeom sampled_geom(const lmtof_ctx *c) {
+    const lmtof_geometry &g = c->g;
+    SampledGeom G{};
+    G.ox = (float)g.x0;
+    G.oy = (float)g.y0;
+    G.oz = (float)g.z0;
+    G.ivx = (float)(1.0 / g.vx);
+    G.ivy = (float)(1.0 / g.vy);
+    G.ivz = (float)(1.0 / g.vz);
+    G.nx = g.nx;
+    G.ny = g.ny;
+    G.nz = g.nz;
+    G.half_c = (float)(g.c_mm_per_ps / 2.0);
+    const double sg = sigma_mm(g), K = g.tof_trunc_sigmas, step = 2.0 * K * sg / kSampledN;
+    G.t_lo = (float)(-K * sg);
+    G.step = (float)step;
+    double w[kSampledN], sum = 0.0;
+    for (int k = 0; k < kSampledN; ++k) {
+        const double t = -K * sg + (k + 0.5) * step;
+        w[k] = std::exp(-0.5 * (t / sg) * (t / sg));
+        sum += w[k];
+    }
+    for (int k = 0; k < kSampledN; ++k) G.w[k] = (float)(w[k] / sum);
+    return G;
+}
+
+// Sampled forward (r == NULL: out = f over events, caller order) or back
+// projection (out = b over voxels) of the loaded events.
+static int sampled_project(lmtof_ctx *c, const float *in, int64_t n_in, float *out, int64_t n_out, int mem,
+                           bool back) {
+    if (!c) return LMTOF_EINVAL;
+    c->err.clear();
+    if (!c->n_events) return fail(c, LMTOF_ESTATE, "load events first");
+    if (!(c->g.tof_fwhm_ps > 0)) return fail(c, LMTOF_EUNSUPPORTED, "the sampled projector needs TOF events");
+    const int64_t want_in = back ? c->n_events : c->V, want_out = back ? c->V : c->n_events;
+    if (!in || !out || n_in != want_in || n_out != want_out || !valid_mem(mem))
+        return fail(c, LMTOF_EINVAL, "need %lld inputs and %lld outputs", (long long)want_in, (long long)want_out);
+    HIPCHK(c, hipSetDevice(c->device));
+    Launch L;
+    L.stream = c->stream;
+    float *din = nullptr, *dout = nullptr, *tmp = nullptr;
+    int rc = LMTOF_OK;
+    auto done = [&](int r) {
+        (void)hipStreamSynchronize(c->stream);
+        if (mem == LMTOF_MEM_HOST) {
+            dev_free(din);
+            dev_free(dout);
+        }
+        dev_free(tmp);
+        return r;
+    };
+    if (mem == LMTOF_MEM_HOST) {
+        if ((rc = dev_alloc(c, &din, want_in)) || (rc = dev_alloc(c, &dout, want_out))) return done(rc);
+        if ((rc = copy_in(c, din, in, sizeof(float) * want_in, LMTOF_MEM_HOST))) return done(rc);
+    } else {
+        din = const_cast<float *>(in);
+        dout = out;
+    }
+    if ((rc = dev_alloc(c, &tmp, c->n_events))) return done(rc);
+    const SampledGeom G = sampled_geom(c);
+    const bool packed = c->stored_packed != 0;
+    hipError_t he;
+    if (back) {
+        he = launch_gather_by_perm(L, din, c->d_perm, c->n_events, tmp);
+        if (he == hipSuccess) he = launch_fill(L, dout, c->V, 0.0f);
+        if (he == hipSuccess) he = launch_sampled(L, c->d_events, packed, c->n_events, G, nullptr, nullptr, tmp, dout);
+    } else {
+        he = launch_sampled(L, c->d_events, packed, c->n_events, G, din, tmp, nullptr, nullptr);
+        if (he == hipSuccess) he = launch_scatter_by_perm(L, tmp, c->d_perm, c->n_events, dout);
+    }
+    if (he != hipSuccess) return done(fail(c, LMTOF_EHIP, "sampled projector: %s", hipGetErrorString(he)));
+    if (mem == LMTOF_MEM_HOST) rc = copy_out(c, out, dout, sizeof(float) * want_out, LMTOF_MEM_HOST);
+    else if (hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(c, LMTOF_EHIP, "sampled projector failed");
+    return done(rc);
+}
+
+int lmtof_sampled_forward_project(lmtof_ctx *c, const float *x, int64_t nx_, float *f, int64_t nf, int mem) {
+    return sampled_project(c, x, nx_, f, nf, mem, false);
+}
+
+int lmtof_sampled_back_project(lmtof_ctx *c, const float *r, int64_t nr, float *b, int64_t nb, int mem) {
+    return sampled_project(c, r, nr, b, nb, mem, true);
+}
+
 int lmtof_tof_keep(lmtof_ctx *c, const uint8_t *mask, int64_t nmask, uint8_t *keep, int64_t nkeep, int mem) {
     if (!c) return LMTOF_EINVAL;
     c->err.clear();

@@ -151,6 +151,20 @@ hipError_t launch_count_pieces(const Launch &L, bool tof, const Problem *d_probs
 hipError_t launch_tof_keep(const Launch &L, const Problem *d_probs, bool packed, int64_t n_events, float half_width,
                           const uint8_t *mask, const int64_t *perm, uint8_t *keep);
 
+// ---- the paper's sampled TOF projector (sampled.hip)
+constexpr int kSampledN = 32;  // samples per event
+struct SampledGeom {
+    float ox, oy, oz, ivx, ivy, ivz;  // grid corner (mm) and inverse voxel sizes
+    int nx, ny, nz;
+    float half_c;       // c / 2 (mm/ps)
+    float t_lo, step;   // sample k at t_lo + (k + 1/2) step (mm from the TOF centre)
+    float w[kSampledN]; // weights, summing to 1
+};
+// Forward (r == NULL): f[i] = sum_k w_k x[voxel of sample k], per stored
+// event.  Back (r != NULL): b[voxel] += w_k r[i] (b accumulated, FP32 atomics).
+hipError_t launch_sampled(const Launch &L, const void *events, bool packed, int64_t n, const SampledGeom &G,
+                          const float *x, float *f, const float *r, float *b);
+
 // ---- median sieve (median.hip)
 // y = 3x3x3 median of x (nx * ny * nz voxels, x fastest), 0 outside the grid; y != x.
 hipError_t launch_median3(const Launch &L, const float *x, float *y, int nx, int ny, int nz);

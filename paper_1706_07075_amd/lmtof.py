@@ -108,6 +108,8 @@ _sig = {
     "lmtof_tof_keep": ([_P, _P, _i64, _P, _i64, C.c_int], C.c_int),
     "lmtof_attenuation_factors": ([_P, _P, _i64, _P, _i64, C.c_int], C.c_int),
     "lmtof_set_event_weights": ([_P, _P, _i64, C.c_int], C.c_int),
+    "lmtof_sampled_forward_project": ([_P, _P, _i64, _P, _i64, C.c_int], C.c_int),
+    "lmtof_sampled_back_project": ([_P, _P, _i64, _P, _i64, C.c_int], C.c_int),
     "lmtof_count_segments": ([_P, C.POINTER(_i64), C.POINTER(_i64)], C.c_int),
     "lmtof_autotune": ([_P, C.POINTER(_i64), C.POINTER(C.c_float)], C.c_int),
     "lmtof_set_regions": ([_P, C.POINTER(C.c_int32), C.c_int, C.c_int], C.c_int),
@@ -349,6 +351,25 @@ def lmtof_set_event_weights(ctx, w) -> None:
     _check(_lib.lmtof_set_event_weights(ctx, p, int(np.prod(w.shape)), mem), ctx)
 
 
+def _project_call(fn, ctx, a, n_out):
+    p, mem, keep_alive = _in(a, np.float32)
+    out = None
+    if mem == LMTOF_MEM_DEVICE:
+        import torch
+        out = torch.empty(n_out, dtype=torch.float32, device=a.device)
+    o, po, memo = _out(out, n_out, np.float32)
+    _check(fn(ctx, p, int(np.prod(a.shape)), po, n_out, mem), ctx)
+    return o
+
+
+def lmtof_sampled_forward_project(ctx, x, n_events: int):
+    return _project_call(_lib.lmtof_sampled_forward_project, ctx, x, n_events)
+
+
+def lmtof_sampled_back_project(ctx, r, n_voxels: int):
+    return _project_call(_lib.lmtof_sampled_back_project, ctx, r, n_voxels)
+
+
 def lmtof_count_segments(ctx):
     """(pieces visited, pieces with non-zero weight) over all loaded events."""
     a, b = C.c_int64(), C.c_int64()
@@ -543,6 +564,12 @@ class Reconstruction:
 
     def set_event_weights(self, w):
         lmtof_set_event_weights(self.ctx, w)
+
+    def sampled_forward_project(self, x):
+        return lmtof_sampled_forward_project(self.ctx, x, lmtof_num_events(self.ctx))
+
+    def sampled_back_project(self, r):
+        return lmtof_sampled_back_project(self.ctx, r, self.V)
 
     def count_segments(self):
         return lmtof_count_segments(self.ctx)
