@@ -8,13 +8,17 @@ uniform start image and 10 graph-replayed MLEM iterations.
 
 value = events x iterations x steps / wall time of the steps
 (event-iterations per second, end to end).  The same JSON line carries the
-iteration-loop-only rate, the one-time costs, the projector kernel's
-roofline position (algorithmic bytes over its HIP-event-timed duration) and
-the FP64 oracle timed on the host cores on a bounded sample.
+iteration-loop-only rate, the one-time costs, the dominant projector
+kernel's roofline position (algorithmic bytes over its HIP-event-timed
+duration), the same workload in packed storage, as a nine-region division
+and as a served Poisson request stream, and the FP64 oracle timed on the
+host cores on a bounded sample.
 """
 import argparse
+import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -27,16 +31,17 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 # TOF-assisted division of the whole-body grid: nine core slabs (z slices),
 # feet to head
 REGION_CORES = [0, 107, 177, 240, 290, 335, 375, 410, 438, 470]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_back_chunks_wholebody_146M.json")
+PROFILES = os.path.join(ROOT, "profiles")
 PROJECTOR_SRC = os.path.join(ROOT, "paper_1706_07075_amd", "csrc", "project.hip")
 
 
-def measured_traffic(storage):
-    """HBM bytes per launch of the brick kernel from committed rocprofv3
-    counter runs, if they were taken on the current projector source."""
-    import hashlib
+def measured_traffic(kernel, storage):
+    """HBM bytes per launch of `kernel` from committed rocprofv3 counter
+    runs (FETCH_SIZE and WRITE_SIZE, each scaled by a copy of known size),
+    if they were taken on the current projector source; else None."""
+    path = os.path.join(PROFILES, f"traffic_{kernel}_wholebody_146M.json")
     try:
-        rec = json.load(open(TRAFFIC_FILE))
+        rec = json.load(open(path))
         src = hashlib.sha256(open(PROJECTOR_SRC, "rb").read()).hexdigest()
     except (OSError, ValueError):
         return None
@@ -50,19 +55,82 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def mean_stats(stats, key):
+    return float(np.mean([s[key] for st in stats for s in st]))
+
+
+def run_form(r, ev_dev, n_iter, steps, warmup, regions=False, label=""):
+    """Time `steps` whole reconstructions (after `warmup`) on context r;
+    returns per-step timings and per-iteration stats."""
+    times, stats = [], []
+    for k in range(warmup + steps):
+        t = {}
+        a = time.perf_counter()
+        r.load_events(ev_dev)
+        t["load_ms"] = (time.perf_counter() - a) * 1e3
+        b = time.perf_counter()
+        r.compute_sensitivity()
+        t["sens_ms"] = (time.perf_counter() - b) * 1e3
+        b = time.perf_counter()
+        if regions:
+            r.set_regions(REGION_CORES)
+        r.set_image()
+        t["init_ms"] = (time.perf_counter() - b) * 1e3
+        b = time.perf_counter()
+        st = r.iterate(n_iter)
+        t["iter_ms"] = (time.perf_counter() - b) * 1e3
+        t["step_ms"] = (time.perf_counter() - a) * 1e3
+        if k >= warmup:
+            times.append(t)
+            stats.append(st)
+        log(f"{label}{'warmup' if k < warmup else 'step'} {k if k < warmup else k - warmup}: "
+            f"{json.dumps({q: round(v, 2) for q, v in t.items()})}")
+    return times, stats
+
+
+def form_summary(times, stats, N, I):
+    wall = sum(t["step_ms"] for t in times) * 1e-3
+    it_ms = mean_stats(stats, "ms")
+    return {"event_iterations_per_s": N * I * len(times) / wall,
+            "iter_loop_event_iterations_per_s": N / (it_ms * 1e-3),
+            "ms_per_iteration": it_ms,
+            "ms_per_step": float(np.mean([t["step_ms"] for t in times])),
+            "k_forward_ms": mean_stats(stats, "forward_ms"),
+            "k_back_chunks_ms": mean_stats(stats, "back_kernel_ms"),
+            "one_time_ms": {k: float(np.mean([t[k] for t in times])) for k in ("load_ms", "sens_ms", "init_ms")},
+            "steps": len(times)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--events", type=int, default=146_000_000)
     ap.add_argument("--iters", type=int, default=10)
     ap.add_argument("--storage", choices=["plain", "packed"], default="plain")
     ap.add_argument("--cpu-sample", type=int, default=60_000_000,
-                    help="events in the oracle CPU-baseline sample (0 = skip)")
+                    help="events in the oracle CPU-baseline sample on all host threads (0 = skip)")
+    ap.add_argument("--cpu-sample-1core", type=int, default=2_000_000,
+                    help="events in the oracle CPU-baseline sample on one thread (0 = skip)")
     ap.add_argument("--ept", type=int, default=0)
     ap.add_argument("--regions", action="store_true",
-                    help="TOF-assisted 9-region division of the same events (one batched launch per kernel)")
+                    help="headline form: the TOF-assisted 9-region division (one batched launch per kernel)")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the packed, regions and serving comparison legs")
+    ap.add_argument("--form-steps", type=int, default=3, help="timed reconstructions per comparison leg")
+    ap.add_argument("--serve-requests", type=int, default=60, help="requests per serving leg (0 = skip)")
+    ap.add_argument("--serve-rates", default="2,10", help="Poisson arrival rates (req/s) of the serving legs")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--tof-reject", action="store_true",
                     help="also time the TOF scatter rejection pre-pass (3 calls) against the phantom's body outline")
@@ -112,24 +180,6 @@ def main():
         opts["events_per_thread"] = args.ept
     r = L.Reconstruction(g, device=0, **opts)
 
-    def one_step():
-        t = {}
-        a = time.perf_counter()
-        r.load_events(ev_dev)
-        t["load_ms"] = (time.perf_counter() - a) * 1e3
-        a = time.perf_counter()
-        r.compute_sensitivity()
-        t["sens_ms"] = (time.perf_counter() - a) * 1e3
-        a = time.perf_counter()
-        if args.regions:
-            r.set_regions(REGION_CORES)
-        r.set_image()
-        t["init_ms"] = (time.perf_counter() - a) * 1e3
-        a = time.perf_counter()
-        st = r.iterate(w.n_iter)
-        t["iter_ms"] = (time.perf_counter() - a) * 1e3
-        return t, st
-
     tuned = None
     if not args.no_autotune:
         r.load_events(ev_dev)
@@ -141,45 +191,44 @@ def main():
         tuned = {"events_per_thread": chosen, "pass_ms": pass_ms}
         log(f"autotune: {tuned}")
 
-    for k in range(args.warmup):
-        t, st = one_step()
-        log(f"warmup {k}: {t}, last iteration n_eff {st[-1]['n_eff']} sum_sx {st[-1]['sum_sx']:.6e}")
-
+    N, I, K = w.n_events, w.n_iter, args.steps
+    run_form(r, ev_dev, I, 0, args.warmup, regions=args.regions)
     torch.cuda.synchronize()
-    times, stats = [], []
     t_start = time.perf_counter()
-    for k in range(args.steps):
-        a = time.perf_counter()
-        t, st = one_step()
-        t["step_ms"] = (time.perf_counter() - a) * 1e3
-        times.append(t)
-        stats.append(st)
-        log(f"step {k}: {json.dumps({q: round(v, 2) for q, v in t.items()})}")
+    times, stats = run_form(r, ev_dev, I, K, 0, regions=args.regions)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
-
-    N, I, K = w.n_events, w.n_iter, args.steps
     value = N * I * K / wall
-    allst = [s for st in stats for s in st]
-    mean = lambda key: float(np.mean([s[key] for s in allst]))  # noqa: E731
-    proj_ms, fwd_ms, back_ms = mean("project_ms"), mean("forward_ms"), mean("back_ms")
-    backk_ms, upd_ms, iter_ms = mean("back_kernel_ms"), mean("update_ms"), mean("ms")
+
+    proj_ms, fwd_ms, back_ms = mean_stats(stats, "project_ms"), mean_stats(stats, "forward_ms"), mean_stats(stats, "back_ms")
+    backk_ms, upd_ms, iter_ms = mean_stats(stats, "back_kernel_ms"), mean_stats(stats, "update_ms"), mean_stats(stats, "ms")
     loop_rate = N / (iter_ms * 1e-3)
     last = stats[-1][-1]
 
-    # Algorithmic bytes (no reuse across events): an event record of E bytes
-    # and one 4-byte ratio per event, one 4-byte image access per voxel piece
-    # (a gather in the forward pass, a scatter-add in the back pass), and a
-    # 20-byte-per-voxel update pass (x, s, b read; x written; b cleared).
+    # Algorithmic bytes per event-iteration (no reuse across events): the
+    # event record (E bytes) once, one 4-byte image gather per voxel piece in
+    # the forward pass, one 4-byte scatter-add per weighted piece in the back
+    # pass, and 20 bytes per voxel for the update pass (x, s, b read; x
+    # written; b cleared).  Per kernel: forward N E + 4 visited, back
+    # 4 weighted; per iteration their sum plus 20 V.
     visited, weighted = r.count_segments()
     E = 16 if args.storage == "packed" else 32
     V = w.n_voxels
-    bytes_back = N * (E + 4) + 4 * weighted
-    bytes_fwd = N * (E + 4) + 4 * visited
+    bytes_fwd = N * E + 4 * visited
+    bytes_back = 4 * weighted
     bytes_iter = N * E + 4 * (visited + weighted) + 20 * V
     gbs = lambda b, ms: b / (ms * 1e-3) / 1e9  # noqa: E731
-    step_ms = [t["step_ms"] for t in times]
+    kern = {"k_forward": (bytes_fwd, fwd_ms), "k_back_chunks": (bytes_back, backk_ms)}
+    dom = max(kern, key=lambda k: kern[k][1])
 
+    def roof(kname):
+        b, ms = kern[kname]
+        return {"bound": "hbm", "achieved": gbs(b, ms), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": gbs(b, ms) / HBM_PEAK_GBS,
+                "traffic": None if args.regions else measured_traffic(kname, args.storage),
+                "kernel": kname, "bytes_per_launch": b, "launch_ms": ms}
+
+    step_ms = [t["step_ms"] for t in times]
     out = {
         "metric": "event-iterations/s (TOF fwd+back proj) at 146M events; p50/p99 recon latency",
         "value": value,
@@ -198,25 +247,41 @@ def main():
                    "step": "ingest+sort+sensitivity+init+10 graph-replayed iterations"},
         "autotune": tuned,
         "iter_loop_event_iterations_per_s": loop_rate,
-        "recon_latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99))},
+        "recon_latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
+                             "min": float(np.min(step_ms)), "max": float(np.max(step_ms))},
         "one_time_ms": {k: float(np.mean([t[k] for t in times])) for k in ("load_ms", "sens_ms", "init_ms")},
         "iteration_ms": iter_ms,
         "kernel_ms": {"project": proj_ms, "k_forward": fwd_ms, "back_stage": back_ms, "k_back_chunks": backk_ms,
                       "update_stage": upd_ms},
         "segments_per_event": {"visited": visited / N, "weighted": weighted / N},
         "last_iteration": {"n_eff": last["n_eff"], "sum_sx": last["sum_sx"], "loglik": last["loglik"]},
-        "roofline": {"bound": "hbm", "achieved": gbs(bytes_back, backk_ms), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs(bytes_back, backk_ms) / HBM_PEAK_GBS,
-                     "traffic": None if args.regions else measured_traffic(args.storage),
-                     "kernel": "k_back_chunks", "bytes_per_launch": bytes_back},
-        "roofline_forward": {"bound": "hbm", "achieved": gbs(bytes_fwd, fwd_ms), "peak": HBM_PEAK_GBS,
-                             "unit": "GB/s", "frac": gbs(bytes_fwd, fwd_ms) / HBM_PEAK_GBS,
-                             "kernel": "k_forward", "bytes_per_launch": bytes_fwd},
+        "roofline": roof(dom),
+        "roofline_other": roof("k_back_chunks" if dom == "k_forward" else "k_forward"),
         "roofline_iteration": {"bound": "hbm", "achieved": gbs(bytes_iter, iter_ms), "peak": HBM_PEAK_GBS,
                                "unit": "GB/s", "frac": gbs(bytes_iter, iter_ms) / HBM_PEAK_GBS,
                                "bytes_per_event_iteration": bytes_iter / N,
                                "hbm_roofline_event_iterations_per_s": HBM_PEAK_GBS * 1e9 / (bytes_iter / N)},
     }
+    log(f"headline: {value:.4e} ev-it/s end to end, iteration {iter_ms:.2f} ms, "
+        f"{dom} frac {out['roofline']['frac']:.3f}, iteration frac {out['roofline_iteration']['frac']:.3f}")
+
+    if not args.no_forms and args.form_steps > 0:
+        # the same events, reconstructed as the other forms, on this GPU
+        if not args.regions:
+            tr, sr = run_form(r, ev_dev, I, args.form_steps, 1, regions=True, label="regions ")
+            out["regions"] = form_summary(tr, sr, N, I)
+            out["regions"]["events_per_region"] = [r.region_info(k)["n_events"] for k in range(9)]
+            r.clear_regions()
+            log(f"regions: {out['regions']}")
+        if args.storage == "plain":
+            rp = L.Reconstruction(g, device=0, storage=1, **({"events_per_thread": args.ept} if args.ept else {}))
+            if tuned:
+                rp.set_option("events_per_thread", tuned["events_per_thread"])
+            tp, sp = run_form(rp, ev_dev, I, args.form_steps, 1, label="packed ")
+            out["packed"] = form_summary(tp, sp, N, I)
+            rp.close()
+            log(f"packed: {out['packed']}")
+
     if args.sampled:
         xs = torch.ones(w.n_voxels, dtype=torch.float32, device=dev)
         rs = torch.ones(N, dtype=torch.float32, device=dev)
@@ -244,6 +309,8 @@ def main():
         body = (synth.phantom_eval(synth.wholebody_phantom(), pts) > 0).astype(np.uint8)
         del zz, yy, xx, pts
     if args.attenuation:
+        r.load_events(ev_dev)
+        r.compute_sensitivity()
         mu = torch.from_numpy(body.astype(np.float32) * np.float32(0.0096)).to(dev)  # water at 511 keV, 1/mm
         acf_ms = []
         for k in range(3):
@@ -262,6 +329,7 @@ def main():
         log(f"attenuation: {out['attenuation']}")
         del mu, acf
     if args.tof_reject:
+        r.load_events(ev_dev)
         mask = torch.from_numpy(body).to(dev)
         rej_ms = []
         for k in range(3):
@@ -274,24 +342,50 @@ def main():
                              "body_voxels": int(mask.sum())}
         log(f"tof reject: {out['tof_reject']}")
     r.close()
+    torch.cuda.empty_cache()
+
+    if not args.no_forms and args.serve_requests > 0:
+        from paper_1706_07075_amd import serve
+        pools = {("whole", float(w.tof_fwhm_ps)): (w, ev_dev)}
+        out["serving"] = {}
+        for rate in [float(q) for q in args.serve_rates.split(",") if q]:
+            reqs = serve.make_workload(args.serve_requests, rate, 1217, N, pools=pools)
+            log(f"serving: {len(reqs)} Poisson requests at {rate} req/s")
+            res = serve.run(reqs, 200 << 30)
+            res["rate_hz"] = rate
+            out["serving"][f"{rate:g}hz"] = res
+            log(f"  {res}")
+        del pools
     del ev_dev
     torch.cuda.empty_cache()
 
-    if args.cpu_sample > 0:
+    if args.cpu_sample > 0 or args.cpu_sample_1core > 0:
         import oracle
-        M = min(args.cpu_sample, N)
-        ev_s = ev[:M]
         s_ones = np.ones(w.n_voxels)
-        log(f"cpu baseline: oracle MLEM, 1 iteration, first {M} events, {oracle.num_threads()} threads")
-        a = time.perf_counter()
-        oracle.mlem(g, ev_s, s_ones, 1)
-        dt = time.perf_counter() - a
-        out["cpu_baseline"] = {"value": M / dt, "unit": "event-iterations/s", "cores": oracle.num_threads(),
-                               "kind": "oracle",
-                               "sample": f"first {M} of the {N} whole-body events, 1 MLEM iteration on the full "
-                                         f"150x150x600 grid (unit sensitivity; sensitivity time excluded), "
-                                         f"{dt:.1f} s"}
-        log(f"  {M / dt:.3e} ev-it/s in {dt:.1f} s")
+        cb = {"unit": "event-iterations/s", "kind": "oracle", "cpu_model": cpu_model(),
+              "host_threads": os.cpu_count()}
+        if args.cpu_sample > 0:
+            M = min(args.cpu_sample, N)
+            log(f"cpu baseline: oracle MLEM, 1 iteration, first {M} events, {oracle.num_threads()} threads")
+            a = time.perf_counter()
+            oracle.mlem(g, ev[:M], s_ones, 1)
+            dt = time.perf_counter() - a
+            cb.update(value=M / dt, cores=oracle.num_threads(),
+                      sample=f"first {M} of the {N} whole-body events, 1 MLEM iteration on the full "
+                             f"150x150x600 grid (unit sensitivity; sensitivity time excluded), {dt:.1f} s")
+            log(f"  {M / dt:.3e} ev-it/s in {dt:.1f} s")
+        if args.cpu_sample_1core > 0:
+            M1 = min(args.cpu_sample_1core, N)
+            n_all = oracle.num_threads()
+            oracle.set_num_threads(1)
+            a = time.perf_counter()
+            oracle.mlem(g, ev[:M1], s_ones, 1)
+            dt1 = time.perf_counter() - a
+            oracle.set_num_threads(n_all)
+            cb["one_core"] = {"value": M1 / dt1, "cores": 1,
+                              "sample": f"first {M1} events, 1 MLEM iteration, full grid, {dt1:.1f} s"}
+            log(f"  one core: {M1 / dt1:.3e} ev-it/s in {dt1:.1f} s")
+        out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
 

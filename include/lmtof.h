@@ -281,6 +281,12 @@ int lmtof_set_regions(lmtof_ctx *ctx, const int32_t *z_bounds, int n_regions, in
 /* Region k's sub-volume: out4[0] = first slice, out4[1] = slices,
  * out4[2] = core first slice, out4[3] = core end slice; *n_events = events. */
 int lmtof_region_info(const lmtof_ctx *ctx, int k, int32_t *out4, int64_t *n_events);
+/* Section 2.5: the region each loaded event was assigned to by
+ * lmtof_set_regions (its TOF centre's core), region[i] in [0, n_regions)
+ * for event i in the caller's order of the last lmtof_load_events.  n must
+ * equal the number of loaded events; region is caller-owned (n int32 in
+ * `mem`).  ESTATE without a region split. */
+int lmtof_event_regions(lmtof_ctx *ctx, int32_t *region, int64_t n, int mem);
 /* Region k's current image (nx*ny*slices floats). */
 int lmtof_read_region_image(lmtof_ctx *ctx, int k, float *out, int64_t n, int mem);
 /* Drop the region split (back to one whole-volume problem). */

@@ -70,6 +70,8 @@ def _L():
         lib.or_mlem.argtypes = [G, d, C.c_int64, d, d, C.c_int, d, P(Stats)]
         lib.or_initial_image.argtypes = [G, d, C.c_int64, d]
         lib.or_num_threads.restype = C.c_int
+        lib.or_set_num_threads.argtypes = [C.c_int]
+        lib.or_set_num_threads.restype = None
         _lib = lib
     return _lib
 
@@ -192,6 +194,11 @@ def mlem(g: dict, ev, s, n_iter: int, x0: Optional[np.ndarray] = None, history: 
 
 def num_threads() -> int:
     return _L().or_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads the oracle's parallel loops use from now on."""
+    _L().or_set_num_threads(int(n))
 
 
 # ------------------------------------------------------------ packed codec

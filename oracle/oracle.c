@@ -369,3 +369,12 @@ void or_initial_image(const or_geom *g, const double *s, int64_t n_events, doubl
 }
 
 int or_num_threads(void) { return nthreads(); }
+
+/* Threads the parallel loops use from now on (timing runs on one core). */
+void or_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -59,8 +59,14 @@ struct ItemSet {
     uint32_t *pairs = nullptr, *pair_off = nullptr;  // (forward chunk) lists per brick
     char *item_recs = nullptr;                        // walk records in item order (40 B each)
     size_t item_bytes = 0;
-    // capacities of the large arrays, kept across rebuilds of the lists
-    size_t items_cap = 0, item_recs_cap = 0, tiles_cap = 0, pairs_cap = 0;
+    // builder scratch: per-key counters and offsets, per-brick pair
+    // counters, the counting blocks' key tables
+    uint32_t *cnt = nullptr, *off_d = nullptr, *pcnt = nullptr, *tabs = nullptr;
+    // capacities (elements) of every array above: the lists are rebuilt in
+    // place and a buffer is only reallocated when it has to grow, so
+    // reloading events of a similar size allocates and frees nothing
+    size_t items_cap = 0, item_recs_cap = 0, tiles_cap = 0, pairs_cap = 0, chunks_cap = 0, bricks_cap = 0,
+           wmax_cap = 0, pair_off_cap = 0, cnt_cap = 0, off_cap = 0, pcnt_cap = 0, tabs_cap = 0;
     uint32_t n_chunks = 0, n_bricks = 0, n_slots = 0;
     uint64_t n_items = 0, n_pairs = 0;
     std::vector<uint4> h_chunks, h_bricks;  // host copies (batching several problems)
@@ -91,16 +97,23 @@ struct lmtof_ctx {
     // buffers kept between loads: the spare event store and permutation a
     // load or region split writes into (then swapped with the current
     // ones), and the sort's keys, histogram, scan scratch, error flag and
-    // intermediate permutation
-    Scratch sc_events, sc_perm, sc_keys, sc_hist, sc_tmp, sc_err, sc_inner;
+    // intermediate permutation; the device copy of events handed over in
+    // host memory
+    Scratch sc_events, sc_perm, sc_keys, sc_hist, sc_tmp, sc_err, sc_inner, sc_raw;
 
     // whole-volume images
     float *d_s = nullptr, *d_x = nullptr, *d_b = nullptr;
+    size_t img_cap = 0;  // voxels each of d_s, d_x, d_b hold
     bool has_sens = false, has_image = false;
     int iter_count = 0;
 
-    // regions (empty: one whole-volume problem)
+    // regions (empty: one whole-volume problem); their x, b and s images
+    // lie back to back in reg_buf; a region split fills the spare sc_reg
+    // and then swaps it in
     std::vector<Region> regions;
+    float *reg_buf = nullptr;
+    size_t reg_cap = 0;  // bytes
+    Scratch sc_reg;
     int margin_used = 0;
 
     // batch of problems the iteration runs
@@ -204,9 +217,25 @@ void free_items(ItemSet &it) {
     dev_free(it.pairs);
     dev_free(it.pair_off);
     dev_free(it.item_recs);
+    dev_free(it.cnt);
+    dev_free(it.off_d);
+    dev_free(it.pcnt);
+    dev_free(it.tabs);
     it = ItemSet();
 }
 
+// The lists no longer describe the loaded events; their buffers stay for
+// the next build.
+void invalidate_items(ItemSet &it) {
+    it.n_chunks = it.n_bricks = it.n_slots = 0;
+    it.n_items = it.n_pairs = 0;
+    it.item_bytes = 0;
+    it.h_chunks.clear();
+    it.h_bricks.clear();
+}
+
+// Destroy the instantiated iteration graphs (they hold the buffer addresses
+// and launch sizes of the current batch).  Device buffers are kept.
 void drop_graphs(lmtof_ctx *c) {
     for (auto &kv : c->graphs) {
         if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
@@ -214,23 +243,17 @@ void drop_graphs(lmtof_ctx *c) {
         for (hipEvent_t e : kv.second.ev) (void)hipEventDestroy(e);
     }
     c->graphs.clear();
-    free_items(c->items);
+    invalidate_items(c->items);
 }
 
 void drop_regions(lmtof_ctx *c) {
-    for (auto &r : c->regions) {
-        dev_free(r.x);
-        dev_free(r.b);
-        dev_free(r.s);
-    }
     c->regions.clear();
     c->probs_dirty = true;
 }
 
+// No events loaded any more; the event store and permutation buffers stay
+// for the next load (lmtof_destroy frees them).
 void drop_events(lmtof_ctx *c) {
-    dev_free(c->d_events);
-    dev_free(c->d_perm);
-    c->events_cap = c->perm_cap = 0;
     c->n_events = 0;
     c->has_image = false;
     drop_regions(c);
@@ -251,7 +274,8 @@ void install_events(lmtof_ctx *c) {
 
 // Free the buffers kept for the next load (a served request loads once).
 void release_load_scratch(lmtof_ctx *c) {
-    for (Scratch *sc : {&c->sc_events, &c->sc_perm, &c->sc_keys, &c->sc_hist, &c->sc_tmp, &c->sc_err, &c->sc_inner})
+    for (Scratch *sc : {&c->sc_events, &c->sc_perm, &c->sc_keys, &c->sc_hist, &c->sc_tmp, &c->sc_err, &c->sc_inner,
+                        &c->sc_raw})
         scratch_free(*sc);
 }
 
@@ -402,59 +426,35 @@ int reserve(lmtof_ctx *c, T **p, size_t &cap, size_t n) {
 }
 
 int build_items(lmtof_ctx *c, std::vector<Problem> &ps, Problem *d_probs, int64_t n_chunks, int ept,
-                ItemSet &out) {
-    // the large arrays are reused when they are big enough (reloading events
-    // of a similar size then allocates nothing large)
-    ItemSet keep;
-    std::swap(keep.items, out.items);
-    std::swap(keep.item_recs, out.item_recs);
-    std::swap(keep.tiles, out.tiles);
-    std::swap(keep.pairs, out.pairs);
-    keep.items_cap = out.items_cap;
-    keep.item_recs_cap = out.item_recs_cap;
-    keep.tiles_cap = out.tiles_cap;
-    keep.pairs_cap = out.pairs_cap;
-    free_items(out);
+                ItemSet &it) {
+    // Every array is rebuilt in place and only reallocated when it has to
+    // grow.  Until the build completes the set holds no lists.
+    invalidate_items(it);
     uint64_t nb = 0;
     for (const auto &P : ps) {
         const uint64_t n = (uint64_t)P.nbx * P.nby * P.nbz;
-        if (n > (uint64_t)kMaxProblemBricks) {
-            free_items(keep);
+        if (n > (uint64_t)kMaxProblemBricks)
             return fail(c, LMTOF_EUNSUPPORTED, "grid of %llu bricks of 16^3 voxels: at most %d per problem",
                         (unsigned long long)n, kMaxProblemBricks);
-        }
         nb += n;
     }
     const uint64_t nk = nb * kItemClasses;  // (brick, item class) keys
     Launch L;
     L.stream = c->stream;
-    uint32_t *cnt = nullptr, *off_d = nullptr, *pcnt = nullptr, *tabs = nullptr;
-    auto free_tmp = [&]() {
-        dev_free(cnt);
-        dev_free(off_d);
-        dev_free(pcnt);
-        dev_free(tabs);
-    };
-    int rc = dev_alloc(c, &cnt, nk + 1);
-    if (!rc) rc = dev_alloc(c, &pcnt, nb + 1);
-    if (!rc) rc = dev_alloc(c, &tabs, (size_t)brick_item_tab_words(n_chunks));
-    if (rc) {
-        free_tmp();
-        free_items(keep);
+    int rc;
+    if ((rc = reserve(c, &it.cnt, it.cnt_cap, nk + 1)) || (rc = reserve(c, &it.pcnt, it.pcnt_cap, nb + 1)) ||
+        (rc = reserve(c, &it.tabs, it.tabs_cap, (size_t)brick_item_tab_words(n_chunks))) ||
+        (rc = reserve(c, &it.off_d, it.off_cap, nk + 1)) || (rc = reserve(c, &it.pair_off, it.pair_off_cap, nb + 1)))
         return rc;
-    }
     std::vector<uint32_t> hk(nk), hp(nb);
-    hipError_t he = hipMemsetAsync(cnt, 0, sizeof(uint32_t) * (nk + 1), c->stream);
-    if (he == hipSuccess) he = hipMemsetAsync(pcnt, 0, sizeof(uint32_t) * (nb + 1), c->stream);
-    if (he == hipSuccess) he = launch_brick_items(L, d_probs, (int)ps.size(), n_chunks, ept, cnt, nullptr, pcnt, 0, tabs);
-    if (he == hipSuccess) he = hipMemcpyAsync(hk.data(), cnt, sizeof(uint32_t) * nk, hipMemcpyDeviceToHost, c->stream);
-    if (he == hipSuccess) he = hipMemcpyAsync(hp.data(), pcnt, sizeof(uint32_t) * nb, hipMemcpyDeviceToHost, c->stream);
+    hipError_t he = hipMemsetAsync(it.cnt, 0, sizeof(uint32_t) * (nk + 1), c->stream);
+    if (he == hipSuccess) he = hipMemsetAsync(it.pcnt, 0, sizeof(uint32_t) * (nb + 1), c->stream);
+    if (he == hipSuccess)
+        he = launch_brick_items(L, d_probs, (int)ps.size(), n_chunks, ept, it.cnt, nullptr, it.pcnt, 0, it.tabs);
+    if (he == hipSuccess) he = hipMemcpyAsync(hk.data(), it.cnt, sizeof(uint32_t) * nk, hipMemcpyDeviceToHost, c->stream);
+    if (he == hipSuccess) he = hipMemcpyAsync(hp.data(), it.pcnt, sizeof(uint32_t) * nb, hipMemcpyDeviceToHost, c->stream);
     if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
-    if (he != hipSuccess) {
-        free_tmp();
-        free_items(keep);
-        return fail(c, LMTOF_EHIP, "brick item count: %s", hipGetErrorString(he));
-    }
+    if (he != hipSuccess) return fail(c, LMTOF_EHIP, "brick item count: %s", hipGetErrorString(he));
     std::vector<uint32_t> poff(nb + 1);
     uint64_t ptot = 0;
     for (uint64_t b = 0; b < nb; ++b) {
@@ -473,11 +473,7 @@ int build_items(lmtof_ctx *c, std::vector<Problem> &ps, Problem *d_probs, int64_
         tot += hk[k];
         h[k / kItemClasses] += hk[k];
     }
-    if (tot > 0xffffffffULL || ptot > 0xffffffffULL) {
-        free_tmp();
-        free_items(keep);
-        return fail(c, LMTOF_EUNSUPPORTED, "more than 2^32-1 brick items");
-    }
+    if (tot > 0xffffffffULL || ptot > 0xffffffffULL) return fail(c, LMTOF_EUNSUPPORTED, "more than 2^32-1 brick items");
     poff[nb] = (uint32_t)ptot;
     offk[nk] = (uint32_t)tot;
     off[nb] = (uint32_t)tot;
@@ -498,21 +494,12 @@ int build_items(lmtof_ctx *c, std::vector<Problem> &ps, Problem *d_probs, int64_
     }
     std::stable_sort(chunks.begin(), chunks.end(),
                      [](const uint4 &a, const uint4 &b) { return (a.z - a.y) > (b.z - b.y); });
-    ItemSet it = std::move(keep);
-    it.n_chunks = (uint32_t)chunks.size();
-    it.n_bricks = (uint32_t)bricks.size();
-    it.n_slots = slot;
-    it.n_items = tot;
-    it.n_pairs = ptot;
-    if ((rc = reserve(c, &it.items, it.items_cap, tot)) || (rc = dev_alloc(c, &off_d, nk + 1)) ||
-        (rc = dev_alloc(c, &it.chunks, chunks.size())) || (rc = dev_alloc(c, &it.bricks, bricks.size())) ||
-        (rc = reserve(c, &it.tiles, it.tiles_cap, (size_t)slot * kBrickVox)) || (rc = dev_alloc(c, &it.wmax, slot)) ||
-        (rc = reserve(c, &it.pairs, it.pairs_cap, ptot)) || (rc = dev_alloc(c, &it.pair_off, nb + 1)) ||
-        (rc = reserve(c, &it.item_recs, it.item_recs_cap, (size_t)tot * kItemRecBytes))) {
-        free_tmp();
-        free_items(it);
+    if ((rc = reserve(c, &it.items, it.items_cap, tot)) || (rc = reserve(c, &it.chunks, it.chunks_cap, chunks.size())) ||
+        (rc = reserve(c, &it.bricks, it.bricks_cap, bricks.size())) ||
+        (rc = reserve(c, &it.tiles, it.tiles_cap, (size_t)slot * kBrickVox)) ||
+        (rc = reserve(c, &it.wmax, it.wmax_cap, slot)) || (rc = reserve(c, &it.pairs, it.pairs_cap, ptot)) ||
+        (rc = reserve(c, &it.item_recs, it.item_recs_cap, (size_t)tot * kItemRecBytes)))
         return rc;
-    }
     for (auto &P : ps) {
         P.items = it.items;
         P.tiles = it.tiles;
@@ -523,29 +510,31 @@ int build_items(lmtof_ctx *c, std::vector<Problem> &ps, Problem *d_probs, int64_
         P.rec_b = reinterpret_cast<const float4 *>(it.item_recs + (size_t)tot * 16);
         P.rec_k = reinterpret_cast<const uint2 *>(it.item_recs + (size_t)tot * 32);
     }
-    it.item_bytes = (size_t)tot * kItemRecBytes;
     he = hipMemcpyAsync(d_probs, ps.data(), sizeof(Problem) * ps.size(), hipMemcpyHostToDevice, c->stream);
     if (he == hipSuccess)
-        he = hipMemcpyAsync(off_d, offk.data(), sizeof(uint32_t) * (nk + 1), hipMemcpyHostToDevice, c->stream);
+        he = hipMemcpyAsync(it.off_d, offk.data(), sizeof(uint32_t) * (nk + 1), hipMemcpyHostToDevice, c->stream);
     if (he == hipSuccess && !chunks.empty())
         he = hipMemcpyAsync(it.chunks, chunks.data(), sizeof(uint4) * chunks.size(), hipMemcpyHostToDevice, c->stream);
     if (he == hipSuccess && !bricks.empty())
         he = hipMemcpyAsync(it.bricks, bricks.data(), sizeof(uint4) * bricks.size(), hipMemcpyHostToDevice, c->stream);
-    if (he == hipSuccess) he = hipMemcpyAsync(cnt, off_d, sizeof(uint32_t) * (nk + 1), hipMemcpyDeviceToDevice, c->stream);
+    if (he == hipSuccess)
+        he = hipMemcpyAsync(it.cnt, it.off_d, sizeof(uint32_t) * (nk + 1), hipMemcpyDeviceToDevice, c->stream);
     if (he == hipSuccess)
         he = hipMemcpyAsync(it.pair_off, poff.data(), sizeof(uint32_t) * (nb + 1), hipMemcpyHostToDevice, c->stream);
     if (he == hipSuccess)
-        he = hipMemcpyAsync(pcnt, it.pair_off, sizeof(uint32_t) * (nb + 1), hipMemcpyDeviceToDevice, c->stream);
-    if (he == hipSuccess) he = launch_brick_items(L, d_probs, (int)ps.size(), n_chunks, ept, cnt, off_d + 1, pcnt, 1, tabs);
+        he = hipMemcpyAsync(it.pcnt, it.pair_off, sizeof(uint32_t) * (nb + 1), hipMemcpyDeviceToDevice, c->stream);
+    if (he == hipSuccess)
+        he = launch_brick_items(L, d_probs, (int)ps.size(), n_chunks, ept, it.cnt, it.off_d + 1, it.pcnt, 1, it.tabs);
     if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
-    free_tmp();
-    if (he != hipSuccess) {
-        free_items(it);
-        return fail(c, LMTOF_EHIP, "brick item fill: %s", hipGetErrorString(he));
-    }
+    if (he != hipSuccess) return fail(c, LMTOF_EHIP, "brick item fill: %s", hipGetErrorString(he));
+    it.n_chunks = (uint32_t)chunks.size();
+    it.n_bricks = (uint32_t)bricks.size();
+    it.n_slots = slot;
+    it.n_items = tot;
+    it.n_pairs = ptot;
+    it.item_bytes = (size_t)tot * kItemRecBytes;
     it.h_chunks = std::move(chunks);
     it.h_bricks = std::move(bricks);
-    out = std::move(it);
     return LMTOF_OK;
 }
 
@@ -846,15 +835,16 @@ KeyGeom key_geom(const lmtof_ctx *c, bool sort, const std::vector<Region> &regio
 // Device bytes a prepared context holds (events, permutation, per-event
 // weights, brick lists and tiles, images, partials).
 int64_t ctx_device_bytes(const lmtof_ctx *c) {
-    int64_t b = (int64_t)(c->events_cap + c->perm_cap) + c->n_events * 4 + 3 * 4 * c->V;
+    const ItemSet &it = c->items;
+    int64_t b = (int64_t)(c->events_cap + c->perm_cap) + (int64_t)c->rw_cap * 4 + 3 * 4 * (int64_t)c->img_cap;
     for (const Scratch *sc : {&c->sc_events, &c->sc_perm, &c->sc_keys, &c->sc_hist, &c->sc_tmp, &c->sc_err,
-                              &c->sc_inner})
+                              &c->sc_inner, &c->sc_reg, &c->sc_raw})
         b += (int64_t)sc->cap;
-    b += (int64_t)c->items.n_items * 4 + (int64_t)c->items.n_slots * (kBrickVox * 8 + 4);
-    b += (int64_t)c->items.pairs_cap * 4 + (int64_t)(c->V / kBrickVox + 64) * 4 + (int64_t)c->items.item_recs_cap;
-    b += (int64_t)(c->items.items_cap - std::min<size_t>(c->items.items_cap, c->items.n_items)) * 4;
-    b += (int64_t)(c->items.tiles_cap - std::min<size_t>(c->items.tiles_cap, (size_t)c->items.n_slots * kBrickVox)) * 8;
-    b += (int64_t)(c->items.n_chunks + c->items.n_bricks) * 16;
+    b += (int64_t)c->reg_cap;
+    b += (int64_t)it.items_cap * 4 + (int64_t)it.item_recs_cap + (int64_t)it.tiles_cap * 8 + (int64_t)it.pairs_cap * 4;
+    b += (int64_t)(it.chunks_cap + it.bricks_cap) * 16;
+    b += (int64_t)(it.wmax_cap + it.pair_off_cap + it.cnt_cap + it.off_cap + it.pcnt_cap + it.tabs_cap) * 4;
+    b += (int64_t)(c->evw_cap + c->evw_stored_cap) * 4;
     b += (int64_t)c->part_cap * 12 + (int64_t)c->vpart_cap * 16 + (kLutN + 2) * 16 + (int64_t)c->xb_cap * 4;
     return b;
 }
@@ -947,12 +937,16 @@ int lmtof_destroy(lmtof_ctx *c) {
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     drop_events(c);
+    free_items(c->items);
+    dev_free(c->d_events);
+    dev_free(c->d_perm);
+    dev_free(c->reg_buf);
+    scratch_free(c->sc_reg);
     dev_free(c->d_s);
     dev_free(c->d_x);
     dev_free(c->d_b);
     dev_free(c->d_xb);
-    for (Scratch *sc : {&c->sc_events, &c->sc_perm, &c->sc_keys, &c->sc_hist, &c->sc_tmp, &c->sc_err, &c->sc_inner})
-        scratch_free(*sc);
+    release_load_scratch(c);
     dev_free(c->d_probs);
     dev_free(c->d_part_neff);
     dev_free(c->d_part_wmax);
@@ -1060,18 +1054,22 @@ int lmtof_set_geometry(lmtof_ctx *c, const lmtof_geometry *gin) {
     HIPCHK(c, hipSetDevice(c->device));
     try {
         const int64_t V = (int64_t)g.nx * g.ny * g.nz;
-        float *s = nullptr, *x = nullptr, *b = nullptr;
-        if ((rc = dev_alloc(c, &s, V))) return rc;
-        if ((rc = dev_alloc(c, &x, V))) { dev_free(s); return rc; }
-        if ((rc = dev_alloc(c, &b, V))) { dev_free(s); dev_free(x); return rc; }
         HIPCHK(c, hipStreamSynchronize(c->stream));
+        if ((size_t)V > c->img_cap) {
+            // grow: the new images are allocated before the old ones go
+            float *s = nullptr, *x = nullptr, *b = nullptr;
+            if ((rc = dev_alloc(c, &s, V))) return rc;
+            if ((rc = dev_alloc(c, &x, V))) { dev_free(s); return rc; }
+            if ((rc = dev_alloc(c, &b, V))) { dev_free(s); dev_free(x); return rc; }
+            dev_free(c->d_s);
+            dev_free(c->d_x);
+            dev_free(c->d_b);
+            c->d_s = s;
+            c->d_x = x;
+            c->d_b = b;
+            c->img_cap = (size_t)V;
+        }
         drop_events(c);
-        dev_free(c->d_s);
-        dev_free(c->d_x);
-        dev_free(c->d_b);
-        c->d_s = s;
-        c->d_x = x;
-        c->d_b = b;
         c->g = g;
         c->V = V;
         c->has_geom = true;
@@ -1109,12 +1107,9 @@ int lmtof_load_events(lmtof_ctx *c, const void *ev, int64_t n, int format, int m
     char *store = nullptr;
     int64_t *perm = nullptr;
     uint32_t *keys = nullptr, *hist = nullptr, *tmp = nullptr, *err = nullptr;
-    auto cleanup = [&]() {
-        (void)hipStreamSynchronize(c->stream);
-        if (mem == LMTOF_MEM_HOST) dev_free(raw);
-    };
+    auto cleanup = [&]() { (void)hipStreamSynchronize(c->stream); };
     if (mem == LMTOF_MEM_HOST) {
-        if ((rc = dev_alloc(c, (char **)&raw, raw_sz * n))) return rc;
+        if ((rc = take(c, c->sc_raw, (char **)&raw, raw_sz * n))) return rc;
         if ((rc = copy_in(c, raw, ev, raw_sz * n, LMTOF_MEM_HOST))) { cleanup(); return rc; }
     } else {
         raw = const_cast<void *>(ev);
@@ -1839,7 +1834,6 @@ int lmtof_set_regions(lmtof_ctx *c, const int32_t *zb, int n, int margin) {
     const int64_t plane = (int64_t)g.nx * g.ny;
     auto cleanup = [&](int rc) {
         (void)hipStreamSynchronize(c->stream);
-        for (auto &r : regs) { dev_free(r.x); dev_free(r.b); dev_free(r.s); }
         return rc;
     };
     int rc;
@@ -1848,10 +1842,16 @@ int lmtof_set_regions(lmtof_ctx *c, const int32_t *zb, int n, int margin) {
         (rc = take(c, c->sc_inner, &inner, N)) || (rc = take(c, c->sc_perm, &perm, N)) ||
         (rc = take(c, c->sc_events, &store, esz * N)))
         return cleanup(rc);
+    int64_t reg_vox = 0;
+    for (auto &r : regs) reg_vox += plane * r.nz;
+    float *rbuf = nullptr;
+    if ((rc = take(c, c->sc_reg, &rbuf, 3 * (size_t)reg_vox))) return cleanup(rc);
     for (auto &r : regs) {
         const int64_t Vr = plane * r.nz;
-        if ((rc = dev_alloc(c, &r.x, Vr)) || (rc = dev_alloc(c, &r.b, Vr)) || (rc = dev_alloc(c, &r.s, Vr)))
-            return cleanup(rc);
+        r.x = rbuf;
+        r.b = rbuf + Vr;
+        r.s = rbuf + 2 * Vr;
+        rbuf += 3 * Vr;
     }
     const int fmt = c->stored_packed ? 1 : 2;
     hipError_t he = hipMemsetAsync(hist, 0, sizeof(uint32_t) * nkeys, c->stream);
@@ -1881,7 +1881,12 @@ int lmtof_set_regions(lmtof_ctx *c, const int32_t *zb, int n, int margin) {
     drop_graphs(c);
     install_events(c);
     c->regions = regs;
-    for (auto &r : regs) r.x = r.b = r.s = nullptr;  // now owned by the context
+    {
+        void *old = c->reg_buf;
+        c->reg_buf = static_cast<float *>(c->sc_reg.p);
+        c->sc_reg.p = old;
+        std::swap(c->reg_cap, c->sc_reg.cap);
+    }
     c->margin_used = margin;
     c->has_image = false;
     c->probs_dirty = true;
@@ -1897,6 +1902,28 @@ int lmtof_region_info(const lmtof_ctx *c, int k, int32_t *out4, int64_t *n_event
     out4[2] = r.core_lo;
     out4[3] = r.core_hi;
     *n_events = r.n_events;
+    return LMTOF_OK;
+}
+
+int lmtof_event_regions(lmtof_ctx *c, int32_t *region, int64_t n, int mem) {
+    if (!c) return LMTOF_EINVAL;
+    c->err.clear();
+    if (c->regions.empty()) return fail(c, LMTOF_ESTATE, "no region split (lmtof_set_regions) yet");
+    if (!region || n != c->n_events || !valid_mem(mem))
+        return fail(c, LMTOF_EINVAL, "need n = %lld int32 entries", (long long)c->n_events);
+    HIPCHK(c, hipSetDevice(c->device));
+    Launch L;
+    L.stream = c->stream;
+    int32_t *dst = region;
+    int rc;
+    if (mem == LMTOF_MEM_HOST) {
+        // staged through the spare event store (not in use between loads)
+        if ((rc = take(c, c->sc_events, &dst, (size_t)n))) return rc;
+    }
+    for (size_t k = 0; k < c->regions.size(); ++k)
+        HIPCHK(c, launch_fill_by_perm(L, c->d_perm + c->regions[k].ev_offset, c->regions[k].n_events, (int32_t)k, dst));
+    if (mem == LMTOF_MEM_HOST) return copy_out(c, region, dst, sizeof(int32_t) * (size_t)n, LMTOF_MEM_HOST);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     return LMTOF_OK;
 }
 
@@ -1944,6 +1971,11 @@ struct lmtof_pool {
     int64_t budget = 0, used = 0, next_id = 1;
     std::vector<PoolReq> active;
     std::map<int64_t, PoolReq> finished;
+    // contexts of released requests, kept with their device buffers for the
+    // next admissions (a new request reuses one instead of allocating);
+    // their bytes count against the budget and they are destroyed when an
+    // admission needs the room
+    std::vector<lmtof_ctx *> spare;
     // current batch
     bool dirty = true;
     std::vector<Problem> batch;
@@ -2103,6 +2135,7 @@ int lmtof_pool_destroy(lmtof_pool *p) {
     (void)hipStreamSynchronize(p->stream);
     for (auto &r : p->active) lmtof_destroy(r.ctx);
     for (auto &kv : p->finished) lmtof_destroy(kv.second.ctx);
+    for (lmtof_ctx *c : p->spare) lmtof_destroy(c);
     dev_free(p->d_probs);
     dev_free(p->d_chunks);
     dev_free(p->d_bricks);
@@ -2142,9 +2175,41 @@ int lmtof_pool_submit(lmtof_pool *p, const lmtof_request *q, int64_t *id) {
     if (p->used + est > p->budget)
         return pfail(p, LMTOF_EAGAIN, "request needs ~%lld bytes, %lld free now", (long long)est,
                      (long long)(p->budget - p->used));
+    // Reuse a released request's context: the smallest one that already
+    // holds the estimate within the budget, else the largest (it grows).
+    // Other spares are destroyed while the pool's total would exceed it.
+    int pick = -1;
+    {
+        int64_t best = 0;
+        for (size_t k = 0; k < p->spare.size(); ++k) {
+            const int64_t b = ctx_device_bytes(p->spare[k]);
+            if (b >= est && p->used + b <= p->budget && (pick < 0 || b < best)) { pick = (int)k; best = b; }
+        }
+        if (pick < 0)
+            for (size_t k = 0; k < p->spare.size(); ++k) {
+                const int64_t b = ctx_device_bytes(p->spare[k]);
+                if (b < est && (pick < 0 || b > best)) { pick = (int)k; best = b; }
+            }
+    }
     lmtof_ctx *c = nullptr;
-    int rc = lmtof_create(&c, p->device, p->stream);
-    if (rc) return pfail(p, rc, "%s", lmtof_last_error(nullptr));
+    if (pick >= 0) {
+        c = p->spare[pick];
+        p->spare.erase(p->spare.begin() + pick);
+    }
+    for (;;) {
+        int64_t rest = 0;
+        size_t big = 0;
+        for (size_t k = 0; k < p->spare.size(); ++k) {
+            const int64_t b = ctx_device_bytes(p->spare[k]);
+            rest += b;
+            if (b > ctx_device_bytes(p->spare[big])) big = k;
+        }
+        if (p->spare.empty() || p->used + std::max(est, c ? ctx_device_bytes(c) : 0) + rest <= p->budget) break;
+        lmtof_destroy(p->spare[big]);
+        p->spare.erase(p->spare.begin() + big);
+    }
+    int rc;
+    if (!c && (rc = lmtof_create(&c, p->device, p->stream))) return pfail(p, rc, "%s", lmtof_last_error(nullptr));
     auto bail = [&](int code) {
         std::string m = lmtof_last_error(c);
         lmtof_destroy(c);
@@ -2156,7 +2221,6 @@ int lmtof_pool_submit(lmtof_pool *p, const lmtof_request *q, int64_t *id) {
     if ((rc = lmtof_compute_sensitivity(c))) return bail(rc);
     if ((rc = lmtof_set_image(c, nullptr, 0, LMTOF_MEM_HOST))) return bail(rc);
     (void)hipStreamSynchronize(c->stream);
-    release_load_scratch(c);
     if (c->ept_used != p->ept) {  // brick pair lists index the forward chunks of this launch shape
         lmtof_destroy(c);
         return pfail(p, LMTOF_EUNSUPPORTED, "request prepared with a different launch shape");
@@ -2226,7 +2290,7 @@ int lmtof_pool_poll(lmtof_pool *p, int64_t id, int *done, float *out, int64_t n,
         if (rc) return pfail(p, rc, "%s", lmtof_last_error(c));
     }
     p->used -= it->second.bytes;
-    lmtof_destroy(c);
+    p->spare.push_back(c);
     p->finished.erase(it);
     *done = 1;
     return LMTOF_OK;

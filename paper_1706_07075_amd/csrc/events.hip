@@ -303,6 +303,12 @@ __global__ void k_gather_perm_i64(const int64_t *__restrict__ src, const int64_t
     if (i < n) dst[i] = src[perm[i]];
 }
 
+__global__ void k_fill_by_perm(const int64_t *__restrict__ perm, int64_t n, int32_t value,
+                               int32_t *__restrict__ dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[perm[i]] = value;
+}
+
 dim3 grid1(int64_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); }
 
 }  // namespace
@@ -353,6 +359,11 @@ hipError_t launch_scatter_by_perm(const Launch &L, const float *src_stored, cons
                                   float *dst_caller) {
     void *args[] = {&src_stored, &perm, &n, &dst_caller};
     return do_launch(L, reinterpret_cast<const void *>(&k_scatter_perm), grid1(n), dim3(kBlock), 0, args);
+}
+
+hipError_t launch_fill_by_perm(const Launch &L, const int64_t *perm, int64_t n, int32_t value, int32_t *dst_caller) {
+    void *args[] = {&perm, &n, &value, &dst_caller};
+    return do_launch(L, reinterpret_cast<const void *>(&k_fill_by_perm), grid1(n), dim3(kBlock), 0, args);
 }
 
 hipError_t launch_compose_perm(const Launch &L, const int64_t *outer, const int64_t *inner, int64_t n,

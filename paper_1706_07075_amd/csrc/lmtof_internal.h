@@ -244,6 +244,8 @@ hipError_t launch_gather_by_perm(const Launch &L, const float *src_caller, const
                                  float *dst_stored);
 hipError_t launch_scatter_by_perm(const Launch &L, const float *src_stored, const int64_t *perm, int64_t n,
                                   float *dst_caller);
+// dst_caller[perm[i]] = value for i < n.
+hipError_t launch_fill_by_perm(const Launch &L, const int64_t *perm, int64_t n, int32_t value, int32_t *dst_caller);
 // out[i] = outer[inner[i]] (compose two permutations).
 hipError_t launch_compose_perm(const Launch &L, const int64_t *outer, const int64_t *inner, int64_t n,
                                int64_t *out);

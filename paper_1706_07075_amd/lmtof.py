@@ -116,6 +116,7 @@ _sig = {
     "lmtof_region_info": ([_P, C.c_int, C.POINTER(C.c_int32), C.POINTER(_i64)], C.c_int),
     "lmtof_read_region_image": ([_P, C.c_int, _P, _i64, C.c_int], C.c_int),
     "lmtof_clear_regions": ([_P], C.c_int),
+    "lmtof_event_regions": ([_P, _P, _i64, C.c_int], C.c_int),
     "lmtof_pool_create": ([C.POINTER(_P), C.c_int, _P, _i64], C.c_int),
     "lmtof_pool_destroy": ([_P], C.c_int),
     "lmtof_pool_last_error": ([_P], C.c_char_p),
@@ -404,6 +405,12 @@ def lmtof_read_region_image(ctx, k: int, n: int, out=None):
     return o
 
 
+def lmtof_event_regions(ctx, n: int, out=None):
+    o, p, mem = _out(out, n, np.int32)
+    _check(_lib.lmtof_event_regions(ctx, p, n, mem), ctx)
+    return o
+
+
 def lmtof_clear_regions(ctx) -> None:
     _check(_lib.lmtof_clear_regions(ctx), ctx)
 
@@ -590,6 +597,10 @@ class Reconstruction:
         info = self.region_info(k)
         n = int(self.geometry["nx"]) * int(self.geometry["ny"]) * info["nz"]
         return lmtof_read_region_image(self.ctx, k, n, out)
+
+    def event_regions(self, out=None):
+        """Region index of every loaded event (caller order) after set_regions."""
+        return lmtof_event_regions(self.ctx, lmtof_num_events(self.ctx), out)
 
     def clear_regions(self):
         lmtof_clear_regions(self.ctx)

@@ -144,19 +144,23 @@ def poisson_arrivals(n: int, rate_hz: float, seed: int) -> np.ndarray:
     return np.cumsum(rng.exponential(1.0 / rate_hz, n))
 
 
-def make_workload(n_requests: int, rate_hz: float, seed: int, max_events: int, device: str = "cuda:0"):
+def make_workload(n_requests: int, rate_hz: float, seed: int, max_events: int, device: str = "cuda:0",
+                  pools: Optional[Dict] = None):
     """Serving workload: each request draws a kind (whole body, one body
     region, or the cylinder phantom), an event count log-uniform in
     [1M, max_events], 300 or 600 ps TOF and 5-10 iterations.  Events come
     from a few pre-generated pools held on the GPU (any prefix of a pool is a
-    representative sample), so staging is done once."""
+    representative sample), so staging is done once.  `pools` may hand in
+    pools generated already: {(kind, tof_ps): (workload, GPU events)}, kind
+    "whole" or "cylinder"; the dict is filled with the ones generated here."""
     import torch
 
     import synth
 
     rng = np.random.default_rng(seed)
     arrivals = poisson_arrivals(n_requests, rate_hz, seed)
-    pools = {}
+    if pools is None:
+        pools = {}
 
     def pool(kind, tof):
         key = (kind, tof)
@@ -174,16 +178,19 @@ def make_workload(n_requests: int, rate_hz: float, seed: int, max_events: int, d
     region_events = {}
 
     def region_pool(tof, rk):
-        """Events of the whole-body pool whose TOF centre lies in core rk."""
+        """Events of the whole-body pool whose TOF centre lies in core rk,
+        as the library's region split assigns them (Section 2.5)."""
         key = (tof, rk)
         if key not in region_events:
             w, evd = pool("whole", tof)
-            p1, p2, dt = evd[:, 0:3], evd[:, 3:6], evd[:, 6]
-            d = p2 - p1
-            mz = 0.5 * (p1[:, 2] + p2[:, 2]) + (w.c_mm_per_ps * dt / 2) * d[:, 2] / d.norm(dim=1)
-            lo = w.origin[2] + cores[rk] * w.voxel
-            hi = w.origin[2] + cores[rk + 1] * w.voxel
-            region_events[key] = evd[(mz >= lo) & (mz < hi)].contiguous()
+            if (tof, "assign") not in region_events:
+                with L.Reconstruction(w.geometry(), device=int(str(device).split(":")[-1])) as r:
+                    r.load_events(evd)
+                    r.compute_sensitivity()
+                    r.set_regions(cores)
+                    region_events[(tof, "assign")] = r.event_regions(
+                        torch.empty(evd.shape[0], dtype=torch.int32, device=evd.device))
+            region_events[key] = evd[region_events[(tof, "assign")] == rk].contiguous()
         return region_events[key]
 
     reqs = []

@@ -3,14 +3,14 @@
 Kernel table (kernel, calls, average / total milliseconds, share) from a
 ``--kernel-trace --stats --output-format csv`` run:
 
-    python -m paper_1706_07075_amd.profsum <run>_kernel_stats.csv
+    python profsum.py <run>_kernel_stats.csv
 
 HBM traffic of one kernel from ``--pmc FETCH_SIZE`` and ``--pmc WRITE_SIZE``
 runs (each its own run, counter values in KiB per dispatch) of a program
 that first copied ``copy_mib`` MiB device to device: each counter is scaled
 by the bytes that copy moved over what the counter read for it.
 
-    python -m paper_1706_07075_amd.profsum traffic KERNEL COPY_MIB SOURCE OUT.json \\
+    python profsum.py traffic KERNEL COPY_MIB SOURCE OUT.json \\
         plain=<fetch_csv>,<write_csv> [packed=<fetch_csv>,<write_csv>]
 
 (the last 10 dispatches of KERNEL are averaged: one reconstruction's

@@ -299,9 +299,12 @@ def test_single_voxel_grid():
         r.set_image(np.array([5.0], np.float32))
         st = r.iterate(1)
         x = float(r.read_image()[0])
-    # x1 = x0 * (sum_i a_i / (a_i x0)) / s = N / s; FP32 rounds each of the 300
-    # ratios and their atomic sum (random-walk bound ~ sqrt(300) * 2 ulp)
-    assert abs(x - st[0]["n_eff"] / s) <= 1e-5 * x
+    # x1 = x0 * (sum_i a_i / (a_i x0)) / s = N / s.  Each term a_i r_i with
+    # r_i = 1 / (a_i x0) carries at most ~3 FP32 roundings (product,
+    # reciprocal, product: <= 3 2^-24 relative); the back projection adds
+    # the terms exactly as 64-bit fixed-point integers (quantum 2^-51 of the
+    # largest), and the update rounds twice more: |x - N/s| <= ~5 2^-24 x.
+    assert abs(x - st[0]["n_eff"] / s) <= 1e-6 * x
 
 
 def test_error_paths_leave_context_usable(c1):
@@ -420,12 +423,20 @@ def test_packed_storage_bit_exact_and_parity(c1):
     xd, _ = oracle.mlem(c1["g"], dec, c1["s"], 5)
     e_dec = oracle.rel_l2(xp, xd)
     e_orig = oracle.rel_l2(xp, c1["hist"][4])
-    _say(f"  packed vs oracle(decoded) {e_dec:.2e}, vs oracle(original) {e_orig:.2e}")
+    # the input quantisation's own effect, measured by the oracle alone:
+    # the FP64 trajectories on the decoded and on the original events
+    q = oracle.rel_l2(xd, c1["hist"][4])
+    _say(f"  packed vs oracle(decoded) {e_dec:.2e}, vs oracle(original) {e_orig:.2e}, "
+         f"oracle(decoded) vs oracle(original) {q:.2e}")
     assert e_dec < 1e-5
-    # The 0.1 mm endpoint quantum itself moves unregularised MLEM at 100k
-    # events by ~4e-2 (oracle on decoded vs original events; shrinks with the
-    # event count).  This bound only guards against gross packing errors.
-    assert e_orig < 6e-2
+    # Against the original events the packed path differs by the
+    # quantisation effect q (unregularised MLEM at 100k events amplifies the
+    # 0.1 mm / binary16 perturbation of each ray; it shrinks with the event
+    # count, and the <= 1e-3 gate is stated for the 146 M-event whole-body
+    # workload, see test_gpu_wholebody_packed_gate.py) plus the arithmetic
+    # error: by the triangle inequality |e_orig - q| <= e_dec * |xd| / |x|.
+    nd = np.linalg.norm(xd) / np.linalg.norm(c1["hist"][4])
+    assert abs(e_orig - q) <= e_dec * nd * (1 + 1e-9) + 1e-12
 
 
 def test_packed_rays_in_voxel_planes(c1):

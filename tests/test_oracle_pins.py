@@ -253,6 +253,24 @@ def test_acceptance_symmetries():
     rot = np.stack([-p[:, 1], p[:, 0], p[:, 2]], 1)
     assert np.max(np.abs(a - oracle.acceptance(g, zm))) < 1e-12
     assert np.max(np.abs(a - oracle.acceptance(g, rot))) < 1e-12
+    # each generator of the symmetry group the whole-body parity tests use
+    # to fill the sensitivity from one voxel per orbit: x and y mirrors and
+    # the x <-> y swap (each maps the azimuth nodes onto themselves)
+    xm = p * np.array([-1, 1, 1])
+    ym = p * np.array([1, -1, 1])
+    sw = p[:, [1, 0, 2]]
+    for q in (xm, ym, sw):
+        assert np.max(np.abs(a - oracle.acceptance(g, q))) < 1e-12
+
+
+def test_sensitivity_by_orbits_equals_full_grid():
+    from tests import orbits
+    g = dict(nx=10, ny=10, nz=8, vx=6.0, vy=6.0, vz=7.0, x0=-30.0, y0=-30.0, z0=-28.0, scanner_radius=80.0,
+             scanner_half_length=50.0, max_axial_angle_deg=45.0, tof_fwhm_ps=300.0, tof_trunc_sigmas=3.0,
+             c_mm_per_ps=0.299792458)
+    full = oracle.sensitivity(g, n_phi=256)
+    orb = orbits.sensitivity_by_orbits(g, n_phi=256)
+    assert np.max(np.abs(full - orb)) <= 1e-12 * full.max()
 
 
 # ------------------------------------------------------------- EM pins
@@ -273,6 +291,30 @@ def test_em_matches_dense_matrix_iteration():
         r = np.where(f > 0, 1.0 / np.where(f > 0, f, 1.0), 0.0)
         x = np.where(s > 0, x * (A.T @ r) / np.where(s > 0, s, 1.0), 0.0)
     assert oracle.rel_l2(xo, x) < 1e-12
+
+
+def test_em_statistics_match_dense_matrix():
+    """Per-iteration statistics against the brute-force matrix: the
+    list-mode Poisson log-likelihood of the image fed into iteration k,
+    l(x^k) = sum over events with f > 0 of log f_i - sum_j s_j x^k_j
+    (Shepp & Vardi, cited in Section 2.4), N_eff and sum s x^(k+1).  The start
+    image is random, so sum s x^0 differs from N and from every later sum:
+    a sign slip or an off-by-one iterate in the s x term fails here."""
+    g, ev, s = _small_problem(n=400)
+    A = brute.dense_matrix(g, ev)
+    rng = np.random.default_rng(17)
+    x = np.where(s > 0, rng.uniform(0.2, 3.0, s.size), 0.0)
+    assert abs(s @ x - len(ev)) > 0.05 * len(ev)
+    xo, st = oracle.mlem(g, ev, s, 4, x0=x)
+    for k in range(4):
+        f = A @ x
+        pos = f > 0
+        ll = np.sum(np.log(f[pos])) - s @ x
+        r = np.where(pos, 1.0 / np.where(pos, f, 1.0), 0.0)
+        x = np.where(s > 0, x * (A.T @ r) / np.where(s > 0, s, 1.0), 0.0)
+        assert st[k]["n_eff"] == int(pos.sum())
+        assert abs(st[k]["loglik"] - ll) <= 1e-10 * abs(ll), (k, st[k]["loglik"], ll)
+        assert abs(st[k]["sum_sx"] - s @ x) <= 1e-10 * abs(s @ x), k
 
 
 def test_em_invariant_c_and_monotone_loglik_and_nonneg():
