@@ -57,7 +57,7 @@ struct ItemSet {
     unsigned long long *tiles = nullptr;
     float *wmax = nullptr;
     uint32_t *pairs = nullptr, *pair_off = nullptr;  // (forward chunk) lists per brick
-    char *item_recs = nullptr;                        // walk records in item order (kItemRecBytes each)
+    char *item_recs = nullptr;                        // walk records in item order (40 B each)
     size_t item_bytes = 0;
     // builder scratch: per-key counters and offsets, per-brick pair
     // counters, the counting blocks' key tables
@@ -124,10 +124,8 @@ struct lmtof_ctx {
     size_t xb_cap = 0;
     int ept_used = kDefaultEpt;
     ItemSet items;               // brick item lists of the iteration batch
-    float *d_rw = nullptr;       // per stored event: f or a caller's weight (testing passes)
+    float *d_rw = nullptr;       // per stored event: 1 / f (MLEM) or a weight
     size_t rw_cap = 0;
-    float4 *d_evrec = nullptr;   // per stored event: ray record (two float4), see Problem
-    size_t evrec_cap = 0;        // events
     // per-event ratio weights (attenuation correction on the LOR): caller
     // order as given, stored order for the iteration
     bool has_evw = false;
@@ -343,7 +341,10 @@ Problem make_problem(const lmtof_ctx *c, int z_lo, int nz, float *x, float *b, c
 // Phi(u) = erf(u / sqrt 2) / (2 erf(K / sqrt 2)) (so a piece's weight is a
 // difference of two values) and Phi'' = -u Phi'.  Evaluated in FP64.  Node
 // k sits at entry k + 1; entries 0 and n + 1 repeat the end values, flat.
-void fill_lut(double K, float4 *tab) {
+int ensure_lut(lmtof_ctx *c) {
+    const double K = c->g.tof_trunc_sigmas;
+    if (c->d_lut && c->lut_k == K) return LMTOF_OK;
+    std::vector<float4> tab(kLutN + 2);
     const double h = 2.0 * K / (kLutN - 1), den = std::erf(K / std::sqrt(2.0));
     for (int k = 0; k < kLutN; ++k) {
         const double u = -K + k * h;
@@ -353,13 +354,6 @@ void fill_lut(double K, float4 *tab) {
     }
     tab[0] = make_float4(tab[1].x, 0.0f, 0.0f, 0.0f);
     tab[kLutN + 1] = make_float4(tab[kLutN].x, 0.0f, 0.0f, 0.0f);
-}
-
-int ensure_lut(lmtof_ctx *c) {
-    const double K = c->g.tof_trunc_sigmas;
-    if (c->d_lut && c->lut_k == K) return LMTOF_OK;
-    std::vector<float4> tab(kLutN + 2);
-    fill_lut(K, tab.data());
     if (!c->d_lut) {
         int rc = dev_alloc(c, &c->d_lut, kLutN + 2);
         if (rc) return rc;
@@ -512,7 +506,9 @@ int build_items(lmtof_ctx *c, std::vector<Problem> &ps, Problem *d_probs, int64_
         P.wmax = it.wmax;
         P.pairs = it.pairs;
         P.pair_off = it.pair_off + P.brick_base;
-        P.rec = reinterpret_cast<const uint4 *>(it.item_recs);
+        P.rec_a = reinterpret_cast<const float4 *>(it.item_recs);
+        P.rec_b = reinterpret_cast<const float4 *>(it.item_recs + (size_t)tot * 16);
+        P.rec_k = reinterpret_cast<const uint2 *>(it.item_recs + (size_t)tot * 32);
     }
     he = hipMemcpyAsync(d_probs, ps.data(), sizeof(Problem) * ps.size(), hipMemcpyHostToDevice, c->stream);
     if (he == hipSuccess)
@@ -581,11 +577,12 @@ int add_back(lmtof_ctx *c, Launch L, const Problem *d_probs, int np, const ItemS
 }
 
 int ensure_rw(lmtof_ctx *c) {
-    int rc;
-    if ((rc = reserve(c, &c->d_rw, c->rw_cap, (size_t)c->n_events))) return rc;
-    size_t cap2 = c->evrec_cap * 2;
-    if ((rc = reserve(c, &c->d_evrec, cap2, 2 * (size_t)c->n_events))) return rc;
-    c->evrec_cap = cap2 / 2;
+    if ((size_t)c->n_events <= c->rw_cap) return LMTOF_OK;
+    dev_free(c->d_rw);
+    c->rw_cap = 0;
+    int rc = dev_alloc(c, &c->d_rw, c->n_events);
+    if (rc) return rc;
+    c->rw_cap = c->n_events;
     return LMTOF_OK;
 }
 
@@ -604,7 +601,6 @@ int ensure_problems(lmtof_ctx *c) {
         P.n_events = c->n_events;
         P.ev_offset = 0;
         P.rw = c->d_rw;
-        P.evrec = c->d_evrec;
         ps.push_back(P);
     } else {
         for (auto &r : c->regions) {
@@ -613,7 +609,6 @@ int ensure_problems(lmtof_ctx *c) {
             P.n_events = r.n_events;
             P.ev_offset = r.ev_offset;
             P.rw = c->d_rw + r.ev_offset;
-            P.evrec = c->d_evrec + 2 * r.ev_offset;
             ps.push_back(P);
         }
     }
@@ -630,15 +625,10 @@ int ensure_problems(lmtof_ctx *c) {
     c->probs = ps;
     c->ept_used = ept;
     if (c->has_evw) {
-        // the ratio weights in stored order, read by the forward pass
         if ((rc = reserve(c, &c->d_evw, c->evw_stored_cap, (size_t)c->n_events))) return rc;
         Launch Lw;
         Lw.stream = c->stream;
         HIPCHK(c, launch_gather_by_perm(Lw, c->d_evw_caller, c->d_perm, c->n_events, c->d_evw));
-        for (auto &P : ps) P.evw = c->d_evw + P.ev_offset;
-        HIPCHK(c, hipMemcpyAsync(c->d_probs, ps.data(), sizeof(Problem) * ps.size(), hipMemcpyHostToDevice, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        c->probs = ps;
     }
     if ((size_t)c->n_chunks > c->part_cap) {
         dev_free(c->d_part_neff);
@@ -704,10 +694,20 @@ int build_graph(lmtof_ctx *c, int n_iter, GraphEntry &ge) {
         if (node) prev = node;
         L.deps = &prev;
         node = nullptr;
-        // (with ratio weights, the forward pass applies them: w_i / f_i)
         HIPCHK(c, launch_forward(L, tof, c->d_probs, np, c->n_chunks, c->ept_used, 0, c->d_part_neff, c->d_part_ll,
                                  c->d_part_wmax));
         if (node) prev = node;
+        if (c->has_evw) {
+            // weighted ratios w_i / f_i, and the chunk maxima the brick scales use
+            L.deps = &prev;
+            node = nullptr;
+            HIPCHK(c, launch_mul(L, c->d_rw, c->d_evw, c->n_events));
+            if (node) prev = node;
+            L.deps = &prev;
+            node = nullptr;
+            HIPCHK(c, launch_chunk_absmax(L, c->d_probs, np, c->n_chunks, c->ept_used, c->d_part_wmax));
+            if (node) prev = node;
+        }
         if ((rc = record(ge.ev[kEventsPerIter * k + 1]))) return rc;
         if ((rc = add_back(c, L, c->d_probs, np, c->items, c->d_part_wmax, c->n_chunks, &prev, ge.ev[kEventsPerIter * k + 2],
                            ge.ev[kEventsPerIter * k + 3])))
@@ -836,8 +836,7 @@ KeyGeom key_geom(const lmtof_ctx *c, bool sort, const std::vector<Region> &regio
 // weights, brick lists and tiles, images, partials).
 int64_t ctx_device_bytes(const lmtof_ctx *c) {
     const ItemSet &it = c->items;
-    int64_t b = (int64_t)(c->events_cap + c->perm_cap) + (int64_t)c->rw_cap * 4 + (int64_t)c->evrec_cap * kEventRecBytes +
-                3 * 4 * (int64_t)c->img_cap;
+    int64_t b = (int64_t)(c->events_cap + c->perm_cap) + (int64_t)c->rw_cap * 4 + 3 * 4 * (int64_t)c->img_cap;
     for (const Scratch *sc : {&c->sc_events, &c->sc_perm, &c->sc_keys, &c->sc_hist, &c->sc_tmp, &c->sc_err,
                               &c->sc_inner, &c->sc_reg, &c->sc_raw})
         b += (int64_t)sc->cap;
@@ -875,9 +874,7 @@ int64_t request_bytes_estimate(const lmtof_request &q) {
         return q2;
     };
     const int64_t xbv = pow2((g.nx + 3) / 4) * pow2((g.ny + 3) / 4) * ((g.nz + 3) / 4) * 64;  // blocked copy of x
-    // events, permutation, per-event f / weight and ray record; items; x, b,
-    // s; the blocked copy of x
-    int64_t b = N * (esz + 8 + 4 + kEventRecBytes) + items * (4 + kItemRecBytes) + 3 * 4 * V + 4 * xbv;
+    int64_t b = N * (esz + 8 + 4) + items * (4 + kItemRecBytes) + 3 * 4 * V + 4 * xbv;  // x, b, s, blocked x
     b += (items / 2048 + 1 + V / kBrickVox + 1) * (int64_t)kBrickVox * 8 / 4;  // tiles
     b += items;  // (forward chunk, brick) pairs: at most one per item, ~1 in 10 in practice
     // transients: the ingest's, then (not at the same time) the brick list
@@ -959,7 +956,6 @@ int lmtof_destroy(lmtof_ctx *c) {
     dev_free(c->d_stats);
     dev_free(c->d_scratch);
     dev_free(c->d_rw);
-    dev_free(c->d_evrec);
     dev_free(c->d_evw);
     dev_free(c->d_evw_caller);
     dev_free(c->d_lut);
@@ -1634,7 +1630,6 @@ int lmtof_back_project(lmtof_ctx *c, const float *w, int64_t nw, float *b, int64
     Launch L;
     L.stream = c->stream;
     float *dw = nullptr, *ws = nullptr, *db = nullptr, *pw = nullptr;
-    float4 *er = nullptr;
     Problem *dp = nullptr;
     ItemSet its;
     int rc = LMTOF_OK;
@@ -1642,7 +1637,6 @@ int lmtof_back_project(lmtof_ctx *c, const float *w, int64_t nw, float *b, int64
         (void)hipStreamSynchronize(c->stream);
         if (mem == LMTOF_MEM_HOST) { dev_free(dw); dev_free(db); }
         dev_free(ws);
-        dev_free(er);
         dev_free(pw);
         dev_free(dp);
         free_items(its);
@@ -1655,13 +1649,11 @@ int lmtof_back_project(lmtof_ctx *c, const float *w, int64_t nw, float *b, int64
         dw = const_cast<float *>(w);
         db = b;
     }
-    if ((rc = dev_alloc(c, &ws, c->n_events)) || (rc = dev_alloc(c, &er, 2 * c->n_events)) || (rc = ensure_lut(c)))
-        return done(rc);
+    if ((rc = dev_alloc(c, &ws, c->n_events)) || (rc = ensure_lut(c))) return done(rc);
     std::vector<Problem> ps{make_problem(c, 0, c->g.nz, nullptr, db, nullptr)};
     ps[0].events = c->d_events;
     ps[0].n_events = c->n_events;
     ps[0].rw = ws;
-    ps[0].evrec = er;
     int block, ept;
     launch_shape(c, block, ept);
     int64_t nch, nvch;
@@ -1669,7 +1661,7 @@ int lmtof_back_project(lmtof_ctx *c, const float *w, int64_t nw, float *b, int64
     if ((rc = build_items(c, ps, dp, nch, ept, its)) || (rc = dev_alloc(c, &pw, nch))) return done(rc);
     hipError_t he = launch_gather_by_perm(L, dw, c->d_perm, c->n_events, ws);
     if (he == hipSuccess) he = launch_fill(L, db, c->V, 0.0f);
-    if (he == hipSuccess) he = launch_event_records(L, c->stored_packed != 0, dp, 1, nch, ept, pw);
+    if (he == hipSuccess) he = launch_chunk_absmax(L, dp, 1, nch, ept, pw);
     if (he != hipSuccess) return done(fail(c, LMTOF_EHIP, "back projection: %s", hipGetErrorString(he)));
     if ((rc = add_back(c, L, dp, 1, its, pw, nch, nullptr))) return done(rc);
     if (mem == LMTOF_MEM_HOST) rc = copy_out(c, b, db, sizeof(float) * c->V, LMTOF_MEM_HOST);

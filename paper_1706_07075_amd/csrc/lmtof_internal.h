@@ -20,10 +20,8 @@ constexpr int kItemClasses = 16;
 // Largest brick count of one problem (the brick item builder keeps a bitmap
 // of a problem's bricks in LDS).
 constexpr int kMaxProblemBricks = 65536;
-// Bytes of one brick item's walk record (one uint4), and of one event's ray
-// record (two float4).
-constexpr int kItemRecBytes = 16;
-constexpr int kEventRecBytes = 32;
+// Bytes of one brick item's walk record (two float4 and one uint2).
+constexpr int kItemRecBytes = 40;
 constexpr int kForwardBlock = 256;
 constexpr int kBackBlock = 1024;
 
@@ -36,17 +34,14 @@ struct Problem {
     float *x;             // image (nx*ny*nz)
     float *b;             // back-projection accumulator, zero between iterations
     const float *s;       // sensitivity
-    float *rw;            // per event of this problem: f (forward testing pass) or a caller's back-projection weight
-    // per event of this problem, its ray record, rewritten by every MLEM
-    // forward pass: (A_x, A_y, A_z, w), (B_x, B_y, B_z, 0), the crossing
-    // coefficients of its ray and its back-projection weight
-    float4 *evrec;
-    const float *evw;     // per event of this problem: ratio weight, or NULL
+    float *rw;            // per event of this problem: 1 / f (MLEM) or a back-projection weight
     const uint32_t *items;// brick item list array (problem-local event indices) the chunks index
     // per item, its walk inside the brick, precomputed when the lists are
-    // built: (t_a, t_b, k_x | k_y << 16, k_z | local voxel << 16) with k the
-    // first plane index minus the anchor
-    const uint4 *rec;
+    // built: (A_x, A_y, A_z, t_a), (B_x, B_y, B_z, t_b), (k_x | k_y << 16,
+    // k_z | local voxel << 16) with k the first plane index minus the anchor
+    const float4 *rec_a;
+    const float4 *rec_b;
+    const uint2 *rec_k;
     unsigned long long *tiles;  // 64-bit fixed-point chunk tiles, indexed by tile slot
     float *wmax;          // per brick, at its first tile slot: bound on |w| over its items
     const uint32_t *pairs;    // per brick: the problem-local forward chunks holding its items
@@ -114,9 +109,8 @@ inline hipError_t do_launch(const Launch &L, const void *func, dim3 grid, dim3 b
 
 // ---- projector (project.hip)
 int64_t project_chunk_events(int block, int ept);
-// Forward projection per event.  mode 0: the back-projection weight
-// w = 1 / f (0 if f <= 0), times P.evw if set, into the ray record P.evrec,
-// and per-chunk partials (n_eff, sum log f, largest |w|); mode 1: f into P.rw.
+// Forward projection per event into P.rw; mode 0: 1 / f (0 if f <= 0) and
+// per-chunk partials (n_eff, sum log f, largest 1 / f); mode 1: f.
 hipError_t launch_forward(const Launch &L, bool tof, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept,
                           int mode, int *part_neff, double *part_ll, float *part_wmax);
 // Back projection by brick chunks.  Brick table entry (global brick id,
@@ -128,10 +122,9 @@ hipError_t launch_forward(const Launch &L, bool tof, const Problem *d_probs, int
 // the listed bricks of P.b).
 hipError_t launch_brick_wmax(const Launch &L, const Problem *d_probs, int n_probs, const uint4 *bricks,
                              uint32_t n_bricks, const float *part_wmax, int64_t n_part);
-// Ray records P.evrec with the weights P.rw (stored order), and
 // part_wmax[c] = largest |P.rw| over forward chunk c's events.
-hipError_t launch_event_records(const Launch &L, bool packed, const Problem *d_probs, int n_probs, int64_t n_chunks,
-                                int ept, float *part_wmax);
+hipError_t launch_chunk_absmax(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept,
+                               float *part_wmax);
 hipError_t launch_back_chunks(const Launch &L, bool tof, const Problem *d_probs, int n_probs, const uint4 *chunks,
                               uint32_t n_chunks, const uint4 *bricks);
 hipError_t launch_reduce_tiles(const Launch &L, const Problem *d_probs, int n_probs, const uint4 *bricks,
@@ -203,7 +196,8 @@ hipError_t launch_sum_positive(const Launch &L, const float *s, int64_t n, doubl
 hipError_t launch_uniform_image(const Launch &L, const float *s, int64_t n, const double *sum, double n_events,
                                 float *x);
 hipError_t launch_fill(const Launch &L, float *p, int64_t n, float v);
-// a[i] = exp(a[i]) (i < n).
+// a[i] *= w[i]; a[i] = exp(a[i]) (i < n).
+hipError_t launch_mul(const Launch &L, float *a, const float *w, int64_t n);
 hipError_t launch_exp(const Launch &L, float *a, int64_t n);
 // dst[i] = src[z_lo * nx * ny + i] for a z-slab of nzs slices.
 hipError_t launch_copy_slab(const Launch &L, const float *src, int64_t plane, int z_lo, int nzs, float *dst);

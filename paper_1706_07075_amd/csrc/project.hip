@@ -566,51 +566,30 @@ __device__ __forceinline__ float forward_ray(const Problem &P, const Ray &r, con
     return f;
 }
 
-// The per-event ray record the back projection gathers (see the item
-// lists): (A_x, A_y, A_z, w), (B_x, B_y, B_z, 0), zero for an event whose
-// window is empty (it has no items).
-__device__ __forceinline__ void store_event_record(const Problem &P, int64_t i, bool ok, const Ray &r, float w) {
-    f32x4 a, b;
-    a[0] = ok ? in_vgpr(r.ax) : 0.0f;
-    a[1] = ok ? in_vgpr(r.ay) : 0.0f;
-    a[2] = ok ? in_vgpr(r.az) : 0.0f;
-    a[3] = w;
-    b[0] = ok ? in_vgpr(r.bx) : 0.0f;
-    b[1] = ok ? in_vgpr(r.by) : 0.0f;
-    b[2] = ok ? in_vgpr(r.bz) : 0.0f;
-    b[3] = 0.0f;
-    const gptr<f32x4> dst = global(reinterpret_cast<f32x4 *>(P.evrec));
-    dst[2 * i] = a;
-    dst[2 * i + 1] = b;
-}
-
-// Forward projection of one chunk of events.  mode 0 (MLEM): the event's
-// back-projection weight w_i = 1 / f_i (0 if f_i <= 0), times its ratio
-// weight if the problem has them, goes into its ray record, plus per-chunk
-// partials (events with f > 0, sum of log f, largest |w|); mode 1:
-// P.rw[i] = f_i.  i is the stored event position.
+// Forward projection of one chunk of events.  mode 0 (MLEM): out[i] =
+// 1 / f_i (0 if f_i <= 0) plus per-chunk partials (events with f > 0, sum
+// of log f); mode 1: out[i] = f_i.  out is indexed by stored event position.
 template <bool TOF, bool PACKED>
 __device__ __forceinline__ void forward_chunk(const Problem &P, int64_t base, int ept, int mode, const Cdf &cdf,
                                               int &neff, float &ll, float &wmax) {
     const gptr<const float> xb = global(P.xb);
+    const gptr<float> out = global(P.rw);
     // last float of the copy: steps just past the grid edge stay inside it
     const uint32_t last_off = (uint32_t)(xblocks(P) * 256 - 4);
     for (int e = 0; e < ept; ++e) {
         const int64_t i = base + (int64_t)e * blockDim.x + threadIdx.x;
         if (i >= P.n_events) break;
         Ray r;
-        const bool ok = make_ray<PACKED>(P, i, r);
-        const float f = ok ? forward_ray<TOF>(P, r, cdf, xb, last_off) : 0.0f;
+        const float f = make_ray<PACKED>(P, i, r) ? forward_ray<TOF>(P, r, cdf, xb, last_off) : 0.0f;
         if (mode == 0) {
             const bool pos = f > 0.0f;
-            float w = pos ? 1.0f / f : 0.0f;
-            if (P.evw) w *= P.evw[i];
+            const float w = pos ? 1.0f / f : 0.0f;
             neff += pos;
             ll += pos ? logf(f) : 0.0f;
-            wmax = fmaxf(wmax, fabsf(w));
-            store_event_record(P, i, ok, r, w);
+            wmax = fmaxf(wmax, w);
+            out[i] = w;
         } else {
-            global(P.rw)[i] = f;
+            out[i] = f;
         }
     }
 }
@@ -698,12 +677,10 @@ __global__ void __launch_bounds__(64) k_brick_wmax(const Problem *__restrict__ p
     if (threadIdx.x == 0) global(P.wmax)[br.y] = wm;
 }
 
-// Ray records with weights that do not come from the forward pass (a
-// caller's back-projection weights P.rw, stored order), and the largest |w|
-// over each forward chunk's events.
-template <bool PACKED>
-__global__ void __launch_bounds__(kForwardBlock) k_event_records(const Problem *__restrict__ probs, int n_probs,
-                                                                 int ept, float *__restrict__ part_wmax) {
+// Largest |w| over each forward chunk's events (for weights that do not
+// come from the forward pass, e.g. a caller's back-projection weights).
+__global__ void __launch_bounds__(kForwardBlock) k_chunk_absmax(const Problem *__restrict__ probs, int n_probs,
+                                                                int ept, float *__restrict__ part_wmax) {
     __shared__ float s_w[kForwardBlock / 64];
     const int64_t c = blockIdx.x;
     const Problem &P = probs[find_problem(probs, n_probs, c)];
@@ -711,12 +688,7 @@ __global__ void __launch_bounds__(kForwardBlock) k_event_records(const Problem *
     float wm = 0.0f;
     for (int e = 0; e < ept; ++e) {
         const int64_t i = base + (int64_t)e * blockDim.x + threadIdx.x;
-        if (i >= P.n_events) break;
-        const float w = P.rw[i];
-        wm = fmaxf(wm, fabsf(w));
-        Ray r;
-        const bool ok = make_ray<PACKED>(P, i, r);
-        store_event_record(P, i, ok, r, w);
+        if (i < P.n_events) wm = fmaxf(wm, fabsf(P.rw[i]));
     }
     wm = wave_max(wm);
     if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = wm;
@@ -752,22 +724,21 @@ __device__ __forceinline__ unsigned long long fixed_round(float a, double w) {
     return ((unsigned long long)hi << 32) | (uint32_t)u;
 }
 
-// One item's pieces in its brick, from its event's ray record (ea, eb) and
-// its own walk record rk, added to the tile as round(a ws) (ws may be
-// negative; so may a, by ~1e-10 where the interpolated CDF dips between
-// nodes).
+// One item's pieces in its brick, from its walk record, added to the tile
+// as round(a ws) (ws may be negative; so may a, by ~1e-10 where the
+// interpolated CDF dips between nodes).
 template <bool TOF>
-__device__ __forceinline__ void back_item(const f32x4 &ea, const f32x4 &eb, const u32x4 &rk, float ws, const Cdf2 &cdf,
+__device__ __forceinline__ void back_item(const f32x4 &ra, const f32x4 &rb, const u32x2 &rk, float ws, const Cdf2 &cdf,
                                           unsigned long long *tile) {
     Ray r;
-    r.ax = ea[0];
-    r.ay = ea[1];
-    r.az = ea[2];
-    r.bx = eb[0];
-    r.by = eb[1];
-    r.bz = eb[2];
-    Stepper s(r, make_uint2(rk[2], rk[3]), (int)sizeof(unsigned long long));
-    const float ta = __uint_as_float(rk[0]), tb = __uint_as_float(rk[1]);
+    r.ax = ra[0];
+    r.ay = ra[1];
+    r.az = ra[2];
+    r.bx = rb[0];
+    r.by = rb[1];
+    r.bz = rb[2];
+    Stepper s(r, make_uint2(rk[0], rk[1]), (int)sizeof(unsigned long long));
+    const float ta = ra[3], tb = rb[3];
     // j is a byte offset into the tile, inside its margin (see the tile)
     const double wsd = ws;
     walk_from<TOF>(s, r, ta, tb, cdf, [&](int j, float a) {
@@ -779,22 +750,25 @@ template <bool TOF>
 __device__ __forceinline__ void back_chunk_items(const Problem &P, const uint4 &ch, float S, const Cdf2 &cdf,
                                                  unsigned long long *tile) {
     const gptr<const uint32_t> items = global(P.items);
-    const gptr<const f32x4> evrec = global(reinterpret_cast<const f32x4 *>(P.evrec));
-    const gptr<const u32x4> rec = global(reinterpret_cast<const u32x4 *>(P.rec));
+    const gptr<const float> w = global(P.rw);
+    const gptr<const f32x4> rec_a = global(reinterpret_cast<const f32x4 *>(P.rec_a));
+    const gptr<const f32x4> rec_b = global(reinterpret_cast<const f32x4 *>(P.rec_b));
+    const gptr<const u32x2> rec_k = global(reinterpret_cast<const u32x2 *>(P.rec_k));
     // The next item's event index is loaded (unconditionally, at a clamped
-    // position) while this item is walked, and an item's event record and
-    // walk record are loaded together: one memory round trip per item.
+    // position) while this item is walked, and an item's weight and walk
+    // record are loaded together: one memory round trip per item.
     const uint32_t last = ch.z - 1;
     uint32_t k = ch.y + threadIdx.x;
     uint32_t ev = items[min(k, last)];
     for (; k < ch.z; k += blockDim.x) {
         const uint32_t ev_next = items[min(k + blockDim.x, last)];
-        const f32x4 ea = evrec[2 * (size_t)ev];
-        const f32x4 eb = evrec[2 * (size_t)ev + 1];
-        const u32x4 rk = rec[k];
+        const float wv = w[ev];
+        const f32x4 ra = rec_a[k];
+        const f32x4 rb = rec_b[k];
+        const u32x2 rk = rec_k[k];
         // (no test for w = 0, which adds zeros: a branch here would let
         // the compiler move the record loads behind the weight's)
-        back_item<TOF>(ea, eb, rk, ea[3] * S, cdf, tile);
+        back_item<TOF>(ra, rb, rk, wv * S, cdf, tile);
         ev = ev_next;
     }
 }
@@ -944,11 +918,9 @@ __device__ __forceinline__ void brick_walk(const Problem &P, const Ray &r, Visit
 // and same-address global atomics serialise) and keeps the table; when
 // filling, the block reloads its table, reserves each key's range, and
 // walks its events once, handing out positions from the reserved ranges.
-// Walk record of a brick item at position pos (16 bytes): the piece
-// [ta, tb] of the window inside the brick (as the brick walk cut it), the
-// first plane index per axis relative to the anchor and the first voxel, as
-// the back projection's walk starts from them; the crossing coefficients
-// come from the event's ray record.
+// Walk record of a brick item at position pos: the crossing coefficients,
+// the piece [ta, tb] of the window inside the brick (as the brick walk cut
+// it) and the first voxel, as the back projection's walk starts from them.
 __device__ __forceinline__ void write_item_walk(const Problem &P, const Ray &r, int bx, int by, int bz, float ta,
                                                 float tb, uint32_t pos) {
     const Box B = brick_box(P, bx, by, bz);
@@ -957,12 +929,17 @@ __device__ __forceinline__ void write_item_walk(const Problem &P, const Ray &r, 
     const int iz = min(max(voxel_at(ta, r.uz, r.jz, r.dz, P.ivz), B.z0), B.z0 + B.nz - 1);
     const int kx = ix + (r.ux > 0.0f) - r.jx, ky = iy + (r.uy > 0.0f) - r.jy, kz = iz + (r.uz > 0.0f) - r.jz;
     const uint32_t j = (uint32_t)((ix - B.x0) + kBrickX * ((iy - B.y0) + kBrickY * (iz - B.z0)));
-    u32x4 k;
-    k[0] = __float_as_uint(ta);
-    k[1] = __float_as_uint(tb);
-    k[2] = ((uint32_t)kx & 0xffffu) | ((uint32_t)ky << 16);
-    k[3] = ((uint32_t)kz & 0xffffu) | (j << 16);
-    global(reinterpret_cast<u32x4 *>(const_cast<uint4 *>(P.rec)))[pos] = k;
+    // (register copies: element-wise reads of neighbouring Ray fields would
+    // otherwise be merged into vector loads that keep the ray off registers)
+    f32x4 a, b;
+    a[0] = in_vgpr(r.ax); a[1] = in_vgpr(r.ay); a[2] = in_vgpr(r.az); a[3] = ta;
+    b[0] = in_vgpr(r.bx); b[1] = in_vgpr(r.by); b[2] = in_vgpr(r.bz); b[3] = tb;
+    u32x2 k;
+    k[0] = ((uint32_t)kx & 0xffffu) | ((uint32_t)ky << 16);
+    k[1] = ((uint32_t)kz & 0xffffu) | (j << 16);
+    global(reinterpret_cast<f32x4 *>(const_cast<float4 *>(P.rec_a)))[pos] = a;
+    global(reinterpret_cast<f32x4 *>(const_cast<float4 *>(P.rec_b)))[pos] = b;
+    global(reinterpret_cast<u32x2 *>(const_cast<uint2 *>(P.rec_k)))[pos] = k;
 }
 
 // Item class of a brick piece [t0, t1] of ray r by its voxel-plane
@@ -1196,12 +1173,11 @@ hipError_t launch_back_chunks(const Launch &L, bool tof, const Problem *d_probs,
     return do_launch(L, fn, dim3(n_chunks), dim3(kBackBlock), 0, args);
 }
 
-hipError_t launch_event_records(const Launch &L, bool packed, const Problem *d_probs, int n_probs, int64_t n_chunks,
-                                int ept, float *part_wmax) {
+hipError_t launch_chunk_absmax(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept,
+                               float *part_wmax) {
     void *args[] = {&d_probs, &n_probs, &ept, &part_wmax};
-    const void *fn = packed ? reinterpret_cast<const void *>(&k_event_records<true>)
-                            : reinterpret_cast<const void *>(&k_event_records<false>);
-    return do_launch(L, fn, dim3((unsigned)n_chunks), dim3(kForwardBlock), 0, args);
+    return do_launch(L, reinterpret_cast<const void *>(&k_chunk_absmax), dim3((unsigned)n_chunks),
+                     dim3(kForwardBlock), 0, args);
 }
 
 hipError_t launch_brick_wmax(const Launch &L, const Problem *d_probs, int n_probs, const uint4 *bricks,

@@ -145,6 +145,11 @@ __global__ void k_fill(float *__restrict__ p, int64_t n, float v) {
         p[j] = v;
 }
 
+// a <- a * w (per-event ratio weights)
+__global__ void k_mul(float *__restrict__ a, const float *__restrict__ w, int64_t n) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
+        a[j] *= w[j];
+}
 
 // a <- exp(a) (attenuation factors from line integrals)
 __global__ void k_exp(float *__restrict__ a, int64_t n) {
@@ -208,6 +213,11 @@ hipError_t launch_uniform_image(const Launch &L, const float *s, int64_t n, cons
 hipError_t launch_fill(const Launch &L, float *p, int64_t n, float v) {
     void *args[] = {&p, &n, &v};
     return do_launch(L, reinterpret_cast<const void *>(&k_fill), dim3(grid_for(n, 256)), dim3(256), 0, args);
+}
+
+hipError_t launch_mul(const Launch &L, float *a, const float *w, int64_t n) {
+    void *args[] = {&a, &w, &n};
+    return do_launch(L, reinterpret_cast<const void *>(&k_mul), dim3(grid_for(n, 256)), dim3(256), 0, args);
 }
 
 hipError_t launch_exp(const Launch &L, float *a, int64_t n) {
