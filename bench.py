@@ -65,6 +65,30 @@ def cpu_model():
     return platform.processor() or "unknown"
 
 
+def microbench():
+    """Hardware ceilings of the GPU (libmicrobench.so), each a rate."""
+    import ctypes
+    import torch
+    torch.cuda.init()
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1706_07075_amd", "microbench", "libmicrobench.so"))
+    lib.mb_run.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    probes = [("hbm_copy_GBps", 0, 4 << 30, 1e-9), ("hbm_read_GBps", 1, 4 << 30, 1e-9),
+              ("gather4B_L2_2MiB_G_per_s", 2, 2 << 20, 1e-9), ("gather4B_64MiB_G_per_s", 2, 64 << 20, 1e-9),
+              ("gather4B_HBM_4GiB_G_per_s", 2, 4 << 30, 1e-9),
+              ("global_atomic_add_f32_64MiB_G_per_s", 3, 64 << 20, 1e-9),
+              ("global_atomic_add_f32_4GiB_G_per_s", 3, 4 << 30, 1e-9),
+              ("lds_atomic_add_f32_T_per_s", 4, 4096, 1e-12), ("lds_atomic_add_u64_T_per_s", 5, 4096, 1e-12),
+              ("lds_read_b32_T_per_s", 6, 4096, 1e-12), ("valu_fma_f32_T_lane_per_s", 7, 4096, 1e-12)]
+    out = {}
+    for name, which, nbytes, scale in probes:
+        rate = ctypes.c_double()
+        if lib.mb_run(which, nbytes, 5, ctypes.byref(rate)) != 0:
+            raise RuntimeError(f"microbenchmark {name} failed")
+        out[name] = round(rate.value * scale, 3)
+        log(f"  {name}: {out[name]}")
+    return out
+
+
 def mean_stats(stats, key):
     return float(np.mean([s[key] for st in stats for s in st]))
 
@@ -105,7 +129,8 @@ def form_summary(times, stats, N, I):
             "iter_loop_event_iterations_per_s": N / (it_ms * 1e-3),
             "ms_per_iteration": it_ms,
             "ms_per_step": float(np.mean([t["step_ms"] for t in times])),
-            "k_forward_ms": mean_stats(stats, "forward_ms"),
+            "forward_stage_ms": mean_stats(stats, "forward_ms"),
+            "forward_kernel_ms": mean_stats(stats, "forward_kernel_ms"),
             "k_back_chunks_ms": mean_stats(stats, "back_kernel_ms"),
             "one_time_ms": {k: float(np.mean([t[k] for t in times])) for k in ("load_ms", "sens_ms", "init_ms")},
             "steps": len(times)}
@@ -124,6 +149,8 @@ def main():
     ap.add_argument("--cpu-sample-1core", type=int, default=2_000_000,
                     help="events in the oracle CPU-baseline sample on one thread (0 = skip)")
     ap.add_argument("--ept", type=int, default=0)
+    ap.add_argument("--forward", choices=["bricks", "events"], default="bricks",
+                    help="forward projector: brick-owned (LDS-staged image bricks) or event-parallel")
     ap.add_argument("--regions", action="store_true",
                     help="headline form: the TOF-assisted 9-region division (one batched launch per kernel)")
     ap.add_argument("--no-forms", action="store_true",
@@ -139,6 +166,8 @@ def main():
     ap.add_argument("--attenuation", action="store_true",
                     help="also time the attenuation factors of a water map over the body (3 calls) and the "
                          "iteration loop with them as event weights")
+    ap.add_argument("--microbench", action="store_true",
+                    help="only probe the hardware ceilings (HBM copy/read, random gathers, atomics, LDS, FMA)")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device (a reference for HBM byte counters)")
     args = ap.parse_args()
@@ -151,6 +180,10 @@ def main():
     import torch
     import synth
     from paper_1706_07075_amd import lmtof as L
+
+    if args.microbench:
+        print(json.dumps({"microbench": microbench()}), flush=True)
+        return
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -175,7 +208,8 @@ def main():
     ev_dev = torch.from_numpy(ev).to(dev)
     torch.cuda.synchronize()
 
-    opts = dict(storage=1 if args.storage == "packed" else 0)
+    opts = dict(storage=1 if args.storage == "packed" else 0,
+                forward=L.LMTOF_FORWARD_BRICKS if args.forward == "bricks" else L.LMTOF_FORWARD_EVENTS)
     if args.ept:
         opts["events_per_thread"] = args.ept
     r = L.Reconstruction(g, device=0, **opts)
@@ -201,6 +235,7 @@ def main():
     value = N * I * K / wall
 
     proj_ms, fwd_ms, back_ms = mean_stats(stats, "project_ms"), mean_stats(stats, "forward_ms"), mean_stats(stats, "back_ms")
+    fwdk_ms = mean_stats(stats, "forward_kernel_ms")
     backk_ms, upd_ms, iter_ms = mean_stats(stats, "back_kernel_ms"), mean_stats(stats, "update_ms"), mean_stats(stats, "ms")
     loop_rate = N / (iter_ms * 1e-3)
     last = stats[-1][-1]
@@ -209,8 +244,10 @@ def main():
     # event record (E bytes) once, one 4-byte image gather per voxel piece in
     # the forward pass, one 4-byte scatter-add per weighted piece in the back
     # pass, and 20 bytes per voxel for the update pass (x, s, b read; x
-    # written; b cleared).  Per kernel: forward N E + 4 visited, back
-    # 4 weighted; per iteration their sum plus 20 V.
+    # written; b cleared).  Per stage: forward N E + 4 visited, back
+    # 4 weighted; per iteration their sum plus 20 V.  The forward stage is
+    # timed whole (projection kernel and the pass that forms the ratios), the
+    # back projection by its brick kernel alone.
     visited, weighted = r.count_segments()
     E = 16 if args.storage == "packed" else 32
     V = w.n_voxels
@@ -218,7 +255,8 @@ def main():
     bytes_back = 4 * weighted
     bytes_iter = N * E + 4 * (visited + weighted) + 20 * V
     gbs = lambda b, ms: b / (ms * 1e-3) / 1e9  # noqa: E731
-    kern = {"k_forward": (bytes_fwd, fwd_ms), "k_back_chunks": (bytes_back, backk_ms)}
+    fwd_name = ("k_forward_items+k_combine" if args.forward == "bricks" else "k_block_image+k_forward+k_combine")
+    kern = {fwd_name: (bytes_fwd, fwd_ms), "k_back_chunks": (bytes_back, backk_ms)}
     dom = max(kern, key=lambda k: kern[k][1])
 
     def roof(kname):
@@ -251,12 +289,14 @@ def main():
                              "min": float(np.min(step_ms)), "max": float(np.max(step_ms))},
         "one_time_ms": {k: float(np.mean([t[k] for t in times])) for k in ("load_ms", "sens_ms", "init_ms")},
         "iteration_ms": iter_ms,
-        "kernel_ms": {"project": proj_ms, "k_forward": fwd_ms, "back_stage": back_ms, "k_back_chunks": backk_ms,
+        "kernel_ms": {"project": proj_ms, "forward_stage": fwd_ms,
+                      ("k_forward_items" if args.forward == "bricks" else "k_forward"): fwdk_ms,
+                      "k_combine": fwd_ms - fwdk_ms, "back_stage": back_ms, "k_back_chunks": backk_ms,
                       "update_stage": upd_ms},
         "segments_per_event": {"visited": visited / N, "weighted": weighted / N},
         "last_iteration": {"n_eff": last["n_eff"], "sum_sx": last["sum_sx"], "loglik": last["loglik"]},
         "roofline": roof(dom),
-        "roofline_other": roof("k_back_chunks" if dom == "k_forward" else "k_forward"),
+        "roofline_other": roof("k_back_chunks" if dom == fwd_name else fwd_name),
         "roofline_iteration": {"bound": "hbm", "achieved": gbs(bytes_iter, iter_ms), "peak": HBM_PEAK_GBS,
                                "unit": "GB/s", "frac": gbs(bytes_iter, iter_ms) / HBM_PEAK_GBS,
                                "bytes_per_event_iteration": bytes_iter / N,
@@ -274,7 +314,8 @@ def main():
             r.clear_regions()
             log(f"regions: {out['regions']}")
         if args.storage == "plain":
-            rp = L.Reconstruction(g, device=0, storage=1, **({"events_per_thread": args.ept} if args.ept else {}))
+            rp = L.Reconstruction(g, device=0, storage=1, forward=opts["forward"],
+                                  **({"events_per_thread": args.ept} if args.ept else {}))
             if tuned:
                 rp.set_option("events_per_thread", tuned["events_per_thread"])
             tp, sp = run_form(rp, ev_dev, I, args.form_steps, 1, label="packed ")

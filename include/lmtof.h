@@ -87,6 +87,20 @@ extern "C" {
  * next lmtof_iterate. */
 #define LMTOF_OPT_MEDIAN_SIEVE 8
 
+/* Forward projector of the MLEM iteration and of lmtof_forward_project with
+ * TOF (Section 2.4: f_i = sum_j a_ij x_j; both give the same a_ij):
+ * LMTOF_FORWARD_BRICKS (default): brick-owned.  Every event's window is cut
+ *   into pieces per 16^3-voxel brick at load; a workgroup stages one brick
+ *   of the image in LDS and adds up its pieces' a_ij x_j, and a second pass
+ *   sums each event's pieces in the order its window crosses the bricks.
+ * LMTOF_FORWARD_EVENTS: event-parallel, one GPU lane per event walking its
+ *   whole window, the image read from global memory.
+ * The iteration's back projection is brick-owned either way.  Takes effect
+ * at the next call that projects. */
+#define LMTOF_OPT_FORWARD 9
+#define LMTOF_FORWARD_BRICKS 0
+#define LMTOF_FORWARD_EVENTS 1
+
 /* ------------------------------------------------------------------ types */
 typedef struct lmtof_ctx lmtof_ctx;
 
@@ -114,10 +128,11 @@ typedef struct {
     double loglik;    /* sum_i log (A x^k)_i - sum_j s_j x^k_j over n_eff events */
     float ms;         /* wall time of the iteration on the GPU (ms) */
     float project_ms; /* of which: forward + back projection (ms) */
-    float forward_ms; /* forward projection and ratio kernel (ms) */
+    float forward_ms; /* forward stage: projection, ratios written to the brick items (ms) */
     float back_ms;    /* back projection stage: brick scales, brick kernel, tile reduction (ms) */
     float back_kernel_ms; /* of which the brick back projection kernel alone (ms) */
     float update_ms;  /* image update and statistics (ms) */
+    float forward_kernel_ms; /* of forward_ms, the forward projection kernel alone (ms) */
 } lmtof_iter_stats;
 
 /* ------------------------------------------------------------- lifecycle */

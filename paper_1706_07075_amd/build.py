@@ -1,7 +1,8 @@
 """Build liblmtof.so (HIP, gfx950 only) in-tree.
 
 Each csrc/*.hip file is compiled by hipcc for gfx950 in parallel, then linked
-into paper_1706_07075_amd/liblmtof.so.  Packed-FP32 instruction selection is
+into paper_1706_07075_amd/liblmtof.so; the hardware probes of the benchmark
+go into paper_1706_07075_amd/microbench/libmicrobench.so.  Packed-FP32 instruction selection is
 turned off (-packed-fp32-ops) for every device compile.
 """
 from __future__ import annotations
@@ -18,6 +19,9 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "liblmtof.so")
+# hardware ceilings probed by bench.py --microbench (not part of liblmtof.so)
+MB_SRC = os.path.join(HERE, "microbench", "microbench.hip")
+MB_LIB = os.path.join(HERE, "microbench", "libmicrobench.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -46,8 +50,14 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    tmp = MB_LIB + ".tmp"
+    cmd = [HIPCC] + CFLAGS + ["-shared", MB_SRC, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {MB_SRC}:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, MB_LIB)
     if verbose:
-        print("built", LIB)
+        print("built", LIB, "and", MB_LIB)
     return LIB
 
 

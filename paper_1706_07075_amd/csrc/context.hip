@@ -25,9 +25,10 @@ constexpr double kDefaultC = 0.299792458;
 constexpr int kDefaultEpt = 4;
 constexpr float kAutotuneIters = 10.0f;  // iterations a reconstruction is assumed to run
 constexpr double kTofRejectZ = 1.959964;  // two-sided 95 % quantile of the normal distribution
-// Event records per graph-replayed iteration: start, after forward, after
-// brick scales, after brick back projection, after tile reduction, end.
-constexpr int kEventsPerIter = 6;
+// Event records per graph-replayed iteration: start, after the forward
+// kernel, after the forward stage (ratios on the items), after brick
+// scales, after brick back projection, after tile reduction, end.
+constexpr int kEventsPerIter = 7;
 
 struct GraphEntry {
     hipGraph_t graph = nullptr;
@@ -52,7 +53,11 @@ struct Scratch {
 // per non-empty brick its tile slots (brick, first slot, end slot); the
 // tile scratch (one 16^3 FP32 tile per slot).
 struct ItemSet {
-    uint32_t *items = nullptr;
+    float *pw = nullptr;  // per item: forward partial, then its event's back-projection weight
+    // per event (the problems' events, stored order): first entry of its
+    // item positions in evitems (+ 1 entry); the positions in brick order
+    uint32_t *evoff = nullptr, *evitems = nullptr;
+    uint32_t *scan_tmp = nullptr;
     uint4 *chunks = nullptr, *bricks = nullptr;
     unsigned long long *tiles = nullptr;
     float *wmax = nullptr;
@@ -65,8 +70,9 @@ struct ItemSet {
     // capacities (elements) of every array above: the lists are rebuilt in
     // place and a buffer is only reallocated when it has to grow, so
     // reloading events of a similar size allocates and frees nothing
-    size_t items_cap = 0, item_recs_cap = 0, tiles_cap = 0, pairs_cap = 0, chunks_cap = 0, bricks_cap = 0,
-           wmax_cap = 0, pair_off_cap = 0, cnt_cap = 0, off_cap = 0, pcnt_cap = 0, tabs_cap = 0;
+    size_t pw_cap = 0, evoff_cap = 0, evitems_cap = 0, scan_cap = 0, item_recs_cap = 0, tiles_cap = 0,
+           pairs_cap = 0, chunks_cap = 0, bricks_cap = 0, wmax_cap = 0, pair_off_cap = 0, cnt_cap = 0, off_cap = 0,
+           pcnt_cap = 0, tabs_cap = 0;
     uint32_t n_chunks = 0, n_bricks = 0, n_slots = 0;
     uint64_t n_items = 0, n_pairs = 0;
     std::vector<uint4> h_chunks, h_bricks;  // host copies (batching several problems)
@@ -82,6 +88,7 @@ struct lmtof_ctx {
 
     // options
     int opt_storage = 0, opt_sort = 1, opt_nphi = 2048, opt_ept = 0, opt_median = 0;
+    int opt_forward = LMTOF_FORWARD_BRICKS;
     double opt_cell_mm = 16.0;
 
     bool has_geom = false;
@@ -209,7 +216,10 @@ void scratch_free(Scratch &s) {
 }
 
 void free_items(ItemSet &it) {
-    dev_free(it.items);
+    dev_free(it.pw);
+    dev_free(it.evoff);
+    dev_free(it.evitems);
+    dev_free(it.scan_tmp);
     dev_free(it.chunks);
     dev_free(it.bricks);
     dev_free(it.tiles);
@@ -235,14 +245,19 @@ void invalidate_items(ItemSet &it) {
 }
 
 // Destroy the instantiated iteration graphs (they hold the buffer addresses
-// and launch sizes of the current batch).  Device buffers are kept.
-void drop_graphs(lmtof_ctx *c) {
+// and launch sizes of the current batch, and its kernel sequence).
+void drop_graphs_only(lmtof_ctx *c) {
     for (auto &kv : c->graphs) {
         if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
         if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
         for (hipEvent_t e : kv.second.ev) (void)hipEventDestroy(e);
     }
     c->graphs.clear();
+}
+
+// ... and mark the brick lists stale.  Device buffers are kept.
+void drop_graphs(lmtof_ctx *c) {
+    drop_graphs_only(c);
     invalidate_items(c->items);
 }
 
@@ -439,18 +454,28 @@ int build_items(lmtof_ctx *c, std::vector<Problem> &ps, Problem *d_probs, int64_
         nb += n;
     }
     const uint64_t nk = nb * kItemClasses;  // (brick, item class) keys
+    // per-event item offsets over the stored events the problems cover
+    int64_t ne = 0;
+    for (const auto &P : ps) ne = std::max<int64_t>(ne, P.ev_offset + P.n_events);
     Launch L;
     L.stream = c->stream;
     int rc;
     if ((rc = reserve(c, &it.cnt, it.cnt_cap, nk + 1)) || (rc = reserve(c, &it.pcnt, it.pcnt_cap, nb + 1)) ||
         (rc = reserve(c, &it.tabs, it.tabs_cap, (size_t)brick_item_tab_words(n_chunks))) ||
-        (rc = reserve(c, &it.off_d, it.off_cap, nk + 1)) || (rc = reserve(c, &it.pair_off, it.pair_off_cap, nb + 1)))
+        (rc = reserve(c, &it.off_d, it.off_cap, nk + 1)) || (rc = reserve(c, &it.pair_off, it.pair_off_cap, nb + 1)) ||
+        (rc = reserve(c, &it.evoff, it.evoff_cap, (size_t)ne + 1)) ||
+        (rc = reserve(c, &it.scan_tmp, it.scan_cap, (size_t)scan_tmp_elems(ne + 1))))
         return rc;
+    for (auto &P : ps) P.evoff = it.evoff + P.ev_offset;
     std::vector<uint32_t> hk(nk), hp(nb);
-    hipError_t he = hipMemsetAsync(it.cnt, 0, sizeof(uint32_t) * (nk + 1), c->stream);
+    hipError_t he = hipMemcpyAsync(d_probs, ps.data(), sizeof(Problem) * ps.size(), hipMemcpyHostToDevice, c->stream);
+    if (he == hipSuccess) he = hipMemsetAsync(it.cnt, 0, sizeof(uint32_t) * (nk + 1), c->stream);
     if (he == hipSuccess) he = hipMemsetAsync(it.pcnt, 0, sizeof(uint32_t) * (nb + 1), c->stream);
+    if (he == hipSuccess) he = hipMemsetAsync(it.evoff, 0, sizeof(uint32_t) * ((size_t)ne + 1), c->stream);
     if (he == hipSuccess)
         he = launch_brick_items(L, d_probs, (int)ps.size(), n_chunks, ept, it.cnt, nullptr, it.pcnt, 0, it.tabs);
+    // each event's item count -> the first entry of its positions
+    if (he == hipSuccess) he = launch_exclusive_scan(L, it.evoff, ne + 1, it.scan_tmp);
     if (he == hipSuccess) he = hipMemcpyAsync(hk.data(), it.cnt, sizeof(uint32_t) * nk, hipMemcpyDeviceToHost, c->stream);
     if (he == hipSuccess) he = hipMemcpyAsync(hp.data(), it.pcnt, sizeof(uint32_t) * nb, hipMemcpyDeviceToHost, c->stream);
     if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
@@ -494,14 +519,17 @@ int build_items(lmtof_ctx *c, std::vector<Problem> &ps, Problem *d_probs, int64_
     }
     std::stable_sort(chunks.begin(), chunks.end(),
                      [](const uint4 &a, const uint4 &b) { return (a.z - a.y) > (b.z - b.y); });
-    if ((rc = reserve(c, &it.items, it.items_cap, tot)) || (rc = reserve(c, &it.chunks, it.chunks_cap, chunks.size())) ||
+    if ((rc = reserve(c, &it.pw, it.pw_cap, tot)) || (rc = reserve(c, &it.evitems, it.evitems_cap, tot)) ||
+        (rc = reserve(c, &it.chunks, it.chunks_cap, chunks.size())) ||
         (rc = reserve(c, &it.bricks, it.bricks_cap, bricks.size())) ||
         (rc = reserve(c, &it.tiles, it.tiles_cap, (size_t)slot * kBrickVox)) ||
         (rc = reserve(c, &it.wmax, it.wmax_cap, slot)) || (rc = reserve(c, &it.pairs, it.pairs_cap, ptot)) ||
         (rc = reserve(c, &it.item_recs, it.item_recs_cap, (size_t)tot * kItemRecBytes)))
         return rc;
     for (auto &P : ps) {
-        P.items = it.items;
+        P.pw = it.pw;
+        P.n_items = (uint32_t)tot;
+        P.evitems = it.evitems;
         P.tiles = it.tiles;
         P.wmax = it.wmax;
         P.pairs = it.pairs;
@@ -625,10 +653,15 @@ int ensure_problems(lmtof_ctx *c) {
     c->probs = ps;
     c->ept_used = ept;
     if (c->has_evw) {
+        // the ratio weights in stored order, applied where the ratios are
+        // written to the items
         if ((rc = reserve(c, &c->d_evw, c->evw_stored_cap, (size_t)c->n_events))) return rc;
         Launch Lw;
         Lw.stream = c->stream;
         HIPCHK(c, launch_gather_by_perm(Lw, c->d_evw_caller, c->d_perm, c->n_events, c->d_evw));
+        for (auto &P : ps) P.evw = c->d_evw + P.ev_offset;
+        HIPCHK(c, hipMemcpyAsync(c->d_probs, ps.data(), sizeof(Problem) * ps.size(), hipMemcpyHostToDevice, c->stream));
+        c->probs = ps;
     }
     if ((size_t)c->n_chunks > c->part_cap) {
         dev_free(c->d_part_neff);
@@ -662,13 +695,55 @@ int ensure_stats(lmtof_ctx *c, size_t n) {
     return LMTOF_OK;
 }
 
+// Forward stage of an MLEM iteration over the batch (graph nodes after
+// *prev, or on the stream): the brick-owned forward pass and the combine
+// pass (ratios written to the items), or the event-parallel pass and the
+// pass that writes its ratios to the items.  ev_mid (graphs only) is
+// recorded between the two.
+int add_forward(lmtof_ctx *c, Launch L, const Problem *d_probs, int np, int64_t n_chunks, int64_t n_xblk,
+                const ItemSet &it, int ept, int *part_neff, double *part_ll, float *part_wmax, hipGraphNode_t *prev,
+                hipEvent_t ev_mid = nullptr) {
+    const bool tof = c->g.tof_fwhm_ps > 0;
+    hipGraphNode_t node = nullptr;
+    auto chain = [&]() {
+        if (L.graph && node) *prev = node;
+        L.deps = prev;
+        node = nullptr;
+    };
+    if (L.graph) {
+        L.deps = prev;
+        L.n_deps = 1;
+        L.node = &node;
+    }
+    if (c->opt_forward == LMTOF_FORWARD_BRICKS) {
+        HIPCHK(c, launch_forward_items(L, tof, d_probs, np, it.chunks, it.n_chunks, it.bricks));
+        chain();
+    } else {
+        HIPCHK(c, launch_block_image(L, d_probs, np, n_xblk));
+        chain();
+        HIPCHK(c, launch_forward(L, tof, d_probs, np, n_chunks, ept, 0, part_neff, part_ll, part_wmax));
+        chain();
+    }
+    if (L.graph && ev_mid) {
+        hipGraphNode_t n = nullptr;
+        HIPCHK(c, hipGraphAddEventRecordNode(&n, L.graph, prev, 1, ev_mid));
+        *prev = n;
+        L.deps = prev;
+    }
+    HIPCHK(c, launch_combine(L, d_probs, np, n_chunks, ept,
+                             c->opt_forward == LMTOF_FORWARD_BRICKS ? kCombineRatio : kCombineWeights, part_neff,
+                             part_ll, part_wmax));
+    chain();
+    return LMTOF_OK;
+}
+
 // n_iter MLEM iterations as one explicit HIP graph.  Per iteration: event
-// record, forward + ratio, event record, brick scales, event record, brick
-// back projection, event record, tile reduction, event record, update,
-// finalize (stats of iteration k into slot k), event record.
+// record, forward kernel, event record, combine, event record, brick
+// scales, event record, brick back projection, event record, tile
+// reduction, event record, update, finalize (stats of iteration k into
+// slot k), [median sieve], event record.
 int build_graph(lmtof_ctx *c, int n_iter, GraphEntry &ge) {
     const int np = (int)c->probs.size();
-    const bool tof = c->g.tof_fwhm_ps > 0;
     HIPCHK(c, hipGraphCreate(&ge.graph, 0));
     ge.ev.assign(kEventsPerIter * n_iter, nullptr);
     for (auto &e : ge.ev) HIPCHK(c, hipEventCreate(&e));
@@ -683,38 +758,21 @@ int build_graph(lmtof_ctx *c, int n_iter, GraphEntry &ge) {
     };
     for (int k = 0; k < n_iter; ++k) {
         int rc;
-        if ((rc = record(ge.ev[kEventsPerIter * k]))) return rc;
-        hipGraphNode_t node = nullptr;
+        hipEvent_t *e = &ge.ev[(size_t)kEventsPerIter * k];
+        if ((rc = record(e[0]))) return rc;
         Launch L;
         L.graph = ge.graph;
+        if ((rc = add_forward(c, L, c->d_probs, np, c->n_chunks, c->n_xblk, c->items, c->ept_used, c->d_part_neff,
+                              c->d_part_ll, c->d_part_wmax, &prev, e[1])))
+            return rc;
+        if ((rc = record(e[2]))) return rc;
+        if ((rc = add_back(c, L, c->d_probs, np, c->items, c->d_part_wmax, c->n_chunks, &prev, e[3], e[4])))
+            return rc;
+        if ((rc = record(e[5]))) return rc;
+        hipGraphNode_t node = nullptr;
         L.deps = &prev;
         L.n_deps = 1;
         L.node = &node;
-        HIPCHK(c, launch_block_image(L, c->d_probs, np, c->n_xblk));
-        if (node) prev = node;
-        L.deps = &prev;
-        node = nullptr;
-        HIPCHK(c, launch_forward(L, tof, c->d_probs, np, c->n_chunks, c->ept_used, 0, c->d_part_neff, c->d_part_ll,
-                                 c->d_part_wmax));
-        if (node) prev = node;
-        if (c->has_evw) {
-            // weighted ratios w_i / f_i, and the chunk maxima the brick scales use
-            L.deps = &prev;
-            node = nullptr;
-            HIPCHK(c, launch_mul(L, c->d_rw, c->d_evw, c->n_events));
-            if (node) prev = node;
-            L.deps = &prev;
-            node = nullptr;
-            HIPCHK(c, launch_chunk_absmax(L, c->d_probs, np, c->n_chunks, c->ept_used, c->d_part_wmax));
-            if (node) prev = node;
-        }
-        if ((rc = record(ge.ev[kEventsPerIter * k + 1]))) return rc;
-        if ((rc = add_back(c, L, c->d_probs, np, c->items, c->d_part_wmax, c->n_chunks, &prev, ge.ev[kEventsPerIter * k + 2],
-                           ge.ev[kEventsPerIter * k + 3])))
-            return rc;
-        if ((rc = record(ge.ev[kEventsPerIter * k + 4]))) return rc;
-        L.deps = &prev;
-        node = nullptr;
         HIPCHK(c, launch_update(L, c->d_probs, np, c->n_vchunks, c->d_part_old, c->d_part_new));
         if (node) prev = node;
         L.deps = &prev;
@@ -735,7 +793,7 @@ int build_graph(lmtof_ctx *c, int n_iter, GraphEntry &ge) {
                 if (node) prev = node;
             }
         }
-        if ((rc = record(ge.ev[kEventsPerIter * k + 5]))) return rc;
+        if ((rc = record(e[6]))) return rc;
     }
     HIPCHK(c, hipGraphInstantiate(&ge.exec, ge.graph, nullptr, nullptr, 0));
     return LMTOF_OK;
@@ -841,7 +899,8 @@ int64_t ctx_device_bytes(const lmtof_ctx *c) {
                               &c->sc_inner, &c->sc_reg, &c->sc_raw})
         b += (int64_t)sc->cap;
     b += (int64_t)c->reg_cap;
-    b += (int64_t)it.items_cap * 4 + (int64_t)it.item_recs_cap + (int64_t)it.tiles_cap * 8 + (int64_t)it.pairs_cap * 4;
+    b += (int64_t)(it.pw_cap + it.evitems_cap + it.evoff_cap + it.scan_cap) * 4 + (int64_t)it.item_recs_cap +
+         (int64_t)it.tiles_cap * 8 + (int64_t)it.pairs_cap * 4;
     b += (int64_t)(it.chunks_cap + it.bricks_cap) * 16;
     b += (int64_t)(it.wmax_cap + it.pair_off_cap + it.cnt_cap + it.off_cap + it.pcnt_cap + it.tabs_cap) * 4;
     b += (int64_t)(c->evw_cap + c->evw_stored_cap) * 4;
@@ -850,8 +909,8 @@ int64_t ctx_device_bytes(const lmtof_ctx *c) {
 }
 
 // Footprint the pool reserves for a request: stored events, permutation,
-// weights, ~ (1 + 1.7 * window / brick edge) brick items per event (index
-// and walk record) plus tiles, three images, and the transient ingest
+// weights, ~ (1 + 1.7 * window / brick edge) brick items per event (walk
+// record, weight, position) plus tiles, three images, and the transient ingest
 // buffers (raw copy, keys, sort histogram).
 int64_t request_bytes_estimate(const lmtof_request &q) {
     const lmtof_geometry &g = q.geometry;
@@ -874,7 +933,9 @@ int64_t request_bytes_estimate(const lmtof_request &q) {
         return q2;
     };
     const int64_t xbv = pow2((g.nx + 3) / 4) * pow2((g.ny + 3) / 4) * ((g.nz + 3) / 4) * 64;  // blocked copy of x
-    int64_t b = N * (esz + 8 + 4) + items * (4 + kItemRecBytes) + 3 * 4 * V + 4 * xbv;  // x, b, s, blocked x
+    // per event: store, permutation, weight, item offset; per item: walk
+    // record, weight, position in its event's list; x, b, s, blocked x
+    int64_t b = N * (esz + 8 + 4 + 4) + items * (8 + kItemRecBytes) + 3 * 4 * V + 4 * xbv;
     b += (items / 2048 + 1 + V / kBrickVox + 1) * (int64_t)kBrickVox * 8 / 4;  // tiles
     b += items;  // (forward chunk, brick) pairs: at most one per item, ~1 in 10 in practice
     // transients: the ingest's, then (not at the same time) the brick list
@@ -1013,16 +1074,14 @@ int lmtof_set_option(lmtof_ctx *c, int key, int64_t v) {
         return LMTOF_OK;
     case LMTOF_OPT_MEDIAN_SIEVE:
         if (v != 0 && v != 1) return fail(c, LMTOF_EINVAL, "median sieve must be 0 or 1");
-        if ((int)v != c->opt_median) {
-            // the iteration graphs change; the brick lists stay
-            for (auto &kv : c->graphs) {
-                if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
-                if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
-                for (hipEvent_t e : kv.second.ev) (void)hipEventDestroy(e);
-            }
-            c->graphs.clear();
-        }
+        if ((int)v != c->opt_median) drop_graphs_only(c);  // the brick lists stay
         c->opt_median = (int)v;
+        return LMTOF_OK;
+    case LMTOF_OPT_FORWARD:
+        if (v != LMTOF_FORWARD_BRICKS && v != LMTOF_FORWARD_EVENTS)
+            return fail(c, LMTOF_EINVAL, "forward projector must be LMTOF_FORWARD_BRICKS or LMTOF_FORWARD_EVENTS");
+        if ((int)v != c->opt_forward) drop_graphs_only(c);  // the brick lists stay
+        c->opt_forward = (int)v;
         return LMTOF_OK;
     default:
         return fail(c, LMTOF_EINVAL, "unknown option %d", key);
@@ -1038,6 +1097,7 @@ int lmtof_get_option(const lmtof_ctx *c, int key, int64_t *v) {
     case LMTOF_OPT_EVENTS_PER_THREAD: *v = c->opt_ept > 0 ? c->opt_ept : kDefaultEpt; return LMTOF_OK;
     case LMTOF_OPT_SORT_CELL_MM: *v = (int64_t)c->opt_cell_mm; return LMTOF_OK;
     case LMTOF_OPT_MEDIAN_SIEVE: *v = c->opt_median; return LMTOF_OK;
+    case LMTOF_OPT_FORWARD: *v = c->opt_forward; return LMTOF_OK;
     default: return LMTOF_EINVAL;
     }
 }
@@ -1352,11 +1412,12 @@ int lmtof_iterate(lmtof_ctx *c, int n_iter, lmtof_iter_stats *stats) {
                     float t = 0;
                     return hipEventElapsedTime(&t, e[a], e[b]) == hipSuccess ? t : 0.0f;
                 };
-                o.ms = span(0, 5);
-                o.forward_ms = span(0, 1);
-                o.back_ms = span(1, 4);
-                o.back_kernel_ms = span(2, 3);
-                o.update_ms = span(4, 5);
+                o.ms = span(0, 6);
+                o.forward_ms = span(0, 2);
+                o.forward_kernel_ms = span(0, 1);
+                o.back_ms = span(2, 5);
+                o.back_kernel_ms = span(3, 4);
+                o.update_ms = span(5, 6);
                 o.project_ms = o.forward_ms + o.back_ms;
                 (void)hipGetLastError();
             }
@@ -1382,6 +1443,7 @@ static int forward_events(lmtof_ctx *c, const float *x, int64_t nx_, float *f, i
     L.stream = c->stream;
     float *dx = nullptr, *fs = nullptr, *fc = nullptr, *xb = nullptr;
     Problem *dp = nullptr;
+    ItemSet its;
     int rc = LMTOF_OK;
     auto done = [&](int r) {
         (void)hipStreamSynchronize(c->stream);
@@ -1389,6 +1451,7 @@ static int forward_events(lmtof_ctx *c, const float *x, int64_t nx_, float *f, i
         dev_free(fs);
         dev_free(xb);
         dev_free(dp);
+        free_items(its);
         return r;
     };
     if (mem == LMTOF_MEM_HOST) {
@@ -1407,13 +1470,22 @@ static int forward_events(lmtof_ctx *c, const float *x, int64_t nx_, float *f, i
     int block, ept;
     launch_shape(c, block, ept);
     int64_t nch, nvch;
-    const int64_t nxb = assign_xblocks(ps, nullptr);
-    if ((rc = dev_alloc(c, &xb, nxb * 64))) return done(rc);
-    assign_xblocks(ps, xb);
-    if ((rc = upload_problems(c, ps, block, ept, &dp, nch, nvch))) return done(rc);
-    hipError_t he = hipMemsetAsync(xb, 0, sizeof(float) * 64 * (size_t)nxb, c->stream);
-    if (he == hipSuccess) he = launch_block_image(L, dp, 1, nxb);
-    if (he == hipSuccess) he = launch_forward(L, tof, dp, 1, nch, ept, 1, nullptr, nullptr, nullptr);
+    hipError_t he = hipSuccess;
+    if (tof && c->opt_forward == LMTOF_FORWARD_BRICKS) {
+        // the MLEM iteration's projector: brick lists for this one problem
+        if ((rc = upload_problems(c, ps, block, ept, &dp, nch, nvch)) || (rc = build_items(c, ps, dp, nch, ept, its)))
+            return done(rc);
+        he = launch_forward_items(L, true, dp, 1, its.chunks, its.n_chunks, its.bricks);
+        if (he == hipSuccess) he = launch_combine(L, dp, 1, nch, ept, kCombineF, nullptr, nullptr, nullptr);
+    } else {
+        const int64_t nxb = assign_xblocks(ps, nullptr);
+        if ((rc = dev_alloc(c, &xb, nxb * 64))) return done(rc);
+        assign_xblocks(ps, xb);
+        if ((rc = upload_problems(c, ps, block, ept, &dp, nch, nvch))) return done(rc);
+        he = hipMemsetAsync(xb, 0, sizeof(float) * 64 * (size_t)nxb, c->stream);
+        if (he == hipSuccess) he = launch_block_image(L, dp, 1, nxb);
+        if (he == hipSuccess) he = launch_forward(L, tof, dp, 1, nch, ept, 1, nullptr, nullptr, nullptr);
+    }
     if (he == hipSuccess && acf) he = launch_exp(L, fs, c->n_events);
     if (he == hipSuccess) he = launch_scatter_by_perm(L, fs, c->d_perm, c->n_events, fc);
     if (he != hipSuccess) return done(fail(c, LMTOF_EHIP, "forward projection: %s", hipGetErrorString(he)));
@@ -1661,7 +1733,8 @@ int lmtof_back_project(lmtof_ctx *c, const float *w, int64_t nw, float *b, int64
     if ((rc = build_items(c, ps, dp, nch, ept, its)) || (rc = dev_alloc(c, &pw, nch))) return done(rc);
     hipError_t he = launch_gather_by_perm(L, dw, c->d_perm, c->n_events, ws);
     if (he == hipSuccess) he = launch_fill(L, db, c->V, 0.0f);
-    if (he == hipSuccess) he = launch_chunk_absmax(L, dp, 1, nch, ept, pw);
+    // each event's weight onto its items, and the chunk maxima of |w|
+    if (he == hipSuccess) he = launch_combine(L, dp, 1, nch, ept, kCombineWeights, nullptr, nullptr, pw);
     if (he != hipSuccess) return done(fail(c, LMTOF_EHIP, "back projection: %s", hipGetErrorString(he)));
     if ((rc = add_back(c, L, dp, 1, its, pw, nch, nullptr))) return done(rc);
     if (mem == LMTOF_MEM_HOST) rc = copy_out(c, b, db, sizeof(float) * c->V, LMTOF_MEM_HOST);
@@ -1676,7 +1749,6 @@ int lmtof_autotune(lmtof_ctx *c, int64_t *chosen, float *ms) {
     HIPCHK(c, hipSetDevice(c->device));
     static const int cand[4] = {1, 2, 4, 8};
     const int saved = c->opt_ept;
-    const bool tof = c->g.tof_fwhm_ps > 0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     auto cleanup = [&](int rc) {
         if (e0) (void)hipEventDestroy(e0);
@@ -1702,16 +1774,14 @@ int lmtof_autotune(lmtof_ctx *c, int64_t *chosen, float *ms) {
         const int np = (int)c->probs.size();
         Launch L;
         L.stream = c->stream;
-        if (launch_block_image(L, c->d_probs, np, c->n_xblk) != hipSuccess)
-            return cleanup(fail(c, LMTOF_EHIP, "autotune: image relayout failed"));
         float t = 0.0f;
         // the first pass warms caches and code; the fastest of the next three counts
         for (int rep = 0; rep < 4; ++rep) {
             hipError_t he = hipEventRecord(e0, c->stream);
-            if (he == hipSuccess)
-                he = launch_forward(L, tof, c->d_probs, np, c->n_chunks, c->ept_used, 0, c->d_part_neff,
-                                    c->d_part_ll, c->d_part_wmax);
             if (he != hipSuccess) return cleanup(fail(c, LMTOF_EHIP, "autotune: %s", hipGetErrorString(he)));
+            if ((rc = add_forward(c, L, c->d_probs, np, c->n_chunks, c->n_xblk, c->items, c->ept_used,
+                                  c->d_part_neff, c->d_part_ll, c->d_part_wmax, nullptr)))
+                return cleanup(rc);
             if ((rc = add_back(c, L, c->d_probs, np, c->items, c->d_part_wmax, c->n_chunks, nullptr))) return cleanup(rc);
             float tr = 0.0f;
             if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
@@ -2249,8 +2319,9 @@ int lmtof_pool_step(lmtof_pool *p, int *n_active) {
     const bool tof = p->batch[0].tof != 0;  // submit keeps a batch all-TOF or all-non-TOF
     Launch L;
     L.stream = p->stream;
-    PHIP(p, launch_block_image(L, p->d_probs, np, p->n_xblk));
-    PHIP(p, launch_forward(L, tof, p->d_probs, np, p->n_chunks, p->ept, 0, p->part_neff, p->part_ll, p->part_wmax));
+    PHIP(p, launch_forward_items(L, tof, p->d_probs, np, p->d_chunks, p->n_bchunks, p->d_bricks));
+    PHIP(p, launch_combine(L, p->d_probs, np, p->n_chunks, p->ept, kCombineRatio, p->part_neff, p->part_ll,
+                           p->part_wmax));
     PHIP(p, launch_brick_wmax(L, p->d_probs, np, p->d_bricks, p->n_bbricks, p->part_wmax, p->n_chunks));
     PHIP(p, launch_back_chunks(L, tof, p->d_probs, np, p->d_chunks, p->n_bchunks, p->d_bricks));
     PHIP(p, launch_reduce_tiles(L, p->d_probs, np, p->d_bricks, p->n_bbricks));

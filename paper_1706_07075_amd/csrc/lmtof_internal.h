@@ -34,8 +34,18 @@ struct Problem {
     float *x;             // image (nx*ny*nz)
     float *b;             // back-projection accumulator, zero between iterations
     const float *s;       // sensitivity
-    float *rw;            // per event of this problem: 1 / f (MLEM) or a back-projection weight
-    const uint32_t *items;// brick item list array (problem-local event indices) the chunks index
+    float *rw;            // per event of this problem: 1 / f or f (event-parallel forward), or a caller's weight
+    const float *evw;     // per event of this problem: ratio weight (attenuation correction), or NULL
+    // Brick items (the pieces of the events' windows inside 16^3-voxel
+    // bricks), at positions the chunks index: per item its forward partial
+    // sum of a x over the piece, replaced by its event's back-projection
+    // weight before the back projection reads it
+    float *pw;
+    uint32_t n_items;     // items of the item set this problem's positions index
+    // item positions of each event, in the order its window crosses the
+    // bricks: evitems[evoff[i] .. evoff[i + 1]) for problem-local event i
+    const uint32_t *evoff;
+    const uint32_t *evitems;
     // per item, its walk inside the brick, precomputed when the lists are
     // built: (A_x, A_y, A_z, t_a), (B_x, B_y, B_z, t_b), (k_x | k_y << 16,
     // k_z | local voxel << 16) with k the first plane index minus the anchor
@@ -109,32 +119,48 @@ inline hipError_t do_launch(const Launch &L, const void *func, dim3 grid, dim3 b
 
 // ---- projector (project.hip)
 int64_t project_chunk_events(int block, int ept);
-// Forward projection per event into P.rw; mode 0: 1 / f (0 if f <= 0) and
-// per-chunk partials (n_eff, sum log f, largest 1 / f); mode 1: f.
+// Event-parallel forward projection per event into P.rw, gathering from
+// the blocked image copy P.xb; mode 0: 1 / f (0 if f <= 0) and per-chunk
+// partials (n_eff, sum log f, largest 1 / f); mode 1: f.
 hipError_t launch_forward(const Launch &L, bool tof, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept,
                           int mode, int *part_neff, double *part_ll, float *part_wmax);
+// Brick-owned forward projection: every brick chunk (see the back
+// projection) stages its brick of P.x in LDS and writes each item's partial
+// sum of a x to P.pw.
+hipError_t launch_forward_items(const Launch &L, bool tof, const Problem *d_probs, int n_probs, const uint4 *chunks,
+                                uint32_t n_chunks, const uint4 *bricks);
+// Per event (forward chunks of the launch shape of launch_forward), over
+// its items' positions evitems[evoff[i] .. evoff[i + 1]):
+//   kCombineRatio: f = sum of the items' partials P.pw; w = 1 / f (0 if
+//     f <= 0), times P.evw[i] if set, written back to every item of the
+//     event; per-chunk partials as launch_forward mode 0 (largest |w|);
+//   kCombineF: P.rw[i] = f;
+//   kCombineWeights: w = P.rw[i], times P.evw[i] if set, written to every
+//     item of the event; part_wmax[chunk] = largest |w|.
+enum { kCombineRatio = 0, kCombineF = 1, kCombineWeights = 2 };
+hipError_t launch_combine(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept, int mode,
+                          int *part_neff, double *part_ll, float *part_wmax);
 // Back projection by brick chunks.  Brick table entry (global brick id,
 // first tile slot, end tile slot, items in the brick); chunk (brick table
-// index, first item, end item, tile slot) over P.items / P.tiles of the
-// brick's problem with weights P.rw.  launch_brick_wmax (per-brick bound
+// index, first item, end item, tile slot) over the items of the brick's
+// problem with their weights P.pw.  launch_brick_wmax (per-brick bound
 // on |w| from the forward chunks' maxima part_wmax[0, n_part)), then
 // launch_back_chunks, then launch_reduce_tiles (which writes every voxel of
 // the listed bricks of P.b).
 hipError_t launch_brick_wmax(const Launch &L, const Problem *d_probs, int n_probs, const uint4 *bricks,
                              uint32_t n_bricks, const float *part_wmax, int64_t n_part);
-// part_wmax[c] = largest |P.rw| over forward chunk c's events.
-hipError_t launch_chunk_absmax(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept,
-                               float *part_wmax);
 hipError_t launch_back_chunks(const Launch &L, bool tof, const Problem *d_probs, int n_probs, const uint4 *chunks,
                               uint32_t n_chunks, const uint4 *bricks);
 hipError_t launch_reduce_tiles(const Launch &L, const Problem *d_probs, int n_probs, const uint4 *bricks,
                                uint32_t n_bricks);
 // Brick item lists, keyed by global brick * kItemClasses + item class.
-// fill == 0 counts pieces per key into ctr and (forward chunk, brick) pairs
-// per global brick into pctr (one per chunk touching the brick); else writes
-// problem-local event indices to P.items at ctr[key]++ (never past end[key])
-// and problem-local forward chunk indices to P.pairs at pctr[brick]++ (never
-// past the brick's P.pair_off end).  Same launch shape as the forward pass
+// fill == 0 counts pieces per key into ctr, (forward chunk, brick) pairs
+// per global brick into pctr (one per chunk touching the brick) and each
+// event's pieces into P.evoff[i]; else writes every piece's walk record at
+// position ctr[key]++ (never past end[key]), the position to
+// P.evitems[P.evoff[i] + k] for the event's k-th piece, and problem-local
+// forward chunk indices to P.pairs at pctr[brick]++ (never past the brick's
+// P.pair_off end).  Same launch shape as the forward pass
 // (its chunks are the pairs' chunks).  Every problem has at most
 // kMaxProblemBricks bricks.  tabs (brick_item_tab_words(n_chunks) words)
 // carries each block's key table from the counting launch to the filling one.

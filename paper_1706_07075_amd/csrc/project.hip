@@ -24,14 +24,21 @@
 //    value and the first- and second-order Taylor coefficients, so one LDS
 //    read and two FMAs give Phi to ~2e-9, with no divergent branch (the back
 //    projection keeps 8-byte nodes and derives the second-order term).
-//  * Forward + ratio is event-parallel: one lane per event, events bucketed
-//    at load so a wavefront traces near-parallel, co-located rays and its
-//    image gathers coalesce; the lane keeps f_i and writes r_i = 1 / f_i.
-//  * Back projection is brick-parallel.  At load every event's window is cut
-//    into pieces per 16^3-voxel brick (item lists), and each brick's list
-//    into chunks of bounded length.  One workgroup takes one chunk: it
-//    accumulates a_ij r_i with LDS atomics and writes its tile with plain
-//    stores; a small kernel adds a brick's chunk tiles into b.  There is no
+//  * Both projections are brick-parallel.  At load every event's window is
+//    cut into pieces per 16^3-voxel brick (items), and each brick's list
+//    into chunks of bounded length.  One workgroup takes one chunk.
+//  * Forward: the workgroup stages its brick of x in LDS, so every image
+//    gather of its items is an LDS read, and writes each item's partial sum
+//    of a x; a combine pass adds an event's partials (in the order its
+//    window crosses the bricks), forms r_i = 1 / f_i and writes r_i back to
+//    the event's items, where the back projection reads it coalesced.  (An
+//    event-parallel forward pass, one lane per event gathering from a
+//    blocked copy of x in global memory, is kept for the testing surface
+//    and as a launch option: it is bound by the texture units' per-line
+//    work, ~50 distinct cache lines per wavefront gather.)
+//  * Back: the workgroup accumulates a_ij r_i with LDS atomics and writes
+//    its tile with plain stores; a small kernel adds a brick's chunk tiles
+//    into b.  There is no
 //    global atomic on the image (device-scope FP32 atomics sustain only
 //    ~21 G/s on this part, a third of a random gather's rate).  Chunks are
 //    launched largest first so the uneven work balances across CUs, and a
@@ -677,29 +684,6 @@ __global__ void __launch_bounds__(64) k_brick_wmax(const Problem *__restrict__ p
     if (threadIdx.x == 0) global(P.wmax)[br.y] = wm;
 }
 
-// Largest |w| over each forward chunk's events (for weights that do not
-// come from the forward pass, e.g. a caller's back-projection weights).
-__global__ void __launch_bounds__(kForwardBlock) k_chunk_absmax(const Problem *__restrict__ probs, int n_probs,
-                                                                int ept, float *__restrict__ part_wmax) {
-    __shared__ float s_w[kForwardBlock / 64];
-    const int64_t c = blockIdx.x;
-    const Problem &P = probs[find_problem(probs, n_probs, c)];
-    const int64_t base = (c - P.chunk_begin) * (int64_t)blockDim.x * ept;
-    float wm = 0.0f;
-    for (int e = 0; e < ept; ++e) {
-        const int64_t i = base + (int64_t)e * blockDim.x + threadIdx.x;
-        if (i < P.n_events) wm = fmaxf(wm, fabsf(P.rw[i]));
-    }
-    wm = wave_max(wm);
-    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = wm;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        float tw = 0.0f;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tw = fmaxf(tw, s_w[w]);
-        part_wmax[c] = tw;
-    }
-}
-
 // Fixed-point exponent of a brick (same value in every chunk and the reduce).
 __device__ __forceinline__ int brick_exponent(const Problem &P, const uint4 &br, float &wmax) {
     const float wm = P.wmax[br.y];
@@ -749,27 +733,20 @@ __device__ __forceinline__ void back_item(const f32x4 &ra, const f32x4 &rb, cons
 template <bool TOF>
 __device__ __forceinline__ void back_chunk_items(const Problem &P, const uint4 &ch, float S, const Cdf2 &cdf,
                                                  unsigned long long *tile) {
-    const gptr<const uint32_t> items = global(P.items);
-    const gptr<const float> w = global(P.rw);
+    const gptr<const float> w = global(P.pw);
     const gptr<const f32x4> rec_a = global(reinterpret_cast<const f32x4 *>(P.rec_a));
     const gptr<const f32x4> rec_b = global(reinterpret_cast<const f32x4 *>(P.rec_b));
     const gptr<const u32x2> rec_k = global(reinterpret_cast<const u32x2 *>(P.rec_k));
-    // The next item's event index is loaded (unconditionally, at a clamped
-    // position) while this item is walked, and an item's weight and walk
-    // record are loaded together: one memory round trip per item.
-    const uint32_t last = ch.z - 1;
-    uint32_t k = ch.y + threadIdx.x;
-    uint32_t ev = items[min(k, last)];
-    for (; k < ch.z; k += blockDim.x) {
-        const uint32_t ev_next = items[min(k + blockDim.x, last)];
-        const float wv = w[ev];
+    // An item's weight sits at its own position (the combine pass put it
+    // there), so a wavefront reads weights and walk records coalesced.
+    for (uint32_t k = ch.y + threadIdx.x; k < ch.z; k += blockDim.x) {
+        const float wv = w[k];
         const f32x4 ra = rec_a[k];
         const f32x4 rb = rec_b[k];
         const u32x2 rk = rec_k[k];
         // (no test for w = 0, which adds zeros: a branch here would let
         // the compiler move the record loads behind the weight's)
         back_item<TOF>(ra, rb, rk, wv * S, cdf, tile);
-        ev = ev_next;
     }
 }
 
@@ -830,6 +807,172 @@ __global__ void __launch_bounds__(256) k_reduce_tiles(const Problem *__restrict_
         if (lx < B.nx && ly < B.ny && lz < B.nz)
             b[(B.x0 + lx) + (int64_t)P.nx * ((B.y0 + ly) + (int64_t)P.ny * (B.z0 + lz))] =
                 __ll2float_rn((long long)acc[q]) * inv;
+    }
+}
+
+// Forward projection by brick chunks (the back projection's chunks).  A
+// workgroup stages its brick of x in an LDS tile (the back projection's
+// slot layout, FP32, margin 0: the ~zero-weight piece that a walk can take
+// one step past the brick reads 0, as do voxels past the grid edge), then
+// walks its items' pieces with every gather served by the LDS, and writes
+// each item's partial sum of a x to the item's position in P.pw.  An
+// event's partials are added by the combine pass, in the order its window
+// crosses the bricks, so f does not depend on chunking or batch.
+template <bool TOF>
+__global__ void __launch_bounds__(kBackBlock) k_forward_items(const Problem *__restrict__ probs, int n_probs,
+                                                              const uint4 *__restrict__ chunks,
+                                                              const uint4 *__restrict__ bricks) {
+    __shared__ float tile[kTileSlots];
+    __shared__ float2 lut[kLutN + 2];
+    const uint4 ch = chunks[blockIdx.x];
+    const uint4 br = bricks[ch.x];
+    const Problem P = probs[find_brick_problem(probs, n_probs, br.x)];
+    const uint32_t bl = br.x - (uint32_t)P.brick_base;
+    const int bx = (int)(bl % (uint32_t)P.nbx), by = (int)((bl / (uint32_t)P.nbx) % (uint32_t)P.nby),
+              bz = (int)(bl / ((uint32_t)P.nbx * (uint32_t)P.nby));
+    const Box B = brick_box(P, bx, by, bz);
+    for (int k = threadIdx.x; k < kTileSlots; k += blockDim.x) tile[k] = 0.0f;
+    if (TOF)
+        for (int k = threadIdx.x; k < kLutN + 2; k += blockDim.x) lut[k] = make_float2(P.lut[k].x, P.lut[k].y);
+    __syncthreads();
+    const gptr<const float> x = global(P.x);
+    for (int k = threadIdx.x; k < kBrickVox; k += blockDim.x) {
+        const int lx = k & (kBrickX - 1), ly = (k / kBrickX) & (kBrickY - 1), lz = k / (kBrickX * kBrickY);
+        if (lx < B.nx && ly < B.ny && lz < B.nz)
+            tile[kTileBase + lx + kTileSy * ly + kTileSz * lz] =
+                x[(B.x0 + lx) + (int64_t)P.nx * ((B.y0 + ly) + (int64_t)P.ny * (B.z0 + lz))];
+    }
+    __syncthreads();
+    const Cdf2 cdf{lut, in_vgpr(P.lut_a), P.lut_b, P.lut_h2};
+    const gptr<float> pw = global(P.pw);
+    const gptr<const f32x4> rec_a = global(reinterpret_cast<const f32x4 *>(P.rec_a));
+    const gptr<const f32x4> rec_b = global(reinterpret_cast<const f32x4 *>(P.rec_b));
+    const gptr<const u32x2> rec_k = global(reinterpret_cast<const u32x2 *>(P.rec_k));
+    for (uint32_t k = ch.y + threadIdx.x; k < ch.z; k += blockDim.x) {
+        const f32x4 ra = rec_a[k];
+        const f32x4 rb = rec_b[k];
+        const u32x2 rk = rec_k[k];
+        Ray r;
+        r.ax = ra[0];
+        r.ay = ra[1];
+        r.az = ra[2];
+        r.bx = rb[0];
+        r.by = rb[1];
+        r.bz = rb[2];
+        Stepper s(r, make_uint2(rk[0], rk[1]), (int)sizeof(float));
+        float p = 0.0f;
+        // j is a byte offset into the tile, inside its margin (see the tile)
+        walk_from<TOF>(s, r, ra[3], rb[3], cdf, [&](int j, float a) {
+            p = fmaf(a, *reinterpret_cast<const float *>(reinterpret_cast<const char *>(tile) + j), p);
+        });
+        pw[k] = p;
+    }
+}
+
+// Per event, over its items (see launch_combine).  Same chunks of events as
+// the event-parallel forward pass, whose per-chunk partials it writes.  An
+// event has a few items (about 3.3 on the whole-body workload): the first
+// kCombineUnroll positions are loaded together, then their partials, so an
+// event costs two dependent memory round trips, and the next event's
+// offsets are loaded while this one is summed.  Partials are added in the
+// order the window crosses the bricks.
+constexpr int kCombineUnroll = 8;
+
+__global__ void __launch_bounds__(kForwardBlock) k_combine(const Problem *__restrict__ probs, int n_probs, int ept,
+                                                           int mode, int *__restrict__ part_neff,
+                                                           double *__restrict__ part_ll,
+                                                           float *__restrict__ part_wmax) {
+    __shared__ int s_n[kForwardBlock / 64];
+    __shared__ double s_l[kForwardBlock / 64];
+    __shared__ float s_w[kForwardBlock / 64];
+    const int64_t c = blockIdx.x;
+    const Problem &P = probs[find_problem(probs, n_probs, c)];
+    const int64_t base = (c - P.chunk_begin) * (int64_t)blockDim.x * ept;
+    const int64_t n_events = P.n_events;
+    const gptr<float> pw = global(P.pw);
+    const gptr<const uint32_t> evitems = global(P.evitems);
+    const gptr<const uint32_t> evoff = global(P.evoff);
+    const float *evw = P.evw;
+    const uint32_t n_items = P.n_items;
+    int neff = 0;
+    float ll = 0.0f, wmax = 0.0f;
+    int64_t i = base + threadIdx.x;
+    uint32_t k0 = 0, k1 = 0;
+    if (i < n_events) {
+        k0 = evoff[i];
+        k1 = evoff[i + 1];
+    }
+    for (int e = 0; e < ept && i < n_events; ++e, i += blockDim.x) {
+        // the next event's offsets, while this one is summed
+        const int64_t in = i + blockDim.x;
+        const bool more = e + 1 < ept && in < n_events;
+        const uint32_t n0 = more ? evoff[in] : 0u, n1 = more ? evoff[in + 1] : 0u;
+        const uint32_t cnt = k1 - k0;
+        uint32_t q[kCombineUnroll];
+#pragma unroll
+        for (int j = 0; j < kCombineUnroll; ++j) q[j] = (uint32_t)j < cnt ? evitems[k0 + j] : 0xffffffffu;
+        float w;
+        if (mode == kCombineWeights) {
+            w = P.rw[i];
+        } else {
+            float v[kCombineUnroll];
+#pragma unroll
+            for (int j = 0; j < kCombineUnroll; ++j) v[j] = q[j] < n_items ? pw[q[j]] : 0.0f;
+            float f = 0.0f;
+#pragma unroll
+            for (int j = 0; j < kCombineUnroll; ++j) f += v[j];  // (adding 0 past the count changes nothing)
+            for (uint32_t k = k0 + kCombineUnroll; k < k1; ++k) {
+                const uint32_t qq = evitems[k];
+                f += qq < n_items ? pw[qq] : 0.0f;
+            }
+            if (mode == kCombineF) {
+                global(P.rw)[i] = f;
+                k0 = n0;
+                k1 = n1;
+                continue;
+            }
+            const bool pos = f > 0.0f;
+            w = pos ? 1.0f / f : 0.0f;
+            neff += pos;
+            ll += pos ? logf(f) : 0.0f;
+        }
+        if (evw) w *= evw[i];
+        wmax = fmaxf(wmax, fabsf(w));
+#pragma unroll
+        for (int j = 0; j < kCombineUnroll; ++j)
+            if (q[j] < n_items) pw[q[j]] = w;
+        for (uint32_t k = k0 + kCombineUnroll; k < k1; ++k) {
+            const uint32_t qq = evitems[k];
+            if (qq < n_items) pw[qq] = w;
+        }
+        k0 = n0;
+        k1 = n1;
+    }
+    if (mode == kCombineF) return;
+    const int wn = wave_sum(neff);
+    const double wl = wave_sum((double)ll);
+    const float ww = wave_max(wmax);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        s_n[wid] = wn;
+        s_l[wid] = wl;
+        s_w[wid] = ww;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tn = 0;
+        double tl = 0.0;
+        float tw = 0.0f;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            tn += s_n[w];
+            tl += s_l[w];
+            tw = fmaxf(tw, s_w[w]);
+        }
+        if (mode == kCombineRatio) {
+            part_neff[c] = tn;
+            part_ll[c] = tl;
+        }
+        part_wmax[c] = tw;
     }
 }
 
@@ -906,13 +1049,15 @@ __device__ __forceinline__ void brick_walk(const Problem &P, const Ray &r, Visit
 }
 
 // Brick item lists, counted and filled per (brick, item class) key =
-// brick * kItemClasses + class.  Counting (fill == 0): ctr[key] += pieces.
-// Filling: every piece gets a position from ctr[key]++ (never past
-// end[key]); P.items[position] = its problem-local event index and the
-// item's walk record (crossing coefficients, its piece of the window, first
-// voxel), so that the back projection streams a chunk's records instead of
-// gathering events and re-deriving rays (each event is walked once per
-// brick it crosses).  When counting, a block
+// brick * kItemClasses + class.  Counting (fill == 0): ctr[key] += pieces,
+// and each event's piece count into P.evoff[i] (the host turns the counts
+// into offsets).  Filling: every piece gets a position from ctr[key]++
+// (never past end[key]) where the item's walk record goes (crossing
+// coefficients, its piece of the window, first voxel), so that both
+// projections stream a chunk's records instead of gathering events and
+// re-deriving rays (each event is walked once per brick it crosses); the
+// event's k-th piece (in the order its window crosses the bricks) has its
+// position at P.evitems[P.evoff[i] + k].  When counting, a block
 // tallies its pieces per key in an LDS hash table, then touches each global
 // counter once (bucketed events make whole blocks hit the same few bricks,
 // and same-address global atomics serialise) and keeps the table; when
@@ -967,8 +1112,9 @@ __device__ __forceinline__ void brick_items_pass(const Problem &P, int64_t base,
                                                  uint32_t *__restrict__ pctr, int fill, uint32_t *hkey,
                                                  uint32_t *hcnt, uint32_t *hbase, uint32_t *bmap,
                                                  gptr<uint32_t> tab) {
-    const gptr<uint32_t> items = global(const_cast<uint32_t *>(P.items));
     const gptr<uint32_t> pairs = global(const_cast<uint32_t *>(P.pairs));
+    const gptr<uint32_t> evoff = global(const_cast<uint32_t *>(P.evoff));
+    const gptr<uint32_t> evitems = global(const_cast<uint32_t *>(P.evitems));
     if (fill) {
         for (int k = threadIdx.x; k < kHashSlots; k += blockDim.x) {
             if (hkey[k] == kEmpty) continue;
@@ -979,9 +1125,13 @@ __device__ __forceinline__ void brick_items_pass(const Problem &P, int64_t base,
     }
     for (int e = 0; e < ept; ++e) {
         const int64_t i = base + (int64_t)e * blockDim.x + threadIdx.x;
+        if (i >= P.n_events) continue;
         Ray r;
-        if (i >= P.n_events || !make_ray<PACKED>(P, i, r)) continue;
-        brick_walk(P, r, [&](uint32_t brick, int bx, int by, int bz, float t0, float t1) {
+        const bool ok = make_ray<PACKED>(P, i, r);
+        // the event's pieces so far; when filling, where its positions go
+        uint32_t n = 0;
+        const uint32_t e0 = fill ? evoff[i] : 0u;
+        if (ok) brick_walk(P, r, [&](uint32_t brick, int bx, int by, int bz, float t0, float t1) {
             const uint32_t bl = brick - (uint32_t)P.brick_base;
             atomicOr(&bmap[bl >> 5], 1u << (bl & 31u));
             const uint32_t key = brick * kItemClasses + item_class(P, r, t0, t1);
@@ -991,16 +1141,20 @@ __device__ __forceinline__ void brick_items_pass(const Problem &P, int64_t base,
                     atomicAdd(&hcnt[h], 1u);
                 else
                     atomicAdd(ctr + key, 1u);  // table full: counted directly
+                ++n;
                 return;
             }
             // a key is in the table in both passes, or counted directly in both
             const int h = hash_find(hkey, key);
             const uint32_t pos = h >= 0 ? hbase[h] + atomicAdd(&hcnt[h], 1u) : atomicAdd(ctr + key, 1u);
-            if (pos < end[key]) {
-                items[pos] = (uint32_t)i;
-                write_item_walk(P, r, bx, by, bz, t0, t1, pos);
-            }
+            const bool in = pos < end[key];
+            if (in) write_item_walk(P, r, bx, by, bz, t0, t1, pos);
+            // (a position past the key's range, which a consistent count
+            // never gives, is marked out of range for the combine pass)
+            evitems[e0 + n] = in ? pos : 0xffffffffu;
+            ++n;
         });
+        if (!fill) evoff[i] = n;
     }
     __syncthreads();
     // One (chunk, brick) pair per brick this block touched.  The set of
@@ -1165,19 +1319,27 @@ hipError_t launch_forward(const Launch &L, bool tof, const Problem *d_probs, int
     return do_launch(L, fn, dim3((unsigned)n_chunks), dim3(kForwardBlock), 0, args);
 }
 
+hipError_t launch_forward_items(const Launch &L, bool tof, const Problem *d_probs, int n_probs, const uint4 *chunks,
+                                uint32_t n_chunks, const uint4 *bricks) {
+    void *args[] = {&d_probs, &n_probs, &chunks, &bricks};
+    const void *fn = tof ? reinterpret_cast<const void *>(&k_forward_items<true>)
+                         : reinterpret_cast<const void *>(&k_forward_items<false>);
+    return do_launch(L, fn, dim3(n_chunks), dim3(kBackBlock), 0, args);
+}
+
+hipError_t launch_combine(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept, int mode,
+                          int *part_neff, double *part_ll, float *part_wmax) {
+    void *args[] = {&d_probs, &n_probs, &ept, &mode, &part_neff, &part_ll, &part_wmax};
+    return do_launch(L, reinterpret_cast<const void *>(&k_combine), dim3((unsigned)n_chunks), dim3(kForwardBlock), 0,
+                     args);
+}
+
 hipError_t launch_back_chunks(const Launch &L, bool tof, const Problem *d_probs, int n_probs, const uint4 *chunks,
                               uint32_t n_chunks, const uint4 *bricks) {
     void *args[] = {&d_probs, &n_probs, &chunks, &bricks};
     const void *fn = tof ? reinterpret_cast<const void *>(&k_back_chunks<true>)
                          : reinterpret_cast<const void *>(&k_back_chunks<false>);
     return do_launch(L, fn, dim3(n_chunks), dim3(kBackBlock), 0, args);
-}
-
-hipError_t launch_chunk_absmax(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept,
-                               float *part_wmax) {
-    void *args[] = {&d_probs, &n_probs, &ept, &part_wmax};
-    return do_launch(L, reinterpret_cast<const void *>(&k_chunk_absmax), dim3((unsigned)n_chunks),
-                     dim3(kForwardBlock), 0, args);
 }
 
 hipError_t launch_brick_wmax(const Launch &L, const Problem *d_probs, int n_probs, const uint4 *bricks,

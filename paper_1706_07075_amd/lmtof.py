@@ -36,6 +36,9 @@ LMTOF_OPT_SENS_NPHI = 3
 LMTOF_OPT_EVENTS_PER_THREAD = 5
 LMTOF_OPT_SORT_CELL_MM = 6
 LMTOF_OPT_MEDIAN_SIEVE = 8
+LMTOF_OPT_FORWARD = 9
+LMTOF_FORWARD_BRICKS = 0
+LMTOF_FORWARD_EVENTS = 1
 
 ERROR_NAMES = {0: "OK", -1: "EINVAL", -2: "ESTATE", -3: "ENOMEM", -4: "EHIP", -5: "EUNSUPPORTED", -6: "EAGAIN"}
 
@@ -60,7 +63,7 @@ class lmtof_iter_stats(C.Structure):
     _fields_ = [("iter", C.c_int32), ("reserved0", C.c_int32), ("n_eff", C.c_int64), ("sum_sx", C.c_double),
                 ("loglik", C.c_double), ("ms", C.c_float), ("project_ms", C.c_float),
                 ("forward_ms", C.c_float), ("back_ms", C.c_float), ("back_kernel_ms", C.c_float),
-                ("update_ms", C.c_float)]
+                ("update_ms", C.c_float), ("forward_kernel_ms", C.c_float)]
 
 
 class lmtof_request(C.Structure):
@@ -279,8 +282,8 @@ def lmtof_iterate(ctx, n_iter: int):
     st = (lmtof_iter_stats * n_iter)()
     _check(_lib.lmtof_iterate(ctx, n_iter, st), ctx)
     return [dict(iter=s.iter, n_eff=s.n_eff, sum_sx=s.sum_sx, loglik=s.loglik, ms=s.ms, project_ms=s.project_ms,
-                 forward_ms=s.forward_ms, back_ms=s.back_ms, back_kernel_ms=s.back_kernel_ms,
-                 update_ms=s.update_ms) for s in st]
+                 forward_ms=s.forward_ms, forward_kernel_ms=s.forward_kernel_ms, back_ms=s.back_ms,
+                 back_kernel_ms=s.back_kernel_ms, update_ms=s.update_ms) for s in st]
 
 
 def lmtof_forward_project(ctx, x, n_events: int, out=None):

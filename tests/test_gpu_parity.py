@@ -103,14 +103,18 @@ def test_sensitivity_wholebody_sampled_voxels():
     assert err.max() < 1e-5
 
 
-@pytest.mark.parametrize("tof", [300.0, 0.0])
-def test_forward_projection(c1, tof):
-    _say(f"case: forward projection tof={tof}")
+@pytest.mark.parametrize("tof,forward", [(300.0, L.LMTOF_FORWARD_BRICKS), (300.0, L.LMTOF_FORWARD_EVENTS),
+                                         (0.0, L.LMTOF_FORWARD_BRICKS)])
+def test_forward_projection(c1, tof, forward):
+    """TOF: the brick-owned projector (LDS-staged bricks, per-event sum of
+    its brick pieces) and the event-parallel one; non-TOF always runs the
+    event-parallel one."""
+    _say(f"case: forward projection tof={tof} forward={forward}")
     g = dict(c1["g"], tof_fwhm_ps=tof)
     ev = c1["ev"]
     rng = np.random.default_rng(7)
     x = rng.uniform(0.2, 2.0, c1["w"].n_voxels).astype(np.float32)
-    with _recon(g, ev) as r:
+    with _recon(g, ev, forward=forward) as r:
         f = r.forward_project(x)
     ref = oracle.forward(g, ev, x.astype(np.float64))
     d = np.abs(f - ref)
@@ -211,7 +215,8 @@ def test_one_step_parity_from_oracle_image(c1):
 
 
 @pytest.mark.parametrize("opts", [dict(sort=0), dict(events_per_thread=3), dict(events_per_thread=1),
-                                  dict(sort=1, sort_cell_mm=40)])
+                                  dict(sort=1, sort_cell_mm=40), dict(forward=L.LMTOF_FORWARD_EVENTS),
+                                  dict(forward=L.LMTOF_FORWARD_EVENTS, sort=0)])
 def test_launch_shapes_and_sort_agree(c1, opts):
     _say(f"case: options {opts}")
     with _recon(c1["g"], c1["ev"], **opts) as r:
