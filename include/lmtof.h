@@ -271,6 +271,18 @@ int lmtof_set_event_weights(lmtof_ctx *ctx, const float *w, int64_t n, int mem);
  * Needs loaded TOF events (ESTATE / EUNSUPPORTED). */
 int lmtof_sampled_forward_project(lmtof_ctx *ctx, const float *x, int64_t nx_, float *f, int64_t nf, int mem);
 int lmtof_sampled_back_project(lmtof_ctx *ctx, const float *r, int64_t nr, float *b, int64_t nb, int mem);
+/* lmtof_sampled_forward_project for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same kernels and the same f, bit for bit, with x
+ * and f in device memory (no `mem` argument), and no allocation or free of
+ * any kind during the call.  The projections in stored event order live in
+ * a fixed device buffer of the library, one per GPU, that holds at most
+ * 4194304 (2^22) events: EINVAL if more events are loaded.  That buffer is
+ * shared by every context on the GPU and keeps the last call's contents:
+ * calls that overlap on one GPU (several host threads or streams) race and
+ * must be serialised by the caller.  Synchronises the context's stream
+ * before returning.  Needs loaded TOF events (ESTATE / EUNSUPPORTED). */
+int lmtof_sampled_forward_project_noalloc(lmtof_ctx *ctx, const float *x, int64_t nx_, float *f, int64_t nf);
 /* Back projection b_j = sum_i a_ij w_i of per-event weights w (caller's
  * order, n_events floats) into b (nx*ny*nz floats, overwritten). */
 int lmtof_back_project(lmtof_ctx *ctx, const float *w, int64_t nw, float *b, int64_t nb, int mem);

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <chrono>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -29,6 +30,18 @@ constexpr double kTofRejectZ = 1.959964;  // two-sided 95 % quantile of the norm
 // kernel, after the forward stage (ratios on the items), after brick
 // scales, after brick back projection, after tile reduction, end.
 constexpr int kEventsPerIter = 7;
+
+// Device scratch of the allocation-free sampled forward projection: the
+// projections in stored event order, before they are put in the caller's
+// order.  Each device holds its own copy while the library is loaded.  In
+// host code `scratch` only names the symbol: its device address, per
+// device, comes from hipGetSymbolAddress (resolved in lmtof_create with the
+// device current) and is the only form passed to kernels.
+constexpr int64_t kNoAllocMaxEvents = int64_t(1) << 22;
+static __device__ __align__(256) float scratch[kNoAllocMaxEvents];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[kMaxDevices] = {};
 
 struct GraphEntry {
     hipGraph_t graph = nullptr;
@@ -971,6 +984,23 @@ int lmtof_create(lmtof_ctx **out, int hip_device, void *hip_stream) {
             g_create_err = std::string("hipSetDevice: ") + hipGetErrorString(e);
             return LMTOF_EHIP;
         }
+        if (hip_device >= kMaxDevices) {
+            g_create_err = "hip_device beyond the supported device count";
+            return LMTOF_EUNSUPPORTED;
+        }
+        {
+            // this device's copy of the allocation-free entry point's scratch
+            std::lock_guard<std::mutex> lk(g_scratch_mu);
+            if (!g_scratch_ptr[hip_device]) {
+                void *p = nullptr;
+                e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+                if (e != hipSuccess || !p) {
+                    g_create_err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+                    return LMTOF_EHIP;
+                }
+                g_scratch_ptr[hip_device] = static_cast<float *>(p);
+            }
+        }
         lmtof_ctx *c = new lmtof_ctx();
         c->device = hip_device;
         if (hip_stream) {
@@ -1639,6 +1669,30 @@ static int sampled_project(lmtof_ctx *c, const float *in, int64_t n_in, float *o
 
 int lmtof_sampled_forward_project(lmtof_ctx *c, const float *x, int64_t nx_, float *f, int64_t nf, int mem) {
     return sampled_project(c, x, nx_, f, nf, mem, false);
+}
+
+int lmtof_sampled_forward_project_noalloc(lmtof_ctx *c, const float *x, int64_t nx_, float *f, int64_t nf) {
+    if (!c) return LMTOF_EINVAL;
+    c->err.clear();
+    if (!c->n_events) return fail(c, LMTOF_ESTATE, "load events first");
+    if (!(c->g.tof_fwhm_ps > 0)) return fail(c, LMTOF_EUNSUPPORTED, "the sampled projector needs TOF events");
+    if (!x || !f || nx_ != c->V || nf != c->n_events)
+        return fail(c, LMTOF_EINVAL, "need x of %lld floats and f of %lld floats", (long long)c->V,
+                    (long long)c->n_events);
+    if (c->n_events > kNoAllocMaxEvents)
+        return fail(c, LMTOF_EINVAL, "%lld events loaded: the allocation-free projection takes at most %lld",
+                    (long long)c->n_events, (long long)kNoAllocMaxEvents);
+    float *tmp = g_scratch_ptr[c->device];  // set by lmtof_create for this device
+    if (!tmp) return fail(c, LMTOF_ESTATE, "no scratch address for device %d", c->device);
+    HIPCHK(c, hipSetDevice(c->device));
+    Launch L;
+    L.stream = c->stream;
+    const SampledGeom G = sampled_geom(c);
+    hipError_t he = launch_sampled(L, c->d_events, c->stored_packed != 0, c->n_events, G, x, tmp, nullptr, nullptr);
+    if (he == hipSuccess) he = launch_scatter_by_perm(L, tmp, c->d_perm, c->n_events, f);
+    if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+    if (he != hipSuccess) return fail(c, LMTOF_EHIP, "sampled projector: %s", hipGetErrorString(he));
+    return LMTOF_OK;
 }
 
 int lmtof_sampled_back_project(lmtof_ctx *c, const float *r, int64_t nr, float *b, int64_t nb, int mem) {

@@ -113,6 +113,7 @@ _sig = {
     "lmtof_set_event_weights": ([_P, _P, _i64, C.c_int], C.c_int),
     "lmtof_sampled_forward_project": ([_P, _P, _i64, _P, _i64, C.c_int], C.c_int),
     "lmtof_sampled_back_project": ([_P, _P, _i64, _P, _i64, C.c_int], C.c_int),
+    "lmtof_sampled_forward_project_noalloc": ([_P, _P, _i64, _P, _i64], C.c_int),
     "lmtof_count_segments": ([_P, C.POINTER(_i64), C.POINTER(_i64)], C.c_int),
     "lmtof_autotune": ([_P, C.POINTER(_i64), C.POINTER(C.c_float)], C.c_int),
     "lmtof_set_regions": ([_P, C.POINTER(C.c_int32), C.c_int, C.c_int], C.c_int),
@@ -370,6 +371,19 @@ def lmtof_sampled_forward_project(ctx, x, n_events: int):
     return _project_call(_lib.lmtof_sampled_forward_project, ctx, x, n_events)
 
 
+def lmtof_sampled_forward_project_noalloc(ctx, x, f):
+    """x and f: contiguous float32 tensors on the context's GPU (f holds
+    the loaded event count); f is filled in place, nothing is allocated."""
+    for a in (x, f):
+        if not (_is_torch(a) and a.is_cuda and a.is_contiguous() and str(a.dtype) == "torch.float32"):
+            raise ValueError("x and f must be contiguous float32 tensors on the GPU")
+    import torch
+    torch.cuda.current_stream(x.device).synchronize()
+    _check(_lib.lmtof_sampled_forward_project_noalloc(ctx, C.c_void_p(x.data_ptr()), x.numel(),
+                                                      C.c_void_p(f.data_ptr()), f.numel()), ctx)
+    return f
+
+
 def lmtof_sampled_back_project(ctx, r, n_voxels: int):
     return _project_call(_lib.lmtof_sampled_back_project, ctx, r, n_voxels)
 
@@ -577,6 +591,9 @@ class Reconstruction:
 
     def sampled_forward_project(self, x):
         return lmtof_sampled_forward_project(self.ctx, x, lmtof_num_events(self.ctx))
+
+    def sampled_forward_project_noalloc(self, x, f):
+        return lmtof_sampled_forward_project_noalloc(self.ctx, x, f)
 
     def sampled_back_project(self, r):
         return lmtof_sampled_back_project(self.ctx, r, self.V)
