@@ -221,8 +221,7 @@ def main():
         if args.regions:
             r.set_regions(REGION_CORES)
         r.set_image()
-        chosen, pass_ms = r.autotune()
-        tuned = {"events_per_thread": chosen, "pass_ms": pass_ms}
+        tuned = r.autotune()
         log(f"autotune: {tuned}")
 
     N, I, K = w.n_events, w.n_iter, args.steps
@@ -317,7 +316,8 @@ def main():
             rp = L.Reconstruction(g, device=0, storage=1, forward=opts["forward"],
                                   **({"events_per_thread": args.ept} if args.ept else {}))
             if tuned:
-                rp.set_option("events_per_thread", tuned["events_per_thread"])
+                for k in ("forward", "events_per_thread", "brick_chunks"):
+                    rp.set_option(k, tuned[k])
             tp, sp = run_form(rp, ev_dev, I, args.form_steps, 1, label="packed ")
             out["packed"] = form_summary(tp, sp, N, I)
             rp.close()

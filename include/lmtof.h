@@ -100,6 +100,11 @@ extern "C" {
 #define LMTOF_OPT_FORWARD 9
 #define LMTOF_FORWARD_BRICKS 0
 #define LMTOF_FORWARD_EVENTS 1
+/* Workgroups of the brick projectors: a problem batch's brick items are cut
+ * into chunks of max(2048, items / value) items (a brick's list into at
+ * least one chunk).  256..65536, default 8192.  Takes effect when the brick
+ * lists are next built (next load, region split or image set). */
+#define LMTOF_OPT_BRICK_CHUNKS 10
 
 /* ------------------------------------------------------------------ types */
 typedef struct lmtof_ctx lmtof_ctx;
@@ -187,12 +192,17 @@ int lmtof_read_sensitivity(lmtof_ctx *ctx, float *out, int64_t n, int mem);
 int lmtof_set_sensitivity(lmtof_ctx *ctx, const float *s, int64_t n, int mem);
 
 /* --------------------------------------------------------------- image */
-/* Set the MLEM start image x^0 (n = nx*ny*nz floats, >= 0, finite), or with
- * x0 == NULL the uniform start x^0_j = N / sum_{s>0} s for s_j > 0, else 0
- * (sum in FP64).  Resets the iteration counter.  Needs events and
+/* The image MLEM starts from (Section 2.4, the iteration's x^0; the paper
+ * feeds it with a starting back projection, Section 3.5.4, read here as the
+ * uniform image of the same total, which keeps sum_j s_j x_j = N from the
+ * first iteration on).  Sets x^0 (n = nx*ny*nz floats, >= 0, finite), or
+ * with x0 == NULL the uniform start x^0_j = N / sum_{s>0} s for s_j > 0,
+ * else 0 (sum in FP64).  Resets the iteration counter.  Needs events and
  * sensitivity (ESTATE). */
 int lmtof_set_image(lmtof_ctx *ctx, const float *x0, int64_t n, int mem);
-/* Copy the current image (n = nx*ny*nz floats) out. */
+/* Copy the current MLEM image x^k (Section 2.4; n = nx*ny*nz floats, x
+ * fastest) out; with a region split (Section 2.5) the region images summed
+ * at their z offsets. */
 int lmtof_read_image(lmtof_ctx *ctx, float *out, int64_t n, int mem);
 
 /* ------------------------------------------------------------ iterations */
@@ -205,23 +215,53 @@ int lmtof_read_image(lmtof_ctx *ctx, float *out, int64_t n, int mem);
  * is non-NULL it receives n_iter entries.  Needs an image (ESTATE). */
 int lmtof_iterate(lmtof_ctx *ctx, int n_iter, lmtof_iter_stats *stats);
 
-/* Launch-shape autotuner (the batched launch of Section 2.5 made to fit the
- * device).  Times one projector pass (forward + ratio, brick back
- * projection) over the loaded events for each candidate events-per-thread
- * value {1, 2, 4, 8} (the fastest of three passes after a warm-up pass),
- * adds a tenth of the time its brick lists took to build (they are built
- * once per reconstruction of ~10 iterations), keeps the lowest total as
- * LMTOF_OPT_EVENTS_PER_THREAD and rebuilds the brick lists for it; the
- * default (4) stays unless another value beats it by more than 1 %.  The image is not changed; the back projection accumulator is
- * cleared afterwards.  *chosen (may be NULL) receives the value, *ms (may be
- * NULL, 4 floats) the pass time of each candidate in that order.  Needs an
+/* One configuration the autotuner timed. */
+typedef struct {
+    int32_t forward;           /* LMTOF_FORWARD_* */
+    int32_t events_per_thread; /* LMTOF_OPT_EVENTS_PER_THREAD */
+    int32_t brick_chunks;      /* LMTOF_OPT_BRICK_CHUNKS */
+    int32_t reserved0;
+    float pass_ms;             /* one projector pass (forward stage + back stage), fastest of three */
+    float build_ms;            /* building its brick lists (host wall time) */
+} lmtof_tune_candidate;
+
+#define LMTOF_TUNE_MAX_CANDIDATES 16
+
+typedef struct {
+    int32_t forward;           /* chosen configuration, now set as the options */
+    int32_t events_per_thread;
+    int32_t brick_chunks;
+    int32_t n_candidates;      /* entries of cand (0 when taken from the cache) */
+    int32_t cached;            /* 1: found in the cache, nothing timed */
+    int32_t reserved0;
+    lmtof_tune_candidate cand[LMTOF_TUNE_MAX_CANDIDATES];
+} lmtof_tune_result;
+
+/* Launch autotuner (the batched launch of Section 2.5 made to fit the
+ * device).  Times one projector pass over the loaded events and current
+ * batch (whole volume or regions) per candidate, each the fastest of three
+ * after a warm-up pass, and scores it as that time plus a tenth of the time
+ * its brick lists took to build (once per reconstruction of ~10
+ * iterations).  The search is coordinate-wise from the defaults (brick
+ * forward projector, 4 events per thread, 8192 brick chunks): events per
+ * thread over {1, 2, 4, 8}, then brick chunks over {4096, 8192, 16384},
+ * then the forward projector over {bricks, events}; a change is kept only
+ * if it beats the incumbent by more than 1 %.  The winner is set as the
+ * options and its brick lists are built.  Results are cached for the
+ * process, keyed by (device architecture, grid, voxel size, TOF FWHM,
+ * storage format, number of regions, event count rounded to a power of
+ * two); with use_cache != 0 a cached configuration is applied without
+ * timing.  The image is not changed; the back projection accumulator is
+ * cleared afterwards.  *out (may be NULL) receives the result.  Needs an
  * image (ESTATE). */
-int lmtof_autotune(lmtof_ctx *ctx, int64_t *chosen, float *ms);
+int lmtof_autotune(lmtof_ctx *ctx, int use_cache, lmtof_tune_result *out);
 
 /* --------------------------------------------------- projector (testing) */
-/* Forward projection f_i = sum_j a_ij x_j of image x (nx*ny*nz floats) for
- * every loaded event, f in the caller's event order (n_events floats).
- * x and f live in `mem`.  Needs events (ESTATE). */
+/* Forward projection of Section 2.4's MLEM, f_i = sum_j a_ij x_j with the
+ * TOF-weighted a_ij of lmtof_iterate (Section 2.3's kernel integrated over
+ * each voxel piece), of image x (nx*ny*nz floats) for every loaded event,
+ * f in the caller's event order (n_events floats).  x and f live in `mem`.
+ * Needs events (ESTATE). */
 int lmtof_forward_project(lmtof_ctx *ctx, const float *x, int64_t nx_, float *f, int64_t nf, int mem);
 /* Median sieve of Section 2.4, applied once: y_j = median of x over the
  * 3 x 3 x 3 block of voxels around j, voxels outside the grid counting as 0
@@ -283,8 +323,10 @@ int lmtof_sampled_back_project(lmtof_ctx *ctx, const float *r, int64_t nr, float
  * must be serialised by the caller.  Synchronises the context's stream
  * before returning.  Needs loaded TOF events (ESTATE / EUNSUPPORTED). */
 int lmtof_sampled_forward_project_noalloc(lmtof_ctx *ctx, const float *x, int64_t nx_, float *f, int64_t nf);
-/* Back projection b_j = sum_i a_ij w_i of per-event weights w (caller's
- * order, n_events floats) into b (nx*ny*nz floats, overwritten). */
+/* Back projection of Section 2.4's MLEM (the transpose of the forward
+ * projection above), b_j = sum_i a_ij w_i of per-event weights w (caller's
+ * order, n_events floats) into b (nx*ny*nz floats, overwritten).  Sums are
+ * exact 64-bit fixed point: b does not depend on event order. */
 int lmtof_back_project(lmtof_ctx *ctx, const float *w, int64_t nw, float *b, int64_t nb, int mem);
 
 /* Diagnostic: total voxel pieces the loaded events' rays visit inside their
@@ -338,7 +380,13 @@ typedef struct {
     int32_t mem;         /* LMTOF_MEM_* */
     int32_t n_iter;      /* MLEM iterations, >= 1 */
     int32_t storage;     /* 0 plain, 1 packed */
+    int32_t flags;       /* 0 or LMTOF_REQ_BACKGROUND */
+    int32_t reserved0;   /* must be 0 */
 } lmtof_request;
+
+/* Request flag: prepare the request in the background (see
+ * lmtof_pool_submit), so that running requests keep stepping meanwhile. */
+#define LMTOF_REQ_BACKGROUND 1
 
 /* Create a pool on `hip_device` (stream as in lmtof_create) with an HBM
  * budget in bytes for resident requests (> 0). */
@@ -349,20 +397,34 @@ const char *lmtof_pool_last_error(const lmtof_pool *pool);
 int lmtof_pool_request_bytes(const lmtof_request *req, int64_t *bytes);
 /* Validate, copy and prepare (ingest, bucketing, sensitivity, start image,
  * brick lists) a request; *id receives its handle.  LMTOF_EAGAIN (nothing
- * done) if its footprint does not fit the budget next to the resident
- * requests now, or if it is TOF and the active requests are not (or the
- * reverse: a batch is all-TOF or all-non-TOF); LMTOF_ENOMEM if it can
- * never fit. */
+ * done) if its footprint does not fit the budget next to the resident and
+ * preparing requests now, or if it is TOF and those requests are not (or
+ * the reverse: a batch is all-TOF or all-non-TOF); LMTOF_ENOMEM if it can
+ * never fit.
+ * Without LMTOF_REQ_BACKGROUND the preparation runs on the pool's stream
+ * before the call returns (and no step runs meanwhile); the caller may free
+ * the events on return.  With it, the call reserves the footprint and
+ * returns at once; a thread of the pool prepares the request on a second
+ * stream of the device (default priority), concurrently with the steps of
+ * the active requests, and the request joins the batch at the first
+ * lmtof_pool_step after its preparation has finished.  The events must then
+ * stay valid and unchanged until lmtof_pool_poll has reported the request
+ * done (or failed), or the pool is destroyed.  A failed preparation is
+ * reported by lmtof_pool_poll for that id. */
 int lmtof_pool_submit(lmtof_pool *pool, const lmtof_request *req, int64_t *id);
-/* One batched iteration over all active requests; *n_active receives how
- * many were active (0: nothing to do).  Requests that reach their
- * iteration count become finished (images kept until polled). */
+/* One batched iteration over all active requests (requests whose
+ * background preparation has finished join first); *n_active receives how
+ * many were active (0: nothing to do now, though background preparations
+ * may still be running).  Requests that reach their iteration count become
+ * finished (images kept until polled). */
 int lmtof_pool_step(lmtof_pool *pool, int *n_active);
 /* *done = 1 and the image copied to out (nx*ny*nz floats in `mem`) if
  * request id has finished; the request is then released.  *done = 0 if it
- * is still running.  EINVAL for an unknown id. */
+ * is still being prepared or running.  EINVAL for an unknown id; the code
+ * of a failed background preparation (the request is then released). */
 int lmtof_pool_poll(lmtof_pool *pool, int64_t id, int *done, float *out, int64_t n, int mem);
-/* Bytes reserved, budget, active and finished-but-unpolled request counts. */
+/* Bytes reserved, budget, active and finished-but-unpolled request counts
+ * (requests being prepared in the background count in `used` only). */
 int lmtof_pool_info(const lmtof_pool *pool, int64_t *used, int64_t *budget, int *n_active, int *n_finished);
 
 #ifdef __cplusplus

@@ -9,10 +9,14 @@
 #include <cstdio>
 #include <cstring>
 #include <chrono>
+#include <condition_variable>
+#include <deque>
 #include <map>
 #include <mutex>
 #include <new>
+#include <set>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "lmtof.h"
@@ -24,6 +28,7 @@ namespace {
 
 constexpr double kDefaultC = 0.299792458;
 constexpr int kDefaultEpt = 4;
+constexpr int kDefaultBrickChunks = 8192;
 constexpr float kAutotuneIters = 10.0f;  // iterations a reconstruction is assumed to run
 constexpr double kTofRejectZ = 1.959964;  // two-sided 95 % quantile of the normal distribution
 // Event records per graph-replayed iteration: start, after the forward
@@ -42,6 +47,10 @@ static __device__ __align__(256) float scratch[kNoAllocMaxEvents];
 constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mu;
 float *g_scratch_ptr[kMaxDevices] = {};
+// autotuner results of this process, by (arch, grid, voxel, FWHM, storage,
+// regions, event-count class)
+std::mutex g_tune_mu;
+std::map<std::string, lmtof_tune_result> g_tune_cache;
 
 struct GraphEntry {
     hipGraph_t graph = nullptr;
@@ -71,23 +80,27 @@ struct ItemSet {
     // item positions in evitems (+ 1 entry); the positions in brick order
     uint32_t *evoff = nullptr, *evitems = nullptr;
     uint32_t *scan_tmp = nullptr;
+    uint16_t *itemslot = nullptr;  // per item: its (event in chunk, ordinal) slot of the combine pass
+    uint8_t *evflag = nullptr;     // per event: reached through evitems by the combine pass
     uint4 *chunks = nullptr, *bricks = nullptr;
     unsigned long long *tiles = nullptr;
-    float *wmax = nullptr;
-    uint32_t *pairs = nullptr, *pair_off = nullptr;  // (forward chunk) lists per brick
-    char *item_recs = nullptr;                        // walk records in item order (40 B each)
+    // per brick of the batch (every problem's, empty ones too): its
+    // largest |w| (FP32 bits, set by the combine pass) and its first item
+    // (+ 1 entry)
+    uint32_t *bwmax = nullptr, *brick_off = nullptr;
+    char *item_recs = nullptr;  // walk records in item order (40 B each)
     size_t item_bytes = 0;
-    // builder scratch: per-key counters and offsets, per-brick pair
-    // counters, the counting blocks' key tables
-    uint32_t *cnt = nullptr, *off_d = nullptr, *pcnt = nullptr, *tabs = nullptr;
+    // builder scratch: per-key counters and offsets, the counting blocks'
+    // key tables (then the forward chunks' run lists)
+    uint32_t *cnt = nullptr, *off_d = nullptr, *tabs = nullptr;
     // capacities (elements) of every array above: the lists are rebuilt in
     // place and a buffer is only reallocated when it has to grow, so
     // reloading events of a similar size allocates and frees nothing
-    size_t pw_cap = 0, evoff_cap = 0, evitems_cap = 0, scan_cap = 0, item_recs_cap = 0, tiles_cap = 0,
-           pairs_cap = 0, chunks_cap = 0, bricks_cap = 0, wmax_cap = 0, pair_off_cap = 0, cnt_cap = 0, off_cap = 0,
-           pcnt_cap = 0, tabs_cap = 0;
+    size_t pw_cap = 0, evoff_cap = 0, evitems_cap = 0, scan_cap = 0, itemslot_cap = 0, evflag_cap = 0,
+           item_recs_cap = 0, tiles_cap = 0, chunks_cap = 0, bricks_cap = 0, bwmax_cap = 0, brick_off_cap = 0,
+           cnt_cap = 0, off_cap = 0, tabs_cap = 0;
     uint32_t n_chunks = 0, n_bricks = 0, n_slots = 0;
-    uint64_t n_items = 0, n_pairs = 0;
+    uint64_t n_items = 0, n_all_bricks = 0;  // n_bricks: non-empty ones
     std::vector<uint4> h_chunks, h_bricks;  // host copies (batching several problems)
 };
 
@@ -102,6 +115,7 @@ struct lmtof_ctx {
     // options
     int opt_storage = 0, opt_sort = 1, opt_nphi = 2048, opt_ept = 0, opt_median = 0;
     int opt_forward = LMTOF_FORWARD_BRICKS;
+    int opt_bchunks = kDefaultBrickChunks;
     double opt_cell_mm = 16.0;
 
     bool has_geom = false;
@@ -152,10 +166,10 @@ struct lmtof_ctx {
     float *d_evw_caller = nullptr, *d_evw = nullptr;
     size_t evw_cap = 0, evw_stored_cap = 0;
     float4 *d_lut = nullptr;     // kernel-CDF table
+    float2 *d_lin = nullptr;     // piecewise-linear kernel-CDF table (brick projectors)
     double lut_k = -1.0;
     int *d_part_neff = nullptr;
     double *d_part_ll = nullptr, *d_part_old = nullptr, *d_part_new = nullptr;
-    float *d_part_wmax = nullptr;
     size_t part_cap = 0, vpart_cap = 0;
     DevStats *d_stats = nullptr;
     size_t stats_cap = 0;
@@ -233,16 +247,16 @@ void free_items(ItemSet &it) {
     dev_free(it.evoff);
     dev_free(it.evitems);
     dev_free(it.scan_tmp);
+    dev_free(it.itemslot);
+    dev_free(it.evflag);
     dev_free(it.chunks);
     dev_free(it.bricks);
     dev_free(it.tiles);
-    dev_free(it.wmax);
-    dev_free(it.pairs);
-    dev_free(it.pair_off);
+    dev_free(it.bwmax);
+    dev_free(it.brick_off);
     dev_free(it.item_recs);
     dev_free(it.cnt);
     dev_free(it.off_d);
-    dev_free(it.pcnt);
     dev_free(it.tabs);
     it = ItemSet();
 }
@@ -251,7 +265,7 @@ void free_items(ItemSet &it) {
 // the next build.
 void invalidate_items(ItemSet &it) {
     it.n_chunks = it.n_bricks = it.n_slots = 0;
-    it.n_items = it.n_pairs = 0;
+    it.n_items = it.n_all_bricks = 0;
     it.item_bytes = 0;
     it.h_chunks.clear();
     it.h_bricks.clear();
@@ -341,11 +355,14 @@ Problem make_problem(const lmtof_ctx *c, int z_lo, int nz, float *x, float *b, c
         P.norm = (float)(1.0 / (2.0 * std::erf(g.tof_trunc_sigmas / std::sqrt(2.0))));
     }
     P.lut = c->d_lut;
+    P.lin = c->d_lin;
     if (P.tof) {
         const double h = 2.0 * g.tof_trunc_sigmas / (kLutN - 1);
         P.lut_a = (float)(1.0 / (sigma_mm(g) * h));
         P.lut_b = (float)((kLutN - 1) / 2) + 12582912.0f;  // centre node + 1.5 2^23, exact
-        P.lut_h2 = (float)(h * h / 2.0);
+        const double hl = 2.0 * g.tof_trunc_sigmas / kLinN;
+        P.lin_a = (float)(1.0 / (sigma_mm(g) * hl));
+        P.lin_b = (float)((kLinN - 1) / 2) + 12582912.0f;  // centre cell + 1.5 2^23, exact
     }
     P.a_max = P.tof ? 1.0f : (float)std::sqrt(g.vx * g.vx + g.vy * g.vy + g.vz * g.vz);
     P.nbx = (g.nx + kBrickX - 1) / kBrickX;
@@ -382,11 +399,31 @@ int ensure_lut(lmtof_ctx *c) {
     }
     tab[0] = make_float4(tab[1].x, 0.0f, 0.0f, 0.0f);
     tab[kLutN + 1] = make_float4(tab[kLutN].x, 0.0f, 0.0f, 0.0f);
+    // Piecewise-linear table: cell j spans [-K + j hl, -K + (j + 1) hl],
+    // hl = 2K / kLinN; it holds the chord's value at the cell's middle and
+    // the CDF difference over the cell, so CDF(t) ~ mid + f diff with f the
+    // offset from the middle in cells, in [-1/2, 1/2]: continuous and
+    // non-decreasing, |error| <= hl^2 max|Phi''| / 8 (~6.5e-8 at K = 3).
+    // The pads repeat the end values with no slope.
+    std::vector<float2> lin(kLinN + 2);
+    const double hl = 2.0 * K / kLinN;
+    auto cdf = [&](double u) { return std::erf(u / std::sqrt(2.0)) / (2.0 * den); };
+    for (int j = 0; j < kLinN; ++j) {
+        const double a = cdf(-K + j * hl), b = cdf(-K + (j + 1) * hl);
+        lin[j + 1] = make_float2((float)(0.5 * (a + b)), (float)(b - a));
+    }
+    lin[0] = make_float2((float)cdf(-K), 0.0f);
+    lin[kLinN + 1] = make_float2((float)cdf(K), 0.0f);
     if (!c->d_lut) {
         int rc = dev_alloc(c, &c->d_lut, kLutN + 2);
         if (rc) return rc;
     }
+    if (!c->d_lin) {
+        int rc = dev_alloc(c, &c->d_lin, kLinN + 2);
+        if (rc) return rc;
+    }
     HIPCHK(c, hipMemcpyAsync(c->d_lut, tab.data(), sizeof(float4) * (kLutN + 2), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_lin, lin.data(), sizeof(float2) * (kLinN + 2), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->lut_k = K;
     return LMTOF_OK;
@@ -459,13 +496,10 @@ int build_items(lmtof_ctx *c, std::vector<Problem> &ps, Problem *d_probs, int64_
     // grow.  Until the build completes the set holds no lists.
     invalidate_items(it);
     uint64_t nb = 0;
-    for (const auto &P : ps) {
-        const uint64_t n = (uint64_t)P.nbx * P.nby * P.nbz;
-        if (n > (uint64_t)kMaxProblemBricks)
-            return fail(c, LMTOF_EUNSUPPORTED, "grid of %llu bricks of 16^3 voxels: at most %d per problem",
-                        (unsigned long long)n, kMaxProblemBricks);
-        nb += n;
-    }
+    for (const auto &P : ps) nb += (uint64_t)P.nbx * P.nby * P.nbz;
+    if (nb * kItemClasses >= 0xffffffffULL)
+        return fail(c, LMTOF_EUNSUPPORTED, "%llu bricks of 16^3 voxels: too many for 32-bit (brick, class) keys",
+                    (unsigned long long)nb);
     const uint64_t nk = nb * kItemClasses;  // (brick, item class) keys
     // per-event item offsets over the stored events the problems cover
     int64_t ne = 0;
@@ -473,32 +507,32 @@ int build_items(lmtof_ctx *c, std::vector<Problem> &ps, Problem *d_probs, int64_
     Launch L;
     L.stream = c->stream;
     int rc;
-    if ((rc = reserve(c, &it.cnt, it.cnt_cap, nk + 1)) || (rc = reserve(c, &it.pcnt, it.pcnt_cap, nb + 1)) ||
+    if ((rc = reserve(c, &it.cnt, it.cnt_cap, nk + 1)) ||
         (rc = reserve(c, &it.tabs, it.tabs_cap, (size_t)brick_item_tab_words(n_chunks))) ||
-        (rc = reserve(c, &it.off_d, it.off_cap, nk + 1)) || (rc = reserve(c, &it.pair_off, it.pair_off_cap, nb + 1)) ||
+        (rc = reserve(c, &it.off_d, it.off_cap, nk + 1)) || (rc = reserve(c, &it.bwmax, it.bwmax_cap, nb)) ||
+        (rc = reserve(c, &it.brick_off, it.brick_off_cap, nb + 1)) ||
         (rc = reserve(c, &it.evoff, it.evoff_cap, (size_t)ne + 1)) ||
+        (rc = reserve(c, &it.evflag, it.evflag_cap, (size_t)ne + 1)) ||
         (rc = reserve(c, &it.scan_tmp, it.scan_cap, (size_t)scan_tmp_elems(ne + 1))))
         return rc;
-    for (auto &P : ps) P.evoff = it.evoff + P.ev_offset;
-    std::vector<uint32_t> hk(nk), hp(nb);
+    for (auto &P : ps) {
+        P.evoff = it.evoff + P.ev_offset;
+        P.evflag = it.evflag + P.ev_offset;
+        P.runs = it.tabs + P.chunk_begin * kTabWords;
+        P.bwmax = it.bwmax + P.brick_base;
+        P.brick_off = it.brick_off + P.brick_base;
+    }
+    std::vector<uint32_t> hk(nk);
     hipError_t he = hipMemcpyAsync(d_probs, ps.data(), sizeof(Problem) * ps.size(), hipMemcpyHostToDevice, c->stream);
     if (he == hipSuccess) he = hipMemsetAsync(it.cnt, 0, sizeof(uint32_t) * (nk + 1), c->stream);
-    if (he == hipSuccess) he = hipMemsetAsync(it.pcnt, 0, sizeof(uint32_t) * (nb + 1), c->stream);
     if (he == hipSuccess) he = hipMemsetAsync(it.evoff, 0, sizeof(uint32_t) * ((size_t)ne + 1), c->stream);
     if (he == hipSuccess)
-        he = launch_brick_items(L, d_probs, (int)ps.size(), n_chunks, ept, it.cnt, nullptr, it.pcnt, 0, it.tabs);
+        he = launch_brick_items(L, d_probs, (int)ps.size(), n_chunks, ept, it.cnt, nullptr, 0, it.tabs);
     // each event's item count -> the first entry of its positions
     if (he == hipSuccess) he = launch_exclusive_scan(L, it.evoff, ne + 1, it.scan_tmp);
     if (he == hipSuccess) he = hipMemcpyAsync(hk.data(), it.cnt, sizeof(uint32_t) * nk, hipMemcpyDeviceToHost, c->stream);
-    if (he == hipSuccess) he = hipMemcpyAsync(hp.data(), it.pcnt, sizeof(uint32_t) * nb, hipMemcpyDeviceToHost, c->stream);
     if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
     if (he != hipSuccess) return fail(c, LMTOF_EHIP, "brick item count: %s", hipGetErrorString(he));
-    std::vector<uint32_t> poff(nb + 1);
-    uint64_t ptot = 0;
-    for (uint64_t b = 0; b < nb; ++b) {
-        poff[b] = (uint32_t)std::min<uint64_t>(ptot, 0xffffffffULL);
-        ptot += hp[b];
-    }
     // a brick's items are its class ranges back to back
     std::vector<uint32_t> offk(nk + 1), h(nb), off(nb + 1);
     uint64_t tot = 0;
@@ -511,11 +545,11 @@ int build_items(lmtof_ctx *c, std::vector<Problem> &ps, Problem *d_probs, int64_
         tot += hk[k];
         h[k / kItemClasses] += hk[k];
     }
-    if (tot > 0xffffffffULL || ptot > 0xffffffffULL) return fail(c, LMTOF_EUNSUPPORTED, "more than 2^32-1 brick items");
-    poff[nb] = (uint32_t)ptot;
+    if (tot > 0xffffffffULL) return fail(c, LMTOF_EUNSUPPORTED, "more than 2^32-1 brick items");
     offk[nk] = (uint32_t)tot;
     off[nb] = (uint32_t)tot;
-    const uint64_t C = std::max<uint64_t>(2048, (tot + 8191) / 8192);
+    const uint64_t D = (uint64_t)c->opt_bchunks;
+    const uint64_t C = std::max<uint64_t>(2048, (tot + D - 1) / D);
     std::vector<uint4> chunks, bricks;
     uint32_t slot = 0;
     for (uint64_t b = 0; b < nb; ++b) {
@@ -533,20 +567,18 @@ int build_items(lmtof_ctx *c, std::vector<Problem> &ps, Problem *d_probs, int64_
     std::stable_sort(chunks.begin(), chunks.end(),
                      [](const uint4 &a, const uint4 &b) { return (a.z - a.y) > (b.z - b.y); });
     if ((rc = reserve(c, &it.pw, it.pw_cap, tot)) || (rc = reserve(c, &it.evitems, it.evitems_cap, tot)) ||
+        (rc = reserve(c, &it.itemslot, it.itemslot_cap, tot)) ||
         (rc = reserve(c, &it.chunks, it.chunks_cap, chunks.size())) ||
         (rc = reserve(c, &it.bricks, it.bricks_cap, bricks.size())) ||
         (rc = reserve(c, &it.tiles, it.tiles_cap, (size_t)slot * kBrickVox)) ||
-        (rc = reserve(c, &it.wmax, it.wmax_cap, slot)) || (rc = reserve(c, &it.pairs, it.pairs_cap, ptot)) ||
         (rc = reserve(c, &it.item_recs, it.item_recs_cap, (size_t)tot * kItemRecBytes)))
         return rc;
     for (auto &P : ps) {
         P.pw = it.pw;
+        P.itemslot = it.itemslot;
         P.n_items = (uint32_t)tot;
         P.evitems = it.evitems;
         P.tiles = it.tiles;
-        P.wmax = it.wmax;
-        P.pairs = it.pairs;
-        P.pair_off = it.pair_off + P.brick_base;
         P.rec_a = reinterpret_cast<const float4 *>(it.item_recs);
         P.rec_b = reinterpret_cast<const float4 *>(it.item_recs + (size_t)tot * 16);
         P.rec_k = reinterpret_cast<const uint2 *>(it.item_recs + (size_t)tot * 32);
@@ -561,18 +593,16 @@ int build_items(lmtof_ctx *c, std::vector<Problem> &ps, Problem *d_probs, int64_
     if (he == hipSuccess)
         he = hipMemcpyAsync(it.cnt, it.off_d, sizeof(uint32_t) * (nk + 1), hipMemcpyDeviceToDevice, c->stream);
     if (he == hipSuccess)
-        he = hipMemcpyAsync(it.pair_off, poff.data(), sizeof(uint32_t) * (nb + 1), hipMemcpyHostToDevice, c->stream);
+        he = hipMemcpyAsync(it.brick_off, off.data(), sizeof(uint32_t) * (nb + 1), hipMemcpyHostToDevice, c->stream);
     if (he == hipSuccess)
-        he = hipMemcpyAsync(it.pcnt, it.pair_off, sizeof(uint32_t) * (nb + 1), hipMemcpyDeviceToDevice, c->stream);
-    if (he == hipSuccess)
-        he = launch_brick_items(L, d_probs, (int)ps.size(), n_chunks, ept, it.cnt, it.off_d + 1, it.pcnt, 1, it.tabs);
+        he = launch_brick_items(L, d_probs, (int)ps.size(), n_chunks, ept, it.cnt, it.off_d + 1, 1, it.tabs);
     if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
     if (he != hipSuccess) return fail(c, LMTOF_EHIP, "brick item fill: %s", hipGetErrorString(he));
     it.n_chunks = (uint32_t)chunks.size();
     it.n_bricks = (uint32_t)bricks.size();
     it.n_slots = slot;
     it.n_items = tot;
-    it.n_pairs = ptot;
+    it.n_all_bricks = nb;
     it.item_bytes = (size_t)tot * kItemRecBytes;
     it.h_chunks = std::move(chunks);
     it.h_bricks = std::move(bricks);
@@ -582,8 +612,8 @@ int build_items(lmtof_ctx *c, std::vector<Problem> &ps, Problem *d_probs, int64_
 // Back projection of each problem's weights P.rw into its b (as graph nodes
 // after *prev, or on the stream).  In a graph, ev_a and ev_b (if given) are
 // recorded right before and right after the brick kernel, to time it alone.
-int add_back(lmtof_ctx *c, Launch L, const Problem *d_probs, int np, const ItemSet &it, const float *part_wmax,
-             int64_t n_part, hipGraphNode_t *prev, hipEvent_t ev_a = nullptr, hipEvent_t ev_b = nullptr) {
+int add_back(lmtof_ctx *c, Launch L, const Problem *d_probs, int np, const ItemSet &it, hipGraphNode_t *prev,
+             hipEvent_t ev_a = nullptr, hipEvent_t ev_b = nullptr) {
     const bool tof = c->g.tof_fwhm_ps > 0;
     hipGraphNode_t node = nullptr;
     if (L.graph) {
@@ -600,11 +630,6 @@ int add_back(lmtof_ctx *c, Launch L, const Problem *d_probs, int np, const ItemS
         return LMTOF_OK;
     };
     int rc;
-    HIPCHK(c, launch_brick_wmax(L, d_probs, np, it.bricks, it.n_bricks, part_wmax, n_part));
-    if (L.graph && it.n_bricks) {
-        *prev = node;
-        L.deps = prev;
-    }
     if ((rc = record(ev_a))) return rc;
     HIPCHK(c, launch_back_chunks(L, tof, d_probs, np, it.chunks, it.n_chunks, it.bricks));
     if (L.graph && it.n_chunks) {
@@ -679,11 +704,9 @@ int ensure_problems(lmtof_ctx *c) {
     if ((size_t)c->n_chunks > c->part_cap) {
         dev_free(c->d_part_neff);
         dev_free(c->d_part_ll);
-        dev_free(c->d_part_wmax);
         c->part_cap = 0;
         if ((rc = dev_alloc(c, &c->d_part_neff, c->n_chunks))) return rc;
         if ((rc = dev_alloc(c, &c->d_part_ll, c->n_chunks))) return rc;
-        if ((rc = dev_alloc(c, &c->d_part_wmax, c->n_chunks))) return rc;
         c->part_cap = c->n_chunks;
     }
     if ((size_t)c->n_vchunks > c->vpart_cap) {
@@ -714,7 +737,7 @@ int ensure_stats(lmtof_ctx *c, size_t n) {
 // pass that writes its ratios to the items.  ev_mid (graphs only) is
 // recorded between the two.
 int add_forward(lmtof_ctx *c, Launch L, const Problem *d_probs, int np, int64_t n_chunks, int64_t n_xblk,
-                const ItemSet &it, int ept, int *part_neff, double *part_ll, float *part_wmax, hipGraphNode_t *prev,
+                const ItemSet &it, int ept, int *part_neff, double *part_ll, hipGraphNode_t *prev,
                 hipEvent_t ev_mid = nullptr) {
     const bool tof = c->g.tof_fwhm_ps > 0;
     hipGraphNode_t node = nullptr;
@@ -734,9 +757,11 @@ int add_forward(lmtof_ctx *c, Launch L, const Problem *d_probs, int np, int64_t 
     } else {
         HIPCHK(c, launch_block_image(L, d_probs, np, n_xblk));
         chain();
-        HIPCHK(c, launch_forward(L, tof, d_probs, np, n_chunks, ept, 0, part_neff, part_ll, part_wmax));
+        HIPCHK(c, launch_forward(L, tof, d_probs, np, n_chunks, ept, 0, part_neff, part_ll));
         chain();
     }
+    HIPCHK(c, launch_clear_bwmax(L, d_probs, np, (int64_t)it.n_all_bricks));
+    chain();
     if (L.graph && ev_mid) {
         hipGraphNode_t n = nullptr;
         HIPCHK(c, hipGraphAddEventRecordNode(&n, L.graph, prev, 1, ev_mid));
@@ -745,7 +770,7 @@ int add_forward(lmtof_ctx *c, Launch L, const Problem *d_probs, int np, int64_t 
     }
     HIPCHK(c, launch_combine(L, d_probs, np, n_chunks, ept,
                              c->opt_forward == LMTOF_FORWARD_BRICKS ? kCombineRatio : kCombineWeights, part_neff,
-                             part_ll, part_wmax));
+                             part_ll));
     chain();
     return LMTOF_OK;
 }
@@ -776,10 +801,10 @@ int build_graph(lmtof_ctx *c, int n_iter, GraphEntry &ge) {
         Launch L;
         L.graph = ge.graph;
         if ((rc = add_forward(c, L, c->d_probs, np, c->n_chunks, c->n_xblk, c->items, c->ept_used, c->d_part_neff,
-                              c->d_part_ll, c->d_part_wmax, &prev, e[1])))
+                              c->d_part_ll, &prev, e[1])))
             return rc;
         if ((rc = record(e[2]))) return rc;
-        if ((rc = add_back(c, L, c->d_probs, np, c->items, c->d_part_wmax, c->n_chunks, &prev, e[3], e[4])))
+        if ((rc = add_back(c, L, c->d_probs, np, c->items, &prev, e[3], e[4])))
             return rc;
         if ((rc = record(e[5]))) return rc;
         hipGraphNode_t node = nullptr;
@@ -912,12 +937,13 @@ int64_t ctx_device_bytes(const lmtof_ctx *c) {
                               &c->sc_inner, &c->sc_reg, &c->sc_raw})
         b += (int64_t)sc->cap;
     b += (int64_t)c->reg_cap;
-    b += (int64_t)(it.pw_cap + it.evitems_cap + it.evoff_cap + it.scan_cap) * 4 + (int64_t)it.item_recs_cap +
-         (int64_t)it.tiles_cap * 8 + (int64_t)it.pairs_cap * 4;
+    b += (int64_t)(it.pw_cap + it.evitems_cap + it.evoff_cap + it.scan_cap) * 4 + (int64_t)it.itemslot_cap * 2 +
+         (int64_t)it.evflag_cap + (int64_t)it.item_recs_cap +
+         (int64_t)it.tiles_cap * 8;
     b += (int64_t)(it.chunks_cap + it.bricks_cap) * 16;
-    b += (int64_t)(it.wmax_cap + it.pair_off_cap + it.cnt_cap + it.off_cap + it.pcnt_cap + it.tabs_cap) * 4;
+    b += (int64_t)(it.bwmax_cap + it.brick_off_cap + it.cnt_cap + it.off_cap + it.tabs_cap) * 4;
     b += (int64_t)(c->evw_cap + c->evw_stored_cap) * 4;
-    b += (int64_t)c->part_cap * 12 + (int64_t)c->vpart_cap * 16 + (kLutN + 2) * 16 + (int64_t)c->xb_cap * 4;
+    b += (int64_t)c->part_cap * 12 + (int64_t)c->vpart_cap * 16 + (kLutN + 2) * 16 + (kLinN + 2) * 8 + (int64_t)c->xb_cap * 4;
     return b;
 }
 
@@ -946,11 +972,14 @@ int64_t request_bytes_estimate(const lmtof_request &q) {
         return q2;
     };
     const int64_t xbv = pow2((g.nx + 3) / 4) * pow2((g.ny + 3) / 4) * ((g.nz + 3) / 4) * 64;  // blocked copy of x
-    // per event: store, permutation, weight, item offset; per item: walk
-    // record, weight, position in its event's list; x, b, s, blocked x
-    int64_t b = N * (esz + 8 + 4 + 4) + items * (8 + kItemRecBytes) + 3 * 4 * V + 4 * xbv;
+    // per event: store, permutation, weight, item offset, flag; per item:
+    // walk record, weight, position in its event's list, combine slot;
+    // x, b, s, blocked x
+    int64_t b = N * (esz + 8 + 4 + 4 + 1) + items * (10 + kItemRecBytes) + 3 * 4 * V + 4 * xbv;
     b += (items / 2048 + 1 + V / kBrickVox + 1) * (int64_t)kBrickVox * 8 / 4;  // tiles
-    b += items;  // (forward chunk, brick) pairs: at most one per item, ~1 in 10 in practice
+    const int64_t nbr = (int64_t)((g.nx + kBrickX - 1) / kBrickX) * ((g.ny + kBrickY - 1) / kBrickY) *
+                        ((g.nz + kBrickZ - 1) / kBrickZ);
+    b += nbr * (8 + 4 * kItemClasses * 2);  // per brick: maximum, first item; builder counters and offsets
     // transients: the ingest's, then (not at the same time) the brick list
     // builder's key tables, 8 KiB per projector block, at most 32 B an event
     b += N * (q.mem == LMTOF_MEM_HOST ? 28 : 0) + N * std::max<int64_t>(esz + 8 + 4, 32);
@@ -1040,7 +1069,6 @@ int lmtof_destroy(lmtof_ctx *c) {
     release_load_scratch(c);
     dev_free(c->d_probs);
     dev_free(c->d_part_neff);
-    dev_free(c->d_part_wmax);
     dev_free(c->d_part_ll);
     dev_free(c->d_part_old);
     dev_free(c->d_part_new);
@@ -1050,6 +1078,7 @@ int lmtof_destroy(lmtof_ctx *c) {
     dev_free(c->d_evw);
     dev_free(c->d_evw_caller);
     dev_free(c->d_lut);
+    dev_free(c->d_lin);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
     return LMTOF_OK;
@@ -1107,6 +1136,11 @@ int lmtof_set_option(lmtof_ctx *c, int key, int64_t v) {
         if ((int)v != c->opt_median) drop_graphs_only(c);  // the brick lists stay
         c->opt_median = (int)v;
         return LMTOF_OK;
+    case LMTOF_OPT_BRICK_CHUNKS:
+        if (v < 256 || v > 65536) return fail(c, LMTOF_EINVAL, "brick chunks must be in [256, 65536]");
+        if ((int)v != c->opt_bchunks) c->probs_dirty = true;
+        c->opt_bchunks = (int)v;
+        return LMTOF_OK;
     case LMTOF_OPT_FORWARD:
         if (v != LMTOF_FORWARD_BRICKS && v != LMTOF_FORWARD_EVENTS)
             return fail(c, LMTOF_EINVAL, "forward projector must be LMTOF_FORWARD_BRICKS or LMTOF_FORWARD_EVENTS");
@@ -1128,6 +1162,7 @@ int lmtof_get_option(const lmtof_ctx *c, int key, int64_t *v) {
     case LMTOF_OPT_SORT_CELL_MM: *v = (int64_t)c->opt_cell_mm; return LMTOF_OK;
     case LMTOF_OPT_MEDIAN_SIEVE: *v = c->opt_median; return LMTOF_OK;
     case LMTOF_OPT_FORWARD: *v = c->opt_forward; return LMTOF_OK;
+    case LMTOF_OPT_BRICK_CHUNKS: *v = c->opt_bchunks; return LMTOF_OK;
     default: return LMTOF_EINVAL;
     }
 }
@@ -1506,7 +1541,7 @@ static int forward_events(lmtof_ctx *c, const float *x, int64_t nx_, float *f, i
         if ((rc = upload_problems(c, ps, block, ept, &dp, nch, nvch)) || (rc = build_items(c, ps, dp, nch, ept, its)))
             return done(rc);
         he = launch_forward_items(L, true, dp, 1, its.chunks, its.n_chunks, its.bricks);
-        if (he == hipSuccess) he = launch_combine(L, dp, 1, nch, ept, kCombineF, nullptr, nullptr, nullptr);
+        if (he == hipSuccess) he = launch_combine(L, dp, 1, nch, ept, kCombineF, nullptr, nullptr);
     } else {
         const int64_t nxb = assign_xblocks(ps, nullptr);
         if ((rc = dev_alloc(c, &xb, nxb * 64))) return done(rc);
@@ -1514,7 +1549,7 @@ static int forward_events(lmtof_ctx *c, const float *x, int64_t nx_, float *f, i
         if ((rc = upload_problems(c, ps, block, ept, &dp, nch, nvch))) return done(rc);
         he = hipMemsetAsync(xb, 0, sizeof(float) * 64 * (size_t)nxb, c->stream);
         if (he == hipSuccess) he = launch_block_image(L, dp, 1, nxb);
-        if (he == hipSuccess) he = launch_forward(L, tof, dp, 1, nch, ept, 1, nullptr, nullptr, nullptr);
+        if (he == hipSuccess) he = launch_forward(L, tof, dp, 1, nch, ept, 1, nullptr, nullptr);
     }
     if (he == hipSuccess && acf) he = launch_exp(L, fs, c->n_events);
     if (he == hipSuccess) he = launch_scatter_by_perm(L, fs, c->d_perm, c->n_events, fc);
@@ -1755,7 +1790,7 @@ int lmtof_back_project(lmtof_ctx *c, const float *w, int64_t nw, float *b, int64
     HIPCHK(c, hipSetDevice(c->device));
     Launch L;
     L.stream = c->stream;
-    float *dw = nullptr, *ws = nullptr, *db = nullptr, *pw = nullptr;
+    float *dw = nullptr, *ws = nullptr, *db = nullptr;
     Problem *dp = nullptr;
     ItemSet its;
     int rc = LMTOF_OK;
@@ -1763,7 +1798,6 @@ int lmtof_back_project(lmtof_ctx *c, const float *w, int64_t nw, float *b, int64
         (void)hipStreamSynchronize(c->stream);
         if (mem == LMTOF_MEM_HOST) { dev_free(dw); dev_free(db); }
         dev_free(ws);
-        dev_free(pw);
         dev_free(dp);
         free_items(its);
         return r;
@@ -1784,25 +1818,80 @@ int lmtof_back_project(lmtof_ctx *c, const float *w, int64_t nw, float *b, int64
     launch_shape(c, block, ept);
     int64_t nch, nvch;
     if ((rc = upload_problems(c, ps, block, ept, &dp, nch, nvch))) return done(rc);
-    if ((rc = build_items(c, ps, dp, nch, ept, its)) || (rc = dev_alloc(c, &pw, nch))) return done(rc);
+    if ((rc = build_items(c, ps, dp, nch, ept, its))) return done(rc);
     hipError_t he = launch_gather_by_perm(L, dw, c->d_perm, c->n_events, ws);
     if (he == hipSuccess) he = launch_fill(L, db, c->V, 0.0f);
-    // each event's weight onto its items, and the chunk maxima of |w|
-    if (he == hipSuccess) he = launch_combine(L, dp, 1, nch, ept, kCombineWeights, nullptr, nullptr, pw);
+    // each event's weight onto its items, and each brick's largest |w|
+    if (he == hipSuccess) he = launch_clear_bwmax(L, dp, 1, (int64_t)its.n_all_bricks);
+    if (he == hipSuccess) he = launch_combine(L, dp, 1, nch, ept, kCombineWeights, nullptr, nullptr);
     if (he != hipSuccess) return done(fail(c, LMTOF_EHIP, "back projection: %s", hipGetErrorString(he)));
-    if ((rc = add_back(c, L, dp, 1, its, pw, nch, nullptr))) return done(rc);
+    if ((rc = add_back(c, L, dp, 1, its, nullptr))) return done(rc);
     if (mem == LMTOF_MEM_HOST) rc = copy_out(c, b, db, sizeof(float) * c->V, LMTOF_MEM_HOST);
     else if (hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(c, LMTOF_EHIP, "back projection failed");
     return done(rc);
 }
 
-int lmtof_autotune(lmtof_ctx *c, int64_t *chosen, float *ms) {
+int lmtof_autotune(lmtof_ctx *c, int use_cache, lmtof_tune_result *out) {
     if (!c) return LMTOF_EINVAL;
     c->err.clear();
     if (!c->has_image) return fail(c, LMTOF_ESTATE, "set the image (lmtof_set_image) first");
     HIPCHK(c, hipSetDevice(c->device));
-    static const int cand[4] = {1, 2, 4, 8};
-    const int saved = c->opt_ept;
+    lmtof_tune_result res{};
+    // cache key: device architecture, grid, voxel, TOF FWHM, storage,
+    // regions, event count to a power of two
+    std::string key;
+    {
+        hipDeviceProp_t prop{};
+        HIPCHK(c, hipGetDeviceProperties(&prop, c->device));
+        char buf[512];
+        int l2n = 0;
+        while ((int64_t(1) << (l2n + 1)) <= c->n_events) ++l2n;
+        snprintf(buf, sizeof buf, "%s|%d,%d,%d|%.6g,%.6g,%.6g|%.6g|%d|%zu|%d", prop.gcnArchName, c->g.nx, c->g.ny,
+                 c->g.nz, c->g.vx, c->g.vy, c->g.vz, c->g.tof_fwhm_ps, c->opt_storage, c->regions.size(), l2n);
+        key = buf;
+    }
+    const int saved_fwd = c->opt_forward, saved_ept = c->opt_ept, saved_bch = c->opt_bchunks;
+    auto restore = [&](int rc) {
+        c->opt_forward = saved_fwd;
+        c->opt_ept = saved_ept;
+        c->opt_bchunks = saved_bch;
+        c->probs_dirty = true;
+        drop_graphs_only(c);
+        return rc;
+    };
+    // apply a configuration: options, brick lists, b cleared
+    auto apply = [&](int fwd, int ept, int bch) -> int {
+        if (ept != (c->opt_ept > 0 ? c->opt_ept : kDefaultEpt) || bch != c->opt_bchunks) c->probs_dirty = true;
+        c->opt_forward = fwd;
+        c->opt_ept = ept;
+        c->opt_bchunks = bch;
+        drop_graphs_only(c);
+        int rc = ensure_problems(c);
+        if (rc) return rc;
+        Launch L;
+        L.stream = c->stream;
+        for (const auto &P : c->probs)
+            HIPCHK(c, launch_fill(L, P.b, (int64_t)P.nx * P.ny * P.nz, 0.0f));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        return LMTOF_OK;
+    };
+    bool hit = false;
+    if (use_cache) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            res = it->second;
+            hit = true;
+        }
+    }
+    if (hit) {
+        int rc = apply(res.forward, res.events_per_thread, res.brick_chunks);
+        if (rc) return restore(rc);
+        res.n_candidates = 0;
+        res.cached = 1;
+        if (out) *out = res;
+        return LMTOF_OK;
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     auto cleanup = [&](int rc) {
         if (e0) (void)hipEventDestroy(e0);
@@ -1810,69 +1899,81 @@ int lmtof_autotune(lmtof_ctx *c, int64_t *chosen, float *ms) {
         return rc;
     };
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
-        return cleanup(fail(c, LMTOF_EHIP, "event creation failed"));
-    float t_cand[4] = {}, score[4] = {};
-    for (int k = 0; k < 4; ++k) {
-        c->opt_ept = cand[k];
-        c->probs_dirty = true;
+        return cleanup(restore(fail(c, LMTOF_EHIP, "event creation failed")));
+    // time one candidate: build its lists, then the fastest of three passes
+    // after a warm-up; cur_build is the build time of the lists now built
+    float cur_build = 0.0f;
+    c->probs_dirty = true;  // the first candidate builds (and times) its lists
+    auto timeit = [&](int fwd, int ept, int bch, float &score) -> int {
         const auto b0 = std::chrono::steady_clock::now();
-        int rc = ensure_problems(c);
-        if (!rc && hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(c, LMTOF_EHIP, "autotune failed");
-        const float build_ms =
-            std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - b0).count();
-        if (rc) {
-            c->opt_ept = saved;
-            c->probs_dirty = true;
-            return cleanup(rc);
-        }
+        const bool rebuild = ept != (c->opt_ept > 0 ? c->opt_ept : kDefaultEpt) || bch != c->opt_bchunks ||
+                             c->probs_dirty;
+        int rc = apply(fwd, ept, bch);
+        if (rc) return rc;
+        if (rebuild)
+            cur_build = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - b0).count();
         const int np = (int)c->probs.size();
         Launch L;
         L.stream = c->stream;
         float t = 0.0f;
-        // the first pass warms caches and code; the fastest of the next three counts
         for (int rep = 0; rep < 4; ++rep) {
-            hipError_t he = hipEventRecord(e0, c->stream);
-            if (he != hipSuccess) return cleanup(fail(c, LMTOF_EHIP, "autotune: %s", hipGetErrorString(he)));
+            HIPCHK(c, hipEventRecord(e0, c->stream));
             if ((rc = add_forward(c, L, c->d_probs, np, c->n_chunks, c->n_xblk, c->items, c->ept_used,
-                                  c->d_part_neff, c->d_part_ll, c->d_part_wmax, nullptr)))
-                return cleanup(rc);
-            if ((rc = add_back(c, L, c->d_probs, np, c->items, c->d_part_wmax, c->n_chunks, nullptr))) return cleanup(rc);
+                                  c->d_part_neff, c->d_part_ll, nullptr)))
+                return rc;
+            if ((rc = add_back(c, L, c->d_probs, np, c->items, nullptr))) return rc;
             float tr = 0.0f;
             if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                 hipEventElapsedTime(&tr, e0, e1) != hipSuccess)
-                return cleanup(fail(c, LMTOF_EHIP, "autotune timing failed"));
+                return fail(c, LMTOF_EHIP, "autotune timing failed");
             if (rep == 1 || (rep > 1 && tr < t)) t = tr;
         }
-        t_cand[k] = t;
-        // the brick lists are built once per reconstruction: a tenth of their
-        // build time is charged to each pass (reconstructions run ~10 iterations)
-        score[k] = t + build_ms / kAutotuneIters;
-        if (ms) ms[k] = t;
-    }
-    // The default shape stays unless another beats it by more than 1 %:
-    // closer passes are within the run-to-run spread of one timing.
-    int best = kDefaultEpt;
-    float best_ms = 0.0f;
-    for (int k = 0; k < 4; ++k)
-        if (cand[k] == kDefaultEpt) best_ms = score[k];
-    for (int k = 0; k < 4; ++k) {
-        if (score[k] < 0.99f * best_ms) {
-            best_ms = score[k];
-            best = cand[k];
+        if (res.n_candidates < LMTOF_TUNE_MAX_CANDIDATES) {
+            lmtof_tune_candidate &q = res.cand[res.n_candidates++];
+            q.forward = fwd;
+            q.events_per_thread = ept;
+            q.brick_chunks = bch;
+            q.pass_ms = t;
+            q.build_ms = cur_build;
         }
+        // the brick lists are built once per reconstruction: a tenth of
+        // their build time is charged to each pass (~10 iterations)
+        score = t + cur_build / kAutotuneIters;
+        return LMTOF_OK;
+    };
+    int best_f = LMTOF_FORWARD_BRICKS, best_e = kDefaultEpt, best_b = kDefaultBrickChunks;
+    float best = 0.0f;
+    int rc = timeit(best_f, best_e, best_b, best);
+    if (rc) return cleanup(restore(rc));
+    // a change must beat the incumbent by more than 1 % (closer is within
+    // the run-to-run spread of one timing)
+    auto consider = [&](int f, int e, int b) -> int {
+        float sc = 0.0f;
+        int r = timeit(f, e, b, sc);
+        if (r) return r;
+        if (sc < 0.99f * best) {
+            best = sc;
+            best_f = f;
+            best_e = e;
+            best_b = b;
+        }
+        return LMTOF_OK;
+    };
+    for (int e : {1, 2, 8})
+        if ((rc = consider(best_f, e, best_b))) return cleanup(restore(rc));
+    for (int b : {4096, 16384})
+        if ((rc = consider(best_f, best_e, b))) return cleanup(restore(rc));
+    if ((rc = consider(LMTOF_FORWARD_EVENTS, best_e, best_b))) return cleanup(restore(rc));
+    if ((rc = apply(best_f, best_e, best_b))) return cleanup(restore(rc));
+    res.forward = best_f;
+    res.events_per_thread = best_e;
+    res.brick_chunks = best_b;
+    res.cached = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = res;
     }
-    c->opt_ept = best;
-    c->probs_dirty = true;
-    int rc = ensure_problems(c);
-    if (rc) return cleanup(rc);
-    // the passes above wrote back projections into b: clear it for the next iteration
-    Launch L;
-    L.stream = c->stream;
-    for (const auto &P : c->probs)
-        if (launch_fill(L, P.b, (int64_t)P.nx * P.ny * P.nz, 0.0f) != hipSuccess)
-            return cleanup(fail(c, LMTOF_EHIP, "autotune: clearing b failed"));
-    if (hipStreamSynchronize(c->stream) != hipSuccess) return cleanup(fail(c, LMTOF_EHIP, "autotune failed"));
-    if (chosen) *chosen = best;
+    if (out) *out = res;
     return cleanup(LMTOF_OK);
 }
 
@@ -2087,6 +2188,14 @@ struct PoolReq {
     int64_t bytes = 0;
 };
 
+// A request handed to the preparation thread (its footprint is reserved).
+struct PrepJob {
+    int64_t id = 0;
+    lmtof_ctx *ctx = nullptr;
+    lmtof_request q{};
+    int64_t bytes = 0;
+};
+
 struct lmtof_pool {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -2095,6 +2204,18 @@ struct lmtof_pool {
     int64_t budget = 0, used = 0, next_id = 1;
     std::vector<PoolReq> active;
     std::map<int64_t, PoolReq> finished;
+    // Background preparation: one thread, its own stream.  mu guards used,
+    // jobs, preparing, prepared and failed (the thread touches nothing else
+    // of the pool); the calling thread owns everything else.
+    std::mutex mu;
+    std::condition_variable cv;
+    std::thread worker;
+    bool stop = false;
+    hipStream_t prep_stream = nullptr;
+    std::deque<PrepJob> jobs;
+    std::map<int64_t, bool> preparing;  // id -> TOF, from submit until the thread is done with it
+    std::vector<PoolReq> prepared;      // ready to join the batch
+    std::map<int64_t, std::pair<int, std::string>> failed;
     // contexts of released requests, kept with their device buffers for the
     // next admissions (a new request reuses one instead of allocating);
     // their bytes count against the budget and they are destroyed when an
@@ -2111,8 +2232,7 @@ struct lmtof_pool {
     int64_t n_chunks = 0, n_vchunks = 0;
     int *part_neff = nullptr;
     double *part_ll = nullptr, *part_old = nullptr, *part_new = nullptr;
-    float *part_wmax = nullptr;
-    int64_t n_xblk = 0;
+    int64_t n_xblk = 0, n_all_bricks = 0;
     size_t part_cap = 0, vpart_cap = 0;
     DevStats *d_stats = nullptr;
     size_t stats_cap = 0;
@@ -2151,6 +2271,57 @@ int pool_grow(lmtof_pool *p, T **ptr, size_t &cap, size_t n) {
     return LMTOF_OK;
 }
 
+// Ingest, bucketing, sensitivity, start image and brick lists of a request
+// on its context (on the context's stream), then wait for them.
+int prepare_request(lmtof_ctx *c, const lmtof_request &q) {
+    int rc;
+    if ((rc = lmtof_set_option(c, LMTOF_OPT_STORAGE, q.storage)) || (rc = lmtof_set_geometry(c, &q.geometry)) ||
+        (rc = lmtof_load_events(c, q.events, q.n_events, q.format, q.mem)) || (rc = lmtof_compute_sensitivity(c)) ||
+        (rc = lmtof_set_image(c, nullptr, 0, LMTOF_MEM_HOST)))
+        return rc;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, LMTOF_EHIP, "request preparation failed");
+    return LMTOF_OK;
+}
+
+// The preparation thread: takes queued requests in order and prepares each
+// on the pool's second stream while the calling thread steps the batch.
+void pool_worker(lmtof_pool *p) {
+    (void)hipSetDevice(p->device);
+    for (;;) {
+        PrepJob j;
+        {
+            std::unique_lock<std::mutex> lk(p->mu);
+            p->cv.wait(lk, [&] { return p->stop || !p->jobs.empty(); });
+            if (p->jobs.empty()) return;  // stop requested and nothing queued
+            j = p->jobs.front();
+            p->jobs.pop_front();
+        }
+        int rc = prepare_request(j.ctx, j.q);
+        std::string msg = rc ? std::string(lmtof_last_error(j.ctx)) : std::string();
+        if (!rc && j.ctx->ept_used != p->ept) {  // run lists and item slots index the forward chunks of this launch shape
+            rc = LMTOF_EUNSUPPORTED;
+            msg = "request prepared with a different launch shape";
+        }
+        const int64_t held = rc ? 0 : std::max(j.bytes, ctx_device_bytes(j.ctx));
+        {
+            std::lock_guard<std::mutex> lk(p->mu);
+            p->preparing.erase(j.id);
+            p->used += held - j.bytes;
+            if (rc) {
+                p->failed[j.id] = {rc, msg};
+            } else {
+                PoolReq r;
+                r.id = j.id;
+                r.ctx = j.ctx;
+                r.n_iter = j.q.n_iter;
+                r.bytes = held;
+                p->prepared.push_back(r);
+            }
+        }
+        if (rc) lmtof_destroy(j.ctx);
+    }
+}
+
 // Batch = every active request's problem; chunk ids, brick ids and update
 // chunks renumbered across the batch; brick chunks of all requests merged
 // largest first.
@@ -2184,10 +2355,8 @@ int pool_build_batch(lmtof_pool *p) {
         (rc = pool_grow(p, &p->d_stats, p->stats_cap, np)))
         return rc;
     if ((size_t)nch > p->part_cap) {
-        size_t c0 = p->part_cap, c1 = p->part_cap, c2 = p->part_cap;
-        if ((rc = pool_grow(p, &p->part_neff, c0, nch)) || (rc = pool_grow(p, &p->part_ll, c1, nch)) ||
-            (rc = pool_grow(p, &p->part_wmax, c2, nch)))
-            return rc;
+        size_t c0 = p->part_cap, c1 = p->part_cap;
+        if ((rc = pool_grow(p, &p->part_neff, c0, nch)) || (rc = pool_grow(p, &p->part_ll, c1, nch))) return rc;
         p->part_cap = nch;
     }
     if ((size_t)nvch > p->vpart_cap) {
@@ -2206,6 +2375,7 @@ int pool_build_batch(lmtof_pool *p) {
     p->n_chunks = nch;
     p->n_vchunks = nvch;
     p->n_xblk = nxb;
+    p->n_all_bricks = nb;
     p->dirty = false;
     return LMTOF_OK;
 }
@@ -2256,6 +2426,20 @@ int lmtof_pool_create(lmtof_pool **out, int hip_device, void *hip_stream, int64_
 int lmtof_pool_destroy(lmtof_pool *p) {
     if (!p) return LMTOF_OK;
     (void)hipSetDevice(p->device);
+    if (p->worker.joinable()) {
+        // drop the queued preparations, let the running one finish
+        std::deque<PrepJob> queued;
+        {
+            std::lock_guard<std::mutex> lk(p->mu);
+            queued.swap(p->jobs);
+            p->stop = true;
+        }
+        p->cv.notify_all();
+        p->worker.join();
+        for (auto &j : queued) lmtof_destroy(j.ctx);
+    }
+    for (auto &r : p->prepared) lmtof_destroy(r.ctx);
+    if (p->prep_stream) (void)hipStreamDestroy(p->prep_stream);
     (void)hipStreamSynchronize(p->stream);
     for (auto &r : p->active) lmtof_destroy(r.ctx);
     for (auto &kv : p->finished) lmtof_destroy(kv.second.ctx);
@@ -2265,7 +2449,6 @@ int lmtof_pool_destroy(lmtof_pool *p) {
     dev_free(p->d_bricks);
     dev_free(p->part_neff);
     dev_free(p->part_ll);
-    dev_free(p->part_wmax);
     dev_free(p->part_old);
     dev_free(p->part_new);
     dev_free(p->d_stats);
@@ -2289,10 +2472,16 @@ int lmtof_pool_submit(lmtof_pool *p, const lmtof_request *q, int64_t *id) {
     if (q->n_iter < 1 || q->n_iter > 10000) return pfail(p, LMTOF_EINVAL, "n_iter must be in [1, 10000]");
     if (q->storage != 0 && q->storage != 1) return pfail(p, LMTOF_EINVAL, "storage must be 0 or 1");
     if (q->n_events < 1) return pfail(p, LMTOF_EINVAL, "n_events must be >= 1");
+    if ((q->flags & ~LMTOF_REQ_BACKGROUND) || q->reserved0 != 0)
+        return pfail(p, LMTOF_EINVAL, "unknown request flags");
+    const bool background = (q->flags & LMTOF_REQ_BACKGROUND) != 0;
     const bool tof = q->geometry.tof_fwhm_ps > 0;
-    for (auto &r : p->active)
-        if ((r.ctx->g.tof_fwhm_ps > 0) != tof)
-            return pfail(p, LMTOF_EAGAIN, "TOF and non-TOF requests are not batched together; retry when drained");
+    std::unique_lock<std::mutex> lk(p->mu);
+    bool mixed = false;
+    for (auto &r : p->active) mixed = mixed || (r.ctx->g.tof_fwhm_ps > 0) != tof;
+    for (auto &r : p->prepared) mixed = mixed || (r.ctx->g.tof_fwhm_ps > 0) != tof;
+    for (auto &kv : p->preparing) mixed = mixed || kv.second != tof;
+    if (mixed) return pfail(p, LMTOF_EAGAIN, "TOF and non-TOF requests are not batched together; retry when drained");
     const int64_t est = request_bytes_estimate(*q);
     if (est > p->budget) return pfail(p, LMTOF_ENOMEM, "request needs ~%lld bytes, over the %lld-byte budget",
                                       (long long)est, (long long)p->budget);
@@ -2333,19 +2522,46 @@ int lmtof_pool_submit(lmtof_pool *p, const lmtof_request *q, int64_t *id) {
         p->spare.erase(p->spare.begin() + big);
     }
     int rc;
-    if (!c && (rc = lmtof_create(&c, p->device, p->stream))) return pfail(p, rc, "%s", lmtof_last_error(nullptr));
-    auto bail = [&](int code) {
+    if (background && !p->prep_stream) {
+        hipError_t e = hipStreamCreateWithFlags(&p->prep_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            p->prep_stream = nullptr;
+            if (c) p->spare.push_back(c);
+            return pfail(p, LMTOF_EHIP, "hipStreamCreate: %s", hipGetErrorString(e));
+        }
+    }
+    hipStream_t st = background ? p->prep_stream : p->stream;
+    if (!c && (rc = lmtof_create(&c, p->device, st))) return pfail(p, rc, "%s", lmtof_last_error(nullptr));
+    c->stream = st;  // (a reused context may come from the other stream)
+    if (background) {
+        if (!p->worker.joinable()) {
+            try {
+                p->worker = std::thread(pool_worker, p);
+            } catch (...) {
+                p->spare.push_back(c);
+                return pfail(p, LMTOF_ENOMEM, "could not start the preparation thread");
+            }
+        }
+        PrepJob j;
+        j.id = p->next_id++;
+        j.ctx = c;
+        j.q = *q;
+        j.bytes = est;
+        p->used += est;
+        p->preparing[j.id] = tof;
+        p->jobs.push_back(j);
+        lk.unlock();
+        p->cv.notify_one();
+        *id = j.id;
+        return LMTOF_OK;
+    }
+    lk.unlock();
+    if ((rc = prepare_request(c, *q))) {
         std::string m = lmtof_last_error(c);
         lmtof_destroy(c);
-        return pfail(p, code, "%s", m.c_str());
-    };
-    if ((rc = lmtof_set_option(c, LMTOF_OPT_STORAGE, q->storage))) return bail(rc);
-    if ((rc = lmtof_set_geometry(c, &q->geometry))) return bail(rc);
-    if ((rc = lmtof_load_events(c, q->events, q->n_events, q->format, q->mem))) return bail(rc);
-    if ((rc = lmtof_compute_sensitivity(c))) return bail(rc);
-    if ((rc = lmtof_set_image(c, nullptr, 0, LMTOF_MEM_HOST))) return bail(rc);
-    (void)hipStreamSynchronize(c->stream);
-    if (c->ept_used != p->ept) {  // brick pair lists index the forward chunks of this launch shape
+        return pfail(p, rc, "%s", m.c_str());
+    }
+    if (c->ept_used != p->ept) {  // run lists and item slots index the forward chunks of this launch shape
         lmtof_destroy(c);
         return pfail(p, LMTOF_EUNSUPPORTED, "request prepared with a different launch shape");
     }
@@ -2354,6 +2570,7 @@ int lmtof_pool_submit(lmtof_pool *p, const lmtof_request *q, int64_t *id) {
     r.ctx = c;
     r.n_iter = q->n_iter;
     r.bytes = std::max(est, ctx_device_bytes(c));
+    lk.lock();
     p->used += r.bytes;
     p->active.push_back(r);
     p->dirty = true;
@@ -2364,6 +2581,16 @@ int lmtof_pool_submit(lmtof_pool *p, const lmtof_request *q, int64_t *id) {
 int lmtof_pool_step(lmtof_pool *p, int *n_active) {
     if (!p) return LMTOF_EINVAL;
     p->err.clear();
+    {
+        // requests whose background preparation has finished join now
+        std::lock_guard<std::mutex> lk(p->mu);
+        for (auto &r : p->prepared) {
+            r.ctx->stream = p->stream;
+            p->active.push_back(r);
+            p->dirty = true;
+        }
+        p->prepared.clear();
+    }
     if (n_active) *n_active = (int)p->active.size();
     if (p->active.empty()) return LMTOF_OK;
     PHIP(p, hipSetDevice(p->device));
@@ -2374,9 +2601,8 @@ int lmtof_pool_step(lmtof_pool *p, int *n_active) {
     Launch L;
     L.stream = p->stream;
     PHIP(p, launch_forward_items(L, tof, p->d_probs, np, p->d_chunks, p->n_bchunks, p->d_bricks));
-    PHIP(p, launch_combine(L, p->d_probs, np, p->n_chunks, p->ept, kCombineRatio, p->part_neff, p->part_ll,
-                           p->part_wmax));
-    PHIP(p, launch_brick_wmax(L, p->d_probs, np, p->d_bricks, p->n_bbricks, p->part_wmax, p->n_chunks));
+    PHIP(p, launch_clear_bwmax(L, p->d_probs, np, p->n_all_bricks));
+    PHIP(p, launch_combine(L, p->d_probs, np, p->n_chunks, p->ept, kCombineRatio, p->part_neff, p->part_ll));
     PHIP(p, launch_back_chunks(L, tof, p->d_probs, np, p->d_chunks, p->n_bchunks, p->d_bricks));
     PHIP(p, launch_reduce_tiles(L, p->d_probs, np, p->d_bricks, p->n_bbricks));
     PHIP(p, launch_update(L, p->d_probs, np, p->n_vchunks, p->part_old, p->part_new));
@@ -2407,6 +2633,17 @@ int lmtof_pool_poll(lmtof_pool *p, int64_t id, int *done, float *out, int64_t n,
     if (it == p->finished.end()) {
         for (auto &r : p->active)
             if (r.id == id) return LMTOF_OK;
+        std::lock_guard<std::mutex> lk(p->mu);
+        auto f = p->failed.find(id);
+        if (f != p->failed.end()) {
+            const int code = f->second.first;
+            const std::string m = f->second.second;
+            p->failed.erase(f);
+            return pfail(p, code, "request %lld: %s", (long long)id, m.c_str());
+        }
+        if (p->preparing.count(id)) return LMTOF_OK;
+        for (auto &r : p->prepared)
+            if (r.id == id) return LMTOF_OK;
         return pfail(p, LMTOF_EINVAL, "unknown request id %lld", (long long)id);
     }
     lmtof_ctx *c = it->second.ctx;
@@ -2414,7 +2651,10 @@ int lmtof_pool_poll(lmtof_pool *p, int64_t id, int *done, float *out, int64_t n,
         int rc = lmtof_read_image(c, out, n, mem);
         if (rc) return pfail(p, rc, "%s", lmtof_last_error(c));
     }
-    p->used -= it->second.bytes;
+    {
+        std::lock_guard<std::mutex> lk(p->mu);
+        p->used -= it->second.bytes;
+    }
     p->spare.push_back(c);
     p->finished.erase(it);
     *done = 1;
@@ -2423,7 +2663,10 @@ int lmtof_pool_poll(lmtof_pool *p, int64_t id, int *done, float *out, int64_t n,
 
 int lmtof_pool_info(const lmtof_pool *p, int64_t *used, int64_t *budget, int *n_active, int *n_finished) {
     if (!p) return LMTOF_EINVAL;
-    if (used) *used = p->used;
+    if (used) {
+        std::lock_guard<std::mutex> lk(const_cast<lmtof_pool *>(p)->mu);
+        *used = p->used;
+    }
     if (budget) *budget = p->budget;
     if (n_active) *n_active = (int)p->active.size();
     if (n_finished) *n_finished = (int)p->finished.size();

@@ -12,14 +12,14 @@ namespace lmtof {
 // problem; the TOF-assisted data division runs one problem per body region.
 // Kernel-CDF table nodes, brick shape and launch shapes of the projector.
 constexpr int kLutN = 1025;  // odd: the centre of the window is a node
+// Cells of the brick projectors' piecewise-linear CDF table (odd: the
+// centre of the window is the middle of a cell).
+constexpr int kLinN = 4095;
 constexpr int kBrickX = 16, kBrickY = 16, kBrickZ = 16;
 constexpr int kBrickVox = kBrickX * kBrickY * kBrickZ;
 // Brick items are grouped by their voxel-plane crossings in the brick
 // (longest first), so that a wavefront's lanes walk similar lengths.
 constexpr int kItemClasses = 16;
-// Largest brick count of one problem (the brick item builder keeps a bitmap
-// of a problem's bricks in LDS).
-constexpr int kMaxProblemBricks = 65536;
 // Bytes of one brick item's walk record (two float4 and one uint2).
 constexpr int kItemRecBytes = 40;
 constexpr int kForwardBlock = 256;
@@ -46,6 +46,19 @@ struct Problem {
     // bricks: evitems[evoff[i] .. evoff[i + 1]) for problem-local event i
     const uint32_t *evoff;
     const uint32_t *evitems;
+    // How the combine pass reaches a forward chunk's items with coalesced
+    // accesses.  runs + chunk * kTabWords (chunk counted from this
+    // problem's first): the number of runs, then (first position, length,
+    // problem-local brick) of each run of consecutive positions the
+    // chunk's events fill (one run per (brick, item class) key).  Per
+    // item: its index in the chunk's items in event-major order (its
+    // event's evoff minus the chunk's first, plus its ordinal), or 0xffff
+    // for an item outside the runs or of a chunk with too many items.  Per
+    // event: 1 if any of its items was placed outside the runs (the combine
+    // pass then reaches all of them through evitems).
+    const uint32_t *runs;
+    const uint16_t *itemslot;
+    const uint8_t *evflag;
     // per item, its walk inside the brick, precomputed when the lists are
     // built: (A_x, A_y, A_z, t_a), (B_x, B_y, B_z, t_b), (k_x | k_y << 16,
     // k_z | local voxel << 16) with k the first plane index minus the anchor
@@ -53,9 +66,13 @@ struct Problem {
     const float4 *rec_b;
     const uint2 *rec_k;
     unsigned long long *tiles;  // 64-bit fixed-point chunk tiles, indexed by tile slot
-    float *wmax;          // per brick, at its first tile slot: bound on |w| over its items
-    const uint32_t *pairs;    // per brick: the problem-local forward chunks holding its items
-    const uint32_t *pair_off; // brick (problem-local id) -> range in pairs; nbx*nby*nbz + 1 entries
+    // per problem-local brick: the largest |w| over its items this
+    // iteration (FP32 bits, an unsigned max; cleared before the combine
+    // pass, which sets it), which fixes the brick's fixed-point scale
+    uint32_t *bwmax;
+    // per problem-local brick + 1: the position of its first item (items
+    // are grouped by brick)
+    const uint32_t *brick_off;
     int32_t packed;
     int32_t tof;
     int32_t nx, ny, nz;
@@ -69,7 +86,13 @@ struct Problem {
     float norm;           // 1 / (2 erf(K / sqrt 2)): makes the full kernel sum to 1
     const float4 *lut;    // kernel-CDF table: a pad entry, kLutN nodes over [-K, K] sigma, a pad entry
     float lut_a, lut_b;   // node position of t (mm): t * lut_a + (kLutN - 1) / 2; lut_b = (kLutN - 1) / 2 + 1.5 2^23
-    float lut_h2;         // h^2 / 2, h the node spacing in sigma units
+    // Piecewise-linear kernel CDF of the brick projectors: a pad entry,
+    // kLinN cells over [-K, K] sigma as (CDF at the cell's middle on the
+    // chord, CDF difference over the cell), a pad entry.  Cell of t (mm):
+    // the nearest integer to t * lin_a + (kLinN - 1) / 2; lin_b =
+    // (kLinN - 1) / 2 + 1.5 2^23.
+    const float2 *lin;
+    float lin_a, lin_b;
     float a_max;          // bound on one piece weight (TOF: 1, the kernel mass; else the voxel diagonal)
     int32_t brick_base;   // global id of this problem's first brick
     int32_t nbx, nby, nbz;// bricks per axis
@@ -121,9 +144,9 @@ inline hipError_t do_launch(const Launch &L, const void *func, dim3 grid, dim3 b
 int64_t project_chunk_events(int block, int ept);
 // Event-parallel forward projection per event into P.rw, gathering from
 // the blocked image copy P.xb; mode 0: 1 / f (0 if f <= 0) and per-chunk
-// partials (n_eff, sum log f, largest 1 / f); mode 1: f.
+// partials (n_eff, sum log f); mode 1: f.
 hipError_t launch_forward(const Launch &L, bool tof, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept,
-                          int mode, int *part_neff, double *part_ll, float *part_wmax);
+                          int mode, int *part_neff, double *part_ll);
 // Brick-owned forward projection: every brick chunk (see the back
 // projection) stages its brick of P.x in LDS and writes each item's partial
 // sum of a x to P.pw.
@@ -133,39 +156,42 @@ hipError_t launch_forward_items(const Launch &L, bool tof, const Problem *d_prob
 // its items' positions evitems[evoff[i] .. evoff[i + 1]):
 //   kCombineRatio: f = sum of the items' partials P.pw; w = 1 / f (0 if
 //     f <= 0), times P.evw[i] if set, written back to every item of the
-//     event; per-chunk partials as launch_forward mode 0 (largest |w|);
+//     event; per-chunk partials as launch_forward mode 0;
 //   kCombineF: P.rw[i] = f;
 //   kCombineWeights: w = P.rw[i], times P.evw[i] if set, written to every
-//     item of the event; part_wmax[chunk] = largest |w|.
+//     item of the event.
+// With kCombineRatio and kCombineWeights, P.bwmax (cleared first by
+// launch_clear_bwmax) receives each brick's largest |w| over its items.
 enum { kCombineRatio = 0, kCombineF = 1, kCombineWeights = 2 };
 hipError_t launch_combine(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept, int mode,
-                          int *part_neff, double *part_ll, float *part_wmax);
+                          int *part_neff, double *part_ll);
+// P.bwmax <- 0 for every brick of every problem (n_bricks in all).
+hipError_t launch_clear_bwmax(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_bricks);
 // Back projection by brick chunks.  Brick table entry (global brick id,
 // first tile slot, end tile slot, items in the brick); chunk (brick table
 // index, first item, end item, tile slot) over the items of the brick's
-// problem with their weights P.pw.  launch_brick_wmax (per-brick bound
-// on |w| from the forward chunks' maxima part_wmax[0, n_part)), then
-// launch_back_chunks, then launch_reduce_tiles (which writes every voxel of
-// the listed bricks of P.b).
-hipError_t launch_brick_wmax(const Launch &L, const Problem *d_probs, int n_probs, const uint4 *bricks,
-                             uint32_t n_bricks, const float *part_wmax, int64_t n_part);
+// problem with their weights P.pw, each brick's fixed-point scale from
+// P.bwmax.  launch_back_chunks, then launch_reduce_tiles (which writes
+// every voxel of the listed bricks of P.b).
 hipError_t launch_back_chunks(const Launch &L, bool tof, const Problem *d_probs, int n_probs, const uint4 *chunks,
                               uint32_t n_chunks, const uint4 *bricks);
 hipError_t launch_reduce_tiles(const Launch &L, const Problem *d_probs, int n_probs, const uint4 *bricks,
                                uint32_t n_bricks);
 // Brick item lists, keyed by global brick * kItemClasses + item class.
-// fill == 0 counts pieces per key into ctr, (forward chunk, brick) pairs
-// per global brick into pctr (one per chunk touching the brick) and each
-// event's pieces into P.evoff[i]; else writes every piece's walk record at
-// position ctr[key]++ (never past end[key]), the position to
-// P.evitems[P.evoff[i] + k] for the event's k-th piece, and problem-local
-// forward chunk indices to P.pairs at pctr[brick]++ (never past the brick's
-// P.pair_off end).  Same launch shape as the forward pass
-// (its chunks are the pairs' chunks).  Every problem has at most
-// kMaxProblemBricks bricks.  tabs (brick_item_tab_words(n_chunks) words)
-// carries each block's key table from the counting launch to the filling one.
+// fill == 0 counts pieces per key into ctr and each event's pieces into
+// P.evoff[i]; else writes every piece's walk record at position ctr[key]++
+// (never past end[key]), the position to P.evitems[P.evoff[i] + k] for the
+// event's k-th piece, the item's combine slot, the event's flag and the
+// chunk's run list.  Same launch shape as the forward pass (its chunks are
+// the combine pass's chunks).  tabs (brick_item_tab_words(n_chunks) words)
+// carries each block's key table from the counting launch to the filling
+// one, which replaces it with the run list.
 hipError_t launch_brick_items(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept,
-                              uint32_t *ctr, const uint32_t *end, uint32_t *pctr, int fill, uint32_t *tabs);
+                              uint32_t *ctr, const uint32_t *end, int fill, uint32_t *tabs);
+// Words of one forward chunk's table: the builder's (key, count) pairs of
+// its LDS hash table (count pass), then the run count and 3 words per run
+// (fill pass).
+constexpr int64_t kTabWords = 3 * 1024 + 2;
 int64_t brick_item_tab_words(int64_t n_chunks);
 // part[2c] = voxel pieces visited by chunk c, part[2c+1] = pieces with non-zero weight.
 hipError_t launch_count_pieces(const Launch &L, bool tof, const Problem *d_probs, int n_probs, int64_t n_chunks,

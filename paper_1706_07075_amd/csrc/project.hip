@@ -236,7 +236,6 @@ __device__ __forceinline__ int voxel_at(float t, float u, int j, float d, float 
 // the position to the nearest node k and returns 1.5 2^23 + k exactly, whose
 // bit pattern is that of 1.5 2^23 plus k: one shift-add gives the entry's
 // byte offset.  |t| <= K sigma keeps k in [0, kLutN - 1].
-constexpr float kLutRound = 12582912.0f;  // 1.5 2^23: the FP32 spacing there is 1
 constexpr uint32_t kLutAddrBias = 16u - (0x4B400000u << 4);  // 16 (k + 1) - (bits(1.5 2^23 + k) << 4)
 
 // One vector-register copy of a uniform value for a loop, instead of a
@@ -260,24 +259,31 @@ struct Cdf {
     }
 };
 
-// The same CDF from (Phi_k, Phi'_k h) pairs, 8 bytes a node (less LDS
-// traffic per lookup): since Phi'' = -u Phi' and u_k = (k - c) h, the
-// curvature term Phi''_k h^2 / 2 is (c - k) (h^2 / 2) Phi'_k h, and c - k is
-// b - y, exactly.
-constexpr uint32_t kLutAddrBias2 = 8u - (0x4B400000u << 3);  // 8 (k + 1) - (bits(1.5 2^23 + k) << 3)
+// Byte offset of entry j + 1 of an 8-byte-entry table from the bits of
+// 1.5 2^23 + j.
+constexpr uint32_t kLutAddrBias2 = 8u - (0x4B400000u << 3);  // 8 (j + 1) - (bits(1.5 2^23 + j) << 3)
 
-struct Cdf2 {
+// The brick projectors' CDF: the piecewise-linear table (see Problem.lin).
+// fma(t, a, b) rounds the cell position to the nearest integer j and
+// returns 1.5 2^23 + j (as the Cdf above); f = position - j is the offset
+// from the cell's middle, and CDF = mid + f diff: one LDS read of 8 bytes
+// and three FMAs (plus the address), against five more for the quadratic
+// nodes.
+struct CdfLin {
     const float2 *tab;
-    float a, b, h2;  // h2 = h^2 / 2, h the node spacing in sigma units
+    float a, b;
     __device__ __forceinline__ float operator()(float t) const {
-        const float y = fmaf(t, a, b);      // 1.5 2^23 + k
-        const float ck = b - y;             // c - k
-        const float f = fmaf(t, a, ck);     // position - k, in [-1/2, 1/2]
+        const float y = fmaf(t, a, b);      // 1.5 2^23 + j
+        const float f = fmaf(t, a, b - y);  // position - j, in [-1/2, 1/2]
         const float2 e = *reinterpret_cast<const float2 *>(reinterpret_cast<const char *>(tab) +
                                                            ((__float_as_uint(y) << 3) + kLutAddrBias2));
-        return fmaf(f * e.y, fmaf(f * ck, h2, 1.0f), e.x);
+        return fmaf(f, e.y, e.x);
     }
 };
+
+__device__ __forceinline__ void stage_lin(float2 *lds, const float2 *src) {
+    for (int k = threadIdx.x; k < kLinN + 2; k += blockDim.x) lds[k] = src[k];
+}
 
 // A voxel box the traversal is confined to (the whole grid or one brick),
 // with the strides of the index it reports.
@@ -527,6 +533,15 @@ __device__ __forceinline__ int find_problem(const Problem *probs, int n_probs, i
     return p;
 }
 
+// Chunk of workgroup b of n: the hardware deals workgroups to the 8 XCDs
+// in turn (b mod 8); this gives XCD x the x-th contiguous eighth of the
+// chunks, in order.
+__device__ __forceinline__ int64_t xcd_chunk(uint32_t b, uint32_t n) {
+    const uint32_t per = (n + 7) / 8, x = b & 7u, r = b >> 3;
+    const uint32_t full = n - (per - 1) * 8;  // XCDs that get `per` chunks (the rest get per - 1)
+    return x < full ? (int64_t)x * per + r : (int64_t)full * per + (int64_t)(x - full) * (per - 1) + r;
+}
+
 __device__ __forceinline__ int find_brick_problem(const Problem *probs, int n_probs, uint32_t b) {
     int p = n_probs - 1;
     while (p > 0 && (uint32_t)probs[p].brick_base > b) --p;
@@ -578,7 +593,7 @@ __device__ __forceinline__ float forward_ray(const Problem &P, const Ray &r, con
 // of log f); mode 1: out[i] = f_i.  out is indexed by stored event position.
 template <bool TOF, bool PACKED>
 __device__ __forceinline__ void forward_chunk(const Problem &P, int64_t base, int ept, int mode, const Cdf &cdf,
-                                              int &neff, float &ll, float &wmax) {
+                                              int &neff, float &ll) {
     const gptr<const float> xb = global(P.xb);
     const gptr<float> out = global(P.rw);
     // last float of the copy: steps just past the grid edge stay inside it
@@ -593,7 +608,6 @@ __device__ __forceinline__ void forward_chunk(const Problem &P, int64_t base, in
             const float w = pos ? 1.0f / f : 0.0f;
             neff += pos;
             ll += pos ? logf(f) : 0.0f;
-            wmax = fmaxf(wmax, w);
             out[i] = w;
         } else {
             out[i] = f;
@@ -604,12 +618,10 @@ __device__ __forceinline__ void forward_chunk(const Problem &P, int64_t base, in
 template <bool TOF>
 __global__ void __launch_bounds__(kForwardBlock) k_forward(const Problem *__restrict__ probs, int n_probs, int ept,
                                                            int mode, int *__restrict__ part_neff,
-                                                           double *__restrict__ part_ll,
-                                                           float *__restrict__ part_wmax) {
+                                                           double *__restrict__ part_ll) {
     __shared__ float4 lut[kLutN + 2];
     __shared__ int s_n[kForwardBlock / 64];
     __shared__ double s_l[kForwardBlock / 64];
-    __shared__ float s_w[kForwardBlock / 64];
     const int64_t c = blockIdx.x;
     const Problem P = probs[find_problem(probs, n_probs, c)];
     if (TOF) stage_lut(lut, P.lut);
@@ -617,39 +629,34 @@ __global__ void __launch_bounds__(kForwardBlock) k_forward(const Problem *__rest
     const Cdf cdf{lut, in_vgpr(P.lut_a), P.lut_b};
     const int64_t base = (c - P.chunk_begin) * (int64_t)blockDim.x * ept;
     int neff = 0;
-    float ll = 0.0f, wmax = 0.0f;
+    float ll = 0.0f;
     if (P.packed)
-        forward_chunk<TOF, true>(P, base, ept, mode, cdf, neff, ll, wmax);
+        forward_chunk<TOF, true>(P, base, ept, mode, cdf, neff, ll);
     else
-        forward_chunk<TOF, false>(P, base, ept, mode, cdf, neff, ll, wmax);
+        forward_chunk<TOF, false>(P, base, ept, mode, cdf, neff, ll);
     if (mode == 0) {
         const int wn = wave_sum(neff);
         const double wl = wave_sum((double)ll);
-        const float ww = wave_max(wmax);
         const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
         if (lane == 0) {
             s_n[wid] = wn;
             s_l[wid] = wl;
-            s_w[wid] = ww;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
             int tn = 0;
             double tl = 0.0;
-            float tw = 0.0f;
             for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
                 tn += s_n[w];
                 tl += s_l[w];
-                tw = fmaxf(tw, s_w[w]);
             }
             part_neff[c] = tn;
             part_ll[c] = tl;
-            part_wmax[c] = tw;
         }
     }
 }
 
-// Back projection, in three launches over the brick chunks.
+// Back projection, in two launches over the brick chunks.
 //
 // The LDS accumulation is 64-bit fixed point: FP32 LDS atomic adds run at
 // ~0.2 T/s on this part, 64-bit integer ones at ~2.8 T/s.  A brick's
@@ -664,29 +671,20 @@ __global__ void __launch_bounds__(kForwardBlock) k_forward(const Problem *__rest
 // Brick table entry (brick id, first tile slot, end tile slot, items in the
 // brick); chunk (brick table index, first item, end item, tile slot).
 
-// 1. Bound on |w| over each brick's items: the largest of the forward
-//    chunk maxima over the chunks holding its events (one wave per brick).
-//    w >= 0 here (MLEM ratios), so the forward pass's max of w is max |w|.
-__global__ void __launch_bounds__(64) k_brick_wmax(const Problem *__restrict__ probs, int n_probs,
-                                                   const uint4 *__restrict__ bricks,
-                                                   const float *__restrict__ part_wmax, int64_t n_part) {
-    const uint4 br = bricks[blockIdx.x];
-    const Problem &P = probs[find_brick_problem(probs, n_probs, br.x)];
-    const uint32_t bl = br.x - (uint32_t)P.brick_base;
-    const gptr<const uint32_t> pairs = global(P.pairs);
-    const uint32_t k0 = P.pair_off[bl], k1 = P.pair_off[bl + 1];
-    float wm = 0.0f;
-    for (uint32_t k = k0 + threadIdx.x; k < k1; k += 64) {
-        const int64_t q = P.chunk_begin + pairs[k];
-        if (q < n_part) wm = fmaxf(wm, part_wmax[q]);
-    }
-    wm = wave_max(wm);
-    if (threadIdx.x == 0) global(P.wmax)[br.y] = wm;
+// P.bwmax <- 0 over every problem's bricks (before the combine pass sets it).
+__global__ void __launch_bounds__(256) k_clear_bwmax(const Problem *__restrict__ probs, int n_probs,
+                                                     int64_t n_bricks) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_bricks) return;
+    const Problem &P = probs[find_brick_problem(probs, n_probs, (uint32_t)g)];
+    P.bwmax[(uint32_t)g - (uint32_t)P.brick_base] = 0u;
 }
 
-// Fixed-point exponent of a brick (same value in every chunk and the reduce).
+// Fixed-point exponent of a brick (same value in every chunk and the
+// reduce), from the largest |w| over its items (an order-independent
+// bound: the same whatever events share the forward chunks).
 __device__ __forceinline__ int brick_exponent(const Problem &P, const uint4 &br, float &wmax) {
-    const float wm = P.wmax[br.y];
+    const float wm = __uint_as_float(P.bwmax[br.x - (uint32_t)P.brick_base]);
     wmax = wm;
     int en, ea, ew;
     frexpf((float)br.w, &en);
@@ -712,7 +710,7 @@ __device__ __forceinline__ unsigned long long fixed_round(float a, double w) {
 // as round(a ws) (ws may be negative; so may a, by ~1e-10 where the
 // interpolated CDF dips between nodes).
 template <bool TOF>
-__device__ __forceinline__ void back_item(const f32x4 &ra, const f32x4 &rb, const u32x2 &rk, float ws, const Cdf2 &cdf,
+__device__ __forceinline__ void back_item(const f32x4 &ra, const f32x4 &rb, const u32x2 &rk, float ws, const CdfLin &cdf,
                                           unsigned long long *tile) {
     Ray r;
     r.ax = ra[0];
@@ -731,7 +729,7 @@ __device__ __forceinline__ void back_item(const f32x4 &ra, const f32x4 &rb, cons
 }
 
 template <bool TOF>
-__device__ __forceinline__ void back_chunk_items(const Problem &P, const uint4 &ch, float S, const Cdf2 &cdf,
+__device__ __forceinline__ void back_chunk_items(const Problem &P, const uint4 &ch, float S, const CdfLin &cdf,
                                                  unsigned long long *tile) {
     const gptr<const float> w = global(P.pw);
     const gptr<const f32x4> rec_a = global(reinterpret_cast<const f32x4 *>(P.rec_a));
@@ -757,19 +755,18 @@ __global__ void __launch_bounds__(kBackBlock) k_back_chunks(const Problem *__res
                                                             const uint4 *__restrict__ chunks,
                                                             const uint4 *__restrict__ bricks) {
     __shared__ unsigned long long tile[kTileSlots];
-    __shared__ float2 lut[kLutN + 2];
+    __shared__ float2 lut[kLinN + 2];
     const uint4 ch = chunks[blockIdx.x];
     const uint4 br = bricks[ch.x];
     const uint32_t bid = br.x;
     const Problem P = probs[find_brick_problem(probs, n_probs, bid)];
     for (int k = threadIdx.x; k < kTileSlots; k += blockDim.x) tile[k] = 0ull;
-    if (TOF)
-        for (int k = threadIdx.x; k < kLutN + 2; k += blockDim.x) lut[k] = make_float2(P.lut[k].x, P.lut[k].y);
+    if (TOF) stage_lin(lut, P.lin);
     __syncthreads();
     float wm;
     const int e = brick_exponent(P, br, wm);
     const float S = ldexpf(1.0f, e);
-    const Cdf2 cdf{lut, in_vgpr(P.lut_a), P.lut_b, P.lut_h2};
+    const CdfLin cdf{lut, in_vgpr(P.lin_a), P.lin_b};
     if (wm > 0.0f) back_chunk_items<TOF>(P, ch, S, cdf, tile);
     __syncthreads();
     const gptr<unsigned long long> dst = global(P.tiles) + (size_t)ch.w * kBrickVox;
@@ -823,7 +820,7 @@ __global__ void __launch_bounds__(kBackBlock) k_forward_items(const Problem *__r
                                                               const uint4 *__restrict__ chunks,
                                                               const uint4 *__restrict__ bricks) {
     __shared__ float tile[kTileSlots];
-    __shared__ float2 lut[kLutN + 2];
+    __shared__ float2 lut[kLinN + 2];
     const uint4 ch = chunks[blockIdx.x];
     const uint4 br = bricks[ch.x];
     const Problem P = probs[find_brick_problem(probs, n_probs, br.x)];
@@ -832,8 +829,7 @@ __global__ void __launch_bounds__(kBackBlock) k_forward_items(const Problem *__r
               bz = (int)(bl / ((uint32_t)P.nbx * (uint32_t)P.nby));
     const Box B = brick_box(P, bx, by, bz);
     for (int k = threadIdx.x; k < kTileSlots; k += blockDim.x) tile[k] = 0.0f;
-    if (TOF)
-        for (int k = threadIdx.x; k < kLutN + 2; k += blockDim.x) lut[k] = make_float2(P.lut[k].x, P.lut[k].y);
+    if (TOF) stage_lin(lut, P.lin);
     __syncthreads();
     const gptr<const float> x = global(P.x);
     for (int k = threadIdx.x; k < kBrickVox; k += blockDim.x) {
@@ -843,7 +839,7 @@ __global__ void __launch_bounds__(kBackBlock) k_forward_items(const Problem *__r
                 x[(B.x0 + lx) + (int64_t)P.nx * ((B.y0 + ly) + (int64_t)P.ny * (B.z0 + lz))];
     }
     __syncthreads();
-    const Cdf2 cdf{lut, in_vgpr(P.lut_a), P.lut_b, P.lut_h2};
+    const CdfLin cdf{lut, in_vgpr(P.lin_a), P.lin_b};
     const gptr<float> pw = global(P.pw);
     const gptr<const f32x4> rec_a = global(reinterpret_cast<const f32x4 *>(P.rec_a));
     const gptr<const f32x4> rec_b = global(reinterpret_cast<const f32x4 *>(P.rec_b));
@@ -869,115 +865,356 @@ __global__ void __launch_bounds__(kBackBlock) k_forward_items(const Problem *__r
     }
 }
 
-// Per event, over its items (see launch_combine).  Same chunks of events as
-// the event-parallel forward pass, whose per-chunk partials it writes.  An
-// event has a few items (about 3.3 on the whole-body workload): the first
-// kCombineUnroll positions are loaded together, then their partials, so an
-// event costs two dependent memory round trips, and the next event's
-// offsets are loaded while this one is summed.  Partials are added in the
-// order the window crosses the bricks.
-constexpr int kCombineUnroll = 8;
+// The combine pass (see launch_combine), one forward chunk of events per
+// 1024-lane workgroup.  The builder recorded the runs of consecutive
+// positions the chunk's events fill (one per (brick, item class) key) and,
+// per item, its slot in the chunk's event-major order (its event's offset
+// plus its ordinal).  Phase 1 reads the items run by run (consecutive lanes,
+// consecutive positions) into their LDS slots; phase 2 sums each event's
+// slots in ordinal order (the order its window crosses the bricks) and puts
+// its weight in every one of its slots; phase 3 writes the slots back to the
+// items run by run and keeps their |w| in run order; phase 4 takes each
+// brick's largest |w| in LDS, then adds it to P.bwmax (one global atomic per
+// brick the chunk touches).  Events the builder flagged (an item placed outside the
+// runs) are summed and written through evitems in phase 2, their items'
+// bricks found by binary search; a chunk with more than kRunEvents events or
+// kRunItems items takes that path for every event.
+constexpr int kRunEvents = 2048;
+constexpr int kRunItems = 8192;
+constexpr int kMaxRuns = 1024;  // a chunk has at most one run per slot of the builder's hash table
+constexpr int kCombineBlock = 1024;
+constexpr int kRunItemsPerThread = kRunItems / kCombineBlock;
+constexpr int kCombineEventsPerThread = 4;  // chunks of up to 4096 events (16 per lane of a 256-lane chunk)
+constexpr int kBrickSlots = 256;            // LDS table of a chunk's bricks (their maxima)
+constexpr int kRunsEager = 256;             // run rows loaded before the run count is known
 
-__global__ void __launch_bounds__(kForwardBlock) k_combine(const Problem *__restrict__ probs, int n_probs, int ept,
-                                                           int mode, int *__restrict__ part_neff,
-                                                           double *__restrict__ part_ll,
-                                                           float *__restrict__ part_wmax) {
-    __shared__ int s_n[kForwardBlock / 64];
-    __shared__ double s_l[kForwardBlock / 64];
-    __shared__ float s_w[kForwardBlock / 64];
-    const int64_t c = blockIdx.x;
-    const Problem &P = probs[find_problem(probs, n_probs, c)];
-    const int64_t base = (c - P.chunk_begin) * (int64_t)blockDim.x * ept;
-    const int64_t n_events = P.n_events;
+// v from the lane `off` below in its row of 16 (row_shr); the row's first
+// `off` lanes get no valid value (callers test the lane's place).
+template <int off>
+__device__ __forceinline__ uint32_t row_up(uint32_t v, uint32_t none) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)none, (int)v, 0x110 | off, 0xf, 0xf, false);
+}
+// v from the next lane in its row of 16 (row_shl:1); not valid in the row's
+// last lane.
+__device__ __forceinline__ uint32_t row_next(uint32_t v, uint32_t none) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)none, (int)v, 0x101, 0xf, 0xf, false);
+}
+
+// Problem-local brick holding item position q (items are grouped by brick).
+__device__ __forceinline__ uint32_t brick_of(const Problem &P, uint32_t q) {
+    const gptr<const uint32_t> off = global(P.brick_off);
+    uint32_t lo = 0, hi = (uint32_t)P.nbx * (uint32_t)P.nby * (uint32_t)P.nbz;  // off[lo] <= q < off[hi]
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (off[mid] <= q)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// An event's f from its items' partials, through evitems.
+__device__ __forceinline__ float combine_event_global(const Problem &P, uint32_t k0, uint32_t k1) {
+    const gptr<const float> pw = global(P.pw);
+    const gptr<const uint32_t> evitems = global(P.evitems);
+    float f = 0.0f;
+    for (uint32_t k = k0; k < k1; ++k) {
+        const uint32_t q = evitems[k];
+        f += q < P.n_items ? pw[q] : 0.0f;
+    }
+    return f;
+}
+
+// An event's weight onto its items, through evitems; with maxima, each
+// item's brick maximum too.
+__device__ __forceinline__ void scatter_event_global(const Problem &P, uint32_t k0, uint32_t k1, float w,
+                                                     bool maxima) {
     const gptr<float> pw = global(P.pw);
     const gptr<const uint32_t> evitems = global(P.evitems);
-    const gptr<const uint32_t> evoff = global(P.evoff);
-    const float *evw = P.evw;
-    const uint32_t n_items = P.n_items;
-    int neff = 0;
-    float ll = 0.0f, wmax = 0.0f;
-    int64_t i = base + threadIdx.x;
-    uint32_t k0 = 0, k1 = 0;
-    if (i < n_events) {
-        k0 = evoff[i];
-        k1 = evoff[i + 1];
+    for (uint32_t k = k0; k < k1; ++k) {
+        const uint32_t q = evitems[k];
+        if (q >= P.n_items) continue;
+        pw[q] = w;
+        if (maxima) atomicMax(P.bwmax + brick_of(P, q), __float_as_uint(fabsf(w)));
     }
-    for (int e = 0; e < ept && i < n_events; ++e, i += blockDim.x) {
-        // the next event's offsets, while this one is summed
-        const int64_t in = i + blockDim.x;
-        const bool more = e + 1 < ept && in < n_events;
-        const uint32_t n0 = more ? evoff[in] : 0u, n1 = more ? evoff[in + 1] : 0u;
-        const uint32_t cnt = k1 - k0;
-        uint32_t q[kCombineUnroll];
+}
+
+__device__ __forceinline__ int brick_slot(uint32_t *keys, uint32_t key) {
+    int h = (int)((key * 2654435761u) >> 24);
+    for (int probe = 0; probe < kBrickSlots; ++probe) {
+        uint32_t k = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (k == 0xffffffffu) {
+            k = atomicCAS(&keys[h], 0xffffffffu, key);
+            if (k == 0xffffffffu) return h;
+        }
+        if (k == key) return h;
+        h = (h + 1) & (kBrickSlots - 1);
+    }
+    return -1;
+}
+
+__global__ void __launch_bounds__(kCombineBlock) k_combine(const Problem *__restrict__ probs, int n_probs, int ept,
+                                                           int mode, int *__restrict__ part_neff,
+                                                           double *__restrict__ part_ll) {
+    __shared__ __align__(16) float slot[kRunItems];
+    __shared__ __align__(16) uint16_t rid[kRunItems];
+    __shared__ uint32_t rbase[kMaxRuns], rpre[kMaxRuns], rbrick[kMaxRuns];
+    __shared__ int16_t rslot[kMaxRuns];
+    __shared__ uint32_t bkey[kBrickSlots], bmax[kBrickSlots];
+    __shared__ uint32_t s_tot[kCombineBlock / 64 + 1];
+    __shared__ int s_n[kCombineBlock / 64];
+    __shared__ double s_l[kCombineBlock / 64];
+    // Workgroups are dealt to the 8 XCDs in turn; chunk c of XCD x's share
+    // goes to x's workgroups in order, so neighbouring chunks (whose runs
+    // sit side by side in the item lists and share cache lines) are
+    // combined by one XCD at about the same time, in one L2.
+    const int64_t c = xcd_chunk(blockIdx.x, gridDim.x);
+    const Problem &P = probs[find_problem(probs, n_probs, c)];
+    const int64_t base = (c - P.chunk_begin) * (int64_t)kForwardBlock * ept;
+    const int n_ev = (int)min((int64_t)kForwardBlock * ept, P.n_events - base);
+    const bool maxima = mode != kCombineF;
+    const gptr<float> pw = global(P.pw);
+    const gptr<const uint16_t> itemslot = global(P.itemslot);
+    const gptr<const uint32_t> evoff = global(P.evoff);
+    const gptr<const uint32_t> runs = global(P.runs) + (size_t)(c - P.chunk_begin) * kTabWords;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    // this thread's events (tid + q blockDim), their offsets and flags,
+    // loaded with the first runs
+    uint32_t k0[kCombineEventsPerThread], k1[kCombineEventsPerThread];
+    bool has_ev[kCombineEventsPerThread], flagged[kCombineEventsPerThread];
 #pragma unroll
-        for (int j = 0; j < kCombineUnroll; ++j) q[j] = (uint32_t)j < cnt ? evitems[k0 + j] : 0xffffffffu;
+    for (int q = 0; q < kCombineEventsPerThread; ++q) {
+        const int le = tid + q * kCombineBlock;
+        has_ev[q] = le < n_ev;
+        k0[q] = has_ev[q] ? evoff[base + le] : 0u;
+        k1[q] = has_ev[q] ? evoff[base + le + 1] : 0u;
+        flagged[q] = has_ev[q] && P.evflag[base + le];
+    }
+    const uint32_t E0 = evoff[base], E1 = evoff[base + n_ev];
+    const uint32_t nr = runs[0];
+    // rows past kRunsEager are loaded once the count says they exist (a
+    // chunk has ~100 runs: the whole table would be 12 KB a chunk)
+    uint32_t rb = 0, rl = 0, rk = 0;
+    if (tid < kRunsEager) {
+        rb = runs[1 + 3 * tid];
+        rl = runs[2 + 3 * tid];
+        rk = runs[3 + 3 * tid];
+    } else if ((uint32_t)tid < nr) {
+        rb = runs[1 + 3 * tid];
+        rl = runs[2 + 3 * tid];
+        rk = runs[3 + 3 * tid];
+    }
+    const uint32_t len = (uint32_t)tid < nr ? rl : 0u;
+    if ((uint32_t)tid < nr) {
+        rbase[tid] = rb;
+        rbrick[tid] = rk;
+    }
+    if (tid < kBrickSlots) {
+        bkey[tid] = 0xffffffffu;
+        bmax[tid] = 0u;
+    }
+    // exclusive prefix of the run lengths
+    uint32_t x = len;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) s_tot[wid] = x;
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t run = 0;
+        for (int w = 0; w < kCombineBlock / 64; ++w) {
+            const uint32_t t = s_tot[w];
+            s_tot[w] = run;
+            run += t;
+        }
+        s_tot[kCombineBlock / 64] = run;
+    }
+    __syncthreads();
+    const uint32_t pre = x - len + s_tot[wid];
+    const uint32_t T = s_tot[kCombineBlock / 64];
+    const bool by_runs = n_ev <= kRunEvents && E1 - E0 <= (uint32_t)kRunItems && T <= E1 - E0;
+    if (by_runs && (uint32_t)tid < nr) {
+        rpre[tid] = pre;
+        for (uint32_t q = 0; q < len; ++q) rid[pre + q] = (uint16_t)tid;
+        rslot[tid] = maxima ? (int16_t)brick_slot(bkey, rk) : (int16_t)-1;
+    }
+    __syncthreads();
+    // phase 1: the thread's items (positions and slots kept for phase 3)
+    uint32_t pos[kRunItemsPerThread], sl[kRunItemsPerThread];
+#pragma unroll
+    for (int m = 0; m < kRunItemsPerThread; ++m) {
+        const uint32_t t = (uint32_t)(tid + m * kCombineBlock);
+        pos[m] = 0;
+        sl[m] = 0xffffu;
+        if (by_runs && t < T) {
+            const uint32_t r = rid[t];
+            pos[m] = rbase[r] + (t - rpre[r]);
+            sl[m] = itemslot[pos[m]];
+        }
+    }
+    if (mode != kCombineWeights) {
+        // (loaded with the slots, not after them: pos is a run position)
+        float v[kRunItemsPerThread];
+#pragma unroll
+        for (int m = 0; m < kRunItemsPerThread; ++m)
+            v[m] = by_runs && (uint32_t)(tid + m * kCombineBlock) < T ? pw[pos[m]] : 0.0f;
+#pragma unroll
+        for (int m = 0; m < kRunItemsPerThread; ++m)
+            if (sl[m] != 0xffffu) slot[sl[m]] = v[m];
+    }
+    __syncthreads();
+    // phase 2: the thread's events
+    int neff = 0;
+    float ll = 0.0f;
+#pragma unroll
+    for (int q = 0; q < kCombineEventsPerThread; ++q) {
+        if (!has_ev[q]) continue;
+        const int64_t i = base + tid + q * kCombineBlock;
+        const bool glob = !by_runs || flagged[q];
+        const uint32_t s0 = k0[q] - E0, cnt = k1[q] - k0[q];
         float w;
         if (mode == kCombineWeights) {
             w = P.rw[i];
         } else {
-            float v[kCombineUnroll];
-#pragma unroll
-            for (int j = 0; j < kCombineUnroll; ++j) v[j] = q[j] < n_items ? pw[q[j]] : 0.0f;
             float f = 0.0f;
-#pragma unroll
-            for (int j = 0; j < kCombineUnroll; ++j) f += v[j];  // (adding 0 past the count changes nothing)
-            for (uint32_t k = k0 + kCombineUnroll; k < k1; ++k) {
-                const uint32_t qq = evitems[k];
-                f += qq < n_items ? pw[qq] : 0.0f;
+            if (glob) {
+                f = combine_event_global(P, k0[q], k1[q]);
+            } else {
+                for (uint32_t k = 0; k < cnt; ++k) f += slot[s0 + k];
             }
             if (mode == kCombineF) {
                 global(P.rw)[i] = f;
-                k0 = n0;
-                k1 = n1;
                 continue;
             }
-            const bool pos = f > 0.0f;
-            w = pos ? 1.0f / f : 0.0f;
-            neff += pos;
-            ll += pos ? logf(f) : 0.0f;
+            const bool ok = f > 0.0f;
+            w = ok ? 1.0f / f : 0.0f;
+            neff += ok;
+            ll += ok ? logf(f) : 0.0f;
         }
-        if (evw) w *= evw[i];
-        wmax = fmaxf(wmax, fabsf(w));
-#pragma unroll
-        for (int j = 0; j < kCombineUnroll; ++j)
-            if (q[j] < n_items) pw[q[j]] = w;
-        for (uint32_t k = k0 + kCombineUnroll; k < k1; ++k) {
-            const uint32_t qq = evitems[k];
-            if (qq < n_items) pw[qq] = w;
-        }
-        k0 = n0;
-        k1 = n1;
+        if (P.evw) w *= P.evw[i];
+        if (by_runs)
+            for (uint32_t k = 0; k < cnt; ++k) slot[s0 + k] = w;
+        if (glob) scatter_event_global(P, k0[q], k1[q], w, true);
     }
     if (mode == kCombineF) return;
+    __syncthreads();
+    // phase 3: weights onto the items; their |w| to the slots in run order
+    float wv[kRunItemsPerThread];
+#pragma unroll
+    for (int m = 0; m < kRunItemsPerThread; ++m) {
+        wv[m] = sl[m] != 0xffffu ? slot[sl[m]] : 0.0f;
+        if (sl[m] != 0xffffu) pw[pos[m]] = wv[m];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < kRunItemsPerThread; ++m)
+        if (sl[m] != 0xffffu) slot[tid + m * kCombineBlock] = fabsf(wv[m]);
+    __syncthreads();
+    // phase 4: each brick's largest |w|.  A thread takes 8 consecutive slots
+    // of the run order: a run that starts and ends among them goes to its
+    // brick at once; the pieces of runs that cross thread boundaries are
+    // combined by a segmented max scan over each row of 16 lanes (run ids
+    // do not decrease along the lanes; DPP moves, no LDS), and the lane where
+    // such a run ends, or the row's last lane, adds it.  The bricks' maxima
+    // are kept in LDS, then added to P.bwmax.
+    {
+        const uint32_t t8 = 8u * (uint32_t)tid;
+        constexpr uint32_t kNone = 0xffffffffu;
+        uint32_t fk = kNone, lk = kNone;  // first and last piece's run
+        float fv = 0.0f, lv = 0.0f;
+        bool multi = false;
+        auto to_brick = [&](uint32_t run, float mx) {
+            const int b = rslot[run];
+            if (b >= 0)
+                atomicMax(&bmax[b], __float_as_uint(mx));
+            else
+                atomicMax(P.bwmax + rbrick[run], __float_as_uint(mx));  // brick table full
+        };
+        if (by_runs && t8 < T) {
+            const float4 va = *reinterpret_cast<const float4 *>(&slot[t8]);
+            const float4 vb = *reinterpret_cast<const float4 *>(&slot[t8 + 4]);
+            const uint4 rr = *reinterpret_cast<const uint4 *>(&rid[t8]);
+            const float v[8] = {va.x, va.y, va.z, va.w, vb.x, vb.y, vb.z, vb.w};
+            const uint32_t r[8] = {rr.x & 0xffffu, rr.x >> 16, rr.y & 0xffffu, rr.y >> 16,
+                                   rr.z & 0xffffu, rr.z >> 16, rr.w & 0xffffu, rr.w >> 16};
+            const uint32_t n = min(8u, T - t8);
+            fk = r[0];
+            uint32_t cur = r[0];
+            float mx = v[0];
+#pragma unroll
+            for (uint32_t k = 1; k < 8; ++k) {
+                if (k >= n) break;
+                if (r[k] != cur) {
+                    if (!multi) {
+                        fv = mx;
+                        multi = true;
+                    } else {
+                        to_brick(cur, mx);  // the whole run is here
+                    }
+                    cur = r[k];
+                    mx = v[k];
+                } else {
+                    mx = fmaxf(mx, v[k]);
+                }
+            }
+            lk = cur;
+            lv = mx;
+        }
+        // (the lane's place in its row decides which moves are valid)
+        const int rl16 = lane & 15;
+        uint32_t sv = __float_as_uint(lv);  // |w| bits order like the values
+        {
+            // (every lane makes each move: none is inside a branch)
+            uint32_t o = row_up<1>(sv, 0u), ok = row_up<1>(lk, kNone);
+            sv = rl16 >= 1 && ok == lk ? max(sv, o) : sv;
+            o = row_up<2>(sv, 0u);
+            ok = row_up<2>(lk, kNone);
+            sv = rl16 >= 2 && ok == lk ? max(sv, o) : sv;
+            o = row_up<4>(sv, 0u);
+            ok = row_up<4>(lk, kNone);
+            sv = rl16 >= 4 && ok == lk ? max(sv, o) : sv;
+            o = row_up<8>(sv, 0u);
+            ok = row_up<8>(lk, kNone);
+            sv = rl16 >= 8 && ok == lk ? max(sv, o) : sv;
+        }
+        const uint32_t pv = row_up<1>(sv, 0u), pk = row_up<1>(lk, kNone);
+        const uint32_t nf = row_next(fk, kNone);
+        // the first piece ends a run that began in an earlier lane or here
+        if (multi)
+            to_brick(fk, __uint_as_float(rl16 >= 1 && pk == fk ? max(__float_as_uint(fv), pv) : __float_as_uint(fv)));
+        if (lk != kNone && (rl16 == 15 || nf != lk)) to_brick(lk, __uint_as_float(sv));
+    }
+    __syncthreads();
+    if (tid < kBrickSlots && bkey[tid] != 0xffffffffu) atomicMax(P.bwmax + bkey[tid], bmax[tid]);
     const int wn = wave_sum(neff);
     const double wl = wave_sum((double)ll);
-    const float ww = wave_max(wmax);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     if (lane == 0) {
         s_n[wid] = wn;
         s_l[wid] = wl;
-        s_w[wid] = ww;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid == 0 && mode == kCombineRatio) {
         int tn = 0;
         double tl = 0.0;
-        float tw = 0.0f;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+        for (int w = 0; w < kCombineBlock / 64; ++w) {
             tn += s_n[w];
             tl += s_l[w];
-            tw = fmaxf(tw, s_w[w]);
         }
-        if (mode == kCombineRatio) {
-            part_neff[c] = tn;
-            part_ll[c] = tl;
-        }
-        part_wmax[c] = tw;
+        part_neff[c] = tn;
+        part_ll[c] = tl;
     }
 }
 
 // Per-block open-addressing table in LDS mapping a brick id to a slot.
 constexpr int kHashSlots = 1024;
+static_assert(kTabWords >= 2 * kHashSlots && kTabWords >= 3 * kMaxRuns + 2,
+              "a chunk's table holds its hash table, then its run list");
+static_assert(kHashSlots <= kMaxRuns && kMaxRuns <= kCombineBlock, "the combine pass loads every run of a chunk");
+static_assert(kRunItems <= 65535 && kRunEvents <= kCombineEventsPerThread * kCombineBlock,
+              "item slots are 16-bit; a thread holds its events");
 constexpr uint32_t kEmpty = 0xffffffffu;
 
 __device__ __forceinline__ int hash_slot(uint32_t key) { return (int)((key * 2654435761u) >> 22); }
@@ -1107,21 +1344,38 @@ __device__ __forceinline__ uint32_t item_class(const Problem &P, const Ray &r, f
 // add them to ctr, and store the table to tab.  Filling: reload the table,
 // reserve each key's range, then walk the events once.
 template <bool PACKED>
-__device__ __forceinline__ void brick_items_pass(const Problem &P, int64_t base, uint32_t chunk, int ept,
+__device__ __forceinline__ void brick_items_pass(const Problem &P, int64_t base, int ept,
                                                  uint32_t *__restrict__ ctr, const uint32_t *__restrict__ end,
-                                                 uint32_t *__restrict__ pctr, int fill, uint32_t *hkey,
-                                                 uint32_t *hcnt, uint32_t *hbase, uint32_t *bmap,
-                                                 gptr<uint32_t> tab) {
-    const gptr<uint32_t> pairs = global(const_cast<uint32_t *>(P.pairs));
+                                                 int fill, uint32_t *hkey, uint32_t *hcnt, uint32_t *hbase,
+                                                 uint32_t *nruns, gptr<uint32_t> tab) {
     const gptr<uint32_t> evoff = global(const_cast<uint32_t *>(P.evoff));
     const gptr<uint32_t> evitems = global(const_cast<uint32_t *>(P.evitems));
+    const gptr<uint16_t> itemslot = global(const_cast<uint16_t *>(P.itemslot));
+    const gptr<uint8_t> evflag = global(const_cast<uint8_t *>(P.evflag));
+    // the chunk's items in event-major order: [c0, c0 + its count); the
+    // combine pass handles a chunk of at most kRunItems items by runs
+    uint32_t c0 = 0;
+    bool small = false;
     if (fill) {
+        const int64_t last = min(base + (int64_t)blockDim.x * ept, P.n_events);
+        c0 = evoff[base];
+        small = evoff[last] - c0 <= (uint32_t)kRunItems;
+    }
+    if (fill) {
+        // reserve each table key's run of positions; the runs (first
+        // position, length, problem-local brick; in any order) replace the
+        // chunk's (key, count) table, already loaded
         for (int k = threadIdx.x; k < kHashSlots; k += blockDim.x) {
             if (hkey[k] == kEmpty) continue;
             hbase[k] = atomicAdd(ctr + hkey[k], hcnt[k]);
+            const uint32_t q = atomicAdd(nruns, 1u);
+            tab[1 + 3 * q] = hbase[k];
+            tab[2 + 3 * q] = hcnt[k];
+            tab[3 + 3 * q] = hkey[k] / kItemClasses - (uint32_t)P.brick_base;
             hcnt[k] = 0;
         }
         __syncthreads();
+        if (threadIdx.x == 0) tab[0] = *nruns;
     }
     for (int e = 0; e < ept; ++e) {
         const int64_t i = base + (int64_t)e * blockDim.x + threadIdx.x;
@@ -1129,11 +1383,11 @@ __device__ __forceinline__ void brick_items_pass(const Problem &P, int64_t base,
         Ray r;
         const bool ok = make_ray<PACKED>(P, i, r);
         // the event's pieces so far; when filling, where its positions go
+        // and whether an item falls outside the runs
         uint32_t n = 0;
         const uint32_t e0 = fill ? evoff[i] : 0u;
+        bool outside = false;
         if (ok) brick_walk(P, r, [&](uint32_t brick, int bx, int by, int bz, float t0, float t1) {
-            const uint32_t bl = brick - (uint32_t)P.brick_base;
-            atomicOr(&bmap[bl >> 5], 1u << (bl & 31u));
             const uint32_t key = brick * kItemClasses + item_class(P, r, t0, t1);
             if (!fill) {
                 const int h = hash_insert(hkey, key);
@@ -1148,28 +1402,24 @@ __device__ __forceinline__ void brick_items_pass(const Problem &P, int64_t base,
             const int h = hash_find(hkey, key);
             const uint32_t pos = h >= 0 ? hbase[h] + atomicAdd(&hcnt[h], 1u) : atomicAdd(ctr + key, 1u);
             const bool in = pos < end[key];
-            if (in) write_item_walk(P, r, bx, by, bz, t0, t1, pos);
+            const bool run = h >= 0 && small;
+            if (in) {
+                write_item_walk(P, r, bx, by, bz, t0, t1, pos);
+                itemslot[pos] = run ? (uint16_t)(e0 + n - c0) : (uint16_t)0xffffu;
+            }
+            outside = outside || h < 0 || !in;
             // (a position past the key's range, which a consistent count
             // never gives, is marked out of range for the combine pass)
             evitems[e0 + n] = in ? pos : 0xffffffffu;
             ++n;
         });
-        if (!fill) evoff[i] = n;
-    }
-    __syncthreads();
-    // One (chunk, brick) pair per brick this block touched.  The set of
-    // bricks does not depend on thread timing (unlike which keys found room
-    // in the table), so both passes emit exactly the same pairs and the fill
-    // pass writes every slot the count pass reserved, once.
-    const uint32_t nb = (uint32_t)P.nbx * (uint32_t)P.nby * (uint32_t)P.nbz;
-    for (uint32_t w = threadIdx.x; w < (nb + 31) / 32; w += blockDim.x) {
-        for (uint32_t bits = bmap[w]; bits; bits &= bits - 1) {
-            const uint32_t bl = w * 32 + (uint32_t)__builtin_ctz(bits);
-            const uint32_t pos = atomicAdd(pctr + P.brick_base + bl, 1u);
-            if (fill && pos < P.pair_off[bl + 1]) pairs[pos] = chunk;
-        }
+        if (!fill)
+            evoff[i] = n;
+        else
+            evflag[i] = outside ? 1 : 0;
     }
     if (fill) return;
+    __syncthreads();
     for (int k = threadIdx.x; k < kHashSlots; k += blockDim.x) {
         if (hkey[k] != kEmpty) atomicAdd(ctr + hkey[k], hcnt[k]);
         tab[k] = hkey[k];
@@ -1179,27 +1429,24 @@ __device__ __forceinline__ void brick_items_pass(const Problem &P, int64_t base,
 
 __global__ void __launch_bounds__(kForwardBlock) k_brick_items(const Problem *__restrict__ probs, int n_probs,
                                                                int ept, uint32_t *__restrict__ ctr,
-                                                               const uint32_t *__restrict__ end,
-                                                               uint32_t *__restrict__ pctr, int fill,
+                                                               const uint32_t *__restrict__ end, int fill,
                                                                uint32_t *__restrict__ tabs) {
     __shared__ uint32_t hkey[kHashSlots], hcnt[kHashSlots], hbase[kHashSlots];
-    __shared__ uint32_t bmap[kMaxProblemBricks / 32];  // bricks of the problem this block touches
+    __shared__ uint32_t nruns;
     const int64_t c = blockIdx.x;
     const Problem P = probs[find_problem(probs, n_probs, c)];
-    const gptr<uint32_t> tab = global(tabs) + (size_t)c * (2 * kHashSlots);
+    const gptr<uint32_t> tab = global(tabs) + (size_t)c * kTabWords;
     for (int k = threadIdx.x; k < kHashSlots; k += blockDim.x) {
         hkey[k] = fill ? tab[k] : kEmpty;
         hcnt[k] = fill ? tab[kHashSlots + k] : 0u;
     }
-    const uint32_t nw = ((uint32_t)P.nbx * (uint32_t)P.nby * (uint32_t)P.nbz + 31) / 32;
-    for (uint32_t w = threadIdx.x; w < nw; w += blockDim.x) bmap[w] = 0;
+    if (threadIdx.x == 0) nruns = 0;
     __syncthreads();
     const int64_t base = (c - P.chunk_begin) * (int64_t)blockDim.x * ept;
-    const uint32_t chunk = (uint32_t)(c - P.chunk_begin);
     if (P.packed)
-        brick_items_pass<true>(P, base, chunk, ept, ctr, end, pctr, fill, hkey, hcnt, hbase, bmap, tab);
+        brick_items_pass<true>(P, base, ept, ctr, end, fill, hkey, hcnt, hbase, &nruns, tab);
     else
-        brick_items_pass<false>(P, base, chunk, ept, ctr, end, pctr, fill, hkey, hcnt, hbase, bmap, tab);
+        brick_items_pass<false>(P, base, ept, ctr, end, fill, hkey, hcnt, hbase, &nruns, tab);
 }
 
 // Diagnostic: voxel pieces visited per chunk and how many have non-zero weight.
@@ -1303,7 +1550,7 @@ __global__ void __launch_bounds__(256) k_tof_keep(const Problem *__restrict__ pr
 
 int64_t project_chunk_events(int block, int ept) { return (int64_t)block * ept; }
 
-int64_t brick_item_tab_words(int64_t n_chunks) { return n_chunks * 2 * kHashSlots; }
+int64_t brick_item_tab_words(int64_t n_chunks) { return n_chunks * kTabWords; }
 
 hipError_t launch_block_image(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_xblk) {
     void *args[] = {&d_probs, &n_probs};
@@ -1312,8 +1559,8 @@ hipError_t launch_block_image(const Launch &L, const Problem *d_probs, int n_pro
 }
 
 hipError_t launch_forward(const Launch &L, bool tof, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept,
-                          int mode, int *part_neff, double *part_ll, float *part_wmax) {
-    void *args[] = {&d_probs, &n_probs, &ept, &mode, &part_neff, &part_ll, &part_wmax};
+                          int mode, int *part_neff, double *part_ll) {
+    void *args[] = {&d_probs, &n_probs, &ept, &mode, &part_neff, &part_ll};
     const void *fn = tof ? reinterpret_cast<const void *>(&k_forward<true>)
                          : reinterpret_cast<const void *>(&k_forward<false>);
     return do_launch(L, fn, dim3((unsigned)n_chunks), dim3(kForwardBlock), 0, args);
@@ -1328,9 +1575,10 @@ hipError_t launch_forward_items(const Launch &L, bool tof, const Problem *d_prob
 }
 
 hipError_t launch_combine(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept, int mode,
-                          int *part_neff, double *part_ll, float *part_wmax) {
-    void *args[] = {&d_probs, &n_probs, &ept, &mode, &part_neff, &part_ll, &part_wmax};
-    return do_launch(L, reinterpret_cast<const void *>(&k_combine), dim3((unsigned)n_chunks), dim3(kForwardBlock), 0,
+                          int *part_neff, double *part_ll) {
+    if ((int64_t)kForwardBlock * ept > (int64_t)kCombineEventsPerThread * kCombineBlock) return hipErrorInvalidValue;
+    void *args[] = {&d_probs, &n_probs, &ept, &mode, &part_neff, &part_ll};
+    return do_launch(L, reinterpret_cast<const void *>(&k_combine), dim3((unsigned)n_chunks), dim3(kCombineBlock), 0,
                      args);
 }
 
@@ -1342,10 +1590,10 @@ hipError_t launch_back_chunks(const Launch &L, bool tof, const Problem *d_probs,
     return do_launch(L, fn, dim3(n_chunks), dim3(kBackBlock), 0, args);
 }
 
-hipError_t launch_brick_wmax(const Launch &L, const Problem *d_probs, int n_probs, const uint4 *bricks,
-                             uint32_t n_bricks, const float *part_wmax, int64_t n_part) {
-    void *args[] = {&d_probs, &n_probs, &bricks, &part_wmax, &n_part};
-    return do_launch(L, reinterpret_cast<const void *>(&k_brick_wmax), dim3(n_bricks), dim3(64), 0, args);
+hipError_t launch_clear_bwmax(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_bricks) {
+    void *args[] = {&d_probs, &n_probs, &n_bricks};
+    return do_launch(L, reinterpret_cast<const void *>(&k_clear_bwmax), dim3((unsigned)((n_bricks + 255) / 256)),
+                     dim3(256), 0, args);
 }
 
 hipError_t launch_reduce_tiles(const Launch &L, const Problem *d_probs, int n_probs, const uint4 *bricks,
@@ -1355,8 +1603,8 @@ hipError_t launch_reduce_tiles(const Launch &L, const Problem *d_probs, int n_pr
 }
 
 hipError_t launch_brick_items(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept,
-                              uint32_t *ctr, const uint32_t *end, uint32_t *pctr, int fill, uint32_t *tabs) {
-    void *args[] = {&d_probs, &n_probs, &ept, &ctr, &end, &pctr, &fill, &tabs};
+                              uint32_t *ctr, const uint32_t *end, int fill, uint32_t *tabs) {
+    void *args[] = {&d_probs, &n_probs, &ept, &ctr, &end, &fill, &tabs};
     return do_launch(L, reinterpret_cast<const void *>(&k_brick_items), dim3((unsigned)n_chunks),
                      dim3(kForwardBlock), 0, args);
 }

@@ -39,6 +39,9 @@ LMTOF_OPT_MEDIAN_SIEVE = 8
 LMTOF_OPT_FORWARD = 9
 LMTOF_FORWARD_BRICKS = 0
 LMTOF_FORWARD_EVENTS = 1
+LMTOF_REQ_BACKGROUND = 1
+LMTOF_OPT_BRICK_CHUNKS = 10
+LMTOF_TUNE_MAX_CANDIDATES = 16
 
 ERROR_NAMES = {0: "OK", -1: "EINVAL", -2: "ESTATE", -3: "ENOMEM", -4: "EHIP", -5: "EUNSUPPORTED", -6: "EAGAIN"}
 
@@ -66,9 +69,21 @@ class lmtof_iter_stats(C.Structure):
                 ("update_ms", C.c_float), ("forward_kernel_ms", C.c_float)]
 
 
+class lmtof_tune_candidate(C.Structure):
+    _fields_ = [("forward", C.c_int32), ("events_per_thread", C.c_int32), ("brick_chunks", C.c_int32),
+                ("reserved0", C.c_int32), ("pass_ms", C.c_float), ("build_ms", C.c_float)]
+
+
+class lmtof_tune_result(C.Structure):
+    _fields_ = [("forward", C.c_int32), ("events_per_thread", C.c_int32), ("brick_chunks", C.c_int32),
+                ("n_candidates", C.c_int32), ("cached", C.c_int32), ("reserved0", C.c_int32),
+                ("cand", lmtof_tune_candidate * LMTOF_TUNE_MAX_CANDIDATES)]
+
+
 class lmtof_request(C.Structure):
     _fields_ = [("geometry", lmtof_geometry), ("events", C.c_void_p), ("n_events", C.c_int64),
-                ("format", C.c_int32), ("mem", C.c_int32), ("n_iter", C.c_int32), ("storage", C.c_int32)]
+                ("format", C.c_int32), ("mem", C.c_int32), ("n_iter", C.c_int32), ("storage", C.c_int32),
+                ("flags", C.c_int32), ("reserved0", C.c_int32)]
 
 
 if not os.path.exists(LIB_PATH):
@@ -115,7 +130,7 @@ _sig = {
     "lmtof_sampled_back_project": ([_P, _P, _i64, _P, _i64, C.c_int], C.c_int),
     "lmtof_sampled_forward_project_noalloc": ([_P, _P, _i64, _P, _i64], C.c_int),
     "lmtof_count_segments": ([_P, C.POINTER(_i64), C.POINTER(_i64)], C.c_int),
-    "lmtof_autotune": ([_P, C.POINTER(_i64), C.POINTER(C.c_float)], C.c_int),
+    "lmtof_autotune": ([_P, C.c_int, C.POINTER(lmtof_tune_result)], C.c_int),
     "lmtof_set_regions": ([_P, C.POINTER(C.c_int32), C.c_int, C.c_int], C.c_int),
     "lmtof_region_info": ([_P, C.c_int, C.POINTER(C.c_int32), C.POINTER(_i64)], C.c_int),
     "lmtof_read_region_image": ([_P, C.c_int, _P, _i64, C.c_int], C.c_int),
@@ -395,13 +410,14 @@ def lmtof_count_segments(ctx):
     return a.value, b.value
 
 
-def lmtof_autotune(ctx):
-    """Pick the events-per-thread launch shape by timing one projector pass
-    per candidate (1, 2, 4, 8).  Returns (chosen, {candidate: ms})."""
-    chosen = C.c_int64()
-    ms = (C.c_float * 4)()
-    _check(_lib.lmtof_autotune(ctx, C.byref(chosen), ms), ctx)
-    return chosen.value, dict(zip((1, 2, 4, 8), [float(v) for v in ms]))
+def lmtof_autotune(ctx, use_cache: bool = False):
+    """Chosen configuration (now set) and the timed candidates."""
+    r = lmtof_tune_result()
+    _check(_lib.lmtof_autotune(ctx, 1 if use_cache else 0, C.byref(r)), ctx)
+    names = ("forward", "events_per_thread", "brick_chunks")
+    return dict({k: getattr(r, k) for k in names}, cached=bool(r.cached),
+                candidates=[dict({k: getattr(q, k) for k in names}, pass_ms=q.pass_ms, build_ms=q.build_ms)
+                            for q in r.cand[:r.n_candidates]])
 
 
 def lmtof_set_regions(ctx, z_bounds, margin_slices: int = -1) -> None:
@@ -455,8 +471,11 @@ def lmtof_pool_destroy(pool) -> None:
     _pcheck(_lib.lmtof_pool_destroy(pool), None)
 
 
-def make_request(geometry, ev, n_iter: int, storage: int = 0, fmt: Optional[int] = None):
-    """(lmtof_request, keep-alive) for events ev (NumPy or GPU tensor)."""
+def make_request(geometry, ev, n_iter: int, storage: int = 0, fmt: Optional[int] = None,
+                 background: bool = False):
+    """(lmtof_request, keep-alive) for events ev (NumPy or GPU tensor).  With
+    background=True the pool prepares it on its own thread and stream: keep
+    the keep-alive object until the request is polled done."""
     if fmt is None:
         fmt = LMTOF_FMT_PACKED16 if "int16" in str(ev.dtype) else LMTOF_FMT_F32X7
     per = 7 if fmt == LMTOF_FMT_F32X7 else 8
@@ -469,6 +488,7 @@ def make_request(geometry, ev, n_iter: int, storage: int = 0, fmt: Optional[int]
     q.mem = mem
     q.n_iter = int(n_iter)
     q.storage = int(storage)
+    q.flags = LMTOF_REQ_BACKGROUND if background else 0
     return q, keep
 
 
@@ -601,8 +621,8 @@ class Reconstruction:
     def count_segments(self):
         return lmtof_count_segments(self.ctx)
 
-    def autotune(self):
-        return lmtof_autotune(self.ctx)
+    def autotune(self, use_cache: bool = False):
+        return lmtof_autotune(self.ctx, use_cache)
 
     def read_packed_events(self, out=None):
         return lmtof_read_packed_events(self.ctx, out)

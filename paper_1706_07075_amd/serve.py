@@ -3,9 +3,11 @@
 The pool in liblmtof.so (lmtof_pool_*) keeps admitted requests resident and
 runs one batched MLEM iteration over all of them per step; this module is
 the host loop around it: requests arrive (Poisson), are admitted first come
-first served whenever their HBM footprint fits, join the running batch at
-the next step, and leave when their iterations are done.  Latency is
-measured from arrival to the image in host memory.
+first served whenever their HBM footprint fits, are prepared in the
+background (the pool's own thread and stream) while the running batch keeps
+stepping, join the batch at the next step after that, and leave when their
+iterations are done.  Latency is measured from arrival to the image in host
+memory.
 
     python -m paper_1706_07075_amd.serve --requests 300 --rate 2
 """
@@ -49,9 +51,10 @@ class Request:
 class Server:
     """Thin owner of one lmtof pool."""
 
-    def __init__(self, hbm_budget_bytes: int, device: int = 0):
+    def __init__(self, hbm_budget_bytes: int, device: int = 0, background: bool = True):
         self.pool = L.lmtof_pool_create(hbm_budget_bytes, device)
-        self._keep: Dict[int, Any] = {}
+        self.background = background
+        self._keep: Dict[int, Any] = {}  # request id -> events kept alive until polled
 
     def close(self):
         if getattr(self, "pool", None):
@@ -65,13 +68,14 @@ class Server:
         self.close()
 
     def try_submit(self, r: Request) -> bool:
-        q, keep = L.make_request(r.geometry, r.events, r.n_iter, r.storage)
+        q, keep = L.make_request(r.geometry, r.events, r.n_iter, r.storage, background=self.background)
         try:
             r.rid = L.lmtof_pool_submit(self.pool, q)
         except L.LmtofError as e:
             if e.code == L.LMTOF_EAGAIN:
                 return False
             raise
+        self._keep[r.rid] = keep
         return True
 
     def step(self) -> int:
@@ -82,6 +86,7 @@ class Server:
         if img is None:
             return False
         r.image = img
+        self._keep.pop(r.rid, None)
         return True
 
     def info(self):
@@ -89,16 +94,17 @@ class Server:
 
 
 def run(requests: List[Request], hbm_budget_bytes: int, device: int = 0, realtime: bool = True,
-        log=None) -> Dict[str, Any]:
+        log=None, background: bool = True) -> Dict[str, Any]:
     """Serve `requests` (sorted by arrival).  realtime=False submits each
-    request as soon as it fits, ignoring arrival times (offline batch)."""
+    request as soon as it fits, ignoring arrival times (offline batch);
+    background=False prepares each request before its submit returns."""
     reqs = sorted(requests, key=lambda r: r.arrival)
     queue = list(reqs)
     running: List[Request] = []
     t0 = time.perf_counter()
     steps = 0
     batch_sizes = []
-    with Server(hbm_budget_bytes, device) as srv:
+    with Server(hbm_budget_bytes, device, background) as srv:
         while queue or running:
             now = time.perf_counter() - t0
             # admit in arrival order while the head of the queue fits
@@ -112,8 +118,11 @@ def run(requests: List[Request], hbm_budget_bytes: int, device: int = 0, realtim
                 running.append(r)
             if running:
                 n = srv.step()
-                steps += 1
-                batch_sizes.append(n)
+                if n:
+                    steps += 1
+                    batch_sizes.append(n)
+                else:
+                    time.sleep(2e-4)  # every admitted request is still being prepared
                 for r in list(running):
                     if srv.poll(r):
                         r.finished = time.perf_counter() - t0

@@ -41,17 +41,22 @@ def table(path: str) -> str:
 
 def counter_values(path: str, kernel: str):
     """Per-dispatch values of the one counter in a counter_collection.csv:
-    (values of `kernel`'s dispatches, values of the device copies)."""
+    (values of `kernel`'s dispatches, values of the device copies).  A
+    kernel name "a+b" adds the dispatches of a and b pairwise (a stage of
+    one launch of each per iteration)."""
     with open(path) as fh:
         rows = list(csv.DictReader(fh))
-    mine, copies = [], []
+    parts = kernel.split("+")
+    mine, copies = {k: [] for k in parts}, []
     for r in rows:
-        name = short_name(r["Kernel_Name"])
-        if name.split("<")[0] == kernel:
-            mine.append(float(r["Counter_Value"]))
+        name = short_name(r["Kernel_Name"]).split("<")[0]
+        if name in mine:
+            mine[name].append(float(r["Counter_Value"]))
         elif "copyBuffer" in r["Kernel_Name"]:
             copies.append(float(r["Counter_Value"]))
-    return mine, copies
+    n = min(len(v) for v in mine.values())
+    total = [sum(mine[k][len(mine[k]) - n + q] for k in parts) for q in range(n)]
+    return total, copies
 
 
 def traffic(kernel: str, copy_mib: int, source: str, storages: dict, last: int = 10) -> dict:

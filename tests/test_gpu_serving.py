@@ -7,7 +7,11 @@
 - A served request matches the FP64 oracle like a plain reconstruction.
 - Admission by HBM footprint: EAGAIN while it does not fit, ENOMEM if it
   never can; the pool frees a request's memory when it is polled.
+- Background admission: a large request is prepared on the pool's own
+  thread and stream while the running request keeps stepping.
 """
+import time
+
 import numpy as np
 import pytest
 
@@ -49,8 +53,10 @@ def test_alone_vs_mix_bitwise():
     alone = {}
     for name, r in (("a", ra), ("b", rb), ("c", rc)):
         alone[name] = _run_alone(serve.Request(geometry=r.geometry, events=r.events, n_iter=r.n_iter))
-    # mix: a starts, b joins after one step, c after two; they finish at different steps
-    with serve.Server(8 << 30) as srv:
+    # mix: a starts, b joins after one step, c after two; they finish at
+    # different steps (prepared before their submits return, so the joins
+    # happen at exactly those steps)
+    with serve.Server(8 << 30, background=False) as srv:
         assert srv.try_submit(ra)
         srv.step()
         assert srv.try_submit(rb)
@@ -122,10 +128,12 @@ def test_tof_and_nontof_not_mixed():
 def test_poisson_loop_small():
     print("case: Poisson loop", flush=True)
     reqs = []
-    arrivals = serve.poisson_arrivals(8, 50.0, 5)
+    # arrivals 2 ms apart on average, each request running 30-37 iterations,
+    # so that the background preparations overlap running requests
+    arrivals = serve.poisson_arrivals(8, 500.0, 5)
     for k in range(8):
         kind = "cyl" if k % 3 else "wb"
-        _, ev, r = _req(kind, 20000 + 5000 * k, 40 + k, 3 + k % 3, tof=300.0 if k % 2 else 600.0)
+        _, ev, r = _req(kind, 20000 + 5000 * k, 40 + k, 30 + k, tof=300.0 if k % 2 else 600.0)
         r.arrival = float(arrivals[k])
         reqs.append(r)
     out = serve.run(reqs, 8 << 30)
@@ -133,3 +141,59 @@ def test_poisson_loop_small():
     assert out["requests"] == 8 and out["max_batch"] >= 2
     assert all(r.image is not None and np.isfinite(r.image).all() for r in reqs)
     assert out["latency_ms"]["p99"] >= out["latency_ms"]["p50"] > 0
+
+
+def test_background_admission_overlaps_running_steps():
+    """A whole-body request of 20 M events is admitted while a cylinder
+    request is running.  Prepared before its submit returns, it would hold
+    the running request for the whole preparation; in the background the
+    submit returns at once, the running request keeps stepping (no step
+    waits as long as the preparation), and the big request joins at a later
+    step.  Both images equal their runs alone, bit for bit."""
+    print("case: background admission", flush=True)
+    _, _, ra = _req("cyl", 1000000, 51, 400)
+    _, evb, rb = _req("wb", 20000000, 52, 2)
+    rb.events = torch.from_numpy(evb).cuda()  # staged on the GPU, as the serving pools are
+    img_a = _run_alone(serve.Request(geometry=ra.geometry, events=ra.events, n_iter=ra.n_iter), budget=64 << 30)
+    with serve.Server(64 << 30, background=False) as srv:
+        t = time.perf_counter()
+        assert srv.try_submit(rb)
+        t_sync = time.perf_counter() - t
+        while not srv.poll(rb):
+            srv.step()
+        img_b = rb.image
+    rb.image = None
+    with serve.Server(64 << 30) as srv:
+        assert srv.try_submit(ra)
+        while srv.step() == 0:
+            pass
+        alone = []
+        for _ in range(3):
+            t = time.perf_counter()
+            assert srv.step() == 1
+            alone.append(time.perf_counter() - t)
+        t = time.perf_counter()
+        assert srv.try_submit(rb)
+        t_submit = time.perf_counter() - t
+        during = []
+        while True:
+            t = time.perf_counter()
+            n = srv.step()
+            if n == 2:
+                break
+            assert n == 1, "the running request stopped before the admission joined"
+            during.append(time.perf_counter() - t)
+        done = {}
+        while len(done) < 2:
+            srv.step()
+            for name, r in (("a", ra), ("b", rb)):
+                if name not in done and srv.poll(r):
+                    done[name] = r.image
+    print(f"  synchronous admission {1e3 * t_sync:.1f} ms; background submit {1e3 * t_submit:.2f} ms; "
+          f"step alone {1e3 * np.median(alone):.2f} ms; {len(during)} steps during the preparation, "
+          f"longest {1e3 * max(during, default=0.0):.2f} ms", flush=True)
+    assert t_submit < 0.2 * t_sync
+    assert len(during) >= 2
+    assert max(during) < 0.5 * t_sync
+    assert np.array_equal(done["a"], img_a)
+    assert np.array_equal(done["b"], img_b)
