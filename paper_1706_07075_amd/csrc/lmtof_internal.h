@@ -189,9 +189,10 @@ hipError_t launch_reduce_tiles(const Launch &L, const Problem *d_probs, int n_pr
 hipError_t launch_brick_items(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept,
                               uint32_t *ctr, const uint32_t *end, int fill, uint32_t *tabs);
 // Words of one forward chunk's table: the builder's (key, count) pairs of
-// its LDS hash table (count pass), then the run count and 3 words per run
+// its LDS hash table (count pass), then a 4-word header and 4 words per run
 // (fill pass).
-constexpr int64_t kTabWords = 3 * 1024 + 2;
+constexpr int kTabHead = 4;
+constexpr int64_t kTabWords = kTabHead + 4 * 1024;
 int64_t brick_item_tab_words(int64_t n_chunks);
 // part[2c] = voxel pieces visited by chunk c, part[2c+1] = pieces with non-zero weight.
 hipError_t launch_count_pieces(const Launch &L, bool tof, const Problem *d_probs, int n_probs, int64_t n_chunks,

@@ -940,29 +940,14 @@ __device__ __forceinline__ void scatter_event_global(const Problem &P, uint32_t 
     }
 }
 
-__device__ __forceinline__ int brick_slot(uint32_t *keys, uint32_t key) {
-    int h = (int)((key * 2654435761u) >> 24);
-    for (int probe = 0; probe < kBrickSlots; ++probe) {
-        uint32_t k = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (k == 0xffffffffu) {
-            k = atomicCAS(&keys[h], 0xffffffffu, key);
-            if (k == 0xffffffffu) return h;
-        }
-        if (k == key) return h;
-        h = (h + 1) & (kBrickSlots - 1);
-    }
-    return -1;
-}
-
 __global__ void __launch_bounds__(kCombineBlock) k_combine(const Problem *__restrict__ probs, int n_probs, int ept,
                                                            int mode, int *__restrict__ part_neff,
                                                            double *__restrict__ part_ll) {
     __shared__ __align__(16) float slot[kRunItems];
     __shared__ __align__(16) uint16_t rid[kRunItems];
-    __shared__ uint32_t rbase[kMaxRuns], rpre[kMaxRuns], rbrick[kMaxRuns];
+    __shared__ uint32_t rbase[kMaxRuns], rpre[kMaxRuns], rbrick[kMaxRuns], rlen[kMaxRuns];
     __shared__ int16_t rslot[kMaxRuns];
-    __shared__ uint32_t bkey[kBrickSlots], bmax[kBrickSlots];
-    __shared__ uint32_t s_tot[kCombineBlock / 64 + 1];
+    __shared__ uint32_t bmax[kBrickSlots];
     __shared__ int s_n[kCombineBlock / 64];
     __shared__ double s_l[kCombineBlock / 64];
     // Workgroups are dealt to the 8 XCDs in turn; chunk c of XCD x's share
@@ -992,55 +977,33 @@ __global__ void __launch_bounds__(kCombineBlock) k_combine(const Problem *__rest
         flagged[q] = has_ev[q] && P.evflag[base + le];
     }
     const uint32_t E0 = evoff[base], E1 = evoff[base + n_ev];
-    const uint32_t nr = runs[0];
-    // rows past kRunsEager are loaded once the count says they exist (a
-    // chunk has ~100 runs: the whole table would be 12 KB a chunk)
-    uint32_t rb = 0, rl = 0, rk = 0;
-    if (tid < kRunsEager) {
-        rb = runs[1 + 3 * tid];
-        rl = runs[2 + 3 * tid];
-        rk = runs[3 + 3 * tid];
-    } else if ((uint32_t)tid < nr) {
-        rb = runs[1 + 3 * tid];
-        rl = runs[2 + 3 * tid];
-        rk = runs[3 + 3 * tid];
-    }
-    const uint32_t len = (uint32_t)tid < nr ? rl : 0u;
-    if ((uint32_t)tid < nr) {
-        rbase[tid] = rb;
-        rbrick[tid] = rk;
-    }
-    if (tid < kBrickSlots) {
-        bkey[tid] = 0xffffffffu;
-        bmax[tid] = 0u;
-    }
-    // exclusive prefix of the run lengths
-    uint32_t x = len;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t y = (uint32_t)__shfl_up((int)x, off, 64);
-        if (lane >= off) x += y;
-    }
-    if (lane == 63) s_tot[wid] = x;
-    __syncthreads();
-    if (tid == 0) {
-        uint32_t run = 0;
-        for (int w = 0; w < kCombineBlock / 64; ++w) {
-            const uint32_t t = s_tot[w];
-            s_tot[w] = run;
-            run += t;
-        }
-        s_tot[kCombineBlock / 64] = run;
-    }
-    __syncthreads();
-    const uint32_t pre = x - len + s_tot[wid];
-    const uint32_t T = s_tot[kCombineBlock / 64];
+    const uint32_t nr = runs[0], T = runs[1];
+    // run rows (see brick_items_pass); rows past kRunsEager are loaded once
+    // the count says they exist (a chunk has ~100 runs)
+    const gptr<const u32x4> rows = (gptr<const u32x4>)(runs + kTabHead);
+    u32x4 row = {0u, 0u, 0u, 0u};
+    if (tid < kRunsEager)
+        row = rows[tid];
+    else if ((uint32_t)tid < nr)
+        row = rows[tid];
+    const uint32_t bslot = (row.y >> 16) & 0x7fffu;
+    const bool owner = maxima && (uint32_t)tid < nr && (row.y >> 31) != 0u && bslot != 0x7fffu;
     const bool by_runs = n_ev <= kRunEvents && E1 - E0 <= (uint32_t)kRunItems && T <= E1 - E0;
-    if (by_runs && (uint32_t)tid < nr) {
-        rpre[tid] = pre;
-        for (uint32_t q = 0; q < len; ++q) rid[pre + q] = (uint16_t)tid;
-        rslot[tid] = maxima ? (int16_t)brick_slot(bkey, rk) : (int16_t)-1;
+    if ((uint32_t)tid < nr) {
+        rbase[tid] = row.x;
+        rlen[tid] = row.y & 0xffffu;
+        rpre[tid] = row.z;
+        rbrick[tid] = row.w;
+        rslot[tid] = bslot != 0x7fffu ? (int16_t)bslot : (int16_t)-1;
     }
+    if (tid < kBrickSlots) bmax[tid] = 0u;
+    __syncthreads();
+    // the run of each run-order slot: a wavefront's lanes fill a run's slots
+    if (by_runs)
+        for (uint32_t r = (uint32_t)wid; r < nr; r += kCombineBlock / 64) {
+            const uint32_t p0 = rpre[r], l = rlen[r];
+            for (uint32_t j = (uint32_t)lane; j < l; j += 64) rid[p0 + j] = (uint16_t)r;
+        }
     __syncthreads();
     // phase 1: the thread's items (positions and slots kept for phase 3)
     uint32_t pos[kRunItemsPerThread], sl[kRunItemsPerThread];
@@ -1188,7 +1151,7 @@ __global__ void __launch_bounds__(kCombineBlock) k_combine(const Problem *__rest
         if (lk != kNone && (rl16 == 15 || nf != lk)) to_brick(lk, __uint_as_float(sv));
     }
     __syncthreads();
-    if (tid < kBrickSlots && bkey[tid] != 0xffffffffu) atomicMax(P.bwmax + bkey[tid], bmax[tid]);
+    if (by_runs && owner) atomicMax(P.bwmax + row.w, bmax[bslot]);
     const int wn = wave_sum(neff);
     const double wl = wave_sum((double)ll);
     if (lane == 0) {
@@ -1210,8 +1173,10 @@ __global__ void __launch_bounds__(kCombineBlock) k_combine(const Problem *__rest
 
 // Per-block open-addressing table in LDS mapping a brick id to a slot.
 constexpr int kHashSlots = 1024;
-static_assert(kTabWords >= 2 * kHashSlots && kTabWords >= 3 * kMaxRuns + 2,
-              "a chunk's table holds its hash table, then its run list");
+static_assert(kTabWords >= 2 * kHashSlots && kTabWords >= kTabHead + 4 * kMaxRuns,
+              "a chunk's table holds its hash table, then its run rows");
+static_assert(kHashSlots % kForwardBlock == 0 && kBrickSlots < 0x7fff && kRunEvents < 0x10000,
+              "run rows: lengths in 16 bits, brick slots in 15");
 static_assert(kHashSlots <= kMaxRuns && kMaxRuns <= kCombineBlock, "the combine pass loads every run of a chunk");
 static_assert(kRunItems <= 65535 && kRunEvents <= kCombineEventsPerThread * kCombineBlock,
               "item slots are 16-bit; a thread holds its events");
@@ -1347,7 +1312,8 @@ template <bool PACKED>
 __device__ __forceinline__ void brick_items_pass(const Problem &P, int64_t base, int ept,
                                                  uint32_t *__restrict__ ctr, const uint32_t *__restrict__ end,
                                                  int fill, uint32_t *hkey, uint32_t *hcnt, uint32_t *hbase,
-                                                 uint32_t *nruns, gptr<uint32_t> tab) {
+                                                 uint32_t *nruns, uint16_t *qslot, uint32_t *bkey,
+                                                 uint32_t *wsum, gptr<uint32_t> tab) {
     const gptr<uint32_t> evoff = global(const_cast<uint32_t *>(P.evoff));
     const gptr<uint32_t> evitems = global(const_cast<uint32_t *>(P.evitems));
     const gptr<uint16_t> itemslot = global(const_cast<uint16_t *>(P.itemslot));
@@ -1362,20 +1328,76 @@ __device__ __forceinline__ void brick_items_pass(const Problem &P, int64_t base,
         small = evoff[last] - c0 <= (uint32_t)kRunItems;
     }
     if (fill) {
-        // reserve each table key's run of positions; the runs (first
-        // position, length, problem-local brick; in any order) replace the
-        // chunk's (key, count) table, already loaded
+        // reserve each table key's run of positions (runs numbered in any order)
         for (int k = threadIdx.x; k < kHashSlots; k += blockDim.x) {
             if (hkey[k] == kEmpty) continue;
             hbase[k] = atomicAdd(ctr + hkey[k], hcnt[k]);
-            const uint32_t q = atomicAdd(nruns, 1u);
-            tab[1 + 3 * q] = hbase[k];
-            tab[2 + 3 * q] = hcnt[k];
-            tab[3 + 3 * q] = hkey[k] / kItemClasses - (uint32_t)P.brick_base;
-            hcnt[k] = 0;
+            qslot[atomicAdd(nruns, 1u)] = (uint16_t)k;
         }
         __syncthreads();
-        if (threadIdx.x == 0) tab[0] = *nruns;
+        // The run rows replace the chunk's (key, count) table, already
+        // loaded: the header (run count, items in runs) and per run its first
+        // position, its length | brick slot << 16 | owner << 31, the prefix
+        // of the lengths before it and its problem-local brick.  Runs of one
+        // brick share a slot of the combine pass's LDS table of brick maxima
+        // (kBrickSlots; 0x7fff once full); the run that took the slot owns it.
+        const uint32_t nr = *nruns;
+        constexpr int kPer = kHashSlots / kForwardBlock;
+        uint32_t len[kPer], tot = 0;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const uint32_t q = kPer * threadIdx.x + j;
+            len[j] = q < nr ? hcnt[qslot[q]] : 0u;
+            tot += len[j];
+        }
+        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+        uint32_t x = tot;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = (uint32_t)__shfl_up((int)x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) wsum[wid] = x;
+        __syncthreads();
+        uint32_t pre = x - tot;
+        for (int w = 0; w < wid; ++w) pre += wsum[w];
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const uint32_t q = kPer * threadIdx.x + j;
+            if (q < nr) {
+                const uint32_t k = qslot[q];
+                const uint32_t brick = hkey[k] / kItemClasses - (uint32_t)P.brick_base;
+                bool owner = false;
+                int bs = -1;
+                int h = (int)((brick * 2654435761u) >> 24);
+                for (int probe = 0; probe < kBrickSlots; ++probe) {
+                    uint32_t kk = __hip_atomic_load(&bkey[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    if (kk == kEmpty) {
+                        kk = atomicCAS(&bkey[h], kEmpty, brick);
+                        if (kk == kEmpty) {
+                            owner = true;
+                            bs = h;
+                            break;
+                        }
+                    }
+                    if (kk == brick) {
+                        bs = h;
+                        break;
+                    }
+                    h = (h + 1) & (kBrickSlots - 1);
+                }
+                const uint32_t y = len[j] | ((bs >= 0 ? (uint32_t)bs : 0x7fffu) << 16) | (owner ? 1u << 31 : 0u);
+                ((gptr<u32x4>)(tab + kTabHead))[q] = u32x4{hbase[k], y, pre, brick};
+            }
+            pre += len[j];
+        }
+        if (threadIdx.x == kForwardBlock - 1) {
+            tab[0] = nr;
+            tab[1] = pre;  // (the last thread's prefix after its runs: the total)
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < kHashSlots; k += blockDim.x) hcnt[k] = 0;
+        __syncthreads();
     }
     for (int e = 0; e < ept; ++e) {
         const int64_t i = base + (int64_t)e * blockDim.x + threadIdx.x;
@@ -1432,6 +1454,8 @@ __global__ void __launch_bounds__(kForwardBlock) k_brick_items(const Problem *__
                                                                const uint32_t *__restrict__ end, int fill,
                                                                uint32_t *__restrict__ tabs) {
     __shared__ uint32_t hkey[kHashSlots], hcnt[kHashSlots], hbase[kHashSlots];
+    __shared__ uint16_t qslot[kHashSlots];
+    __shared__ uint32_t bkey[kBrickSlots], wsum[kForwardBlock / 64];
     __shared__ uint32_t nruns;
     const int64_t c = blockIdx.x;
     const Problem P = probs[find_problem(probs, n_probs, c)];
@@ -1440,13 +1464,14 @@ __global__ void __launch_bounds__(kForwardBlock) k_brick_items(const Problem *__
         hkey[k] = fill ? tab[k] : kEmpty;
         hcnt[k] = fill ? tab[kHashSlots + k] : 0u;
     }
+    for (int k = threadIdx.x; k < kBrickSlots; k += blockDim.x) bkey[k] = kEmpty;
     if (threadIdx.x == 0) nruns = 0;
     __syncthreads();
     const int64_t base = (c - P.chunk_begin) * (int64_t)blockDim.x * ept;
     if (P.packed)
-        brick_items_pass<true>(P, base, ept, ctr, end, fill, hkey, hcnt, hbase, &nruns, tab);
+        brick_items_pass<true>(P, base, ept, ctr, end, fill, hkey, hcnt, hbase, &nruns, qslot, bkey, wsum, tab);
     else
-        brick_items_pass<false>(P, base, ept, ctr, end, fill, hkey, hcnt, hbase, &nruns, tab);
+        brick_items_pass<false>(P, base, ept, ctr, end, fill, hkey, hcnt, hbase, &nruns, qslot, bkey, wsum, tab);
 }
 
 // Diagnostic: voxel pieces visited per chunk and how many have non-zero weight.
