@@ -940,6 +940,8 @@ __device__ __forceinline__ void scatter_event_global(const Problem &P, uint32_t 
     }
 }
 
+// EPT: events per lane (the chunk's events over kCombineBlock, rounded up).
+template <int EPT>
 __global__ void __launch_bounds__(kCombineBlock) k_combine(const Problem *__restrict__ probs, int n_probs, int ept,
                                                            int mode, int *__restrict__ part_neff,
                                                            double *__restrict__ part_ll) {
@@ -966,10 +968,10 @@ __global__ void __launch_bounds__(kCombineBlock) k_combine(const Problem *__rest
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     // this thread's events (tid + q blockDim), their offsets and flags,
     // loaded with the first runs
-    uint32_t k0[kCombineEventsPerThread], k1[kCombineEventsPerThread];
-    bool has_ev[kCombineEventsPerThread], flagged[kCombineEventsPerThread];
+    uint32_t k0[EPT], k1[EPT];
+    bool has_ev[EPT], flagged[EPT];
 #pragma unroll
-    for (int q = 0; q < kCombineEventsPerThread; ++q) {
+    for (int q = 0; q < EPT; ++q) {
         const int le = tid + q * kCombineBlock;
         has_ev[q] = le < n_ev;
         k0[q] = has_ev[q] ? evoff[base + le] : 0u;
@@ -1033,7 +1035,7 @@ __global__ void __launch_bounds__(kCombineBlock) k_combine(const Problem *__rest
     int neff = 0;
     float ll = 0.0f;
 #pragma unroll
-    for (int q = 0; q < kCombineEventsPerThread; ++q) {
+    for (int q = 0; q < EPT; ++q) {
         if (!has_ev[q]) continue;
         const int64_t i = base + tid + q * kCombineBlock;
         const bool glob = !by_runs || flagged[q];
@@ -1601,10 +1603,13 @@ hipError_t launch_forward_items(const Launch &L, bool tof, const Problem *d_prob
 
 hipError_t launch_combine(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept, int mode,
                           int *part_neff, double *part_ll) {
-    if ((int64_t)kForwardBlock * ept > (int64_t)kCombineEventsPerThread * kCombineBlock) return hipErrorInvalidValue;
+    const int64_t events = (int64_t)kForwardBlock * ept;
+    if (events > (int64_t)kCombineEventsPerThread * kCombineBlock) return hipErrorInvalidValue;
     void *args[] = {&d_probs, &n_probs, &ept, &mode, &part_neff, &part_ll};
-    return do_launch(L, reinterpret_cast<const void *>(&k_combine), dim3((unsigned)n_chunks), dim3(kCombineBlock), 0,
-                     args);
+    const void *fn = events <= kCombineBlock       ? reinterpret_cast<const void *>(&k_combine<1>)
+                     : events <= 2 * kCombineBlock ? reinterpret_cast<const void *>(&k_combine<2>)
+                                                   : reinterpret_cast<const void *>(&k_combine<kCombineEventsPerThread>);
+    return do_launch(L, fn, dim3((unsigned)n_chunks), dim3(kCombineBlock), 0, args);
 }
 
 hipError_t launch_back_chunks(const Launch &L, bool tof, const Problem *d_probs, int n_probs, const uint4 *chunks,
