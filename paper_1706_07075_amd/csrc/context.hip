@@ -85,9 +85,9 @@ struct ItemSet {
     uint4 *chunks = nullptr, *bricks = nullptr;
     unsigned long long *tiles = nullptr;
     // per brick of the batch (every problem's, empty ones too): its
-    // largest |w| (FP32 bits, set by the combine pass) and its first item
-    // (+ 1 entry)
-    uint32_t *bwmax = nullptr, *brick_off = nullptr;
+    // largest |w| (FP32 bits, set by the combine pass); per problem: the
+    // combine pass's flag for weights written outside its runs
+    uint32_t *bwmax = nullptr, *gflag = nullptr;
     char *item_recs = nullptr;  // walk records in item order (40 B each)
     size_t item_bytes = 0;
     // builder scratch: per-key counters and offsets, the counting blocks'
@@ -97,7 +97,7 @@ struct ItemSet {
     // place and a buffer is only reallocated when it has to grow, so
     // reloading events of a similar size allocates and frees nothing
     size_t pw_cap = 0, evoff_cap = 0, evitems_cap = 0, scan_cap = 0, itemslot_cap = 0, evflag_cap = 0,
-           item_recs_cap = 0, tiles_cap = 0, chunks_cap = 0, bricks_cap = 0, bwmax_cap = 0, brick_off_cap = 0,
+           item_recs_cap = 0, tiles_cap = 0, chunks_cap = 0, bricks_cap = 0, bwmax_cap = 0, gflag_cap = 0,
            cnt_cap = 0, off_cap = 0, tabs_cap = 0;
     uint32_t n_chunks = 0, n_bricks = 0, n_slots = 0;
     uint64_t n_items = 0, n_all_bricks = 0;  // n_bricks: non-empty ones
@@ -253,7 +253,7 @@ void free_items(ItemSet &it) {
     dev_free(it.bricks);
     dev_free(it.tiles);
     dev_free(it.bwmax);
-    dev_free(it.brick_off);
+    dev_free(it.gflag);
     dev_free(it.item_recs);
     dev_free(it.cnt);
     dev_free(it.off_d);
@@ -510,7 +510,7 @@ int build_items(lmtof_ctx *c, std::vector<Problem> &ps, Problem *d_probs, int64_
     if ((rc = reserve(c, &it.cnt, it.cnt_cap, nk + 1)) ||
         (rc = reserve(c, &it.tabs, it.tabs_cap, (size_t)brick_item_tab_words(n_chunks))) ||
         (rc = reserve(c, &it.off_d, it.off_cap, nk + 1)) || (rc = reserve(c, &it.bwmax, it.bwmax_cap, nb)) ||
-        (rc = reserve(c, &it.brick_off, it.brick_off_cap, nb + 1)) ||
+        (rc = reserve(c, &it.gflag, it.gflag_cap, ps.size())) ||
         (rc = reserve(c, &it.evoff, it.evoff_cap, (size_t)ne + 1)) ||
         (rc = reserve(c, &it.evflag, it.evflag_cap, (size_t)ne + 1)) ||
         (rc = reserve(c, &it.scan_tmp, it.scan_cap, (size_t)scan_tmp_elems(ne + 1))))
@@ -520,7 +520,7 @@ int build_items(lmtof_ctx *c, std::vector<Problem> &ps, Problem *d_probs, int64_
         P.evflag = it.evflag + P.ev_offset;
         P.runs = it.tabs + P.chunk_begin * kTabWords;
         P.bwmax = it.bwmax + P.brick_base;
-        P.brick_off = it.brick_off + P.brick_base;
+        P.gflag = it.gflag + (&P - ps.data());
     }
     std::vector<uint32_t> hk(nk);
     hipError_t he = hipMemcpyAsync(d_probs, ps.data(), sizeof(Problem) * ps.size(), hipMemcpyHostToDevice, c->stream);
@@ -592,8 +592,6 @@ int build_items(lmtof_ctx *c, std::vector<Problem> &ps, Problem *d_probs, int64_
         he = hipMemcpyAsync(it.bricks, bricks.data(), sizeof(uint4) * bricks.size(), hipMemcpyHostToDevice, c->stream);
     if (he == hipSuccess)
         he = hipMemcpyAsync(it.cnt, it.off_d, sizeof(uint32_t) * (nk + 1), hipMemcpyDeviceToDevice, c->stream);
-    if (he == hipSuccess)
-        he = hipMemcpyAsync(it.brick_off, off.data(), sizeof(uint32_t) * (nb + 1), hipMemcpyHostToDevice, c->stream);
     if (he == hipSuccess)
         he = launch_brick_items(L, d_probs, (int)ps.size(), n_chunks, ept, it.cnt, it.off_d + 1, 1, it.tabs);
     if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
@@ -772,6 +770,8 @@ int add_forward(lmtof_ctx *c, Launch L, const Problem *d_probs, int np, int64_t 
                              c->opt_forward == LMTOF_FORWARD_BRICKS ? kCombineRatio : kCombineWeights, part_neff,
                              part_ll));
     chain();
+    HIPCHK(c, launch_brick_wmax(L, d_probs, np, it.chunks, it.n_chunks, it.bricks));
+    chain();
     return LMTOF_OK;
 }
 
@@ -941,7 +941,7 @@ int64_t ctx_device_bytes(const lmtof_ctx *c) {
          (int64_t)it.evflag_cap + (int64_t)it.item_recs_cap +
          (int64_t)it.tiles_cap * 8;
     b += (int64_t)(it.chunks_cap + it.bricks_cap) * 16;
-    b += (int64_t)(it.bwmax_cap + it.brick_off_cap + it.cnt_cap + it.off_cap + it.tabs_cap) * 4;
+    b += (int64_t)(it.bwmax_cap + it.gflag_cap + it.cnt_cap + it.off_cap + it.tabs_cap) * 4;
     b += (int64_t)(c->evw_cap + c->evw_stored_cap) * 4;
     b += (int64_t)c->part_cap * 12 + (int64_t)c->vpart_cap * 16 + (kLutN + 2) * 16 + (kLinN + 2) * 8 + (int64_t)c->xb_cap * 4;
     return b;
@@ -979,7 +979,7 @@ int64_t request_bytes_estimate(const lmtof_request &q) {
     b += (items / 2048 + 1 + V / kBrickVox + 1) * (int64_t)kBrickVox * 8 / 4;  // tiles
     const int64_t nbr = (int64_t)((g.nx + kBrickX - 1) / kBrickX) * ((g.ny + kBrickY - 1) / kBrickY) *
                         ((g.nz + kBrickZ - 1) / kBrickZ);
-    b += nbr * (8 + 4 * kItemClasses * 2);  // per brick: maximum, first item; builder counters and offsets
+    b += nbr * (4 + 4 * kItemClasses * 2);  // per brick: maximum; builder counters and offsets
     // transients: the ingest's, then (not at the same time) the brick list
     // builder's key tables, 8 KiB per projector block, at most 32 B an event
     b += N * (q.mem == LMTOF_MEM_HOST ? 28 : 0) + N * std::max<int64_t>(esz + 8 + 4, 32);
@@ -1824,6 +1824,7 @@ int lmtof_back_project(lmtof_ctx *c, const float *w, int64_t nw, float *b, int64
     // each event's weight onto its items, and each brick's largest |w|
     if (he == hipSuccess) he = launch_clear_bwmax(L, dp, 1, (int64_t)its.n_all_bricks);
     if (he == hipSuccess) he = launch_combine(L, dp, 1, nch, ept, kCombineWeights, nullptr, nullptr);
+    if (he == hipSuccess) he = launch_brick_wmax(L, dp, 1, its.chunks, its.n_chunks, its.bricks);
     if (he != hipSuccess) return done(fail(c, LMTOF_EHIP, "back projection: %s", hipGetErrorString(he)));
     if ((rc = add_back(c, L, dp, 1, its, nullptr))) return done(rc);
     if (mem == LMTOF_MEM_HOST) rc = copy_out(c, b, db, sizeof(float) * c->V, LMTOF_MEM_HOST);
@@ -2603,6 +2604,7 @@ int lmtof_pool_step(lmtof_pool *p, int *n_active) {
     PHIP(p, launch_forward_items(L, tof, p->d_probs, np, p->d_chunks, p->n_bchunks, p->d_bricks));
     PHIP(p, launch_clear_bwmax(L, p->d_probs, np, p->n_all_bricks));
     PHIP(p, launch_combine(L, p->d_probs, np, p->n_chunks, p->ept, kCombineRatio, p->part_neff, p->part_ll));
+    PHIP(p, launch_brick_wmax(L, p->d_probs, np, p->d_chunks, p->n_bchunks, p->d_bricks));
     PHIP(p, launch_back_chunks(L, tof, p->d_probs, np, p->d_chunks, p->n_bchunks, p->d_bricks));
     PHIP(p, launch_reduce_tiles(L, p->d_probs, np, p->d_bricks, p->n_bbricks));
     PHIP(p, launch_update(L, p->d_probs, np, p->n_vchunks, p->part_old, p->part_new));

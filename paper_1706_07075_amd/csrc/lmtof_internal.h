@@ -70,9 +70,9 @@ struct Problem {
     // iteration (FP32 bits, an unsigned max; cleared before the combine
     // pass, which sets it), which fixes the brick's fixed-point scale
     uint32_t *bwmax;
-    // per problem-local brick + 1: the position of its first item (items
-    // are grouped by brick)
-    const uint32_t *brick_off;
+    // set (non-zero) by the combine pass when it wrote some item's weight
+    // outside the runs, whose maximum it then leaves to launch_brick_wmax
+    uint32_t *gflag;
     int32_t packed;
     int32_t tof;
     int32_t nx, ny, nz;
@@ -161,12 +161,20 @@ hipError_t launch_forward_items(const Launch &L, bool tof, const Problem *d_prob
 //   kCombineWeights: w = P.rw[i], times P.evw[i] if set, written to every
 //     item of the event.
 // With kCombineRatio and kCombineWeights, P.bwmax (cleared first by
-// launch_clear_bwmax) receives each brick's largest |w| over its items.
+// launch_clear_bwmax) receives each brick's largest |w| over the items the
+// pass reached by runs; launch_brick_wmax then adds the items reached
+// through evitems, if there were any (P.gflag).
 enum { kCombineRatio = 0, kCombineF = 1, kCombineWeights = 2 };
 hipError_t launch_combine(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept, int mode,
                           int *part_neff, double *part_ll);
-// P.bwmax <- 0 for every brick of every problem (n_bricks in all).
+// P.bwmax <- 0 for every brick of every problem (n_bricks in all), and
+// P.gflag <- 0.
 hipError_t launch_clear_bwmax(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_bricks);
+// After the combine pass, if P.gflag is set: P.bwmax of each brick chunk's
+// brick <- max(itself, the largest |w| over the chunk's items).  A chunk of
+// a problem whose flag is clear returns at once.
+hipError_t launch_brick_wmax(const Launch &L, const Problem *d_probs, int n_probs, const uint4 *chunks,
+                             uint32_t n_chunks, const uint4 *bricks);
 // Back projection by brick chunks.  Brick table entry (global brick id,
 // first tile slot, end tile slot, items in the brick); chunk (brick table
 // index, first item, end item, tile slot) over the items of the brick's

@@ -671,13 +671,37 @@ __global__ void __launch_bounds__(kForwardBlock) k_forward(const Problem *__rest
 // Brick table entry (brick id, first tile slot, end tile slot, items in the
 // brick); chunk (brick table index, first item, end item, tile slot).
 
-// P.bwmax <- 0 over every problem's bricks (before the combine pass sets it).
+// P.bwmax <- 0 over every problem's bricks and P.gflag <- 0 (before the
+// combine pass sets them).
 __global__ void __launch_bounds__(256) k_clear_bwmax(const Problem *__restrict__ probs, int n_probs,
                                                      int64_t n_bricks) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n_bricks) return;
     const Problem &P = probs[find_brick_problem(probs, n_probs, (uint32_t)g)];
-    P.bwmax[(uint32_t)g - (uint32_t)P.brick_base] = 0u;
+    const uint32_t bl = (uint32_t)g - (uint32_t)P.brick_base;
+    P.bwmax[bl] = 0u;
+    if (bl == 0) P.gflag[0] = 0u;
+}
+
+// The largest |w| over a brick chunk's items into its brick's P.bwmax, for
+// problems whose combine pass wrote weights outside its runs.
+__global__ void __launch_bounds__(256) k_brick_wmax(const Problem *__restrict__ probs, int n_probs,
+                                                    const uint4 *__restrict__ chunks,
+                                                    const uint4 *__restrict__ bricks) {
+    __shared__ uint32_t s_max;
+    const uint4 ch = chunks[blockIdx.x];
+    const uint4 br = bricks[ch.x];
+    const Problem &P = probs[find_brick_problem(probs, n_probs, br.x)];
+    if (global(P.gflag)[0] == 0u) return;  // (uniform)
+    if (threadIdx.x == 0) s_max = 0u;
+    __syncthreads();
+    const gptr<const float> pw = global(P.pw);
+    float m = 0.0f;
+    for (uint32_t k = ch.y + threadIdx.x; k < ch.z; k += blockDim.x) m = fmaxf(m, fabsf(pw[k]));
+    m = wave_max(m);
+    if ((threadIdx.x & 63) == 0) atomicMax(&s_max, __float_as_uint(m));
+    __syncthreads();
+    if (threadIdx.x == 0) atomicMax(P.bwmax + (br.x - (uint32_t)P.brick_base), s_max);
 }
 
 // Fixed-point exponent of a brick (same value in every chunk and the
@@ -875,10 +899,11 @@ __global__ void __launch_bounds__(kBackBlock) k_forward_items(const Problem *__r
 // its weight in every one of its slots; phase 3 writes the slots back to the
 // items run by run and keeps their |w| in run order; phase 4 takes each
 // brick's largest |w| in LDS, then adds it to P.bwmax (one global atomic per
-// brick the chunk touches).  Events the builder flagged (an item placed outside the
-// runs) are summed and written through evitems in phase 2, their items'
-// bricks found by binary search; a chunk with more than kRunEvents events or
-// kRunItems items takes that path for every event.
+// brick the chunk touches).  Events the builder flagged (an item placed
+// outside the runs) are summed and written through evitems in phase 2, and
+// P.gflag is set so that launch_brick_wmax takes their bricks' maxima; a
+// chunk with more than kRunEvents events or kRunItems items takes that path
+// for every event.
 constexpr int kRunEvents = 2048;
 constexpr int kRunItems = 8192;
 constexpr int kMaxRuns = 1024;  // a chunk has at most one run per slot of the builder's hash table
@@ -900,20 +925,6 @@ __device__ __forceinline__ uint32_t row_next(uint32_t v, uint32_t none) {
     return (uint32_t)__builtin_amdgcn_update_dpp((int)none, (int)v, 0x101, 0xf, 0xf, false);
 }
 
-// Problem-local brick holding item position q (items are grouped by brick).
-__device__ __forceinline__ uint32_t brick_of(const Problem &P, uint32_t q) {
-    const gptr<const uint32_t> off = global(P.brick_off);
-    uint32_t lo = 0, hi = (uint32_t)P.nbx * (uint32_t)P.nby * (uint32_t)P.nbz;  // off[lo] <= q < off[hi]
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (off[mid] <= q)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
 // An event's f from its items' partials, through evitems.
 __device__ __forceinline__ float combine_event_global(const Problem &P, uint32_t k0, uint32_t k1) {
     const gptr<const float> pw = global(P.pw);
@@ -926,17 +937,13 @@ __device__ __forceinline__ float combine_event_global(const Problem &P, uint32_t
     return f;
 }
 
-// An event's weight onto its items, through evitems; with maxima, each
-// item's brick maximum too.
-__device__ __forceinline__ void scatter_event_global(const Problem &P, uint32_t k0, uint32_t k1, float w,
-                                                     bool maxima) {
+// An event's weight onto its items, through evitems.
+__device__ __forceinline__ void scatter_event_global(const Problem &P, uint32_t k0, uint32_t k1, float w) {
     const gptr<float> pw = global(P.pw);
     const gptr<const uint32_t> evitems = global(P.evitems);
     for (uint32_t k = k0; k < k1; ++k) {
         const uint32_t q = evitems[k];
-        if (q >= P.n_items) continue;
-        pw[q] = w;
-        if (maxima) atomicMax(P.bwmax + brick_of(P, q), __float_as_uint(fabsf(w)));
+        if (q < P.n_items) pw[q] = w;
     }
 }
 
@@ -1034,6 +1041,7 @@ __global__ void __launch_bounds__(kCombineBlock) k_combine(const Problem *__rest
     // phase 2: the thread's events
     int neff = 0;
     float ll = 0.0f;
+    bool any_glob = false;
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
         if (!has_ev[q]) continue;
@@ -1062,9 +1070,15 @@ __global__ void __launch_bounds__(kCombineBlock) k_combine(const Problem *__rest
         if (P.evw) w *= P.evw[i];
         if (by_runs)
             for (uint32_t k = 0; k < cnt; ++k) slot[s0 + k] = w;
-        if (glob) scatter_event_global(P, k0[q], k1[q], w, true);
+        if (glob) {
+            scatter_event_global(P, k0[q], k1[q], w);
+            any_glob = true;
+        }
     }
     if (mode == kCombineF) return;
+    // items written through evitems: their bricks' maxima are taken by
+    // launch_brick_wmax
+    if (any_glob) global(P.gflag)[0] = 1u;
     __syncthreads();
     // phase 3: weights onto the items; their |w| to the slots in run order
     float wv[kRunItemsPerThread];
@@ -1624,6 +1638,12 @@ hipError_t launch_clear_bwmax(const Launch &L, const Problem *d_probs, int n_pro
     void *args[] = {&d_probs, &n_probs, &n_bricks};
     return do_launch(L, reinterpret_cast<const void *>(&k_clear_bwmax), dim3((unsigned)((n_bricks + 255) / 256)),
                      dim3(256), 0, args);
+}
+
+hipError_t launch_brick_wmax(const Launch &L, const Problem *d_probs, int n_probs, const uint4 *chunks,
+                             uint32_t n_chunks, const uint4 *bricks) {
+    void *args[] = {&d_probs, &n_probs, &chunks, &bricks};
+    return do_launch(L, reinterpret_cast<const void *>(&k_brick_wmax), dim3(n_chunks), dim3(256), 0, args);
 }
 
 hipError_t launch_reduce_tiles(const Launch &L, const Problem *d_probs, int n_probs, const uint4 *bricks,
