@@ -980,9 +980,11 @@ int64_t request_bytes_estimate(const lmtof_request &q) {
     const int64_t nbr = (int64_t)((g.nx + kBrickX - 1) / kBrickX) * ((g.ny + kBrickY - 1) / kBrickY) *
                         ((g.nz + kBrickZ - 1) / kBrickZ);
     b += nbr * (4 + 4 * kItemClasses * 2);  // per brick: maximum; builder counters and offsets
-    // transients: the ingest's, then (not at the same time) the brick list
-    // builder's key tables, 8 KiB per projector block, at most 32 B an event
-    b += N * (q.mem == LMTOF_MEM_HOST ? 28 : 0) + N * std::max<int64_t>(esz + 8 + 4, 32);
+    // the forward chunks' key tables, then run rows (kTabWords words per
+    // chunk of kForwardBlock x kDefaultEpt events), kept for the iterations
+    b += (N + kForwardBlock * kDefaultEpt - 1) / (kForwardBlock * kDefaultEpt) * kTabWords * 4;
+    // transients of the ingest
+    b += N * (q.mem == LMTOF_MEM_HOST ? 28 : 0) + N * (esz + 8 + 4);
     return b + (64 << 20);
 }
 
