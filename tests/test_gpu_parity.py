@@ -286,6 +286,38 @@ def test_grid_of_many_bricks():
     assert not outer.any()
 
 
+def test_events_missing_the_grid_and_empty_loads():
+    """Degenerate inputs.  A load of no events is refused (EINVAL) and the
+    context keeps its previous events.  Events whose lines all pass beside
+    the grid give no brick items at all: the forward and back projections
+    are 0 and MLEM takes the image to 0 with N_eff = 0, as the oracle's."""
+    _say("case: lines missing the grid, empty load")
+    g = dict(nx=8, ny=8, nz=8, vx=4.0, vy=4.0, vz=4.0, x0=-16.0, y0=-16.0, z0=-16.0, scanner_radius=400.0,
+             scanner_half_length=300.0, max_axial_angle_deg=0.0, tof_fwhm_ps=300.0, tof_trunc_sigmas=3.0,
+             c_mm_per_ps=0.299792458)
+    rng = np.random.default_rng(77)
+    n = 500
+    y = rng.uniform(60.0, 300.0, n) * rng.choice([-1.0, 1.0], n)  # lines parallel to x, |y| >= 60 mm
+    z1, z2 = rng.uniform(-100.0, 100.0, n), rng.uniform(-100.0, 100.0, n)
+    xr = np.sqrt(400.0 ** 2 - y ** 2)
+    ev = np.stack([-xr, y, z1, xr, y, z2, rng.uniform(-300.0, 300.0, n)], 1).astype(np.float32)
+    ones = np.ones(g["nx"] * g["ny"] * g["nz"], np.float32)
+    assert not oracle.forward(g, ev, ones.astype(np.float64)).any()  # the oracle agrees nothing is hit
+    with _recon(g, ev) as r:
+        with pytest.raises(L.LmtofError) as e:
+            r.load_events(ev[:0])
+        assert e.value.code == L.LMTOF_EINVAL
+        assert r.n_events == n
+        f = r.forward_project(ones)
+        b = r.back_project(np.ones(n, np.float32))
+        r.compute_sensitivity()
+        r.set_image()
+        st = r.iterate(2)
+        x = r.read_image()
+    assert not f.any() and not b.any() and not x.any()
+    assert st[-1]["n_eff"] == 0
+
+
 @pytest.mark.parametrize("n", [1, 2, 63, 65, 257, 4099])
 def test_ragged_event_counts(n):
     _say(f"case: ragged n={n}")
