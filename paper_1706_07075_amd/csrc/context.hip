@@ -80,7 +80,7 @@ struct ItemSet {
     // item positions in evitems (+ 1 entry); the positions in brick order
     uint32_t *evoff = nullptr, *evitems = nullptr;
     uint32_t *scan_tmp = nullptr;
-    uint16_t *itemslot = nullptr;  // per item: its (event in chunk, ordinal) slot of the combine pass
+    uint16_t *itemslot = nullptr;  // per run item, in run order: its (event in chunk, ordinal) slot
     uint8_t *evflag = nullptr;     // per event: reached through evitems by the combine pass
     uint4 *chunks = nullptr, *bricks = nullptr;
     unsigned long long *tiles = nullptr;

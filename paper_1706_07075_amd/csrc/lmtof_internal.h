@@ -48,14 +48,16 @@ struct Problem {
     const uint32_t *evitems;
     // How the combine pass reaches a forward chunk's items with coalesced
     // accesses.  runs + chunk * kTabWords (chunk counted from this
-    // problem's first): the number of runs, then (first position, length,
-    // problem-local brick) of each run of consecutive positions the
-    // chunk's events fill (one run per (brick, item class) key).  Per
-    // item: its index in the chunk's items in event-major order (its
-    // event's evoff minus the chunk's first, plus its ordinal), or 0xffff
-    // for an item outside the runs or of a chunk with too many items.  Per
-    // event: 1 if any of its items was placed outside the runs (the combine
-    // pass then reaches all of them through evitems).
+    // problem's first): a header (number of runs, items in runs) and a row
+    // per run of consecutive positions the chunk's events fill (one run per
+    // (brick, item class) key: first position, length | brick slot << 16 |
+    // owner << 31, prefix of the lengths, problem-local brick).  itemslot,
+    // in run order from the chunk's first evitems index (evoff of its first
+    // event): each run item's index in the chunk's items in event-major
+    // order (its event's evoff minus the chunk's first, plus its ordinal);
+    // written for chunks of at most kRunItems items.  Per event: 1 if any
+    // of its items was placed outside the runs (the combine pass then
+    // reaches all of them through evitems).
     const uint32_t *runs;
     const uint16_t *itemslot;
     const uint8_t *evflag;

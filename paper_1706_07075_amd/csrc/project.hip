@@ -1022,9 +1022,9 @@ __global__ void __launch_bounds__(kCombineBlock) k_combine(const Problem *__rest
         pos[m] = 0;
         sl[m] = 0xffffu;
         if (by_runs && t < T) {
+            sl[m] = itemslot[E0 + t];  // (stored in run order: coalesced)
             const uint32_t r = rid[t];
             pos[m] = rbase[r] + (t - rpre[r]);
-            sl[m] = itemslot[pos[m]];
         }
     }
     if (mode != kCombineWeights) {
@@ -1329,7 +1329,7 @@ __device__ __forceinline__ void brick_items_pass(const Problem &P, int64_t base,
                                                  uint32_t *__restrict__ ctr, const uint32_t *__restrict__ end,
                                                  int fill, uint32_t *hkey, uint32_t *hcnt, uint32_t *hbase,
                                                  uint32_t *nruns, uint16_t *qslot, uint32_t *bkey,
-                                                 uint32_t *wsum, gptr<uint32_t> tab) {
+                                                 uint32_t *wsum, uint32_t *hpre, gptr<uint32_t> tab) {
     const gptr<uint32_t> evoff = global(const_cast<uint32_t *>(P.evoff));
     const gptr<uint32_t> evitems = global(const_cast<uint32_t *>(P.evitems));
     const gptr<uint16_t> itemslot = global(const_cast<uint16_t *>(P.itemslot));
@@ -1404,6 +1404,7 @@ __device__ __forceinline__ void brick_items_pass(const Problem &P, int64_t base,
                 }
                 const uint32_t y = len[j] | ((bs >= 0 ? (uint32_t)bs : 0x7fffu) << 16) | (owner ? 1u << 31 : 0u);
                 ((gptr<u32x4>)(tab + kTabHead))[q] = u32x4{hbase[k], y, pre, brick};
+                hpre[k] = pre;
             }
             pre += len[j];
         }
@@ -1441,10 +1442,10 @@ __device__ __forceinline__ void brick_items_pass(const Problem &P, int64_t base,
             const uint32_t pos = h >= 0 ? hbase[h] + atomicAdd(&hcnt[h], 1u) : atomicAdd(ctr + key, 1u);
             const bool in = pos < end[key];
             const bool run = h >= 0 && small;
-            if (in) {
-                write_item_walk(P, r, bx, by, bz, t0, t1, pos);
-                itemslot[pos] = run ? (uint16_t)(e0 + n - c0) : (uint16_t)0xffffu;
-            }
+            if (in) write_item_walk(P, r, bx, by, bz, t0, t1, pos);
+            // a run item's slot, at its run-order index in the chunk's range
+            // of the item lists (the writes of a chunk stay in a few KB)
+            if (run) itemslot[c0 + hpre[h] + (pos - hbase[h])] = (uint16_t)(e0 + n - c0);
             outside = outside || h < 0 || !in;
             // (a position past the key's range, which a consistent count
             // never gives, is marked out of range for the combine pass)
@@ -1471,7 +1472,7 @@ __global__ void __launch_bounds__(kForwardBlock) k_brick_items(const Problem *__
                                                                uint32_t *__restrict__ tabs) {
     __shared__ uint32_t hkey[kHashSlots], hcnt[kHashSlots], hbase[kHashSlots];
     __shared__ uint16_t qslot[kHashSlots];
-    __shared__ uint32_t bkey[kBrickSlots], wsum[kForwardBlock / 64];
+    __shared__ uint32_t bkey[kBrickSlots], wsum[kForwardBlock / 64], hpre[kHashSlots];
     __shared__ uint32_t nruns;
     const int64_t c = blockIdx.x;
     const Problem P = probs[find_problem(probs, n_probs, c)];
@@ -1485,9 +1486,9 @@ __global__ void __launch_bounds__(kForwardBlock) k_brick_items(const Problem *__
     __syncthreads();
     const int64_t base = (c - P.chunk_begin) * (int64_t)blockDim.x * ept;
     if (P.packed)
-        brick_items_pass<true>(P, base, ept, ctr, end, fill, hkey, hcnt, hbase, &nruns, qslot, bkey, wsum, tab);
+        brick_items_pass<true>(P, base, ept, ctr, end, fill, hkey, hcnt, hbase, &nruns, qslot, bkey, wsum, hpre, tab);
     else
-        brick_items_pass<false>(P, base, ept, ctr, end, fill, hkey, hcnt, hbase, &nruns, qslot, bkey, wsum, tab);
+        brick_items_pass<false>(P, base, ept, ctr, end, fill, hkey, hcnt, hbase, &nruns, qslot, bkey, wsum, hpre, tab);
 }
 
 // Diagnostic: voxel pieces visited per chunk and how many have non-zero weight.
