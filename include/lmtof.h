@@ -72,8 +72,12 @@ extern "C" {
 #define LMTOF_OPT_SORT 2
 /* Azimuth nodes of the sensitivity quadrature.  Default 2048. */
 #define LMTOF_OPT_SENS_NPHI 3
-/* Forward-projector launch shape: events per thread (1..16; 256 threads per
- * block).  0 = library default. */
+/* Events per forward chunk, over 256: 1..16, 0 = library default (4).  A
+ * forward chunk (256 x value events, in stored order) is the unit of the
+ * event-parallel forward pass, of the brick-list builder's key tables and
+ * of the combine pass, which handles a chunk of at most 2048 events and
+ * 8192 brick items through LDS and larger ones through each event's item
+ * list (slower).  Takes effect when the brick lists are next built. */
 #define LMTOF_OPT_EVENTS_PER_THREAD 5
 /* Approximate edge of the sort key's sub-cells inside a brick, in mm
  * (default 16: 4 x 4 x 4 sub-cells of a brick of 4 mm voxels). */
