@@ -149,6 +149,8 @@ def main():
     ap.add_argument("--cpu-sample-1core", type=int, default=2_000_000,
                     help="events in the oracle CPU-baseline sample on one thread (0 = skip)")
     ap.add_argument("--ept", type=int, default=0)
+    ap.add_argument("--sort-cell-mm", type=int, default=0,
+                    help="edge of the bucketing sort's sub-cells (0: the library's default, 16 mm)")
     ap.add_argument("--forward", choices=["bricks", "events"], default="bricks",
                     help="forward projector: brick-owned (LDS-staged image bricks) or event-parallel")
     ap.add_argument("--regions", action="store_true",
@@ -212,6 +214,8 @@ def main():
                 forward=L.LMTOF_FORWARD_BRICKS if args.forward == "bricks" else L.LMTOF_FORWARD_EVENTS)
     if args.ept:
         opts["events_per_thread"] = args.ept
+    if args.sort_cell_mm:
+        opts["sort_cell_mm"] = args.sort_cell_mm
     r = L.Reconstruction(g, device=0, **opts)
 
     tuned = None
