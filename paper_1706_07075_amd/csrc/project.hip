@@ -369,9 +369,13 @@ struct Stepper {
     }
     __device__ __forceinline__ float next() const { return fminf(fminf(tx, ty), tz); }
     __device__ __forceinline__ void advance(const Ray &r, float tmin) {
-        const bool mx = tx == tmin;
-        const bool my = !mx && ty == tmin;
-        const bool mz = !mx && !my;
+        // (the masks are combined as wavefront bit masks: the tie rules
+        // then cost two vector compares, not three)
+        const uint64_t ex = __builtin_amdgcn_ballot_w64(tx == tmin);
+        const uint64_t ey = __builtin_amdgcn_ballot_w64(ty == tmin);
+        const bool mx = __builtin_amdgcn_inverse_ballot_w64(ex);
+        const bool my = __builtin_amdgcn_inverse_ballot_w64(ey & ~ex);
+        const bool mz = __builtin_amdgcn_inverse_ballot_w64(~(ex | ey));
         kx += mx ? sx : 0.0f;
         ky += my ? sy : 0.0f;
         kz += mz ? sz : 0.0f;
@@ -463,6 +467,33 @@ __device__ __forceinline__ void walk_from(Stepper &s, const Ray &r, float ta, fl
     float t = ta;
     float c = TOF ? cdf(ta) : 0.0f;
     for (int step = 0; step < s.max_steps; ++step) {
+        const float tmin = s.next();
+        const float tn = __builtin_amdgcn_fmed3f(tmin, t, tb);
+        float a;
+        if (TOF) {
+            const float cn = cdf(tn);
+            a = cn - c;
+            c = cn;
+        } else {
+            a = tn - t;
+        }
+        t = tn;
+        visit(s.j, a);
+        if (tmin >= tb) break;
+        s.advance(r, tmin);
+    }
+}
+
+// walk_from for a brick item (a Stepper made from its walk record, at
+// most kBrickX + kBrickY + kBrickZ + 2 steps): the same pieces in the same
+// order, unrolled so that the step bound is tested once per five pieces.
+template <bool TOF, class C, class Visit>
+__device__ __forceinline__ void walk_item(Stepper &s, const Ray &r, float ta, float tb, const C &cdf,
+                                          Visit &&visit) {
+    float t = ta;
+    float c = TOF ? cdf(ta) : 0.0f;
+#pragma unroll 5
+    for (int step = 0; step < kBrickX + kBrickY + kBrickZ + 2; ++step) {
         const float tmin = s.next();
         const float tn = __builtin_amdgcn_fmed3f(tmin, t, tb);
         float a;
@@ -747,7 +778,7 @@ __device__ __forceinline__ void back_item(const f32x4 &ra, const f32x4 &rb, cons
     const float ta = ra[3], tb = rb[3];
     // j is a byte offset into the tile, inside its margin (see the tile)
     const double wsd = ws;
-    walk_from<TOF>(s, r, ta, tb, cdf, [&](int j, float a) {
+    walk_item<TOF>(s, r, ta, tb, cdf, [&](int j, float a) {
         atomicAdd(reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(tile) + j), fixed_round(a, wsd));
     });
 }
@@ -882,7 +913,7 @@ __global__ void __launch_bounds__(kBackBlock) k_forward_items(const Problem *__r
         Stepper s(r, make_uint2(rk[0], rk[1]), (int)sizeof(float));
         float p = 0.0f;
         // j is a byte offset into the tile, inside its margin (see the tile)
-        walk_from<TOF>(s, r, ra[3], rb[3], cdf, [&](int j, float a) {
+        walk_item<TOF>(s, r, ra[3], rb[3], cdf, [&](int j, float a) {
             p = fmaf(a, *reinterpret_cast<const float *>(reinterpret_cast<const char *>(tile) + j), p);
         });
         pw[k] = p;
