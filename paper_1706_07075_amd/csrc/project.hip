@@ -552,9 +552,9 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
-__device__ __forceinline__ float wave_max(float v) {
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    for (int off = 32; off > 0; off >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off, 64));
     return v;
 }
 
@@ -714,8 +714,18 @@ __global__ void __launch_bounds__(256) k_clear_bwmax(const Problem *__restrict__
     if (bl == 0) P.gflag[0] = 0u;
 }
 
-// The largest |w| over a brick chunk's items into its brick's P.bwmax, for
-// problems whose combine pass wrote weights outside its runs.
+// A brick's fixed-point scale depends only on the binary exponent of its
+// largest |w|, so P.bwmax keeps, per brick, the largest exponent field of
+// its items' |w| (1 for a subnormal, 0 for zero), stored as that power of
+// two's float bits: it has the largest |w|'s frexp exponent.
+__device__ __forceinline__ uint32_t weight_exponent(float w) {
+    const uint32_t u = __float_as_uint(w) & 0x7fffffffu;
+    const uint32_t e = u >> 23;
+    return e == 0u && u != 0u ? 1u : e;
+}
+
+// The largest exponent of |w| over a brick chunk's items into its brick's
+// P.bwmax, for problems whose combine pass wrote weights outside its runs.
 __global__ void __launch_bounds__(256) k_brick_wmax(const Problem *__restrict__ probs, int n_probs,
                                                     const uint4 *__restrict__ chunks,
                                                     const uint4 *__restrict__ bricks) {
@@ -727,17 +737,18 @@ __global__ void __launch_bounds__(256) k_brick_wmax(const Problem *__restrict__ 
     if (threadIdx.x == 0) s_max = 0u;
     __syncthreads();
     const gptr<const float> pw = global(P.pw);
-    float m = 0.0f;
-    for (uint32_t k = ch.y + threadIdx.x; k < ch.z; k += blockDim.x) m = fmaxf(m, fabsf(pw[k]));
+    uint32_t m = 0u;
+    for (uint32_t k = ch.y + threadIdx.x; k < ch.z; k += blockDim.x) m = max(m, weight_exponent(pw[k]));
     m = wave_max(m);
-    if ((threadIdx.x & 63) == 0) atomicMax(&s_max, __float_as_uint(m));
+    if ((threadIdx.x & 63) == 0) atomicMax(&s_max, m);
     __syncthreads();
-    if (threadIdx.x == 0) atomicMax(P.bwmax + (br.x - (uint32_t)P.brick_base), s_max);
+    if (threadIdx.x == 0) atomicMax(P.bwmax + (br.x - (uint32_t)P.brick_base), s_max << 23);
 }
 
 // Fixed-point exponent of a brick (same value in every chunk and the
-// reduce), from the largest |w| over its items (an order-independent
-// bound: the same whatever events share the forward chunks).
+// reduce), from the exponent of the largest |w| over its items (an
+// order-independent bound: the same whatever events share the forward
+// chunks).
 __device__ __forceinline__ int brick_exponent(const Problem &P, const uint4 &br, float &wmax) {
     const float wm = __uint_as_float(P.bwmax[br.x - (uint32_t)P.brick_base]);
     wmax = wm;
@@ -987,6 +998,7 @@ __global__ void __launch_bounds__(kCombineBlock) k_combine(const Problem *__rest
     __shared__ __align__(16) uint16_t rid[kRunItems];
     __shared__ uint32_t rbase[kMaxRuns], rpre[kMaxRuns], rbrick[kMaxRuns], rlen[kMaxRuns];
     __shared__ int16_t rslot[kMaxRuns];
+    __shared__ __align__(16) uint8_t wexp[kRunItems];
     __shared__ uint32_t bmax[kBrickSlots];
     __shared__ int s_n[kCombineBlock / 64];
     __shared__ double s_l[kCombineBlock / 64];
@@ -1110,20 +1122,28 @@ __global__ void __launch_bounds__(kCombineBlock) k_combine(const Problem *__rest
     // items written through evitems: their bricks' maxima are taken by
     // launch_brick_wmax
     if (any_glob) global(P.gflag)[0] = 1u;
-    __syncthreads();
-    // phase 3: weights onto the items; their |w| to the slots in run order
-    float wv[kRunItemsPerThread];
-#pragma unroll
-    for (int m = 0; m < kRunItemsPerThread; ++m) {
-        wv[m] = sl[m] != 0xffffu ? slot[sl[m]] : 0.0f;
-        if (sl[m] != 0xffffu) pw[pos[m]] = wv[m];
+    // the wavefront's count and log-likelihood, added up at the end
+    {
+        const int wn = wave_sum(neff);
+        const double wl = wave_sum((double)ll);
+        if (lane == 0) {
+            s_n[wid] = wn;
+            s_l[wid] = wl;
+        }
     }
     __syncthreads();
+    // phase 3: weights onto the items; the exponent field of each |w| to
+    // the run order (in its own array: the slots are still being read)
 #pragma unroll
-    for (int m = 0; m < kRunItemsPerThread; ++m)
-        if (sl[m] != 0xffffu) slot[tid + m * kCombineBlock] = fabsf(wv[m]);
+    for (int m = 0; m < kRunItemsPerThread; ++m) {
+        if (sl[m] != 0xffffu) {
+            const float w = slot[sl[m]];
+            pw[pos[m]] = w;
+            wexp[tid + m * kCombineBlock] = (uint8_t)weight_exponent(w);
+        }
+    }
     __syncthreads();
-    // phase 4: each brick's largest |w|.  A thread takes 8 consecutive slots
+    // phase 4: each brick's largest exponent.  A thread takes 8 consecutive slots
     // of the run order: a run that starts and ends among them goes to its
     // brick at once; the pieces of runs that cross thread boundaries are
     // combined by a segmented max scan over each row of 16 lanes (run ids
@@ -1134,26 +1154,26 @@ __global__ void __launch_bounds__(kCombineBlock) k_combine(const Problem *__rest
         const uint32_t t8 = 8u * (uint32_t)tid;
         constexpr uint32_t kNone = 0xffffffffu;
         uint32_t fk = kNone, lk = kNone;  // first and last piece's run
-        float fv = 0.0f, lv = 0.0f;
+        uint32_t fv = 0u, lv = 0u;        // and their largest exponents
         bool multi = false;
-        auto to_brick = [&](uint32_t run, float mx) {
+        auto to_brick = [&](uint32_t run, uint32_t mx) {
             const int b = rslot[run];
             if (b >= 0)
-                atomicMax(&bmax[b], __float_as_uint(mx));
+                atomicMax(&bmax[b], mx);
             else
-                atomicMax(P.bwmax + rbrick[run], __float_as_uint(mx));  // brick table full
+                atomicMax(P.bwmax + rbrick[run], mx << 23);  // brick table full
         };
         if (by_runs && t8 < T) {
-            const float4 va = *reinterpret_cast<const float4 *>(&slot[t8]);
-            const float4 vb = *reinterpret_cast<const float4 *>(&slot[t8 + 4]);
+            const uint2 ee = *reinterpret_cast<const uint2 *>(&wexp[t8]);
             const uint4 rr = *reinterpret_cast<const uint4 *>(&rid[t8]);
-            const float v[8] = {va.x, va.y, va.z, va.w, vb.x, vb.y, vb.z, vb.w};
+            const uint32_t v[8] = {ee.x & 0xffu, (ee.x >> 8) & 0xffu, (ee.x >> 16) & 0xffu, ee.x >> 24,
+                                   ee.y & 0xffu, (ee.y >> 8) & 0xffu, (ee.y >> 16) & 0xffu, ee.y >> 24};
             const uint32_t r[8] = {rr.x & 0xffffu, rr.x >> 16, rr.y & 0xffffu, rr.y >> 16,
                                    rr.z & 0xffffu, rr.z >> 16, rr.w & 0xffffu, rr.w >> 16};
             const uint32_t n = min(8u, T - t8);
             fk = r[0];
             uint32_t cur = r[0];
-            float mx = v[0];
+            uint32_t mx = v[0];
 #pragma unroll
             for (uint32_t k = 1; k < 8; ++k) {
                 if (k >= n) break;
@@ -1167,7 +1187,7 @@ __global__ void __launch_bounds__(kCombineBlock) k_combine(const Problem *__rest
                     cur = r[k];
                     mx = v[k];
                 } else {
-                    mx = fmaxf(mx, v[k]);
+                    mx = max(mx, v[k]);
                 }
             }
             lk = cur;
@@ -1175,7 +1195,7 @@ __global__ void __launch_bounds__(kCombineBlock) k_combine(const Problem *__rest
         }
         // (the lane's place in its row decides which moves are valid)
         const int rl16 = lane & 15;
-        uint32_t sv = __float_as_uint(lv);  // |w| bits order like the values
+        uint32_t sv = lv;
         {
             // (every lane makes each move: none is inside a branch)
             uint32_t o = row_up<1>(sv, 0u), ok = row_up<1>(lk, kNone);
@@ -1193,19 +1213,11 @@ __global__ void __launch_bounds__(kCombineBlock) k_combine(const Problem *__rest
         const uint32_t pv = row_up<1>(sv, 0u), pk = row_up<1>(lk, kNone);
         const uint32_t nf = row_next(fk, kNone);
         // the first piece ends a run that began in an earlier lane or here
-        if (multi)
-            to_brick(fk, __uint_as_float(rl16 >= 1 && pk == fk ? max(__float_as_uint(fv), pv) : __float_as_uint(fv)));
-        if (lk != kNone && (rl16 == 15 || nf != lk)) to_brick(lk, __uint_as_float(sv));
+        if (multi) to_brick(fk, rl16 >= 1 && pk == fk ? max(fv, pv) : fv);
+        if (lk != kNone && (rl16 == 15 || nf != lk)) to_brick(lk, sv);
     }
     __syncthreads();
-    if (by_runs && owner) atomicMax(P.bwmax + row.w, bmax[bslot]);
-    const int wn = wave_sum(neff);
-    const double wl = wave_sum((double)ll);
-    if (lane == 0) {
-        s_n[wid] = wn;
-        s_l[wid] = wl;
-    }
-    __syncthreads();
+    if (by_runs && owner) atomicMax(P.bwmax + row.w, bmax[bslot] << 23);
     if (tid == 0 && mode == kCombineRatio) {
         int tn = 0;
         double tl = 0.0;
