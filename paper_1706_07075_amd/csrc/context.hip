@@ -88,7 +88,7 @@ struct ItemSet {
     // largest |w| (FP32 bits, set by the combine pass); per problem: the
     // combine pass's flag for weights written outside its runs
     uint32_t *bwmax = nullptr, *gflag = nullptr;
-    char *item_recs = nullptr;  // walk records in item order (40 B each)
+    char *item_recs = nullptr;  // walk records in item order (32 B each)
     size_t item_bytes = 0;
     // builder scratch: per-key counters and offsets, the counting blocks'
     // key tables (then the forward chunks' run lists)
@@ -581,7 +581,6 @@ int build_items(lmtof_ctx *c, std::vector<Problem> &ps, Problem *d_probs, int64_
         P.tiles = it.tiles;
         P.rec_a = reinterpret_cast<const float4 *>(it.item_recs);
         P.rec_b = reinterpret_cast<const float4 *>(it.item_recs + (size_t)tot * 16);
-        P.rec_k = reinterpret_cast<const uint2 *>(it.item_recs + (size_t)tot * 32);
     }
     he = hipMemcpyAsync(d_probs, ps.data(), sizeof(Problem) * ps.size(), hipMemcpyHostToDevice, c->stream);
     if (he == hipSuccess)

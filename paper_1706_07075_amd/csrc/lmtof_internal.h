@@ -21,7 +21,7 @@ constexpr int kBrickVox = kBrickX * kBrickY * kBrickZ;
 // (longest first), so that a wavefront's lanes walk similar lengths.
 constexpr int kItemClasses = 16;
 // Bytes of one brick item's walk record (two float4 and one uint2).
-constexpr int kItemRecBytes = 40;
+constexpr int kItemRecBytes = 32;
 constexpr int kForwardBlock = 256;
 constexpr int kBackBlock = 1024;
 
@@ -62,11 +62,12 @@ struct Problem {
     const uint16_t *itemslot;
     const uint8_t *evflag;
     // per item, its walk inside the brick, precomputed when the lists are
-    // built: (A_x, A_y, A_z, t_a), (B_x, B_y, B_z, t_b), (k_x | k_y << 16,
-    // k_z | local voxel << 16) with k the first plane index minus the anchor
+    // built: (A_x, A_y, A_z, B_x), (B_y, B_z, k_x | k_y << 16, k_z | local
+    // voxel << 16 | entry face << 28) with k the first plane index minus the
+    // anchor; the item's piece of the window follows from the entry face and
+    // the brick's far faces
     const float4 *rec_a;
     const float4 *rec_b;
-    const uint2 *rec_k;
     unsigned long long *tiles;  // 64-bit fixed-point chunk tiles, indexed by tile slot
     // per problem-local brick: the largest |w| over its items this
     // iteration (FP32 bits, an unsigned max; cleared before the combine

@@ -345,27 +345,41 @@ struct Stepper {
         djz = pz ? B.sz : -B.sz;
         max_steps = B.nx + B.ny + B.nz + 2;
     }
-    // Start from a brick item's walk record (see the item lists); j is then
-    // the brick-local voxel index times unit (the caller's bytes per voxel).
-    __device__ __forceinline__ Stepper(const Ray &r, uint2 rk, int unit) {
+    // Start from a brick item's walk record (see write_item_walk): kxy and
+    // kzv are its packed plane indices, first voxel and entry code.  j is
+    // then the brick-local voxel index times unit (the caller's bytes per
+    // voxel), and [ta, tb] the item's piece of the window [tw0, tw1]: ta is
+    // the crossing of the plane behind the first voxel on the axis the code
+    // names (the face the window entered the brick by), or tw0; tb the
+    // first crossing of the brick's three far faces, or tw1.
+    __device__ __forceinline__ Stepper(const Ray &r, uint32_t kxy, uint32_t kzv, int unit, float tw0, float tw1,
+                                       float &ta, float &tb) {
         const bool px = r.ax > 0.0f, py = r.ay > 0.0f, pz = r.az > 0.0f;  // A has the sign of u
         sx = px ? 1.0f : -1.0f;
         sy = py ? 1.0f : -1.0f;
         sz = pz ? 1.0f : -1.0f;
-        kx = (float)(int16_t)(rk.x & 0xffffu);
-        ky = (float)(int16_t)(rk.x >> 16);
-        kz = (float)(int16_t)(rk.y & 0xffffu);
+        kx = (float)(int16_t)(kxy & 0xffffu);
+        ky = (float)(int16_t)(kxy >> 16);
+        kz = (float)(int16_t)(kzv & 0xffffu);
         tx = fmaf(kx, r.ax, r.bx);
         ty = fmaf(ky, r.ay, r.by);
         tz = fmaf(kz, r.az, r.bz);
-        const int v = (int)(rk.y >> 16);  // brick-local voxel, x fastest
-        j = (kTileBase + (v & (kBrickX - 1)) + kTileSy * ((v / kBrickX) & (kBrickY - 1)) +
-             kTileSz * (v / (kBrickX * kBrickY))) *
-            unit;
+        const int v = (int)((kzv >> 16) & (uint32_t)(kBrickVox - 1));  // brick-local voxel, x fastest
+        const int vx = v & (kBrickX - 1), vy = (v / kBrickX) & (kBrickY - 1), vz = v / (kBrickX * kBrickY);
+        j = (kTileBase + vx + kTileSy * vy + kTileSz * vz) * unit;
         djx = px ? unit : -unit;
         djy = (py ? kTileSy : -kTileSy) * unit;
         djz = (pz ? kTileSz : -kTileSz) * unit;
         max_steps = kBrickX + kBrickY + kBrickZ + 2;
+        const uint32_t code = kzv >> 28;
+        const float ex = fmaf(kx - sx, r.ax, r.bx), ey = fmaf(ky - sy, r.ay, r.by), ez = fmaf(kz - sz, r.az, r.bz);
+        ta = code == 1u ? ex : (code == 2u ? ey : (code == 3u ? ez : tw0));
+        // the far face is (brick edge - 1 - v) planes past the next plane
+        // going up an axis, v planes going down
+        const float qx = fmaf(sx, (float)(px ? kBrickX - 1 - vx : vx), kx);
+        const float qy = fmaf(sy, (float)(py ? kBrickY - 1 - vy : vy), ky);
+        const float qz = fmaf(sz, (float)(pz ? kBrickZ - 1 - vz : vz), kz);
+        tb = fminf(fminf(fminf(fmaf(qx, r.ax, r.bx), fmaf(qy, r.ay, r.by)), fmaf(qz, r.az, r.bz)), tw1);
     }
     __device__ __forceinline__ float next() const { return fminf(fminf(tx, ty), tz); }
     __device__ __forceinline__ void advance(const Ray &r, float tmin) {
@@ -776,17 +790,17 @@ __device__ __forceinline__ unsigned long long fixed_round(float a, double w) {
 // as round(a ws) (ws may be negative; so may a, by ~1e-10 where the
 // interpolated CDF dips between nodes).
 template <bool TOF>
-__device__ __forceinline__ void back_item(const f32x4 &ra, const f32x4 &rb, const u32x2 &rk, float ws, const CdfLin &cdf,
-                                          unsigned long long *tile) {
+__device__ __forceinline__ void back_item(const f32x4 &ra, const u32x4 &rb, float tw0, float tw1, float ws,
+                                          const CdfLin &cdf, unsigned long long *tile) {
     Ray r;
     r.ax = ra[0];
     r.ay = ra[1];
     r.az = ra[2];
-    r.bx = rb[0];
-    r.by = rb[1];
-    r.bz = rb[2];
-    Stepper s(r, make_uint2(rk[0], rk[1]), (int)sizeof(unsigned long long));
-    const float ta = ra[3], tb = rb[3];
+    r.bx = ra[3];
+    r.by = __uint_as_float(rb[0]);
+    r.bz = __uint_as_float(rb[1]);
+    float ta, tb;
+    Stepper s(r, rb[2], rb[3], (int)sizeof(unsigned long long), tw0, tw1, ta, tb);
     // j is a byte offset into the tile, inside its margin (see the tile)
     const double wsd = ws;
     walk_item<TOF>(s, r, ta, tb, cdf, [&](int j, float a) {
@@ -799,18 +813,17 @@ __device__ __forceinline__ void back_chunk_items(const Problem &P, const uint4 &
                                                  unsigned long long *tile) {
     const gptr<const float> w = global(P.pw);
     const gptr<const f32x4> rec_a = global(reinterpret_cast<const f32x4 *>(P.rec_a));
-    const gptr<const f32x4> rec_b = global(reinterpret_cast<const f32x4 *>(P.rec_b));
-    const gptr<const u32x2> rec_k = global(reinterpret_cast<const u32x2 *>(P.rec_k));
+    const gptr<const u32x4> rec_b = global(reinterpret_cast<const u32x4 *>(P.rec_b));
+    const float tw0 = TOF ? -P.k_sigma : -kInf, tw1 = TOF ? P.k_sigma : kInf;
     // An item's weight sits at its own position (the combine pass put it
     // there), so a wavefront reads weights and walk records coalesced.
     for (uint32_t k = ch.y + threadIdx.x; k < ch.z; k += blockDim.x) {
         const float wv = w[k];
         const f32x4 ra = rec_a[k];
-        const f32x4 rb = rec_b[k];
-        const u32x2 rk = rec_k[k];
+        const u32x4 rb = rec_b[k];
         // (no test for w = 0, which adds zeros: a branch here would let
         // the compiler move the record loads behind the weight's)
-        back_item<TOF>(ra, rb, rk, wv * S, cdf, tile);
+        back_item<TOF>(ra, rb, tw0, tw1, wv * S, cdf, tile);
     }
 }
 
@@ -908,23 +921,23 @@ __global__ void __launch_bounds__(kBackBlock) k_forward_items(const Problem *__r
     const CdfLin cdf{lut, in_vgpr(P.lin_a), P.lin_b};
     const gptr<float> pw = global(P.pw);
     const gptr<const f32x4> rec_a = global(reinterpret_cast<const f32x4 *>(P.rec_a));
-    const gptr<const f32x4> rec_b = global(reinterpret_cast<const f32x4 *>(P.rec_b));
-    const gptr<const u32x2> rec_k = global(reinterpret_cast<const u32x2 *>(P.rec_k));
+    const gptr<const u32x4> rec_b = global(reinterpret_cast<const u32x4 *>(P.rec_b));
+    const float tw0 = TOF ? -P.k_sigma : -kInf, tw1 = TOF ? P.k_sigma : kInf;
     for (uint32_t k = ch.y + threadIdx.x; k < ch.z; k += blockDim.x) {
         const f32x4 ra = rec_a[k];
-        const f32x4 rb = rec_b[k];
-        const u32x2 rk = rec_k[k];
+        const u32x4 rb = rec_b[k];
         Ray r;
         r.ax = ra[0];
         r.ay = ra[1];
         r.az = ra[2];
-        r.bx = rb[0];
-        r.by = rb[1];
-        r.bz = rb[2];
-        Stepper s(r, make_uint2(rk[0], rk[1]), (int)sizeof(float));
+        r.bx = ra[3];
+        r.by = __uint_as_float(rb[0]);
+        r.bz = __uint_as_float(rb[1]);
+        float ta, tb;
+        Stepper s(r, rb[2], rb[3], (int)sizeof(float), tw0, tw1, ta, tb);
         float p = 0.0f;
         // j is a byte offset into the tile, inside its margin (see the tile)
-        walk_item<TOF>(s, r, ra[3], rb[3], cdf, [&](int j, float a) {
+        walk_item<TOF>(s, r, ta, tb, cdf, [&](int j, float a) {
             p = fmaf(a, *reinterpret_cast<const float *>(reinterpret_cast<const char *>(tile) + j), p);
         });
         pw[k] = p;
@@ -1324,28 +1337,44 @@ __device__ __forceinline__ void brick_walk(const Problem &P, const Ray &r, Visit
 // and same-address global atomics serialise) and keeps the table; when
 // filling, the block reloads its table, reserves each key's range, and
 // walks its events once, handing out positions from the reserved ranges.
-// Walk record of a brick item at position pos: the crossing coefficients,
-// the piece [ta, tb] of the window inside the brick (as the brick walk cut
-// it) and the first voxel, as the back projection's walk starts from them.
+// Walk record of a brick item at position pos (32 bytes): the crossing
+// coefficients (A_x, A_y, A_z, B_x), (B_y, B_z, k_x | k_y << 16, k_z | v <<
+// 16 | entry << 28) with k the next plane index on each axis minus the
+// anchor's and v the brick-local first voxel.  The item's piece [ta, tb]
+// of the window is not stored: ta is either the window's start (entry 0,
+// with TOF) or the crossing of the brick face the window entered by, which
+// is the plane behind the first voxel on that axis (entry 1, 2, 3 for x, y,
+// z: the brick walk cut the window there, with the same formula); tb is
+// the first crossing of the brick's three far faces, or the window's end.
+// (A brick on the grid's far edge reaches past it: its walk then goes on to
+// the full brick's face through voxels outside the grid, where the forward
+// tile holds zeros and the back projection's sums are not read.)
 __device__ __forceinline__ void write_item_walk(const Problem &P, const Ray &r, int bx, int by, int bz, float ta,
-                                                float tb, uint32_t pos) {
+                                                uint32_t pos) {
     const Box B = brick_box(P, bx, by, bz);
     const int ix = min(max(voxel_at(ta, r.ux, r.jx, r.dx, P.ivx), B.x0), B.x0 + B.nx - 1);
     const int iy = min(max(voxel_at(ta, r.uy, r.jy, r.dy, P.ivy), B.y0), B.y0 + B.ny - 1);
     const int iz = min(max(voxel_at(ta, r.uz, r.jz, r.dz, P.ivz), B.z0), B.z0 + B.nz - 1);
     const int kx = ix + (r.ux > 0.0f) - r.jx, ky = iy + (r.uy > 0.0f) - r.jy, kz = iz + (r.uz > 0.0f) - r.jz;
     const uint32_t j = (uint32_t)((ix - B.x0) + kBrickX * ((iy - B.y0) + kBrickY * (iz - B.z0)));
+    // the face the piece starts on: the candidate crossing equal to ta
+    // (the nearest one, should rounding ever leave none equal)
+    const int sxi = r.ux > 0.0f ? 1 : -1, syi = r.uy > 0.0f ? 1 : -1, szi = r.uz > 0.0f ? 1 : -1;
+    const float dx = fabsf(cross(kx - sxi, 0, r.ax, r.bx) - ta), dy = fabsf(cross(ky - syi, 0, r.ay, r.by) - ta),
+                dz = fabsf(cross(kz - szi, 0, r.az, r.bz) - ta);
+    uint32_t entry = dy < dx ? (dz < dy ? 3u : 2u) : (dz < dx ? 3u : 1u);
+    if (P.tof && ta == -P.k_sigma) entry = 0u;
     // (register copies: element-wise reads of neighbouring Ray fields would
     // otherwise be merged into vector loads that keep the ray off registers)
-    f32x4 a, b;
-    a[0] = in_vgpr(r.ax); a[1] = in_vgpr(r.ay); a[2] = in_vgpr(r.az); a[3] = ta;
-    b[0] = in_vgpr(r.bx); b[1] = in_vgpr(r.by); b[2] = in_vgpr(r.bz); b[3] = tb;
-    u32x2 k;
-    k[0] = ((uint32_t)kx & 0xffffu) | ((uint32_t)ky << 16);
-    k[1] = ((uint32_t)kz & 0xffffu) | (j << 16);
+    f32x4 a;
+    u32x4 b;
+    a[0] = in_vgpr(r.ax); a[1] = in_vgpr(r.ay); a[2] = in_vgpr(r.az); a[3] = in_vgpr(r.bx);
+    b[0] = __float_as_uint(in_vgpr(r.by));
+    b[1] = __float_as_uint(in_vgpr(r.bz));
+    b[2] = ((uint32_t)kx & 0xffffu) | ((uint32_t)ky << 16);
+    b[3] = ((uint32_t)kz & 0xffffu) | (j << 16) | (entry << 28);
     global(reinterpret_cast<f32x4 *>(const_cast<float4 *>(P.rec_a)))[pos] = a;
-    global(reinterpret_cast<f32x4 *>(const_cast<float4 *>(P.rec_b)))[pos] = b;
-    global(reinterpret_cast<u32x2 *>(const_cast<uint2 *>(P.rec_k)))[pos] = k;
+    global(reinterpret_cast<u32x4 *>(const_cast<float4 *>(P.rec_b)))[pos] = b;
 }
 
 // Item class of a brick piece [t0, t1] of ray r by its voxel-plane
@@ -1485,7 +1514,7 @@ __device__ __forceinline__ void brick_items_pass(const Problem &P, int64_t base,
             const uint32_t pos = h >= 0 ? hbase[h] + atomicAdd(&hcnt[h], 1u) : atomicAdd(ctr + key, 1u);
             const bool in = pos < end[key];
             const bool run = h >= 0 && small;
-            if (in) write_item_walk(P, r, bx, by, bz, t0, t1, pos);
+            if (in) write_item_walk(P, r, bx, by, bz, t0, pos);
             // a run item's slot, at its run-order index in the chunk's range
             // of the item lists (the writes of a chunk stay in a few KB)
             if (run) itemslot[c0 + hpre[h] + (pos - hbase[h])] = (uint16_t)(e0 + n - c0);
