@@ -872,7 +872,17 @@ __global__ void __launch_bounds__(256) k_reduce_tiles(const Problem *__restrict_
     // each thread sums kReduceVox voxels, their tiles' loads issued together
     constexpr int kReduceVox = kBrickVox / 4 / 256;
     unsigned long long acc[kReduceVox] = {};
-    for (uint32_t sl = br.y; sl < br.z; ++sl) {
+    uint32_t sl = br.y;
+    for (; sl + 1 < br.z; sl += 2) {  // (two tiles' loads in flight; integer sums, any order)
+        unsigned long long u[2][kReduceVox];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int q = 0; q < kReduceVox; ++q) u[h][q] = tiles[(size_t)(sl + h) * kBrickVox + k0 + threadIdx.x + 256 * q];
+#pragma unroll
+        for (int q = 0; q < kReduceVox; ++q) acc[q] += u[0][q] + u[1][q];
+    }
+    if (sl < br.z) {
 #pragma unroll
         for (int q = 0; q < kReduceVox; ++q) acc[q] += tiles[(size_t)sl * kBrickVox + k0 + threadIdx.x + 256 * q];
     }

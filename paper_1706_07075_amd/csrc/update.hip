@@ -74,6 +74,7 @@ __global__ void __launch_bounds__(kUpdBlock) k_update(const Problem *__restrict_
 }
 
 constexpr int kFinBlock = 1024;
+constexpr int kFinLoads = 16;  // partials per thread in flight
 
 __global__ void __launch_bounds__(kFinBlock) k_finalize(const Problem *__restrict__ probs, int n_probs,
                                                   int64_t n_chunks, int64_t n_vchunks,
@@ -90,13 +91,37 @@ __global__ void __launch_bounds__(kFinBlock) k_finalize(const Problem *__restric
     const int64_t v0 = P.vchunk_begin, v1 = (p + 1 < n_probs) ? probs[p + 1].vchunk_begin : n_vchunks;
     int64_t ne = 0;
     double ll = 0.0, so = 0.0, sn = 0.0;
-    for (int64_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
-        ne += part_neff[c];
-        ll += part_ll[c];
+    // each thread adds its partials in index order; kFinLoads of them are
+    // loaded before they are added, so the loads overlap
+    const int64_t step = (int64_t)blockDim.x;
+    for (int64_t c = c0 + threadIdx.x; c < c1; c += kFinLoads * step) {
+        int nv[kFinLoads];
+        double lv[kFinLoads];
+#pragma unroll
+        for (int u = 0; u < kFinLoads; ++u) {
+            const int64_t k = c + u * step;
+            nv[u] = k < c1 ? part_neff[k] : 0;
+            lv[u] = k < c1 ? part_ll[k] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kFinLoads; ++u) {
+            ne += nv[u];
+            ll += lv[u];
+        }
     }
-    for (int64_t c = v0 + threadIdx.x; c < v1; c += blockDim.x) {
-        so += part_old[c];
-        sn += part_new[c];
+    for (int64_t c = v0 + threadIdx.x; c < v1; c += kFinLoads * step) {
+        double ov[kFinLoads], nw[kFinLoads];
+#pragma unroll
+        for (int u = 0; u < kFinLoads; ++u) {
+            const int64_t k = c + u * step;
+            ov[u] = k < v1 ? part_old[k] : 0.0;
+            nw[u] = k < v1 ? part_new[k] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kFinLoads; ++u) {
+            so += ov[u];
+            sn += nw[u];
+        }
     }
     ne = block_sum(ne, smi);
     ll = block_sum(ll, smd);
