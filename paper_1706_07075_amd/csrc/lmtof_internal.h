@@ -19,7 +19,7 @@ constexpr int kBrickX = 16, kBrickY = 16, kBrickZ = 16;
 constexpr int kBrickVox = kBrickX * kBrickY * kBrickZ;
 // Brick items are grouped by their voxel-plane crossings in the brick
 // (longest first), so that a wavefront's lanes walk similar lengths.
-constexpr int kItemClasses = 16;
+constexpr int kItemClasses = 12;
 // Bytes of one brick item's walk record (two float4 and one uint2).
 constexpr int kItemRecBytes = 32;
 constexpr int kForwardBlock = 256;

@@ -1388,15 +1388,17 @@ __device__ __forceinline__ void write_item_walk(const Problem &P, const Ray &r, 
 }
 
 // Item class of a brick piece [t0, t1] of ray r by its voxel-plane
-// crossings (the voxel walk's step count): 0 for 30 or more, then 26-29,
-// 23-25, 20-22, 18-19, 16-17, 14-15, 12-13, 10-11, 8-9, 6-7, 5, 4, 3, 2
-// and 0-1.  Items of one class walk nearly the same number of steps, so a
-// wavefront's lanes finish together.
+// crossings (the voxel walk's step count): 0 for 32 or more, then 28-31,
+// 25-27, 22-24, 19-21, 16-18, 13-15, 10-12, 7-9, 4-6, 2-3 and 0-1.  Items
+// of one class walk nearly the same number of steps, so a wavefront's
+// lanes finish together; finer classes would cut that divergence further
+// but split a forward chunk's items into more runs, which the combine pass
+// and the list build pay for.
 __device__ __forceinline__ uint32_t item_class(const Problem &P, const Ray &r, float t0, float t1) {
     const int n = abs(voxel_at(t1, r.ux, r.jx, r.dx, P.ivx) - voxel_at(t0, r.ux, r.jx, r.dx, P.ivx)) +
                   abs(voxel_at(t1, r.uy, r.jy, r.dy, P.ivy) - voxel_at(t0, r.uy, r.jy, r.dy, P.ivy)) +
                   abs(voxel_at(t1, r.uz, r.jz, r.dz, P.ivz) - voxel_at(t0, r.uz, r.jz, r.dz, P.ivz));
-    const int edge[kItemClasses - 1] = {30, 26, 23, 20, 18, 16, 14, 12, 10, 8, 6, 5, 4, 3, 2};
+    const int edge[kItemClasses - 1] = {32, 28, 25, 22, 19, 16, 13, 10, 7, 4, 2};
     uint32_t k = 0;
 #pragma unroll
     for (int q = 0; q < kItemClasses - 1; ++q) k += n < edge[q];
