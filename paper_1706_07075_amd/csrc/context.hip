@@ -885,8 +885,11 @@ KeyGeom key_geom(const lmtof_ctx *c, bool sort, const std::vector<Region> &regio
     k.ox = (float)g.x0;
     k.oy = (float)g.y0;
     k.oz = (float)g.z0;
-    k.n_phi = 8;
-    k.n_lam = 4;
+    // direction bins: 4 azimuth x 2 elevation (finer bins made the walks no
+    // faster and the combine pass slower; coarser ones, or one bin, put
+    // more events on each sort key, whose atomics then contend at load)
+    k.n_phi = 4;
+    k.n_lam = 2;
     k.sort = sort ? 1 : 0;
     k.tof = g.tof_fwhm_ps > 0;
     k.half_c = (float)(g.c_mm_per_ps / 2.0);
