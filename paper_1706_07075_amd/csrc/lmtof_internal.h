@@ -69,9 +69,10 @@ struct Problem {
     const float4 *rec_a;
     const float4 *rec_b;
     unsigned long long *tiles;  // 64-bit fixed-point chunk tiles, indexed by tile slot
-    // per problem-local brick: the largest |w| over its items this
-    // iteration (FP32 bits, an unsigned max; cleared before the combine
-    // pass, which sets it), which fixes the brick's fixed-point scale
+    // per problem-local brick: the largest exponent field of |w| over its
+    // items this iteration, as that power of two's FP32 bits (an unsigned
+    // max; cleared before the combine pass, which sets it), which fixes the
+    // brick's fixed-point scale
     uint32_t *bwmax;
     // set (non-zero) by the combine pass when it wrote some item's weight
     // outside the runs, whose maximum it then leaves to launch_brick_wmax
@@ -164,9 +165,10 @@ hipError_t launch_forward_items(const Launch &L, bool tof, const Problem *d_prob
 //   kCombineWeights: w = P.rw[i], times P.evw[i] if set, written to every
 //     item of the event.
 // With kCombineRatio and kCombineWeights, P.bwmax (cleared first by
-// launch_clear_bwmax) receives each brick's largest |w| over the items the
-// pass reached by runs; launch_brick_wmax then adds the items reached
-// through evitems, if there were any (P.gflag).
+// launch_clear_bwmax) receives each brick's largest exponent of |w| (as
+// that power of two's float bits) over the items the pass reached by runs;
+// launch_brick_wmax then adds the items reached through evitems, if there
+// were any (P.gflag).
 enum { kCombineRatio = 0, kCombineF = 1, kCombineWeights = 2 };
 hipError_t launch_combine(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_chunks, int ept, int mode,
                           int *part_neff, double *part_ll);
@@ -174,7 +176,7 @@ hipError_t launch_combine(const Launch &L, const Problem *d_probs, int n_probs, 
 // P.gflag <- 0.
 hipError_t launch_clear_bwmax(const Launch &L, const Problem *d_probs, int n_probs, int64_t n_bricks);
 // After the combine pass, if P.gflag is set: P.bwmax of each brick chunk's
-// brick <- max(itself, the largest |w| over the chunk's items).  A chunk of
+// brick <- max(itself, the largest exponent of |w| over the chunk's items).  A chunk of
 // a problem whose flag is clear returns at once.
 hipError_t launch_brick_wmax(const Launch &L, const Problem *d_probs, int n_probs, const uint4 *chunks,
                              uint32_t n_chunks, const uint4 *bricks);

@@ -962,9 +962,9 @@ __global__ void __launch_bounds__(kBackBlock) k_forward_items(const Problem *__r
 // consecutive positions) into their LDS slots; phase 2 sums each event's
 // slots in ordinal order (the order its window crosses the bricks) and puts
 // its weight in every one of its slots; phase 3 writes the slots back to the
-// items run by run and keeps their |w| in run order; phase 4 takes each
-// brick's largest |w| in LDS, then adds it to P.bwmax (one global atomic per
-// brick the chunk touches).  Events the builder flagged (an item placed
+// items run by run and keeps the exponent field of each |w| in run order;
+// phase 4 takes each brick's largest exponent in LDS, then adds it to
+// P.bwmax (one global atomic per brick the chunk touches).  Events the builder flagged (an item placed
 // outside the runs) are summed and written through evitems in phase 2, and
 // P.gflag is set so that launch_brick_wmax takes their bricks' maxima; a
 // chunk with more than kRunEvents events or kRunItems items takes that path
